@@ -1,0 +1,147 @@
+"""Oracle for cooperative conjugate gradient: plain FP64 CPU code.
+
+TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the library under
+``paper_1204_0069_amd`` never does, and the two share no code.
+
+The arithmetic lives in ``ccg_oracle.c`` (plain loops, FP64, column-major).  This
+module only builds it with gcc, loads it with ctypes and marshals numpy arrays.
+
+Entry points
+------------
+``ccg(A, b, X0, tol, maxit, tau)``
+    Alg. 2 of the paper (cooperative CG, Sec. 3.2) with the Table 1 residual
+    recurrence, the Alg. 3 rank step (mcCG) and the Alg. 4 minimum-residual stop
+    test, in the sign convention R = B - A X.  Returns the final agents X
+    (n x p), the per-step alpha/beta trace if asked, the final R and D if asked,
+    and an info dict.
+``residual(A, b, X)``
+    B - A X in FP64 with plain loops.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ccg_oracle.c")
+_LIB = os.path.join(_HERE, "libccg_oracle.so")
+
+# gcc flags: baseline x86-64 (the library built here also runs on other hosts),
+# no FMA contraction so every product and sum rounds as written.
+GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", "-fno-fast-math"]
+
+ORC_STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_nonfinite",
+              -3: "err_not_spd", -5: "err_nomem"}
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("p_final", ctypes.c_int),
+                ("best_agent", ctypes.c_int), ("deflations", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double)]
+
+
+def build(force: bool = True) -> str:
+    """Compile ccg_oracle.c into libccg_oracle.so next to it (gcc)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def bind(path: str):
+    """Load a compiled oracle library from ``path`` and declare its signatures."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_ccg.restype = ctypes.c_int
+    lib.oracle_ccg.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp, dp,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_int, dp, dp, dp, dp,
+                               ctypes.POINTER(_Info)]
+    lib.oracle_residual.restype = ctypes.c_int
+    lib.oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp,
+                                    dp, ctypes.c_int, dp]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = bind(_LIB)
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _colmajor(A):
+    return np.asfortranarray(np.asarray(A, dtype=np.float64))
+
+
+def ccg(A, b, X0, tol: float, maxit: int, tau: float = 1e-14, trace_k: int = 0,
+        want_rd: bool = False, lib=None) -> dict:
+    """Run the oracle cCG.  A (n x n), b (n,), X0 (n x p) are numpy arrays.
+
+    tol == 0 runs exactly ``maxit`` steps with no stop test.  Returns a dict with
+    X, info fields, and (if asked) alphas/betas of shape (trace_k, p, p) indexed
+    [step, row, col] and the final R, D (n x p).  ``lib`` selects another build of
+    the same source (see ``bind``).
+    """
+    lib = lib or _load()
+    A = _colmajor(A)
+    n = A.shape[0]
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+    X = _colmajor(np.array(X0, dtype=np.float64, copy=True).reshape(n, -1))
+    p = X.shape[1]
+    ta = tb = None
+    if trace_k > 0:
+        ta = np.zeros(trace_k * p * p)
+        tb = np.zeros(trace_k * p * p)
+    Rout = Dout = None
+    if want_rd:
+        Rout = np.zeros(n * p)
+        Dout = np.zeros(n * p)
+    info = _Info()
+    lib.oracle_ccg(n, p, _ptr(A), n, _ptr(b), _ptr(X), n, float(tol), int(maxit),
+                   float(tau), int(trace_k), _ptr(ta), _ptr(tb), _ptr(Rout), _ptr(Dout),
+                   ctypes.byref(info))
+    out = {"X": X, "status": info.status, "status_name": ORC_STATUS.get(info.status, "?"),
+           "iters": info.iters, "restarts": info.restarts, "p_final": info.p_final,
+           "best_agent": info.best_agent, "deflations": info.deflations,
+           "rel_res": info.rel_res, "rel_res_max": info.rel_res_max}
+    if trace_k > 0:
+        # stored column-major per step: element (r, c) at r + c*p
+        out["alphas"] = ta.reshape(trace_k, p, p).transpose(0, 2, 1).copy()
+        out["betas"] = tb.reshape(trace_k, p, p).transpose(0, 2, 1).copy()
+    if want_rd:
+        out["R"] = Rout.reshape(p, n).T.copy()
+        out["D"] = Dout.reshape(p, n).T.copy()
+    return out
+
+
+def residual(A, b, X) -> np.ndarray:
+    """B - A X (n x p) in plain FP64 loops."""
+    lib = _load()
+    A = _colmajor(A)
+    n = A.shape[0]
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+    X = _colmajor(np.asarray(X, dtype=np.float64).reshape(n, -1))
+    p = X.shape[1]
+    T = np.zeros(n * p)
+    st = lib.oracle_residual(n, p, _ptr(A), n, _ptr(b), _ptr(X), n, _ptr(T))
+    if st != 0:
+        raise ValueError(f"oracle_residual: status {st}")
+    return T.reshape(p, n).T.copy()
