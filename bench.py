@@ -1,0 +1,154 @@
+#!/usr/bin/env python3
+"""Benchmark: cooperative CG solves per second on one MI355X.
+
+Workload (one "step" = one complete solve): dense SPD A = Q diag(lam) Q^T with
+n = 8192, lam log-uniform in [1, 1e4] (condition number 1e4 exactly), b and the
+p = 8 starting points N(0,1), seeded; stop when the best agent's explicit FP64
+relative residual is <= 1e-10.  Inputs are resident in HBM before timing starts.
+
+Printed: ONE JSON line with solves/s, ms per solve, p50/p99 solve latency, the
+A.D kernel's achieved HBM bandwidth against the 8 TB/s peak (HIP events around
+every A.D launch, on the library's stream, inside the timed region), and the
+oracle's throughput on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solves/s + A·D HBM GB/s vs peak at rel. residual 1e-10; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x2"])
+    ap.add_argument("--cpu-sample-steps", type=int, default=12,
+                    help="block steps of the oracle timed on the host (0: skip)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not time A.D launches (graphs carry no event nodes)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no "
+                                   "multi-GPU path (see DESIGN.md for how it would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import CCG_PROFILE, Context
+
+    dev = "cuda:0"
+    n, p = args.n, args.p
+    A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", ci.BASE_SEED, base=n), device=dev)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", ci.BASE_SEED, base=n)), device=dev)
+    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", ci.BASE_SEED, base=n)), device=dev)
+    torch.cuda.synchronize()
+
+    ctx = Context(0)
+    flags = 0 if args.no_profile else CCG_PROFILE
+    infos = []
+    for _ in range(args.warmup):
+        ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
+    ctx.kernel_time(reset=True)
+
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        X, info = ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
+        lat.append(time.perf_counter() - s0)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total = t1 - t0
+    ad_ms, ad_launches = ctx.kernel_time(reset=True)
+
+    iters = [i["iters"] for i in infos]
+    # explicit residual of the last result, independent of the library (rocBLAS)
+    T = b[:, None] - A @ X
+    rel = (torch.linalg.norm(T, dim=0) / torch.linalg.norm(b)).cpu().numpy()
+
+    s_a = {"fp64": 8, "fp32": 4, "bf16x2": 4}[args.prec]
+    s_v = 8 if args.prec == "fp64" else 4
+    bytes_per_launch = n * n * s_a + 2 * n * p * s_v
+    roofline = None
+    if ad_launches > 0:
+        avg_s = ad_ms / 1e3 / ad_launches
+        achieved = bytes_per_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "kernel": "k_ad",
+                    "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
+                    "bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if args.cpu_sample_steps > 0:
+        import oracle
+        An = A.cpu().numpy()
+        bn = b.cpu().numpy()
+        Xn = X0.cpu().numpy()
+        c0 = time.perf_counter()
+        oracle.ccg(An, bn, Xn, tol=0.0, maxit=args.cpu_sample_steps)
+        c1 = time.perf_counter()
+        per_step = (c1 - c0) / (args.cpu_sample_steps + 1)   # + the initial residual pass
+        steps_per_solve = float(np.mean(iters)) + 2.0        # + initial and confirming residuals
+        cpu = {"value": round(1.0 / (per_step * steps_per_solve), 6), "unit": "solves/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_sample_steps} block steps of the same n={n}, p={p} system "
+                         f"({c1 - c0:.1f} s, {per_step:.3f} s per A stream); solves/s = 1 / "
+                         f"(s per step x {steps_per_solve:.0f} steps per solve)"}
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / total, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x2": "bf16x2"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"dense SPD n={n}, kappa={args.kappa:g} (log-uniform spectrum), "
+                               f"p={p} agents, {args.prec.upper()} A, tol {args.tol:g}",
+                   "n": n, "p": p, "kappa": args.kappa, "tol": args.tol, "prec": args.prec},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "iters_per_solve": float(np.mean(iters)),
+        "restarts": int(sum(i["restarts"] for i in infos)),
+        "rel_res": float(rel.min()),
+        "status": infos[-1]["status_name"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

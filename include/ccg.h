@@ -1,0 +1,132 @@
+/*
+ * ccg.h -- C interface of the MI355X (gfx950) cooperative conjugate gradient library.
+ *
+ * The method is Alg. 2 of Bhaya, Bliman, Niedu and Pazos, "A cooperative conjugate
+ * gradient method for linear systems permitting multithread implementation of low
+ * complexity" (cCG, Sec. 3.2): p agents each hold an estimate x_j, a residual r_j
+ * and a direction d_j of the dense SPD system A x = b, and cooperate through the
+ * p x p matrix step sizes
+ *     alpha = (D^T A D)^{-1} D^T R,    beta = -(D^T A D)^{-1} (A D)^T R_new
+ * (written here in the sign convention R = B - A X, B = b in every column; the
+ * paper uses the gradient A X - B, which negates R and D and transposes alpha and
+ * beta).  The residual follows the Table 1 recurrence R -= (A D) alpha, the rank
+ * step follows Alg. 3 (mcCG), and the stop test is the minimum over agents of
+ * ||r_j|| / ||b|| (Alg. 4), confirmed by the explicit FP64 residual.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Every matrix is column-major.  A is n x n with leading dimension lda >= n;
+ *    X is n x p with leading dimension ldx >= n, column j = agent j.  A must be
+ *    symmetric positive definite; it is read as given (never symmetrised).
+ *  - Pointers are DEVICE pointers on the context's device (e.g. torch tensor
+ *    data_ptr()), unless opts->flags has CCG_HOST_PTRS, in which case they are host
+ *    pointers and are copied in and out.  The caller owns A, b and X; the library
+ *    owns all of its workspace (vector blocks, partial sums, low-precision copies of
+ *    A) and frees it in ccg_destroy.
+ *  - All work is enqueued on the context's stream; every call returns after the
+ *    result is available on that stream (the library synchronises it).
+ *  - Nothing throws across this interface.  Every call returns a ccg_status; on
+ *    failure ccg_last_error(ctx) describes it.  A context is not thread safe.
+ *  - 1 <= p <= min(n, 16).  Agent counts are padded internally to 1, 2, 4, 8 or
+ *    16; padded agents are inactive.
+ */
+#ifndef CCG_H
+#define CCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCG_OK = 0,              /* converged: min_j explicit ||b - A x_j|| / ||b|| <= tol */
+    CCG_NOT_CONVERGED = 1,   /* maxit reached; X holds the last iterate (a warning) */
+    CCG_ERR_ARG = -1,        /* bad argument (sizes, null pointer, tol <= 0, b == 0) */
+    CCG_ERR_NONFINITE = -2,  /* NaN / Inf met in a residual norm or a Gram matrix */
+    CCG_ERR_NOT_SPD = -3,    /* D^T A D not positive for a nonzero direction */
+    CCG_ERR_BREAKDOWN = -4,  /* refinement made no progress */
+    CCG_ERR_NOMEM = -5,      /* device allocation failed or HBM budget exceeded */
+    CCG_ERR_DEVICE = -6,     /* a HIP call failed */
+    CCG_PENDING = -7,        /* served request still running */
+    CCG_CANCELLED = -8       /* served request cancelled */
+} ccg_status;
+
+typedef enum {
+    CCG_FP64 = 0,    /* A streamed in FP64, FP64 vectors: plain cCG */
+    CCG_FP32 = 1,    /* A streamed in FP32 inside an FP64 iterative-refinement loop */
+    CCG_BF16X2 = 2   /* A streamed as BF16 hi + lo planes (FP32 accumulation), FP64 refinement */
+} ccg_prec;
+
+#define CCG_HOST_PTRS 0x1u   /* A, b, X are host pointers */
+#define CCG_NO_GRAPH  0x2u   /* launch every kernel directly (no captured graph) */
+#define CCG_PROFILE   0x4u   /* time every A.D launch with HIP events (ccg_kernel_time) */
+
+/* Solver options; a zero-initialised struct selects the defaults shown. */
+typedef struct {
+    int prec;            /* ccg_prec; default CCG_FP64 */
+    double inner_tol;    /* low-precision modes: inner relative tolerance (default 1e-4) */
+    int inner_maxit;     /* low-precision modes: block steps per refinement (default 500) */
+    int max_refine;      /* low-precision modes: outer refinement steps (default 60) */
+    double rank_tau;     /* rank threshold on scaled pivots (default 1e-14) */
+    int graph_k;         /* block steps per captured graph / per host poll (default 16) */
+    unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE */
+} ccg_opts;
+
+/* Per-solve report. */
+typedef struct {
+    int status;          /* same as the return value */
+    int iters;           /* block steps (all refinements and restarts included) */
+    int refinements;     /* outer refinement steps (0 in FP64 mode) */
+    int restarts;        /* explicit-residual restarts */
+    int p_final;         /* agents still active at the end */
+    int best_agent;      /* argmin_j of the explicit residual */
+    int deflations;      /* rank-drop events (Alg. 3) */
+    int reserved;
+    double rel_res;      /* min_j ||b - A x_j|| / ||b||, explicit FP64 */
+    double rel_res_max;  /* max_j of the same */
+    double seconds;      /* wall time of the solve inside the library */
+    double bytes_A;      /* algorithmic bytes of A streamed (all precisions) */
+} ccg_info;
+
+typedef struct ccg_ctx ccg_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the library's own
+ * device allocations (0: no cap).  hip_stream: a hipStream_t to enqueue on, or NULL
+ * for a stream the context creates (default priority).  Returns CCG_ERR_DEVICE if
+ * the device cannot be used. */
+ccg_status ccg_create(ccg_ctx **ctx, int device, size_t hbm_budget_bytes, void *hip_stream);
+
+/* Free the context and all of its device memory.  NULL is accepted. */
+ccg_status ccg_destroy(ccg_ctx *ctx);
+
+/* Last error message of this context ("" if none).  Owned by the context. */
+const char *ccg_last_error(const ccg_ctx *ctx);
+
+/* Solve A x = b with p cooperating agents (Alg. 2 + Alg. 3, stop test of Alg. 4).
+ * X: in, the p starting points X0; out, the final p agents.  tol > 0 is relative
+ * to ||b||; maxit bounds the block steps.  opts and info may be NULL. */
+ccg_status ccg_solve(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
+                     const double *b, double *X, int64_t ldx, double tol, int maxit,
+                     const ccg_opts *opts, ccg_info *info);
+
+/* Run exactly ksteps block steps of FP64 cCG from X (no stop test) and report each
+ * step's alpha and beta (ksteps x p x p; step k at offset k*p*p, element (r, c) at
+ * r + c*p, i.e. column-major; X[:,c] += sum_r D[:,r] alpha[r,c]) and the final
+ * X, R and D (n x p column-major with leading dimension n for R and D, ldx for X).
+ * For step-by-step comparison with a reference implementation. */
+ccg_status ccg_debug_step(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
+                          const double *b, double *X, int64_t ldx, int ksteps,
+                          const ccg_opts *opts, double *alphas, double *betas,
+                          double *R, double *D);
+
+/* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
+ * block steps run with CCG_PROFILE since the last reset; reset != 0 clears them. */
+ccg_status ccg_kernel_time(ccg_ctx *ctx, double *ms, long long *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCG_H */

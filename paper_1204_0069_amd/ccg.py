@@ -1,0 +1,189 @@
+"""Python binding of libccg.so (include/ccg.h): argument marshalling only.
+
+Every step of the solve runs in the HIP kernels of the library; torch provides the
+device buffers.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccg.so")
+
+CCG_HOST_PTRS = 0x1
+CCG_NO_GRAPH = 0x2
+CCG_PROFILE = 0x4
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
+
+STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_nonfinite", -3: "err_not_spd",
+          -4: "err_breakdown", -5: "err_nomem", -6: "err_device", -7: "pending", -8: "cancelled"}
+
+
+class CcgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("inner_maxit", ctypes.c_int), ("max_refine", ctypes.c_int),
+                ("rank_tau", ctypes.c_double), ("graph_k", ctypes.c_int),
+                ("flags", ctypes.c_uint)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("refinements", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("p_final", ctypes.c_int), ("best_agent", ctypes.c_int),
+                ("deflations", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("bytes_A", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+_lib = None
+
+# Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
+EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
+           "ccg_kernel_time")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libccg.so (after torch, so both share one HIP runtime) and declare signatures."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1204_0069_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lib.ccg_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, vp]
+    lib.ccg_create.restype = ctypes.c_int
+    lib.ccg_destroy.argtypes = [vp]
+    lib.ccg_destroy.restype = ctypes.c_int
+    lib.ccg_last_error.argtypes = [vp]
+    lib.ccg_last_error.restype = ctypes.c_char_p
+    lib.ccg_solve.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64,
+                              ctypes.c_double, ctypes.c_int, ctypes.POINTER(Opts),
+                              ctypes.POINTER(Info)]
+    lib.ccg_solve.restype = ctypes.c_int
+    lib.ccg_debug_step.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64,
+                                   ctypes.c_int, ctypes.POINTER(Opts), dp, dp, dp, dp]
+    lib.ccg_debug_step.restype = ctypes.c_int
+    lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
+    lib.ccg_kernel_time.restype = ctypes.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _colmajor_matrix(A: torch.Tensor):
+    """(pointer, lda) of a column-major view of A.  A row-major contiguous tensor is
+    read as its own transpose, which is A itself for the symmetric matrices the method
+    requires."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    if A.dtype != torch.float64:
+        raise TypeError("A must be float64")
+    n = A.shape[0]
+    if A.stride(0) == 1 and A.stride(1) >= n:
+        return A.data_ptr(), A.stride(1), A
+    if A.stride(1) == 1 and A.stride(0) >= n:
+        return A.data_ptr(), A.stride(0), A
+    Ac = A.contiguous()
+    return Ac.data_ptr(), n, Ac
+
+
+def make_opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_refine=0, rank_tau=0.0,
+              graph_k=0, flags=0) -> Opts:
+    return Opts(PREC[prec] if isinstance(prec, str) else int(prec), float(inner_tol),
+                int(inner_maxit), int(max_refine), float(rank_tau), int(graph_k), int(flags))
+
+
+class Context:
+    """A library context on one GPU (its own HIP stream, default priority)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.ccg_create(ctypes.byref(h), device, hbm_budget, None)
+        if st != 0:
+            raise CcgError(st, "ccg_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ccg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st):
+        return CcgError(st, self.lib.ccg_last_error(self.h).decode())
+
+    def solve(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, tol: float,
+              maxit: int, raise_on_error: bool = True, **opts):
+        """Solve A x = b with X0.shape[1] agents.  Returns (X, info dict); X is n x p."""
+        aptr, lda, keep = _colmajor_matrix(A)
+        n = A.shape[0]
+        b = b.reshape(-1).to(device=A.device, dtype=torch.float64).contiguous()
+        Xt = X0.to(device=A.device, dtype=torch.float64).t().contiguous()   # p x n = col-major n x p
+        p = Xt.shape[0]
+        o = make_opts(**opts)
+        info = Info()
+        torch.cuda.synchronize(A.device)
+        st = self.lib.ccg_solve(self.h, n, p, aptr, lda, b.data_ptr(), Xt.data_ptr(), n,
+                                float(tol), int(maxit), ctypes.byref(o), ctypes.byref(info))
+        if st < 0 and raise_on_error:
+            raise self._err(st)
+        del keep
+        return Xt.t(), info.as_dict()
+
+    def debug_step(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, ksteps: int,
+                   rank_tau: float = 0.0):
+        """Exactly ksteps FP64 block steps; returns dict of X, R, D (n x p, CPU float64)
+        and alphas, betas (ksteps x p x p, [step, row, col])."""
+        aptr, lda, keep = _colmajor_matrix(A)
+        n = A.shape[0]
+        b = b.reshape(-1).to(device=A.device, dtype=torch.float64).contiguous()
+        Xt = X0.to(device=A.device, dtype=torch.float64).t().contiguous()
+        p = Xt.shape[0]
+        R = torch.zeros(p, n, dtype=torch.float64, device=A.device)
+        D = torch.zeros(p, n, dtype=torch.float64, device=A.device)
+        al = (ctypes.c_double * max(1, ksteps * p * p))()
+        be = (ctypes.c_double * max(1, ksteps * p * p))()
+        o = make_opts(rank_tau=rank_tau)
+        torch.cuda.synchronize(A.device)
+        dptr = ctypes.POINTER(ctypes.c_double)
+        st = self.lib.ccg_debug_step(self.h, n, p, aptr, lda, b.data_ptr(), Xt.data_ptr(), n,
+                                     int(ksteps), ctypes.byref(o), al, be,
+                                     ctypes.cast(R.data_ptr(), dptr), ctypes.cast(D.data_ptr(), dptr))
+        if st < 0:
+            raise self._err(st)
+        del keep
+        import numpy as np
+        a = np.frombuffer(al, dtype=np.float64)[: ksteps * p * p].reshape(ksteps, p, p)
+        bb = np.frombuffer(be, dtype=np.float64)[: ksteps * p * p].reshape(ksteps, p, p)
+        return {"X": Xt.t().cpu(), "R": R.t().cpu(), "D": D.t().cpu(),
+                "alphas": a.transpose(0, 2, 1).copy(), "betas": bb.transpose(0, 2, 1).copy()}
+
+    def kernel_time(self, reset: bool = False):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_longlong()
+        self.lib.ccg_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(cnt), int(reset))
+        return ms.value, cnt.value

@@ -1,0 +1,104 @@
+// Internal device-side definitions shared by the HIP kernels and the host driver.
+//
+// Vectors X, R, D, AD live on the device as n_pad x P row-major blocks ("agent
+// interleaved": the P values of one row are contiguous), with P the agent count p
+// rounded up to 1, 2, 4, 8 or 16 and n_pad = n rounded up to a multiple of 512.
+// Rows >= n and columns >= p are kept at zero, so elementwise kernels need no
+// guards and sums over padded rows only add exact zeros.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccg {
+
+constexpr int kMaxP = 16;       // largest padded agent count
+constexpr int kWG = 256;        // threads per workgroup for every kernel
+constexpr int kRowAlign = 512;  // n_pad granularity (largest row tile)
+
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
+
+// Device iteration state, one per solve.  Written only by "last workgroup"
+// epilogues and by the residual kernel; read by every kernel at entry.
+enum Done : int { RUNNING = 0, RECUR_CONV = 1, FINISHED = 2, MAXIT = 3, FAILED = 4 };
+
+struct DevState {
+    int done;          // Done code; kernels are no-ops while done != RUNNING
+    int iter;          // completed block steps
+    int m;             // active agent count (rank of the last accepted D)
+    int status;        // failure code (ccg_status) when done == FAILED
+    unsigned mask;     // bit j set <=> agent j active
+    int deflations;    // rank-drop events
+    int restarts;      // explicit-residual restarts
+    int maxit;         // stop after this many block steps
+    double nb;         // ||b||_2 (for a refinement inner solve: 1, columns are scaled)
+    double tol;        // relative stop tolerance on min_j ||R_j|| / nb
+    double tau;        // rank threshold on the scaled pivots
+    double minres;     // min over active agents of ||R_j|| / nb (last test)
+    int keep[kMaxP];   // active agents, ascending (first m entries)
+    double norms[kMaxP];                 // ||R_j|| per agent (last computed)
+    double alpha[kMaxP * kMaxP];         // alpha[l*kMaxP + j]: X[:,j] += D[:,l] alpha[l][j]
+    double beta[kMaxP * kMaxP];          // beta[l*kMaxP + j]:  D[:,j] = R[:,j] + D[:,l] beta[l][j]
+    double S[kMaxP * kMaxP];             // D^T R for the next alpha (full P x P, zeros off J)
+    double Lc[kMaxP * kMaxP];            // Cholesky factor of G restricted to keep[], compact m x m
+    unsigned cnt_all;                    // last-workgroup tickets (reset by the last one)
+    unsigned cnt_upd;
+    unsigned cnt_res;
+    unsigned pad_;
+};
+
+// Arguments of the A.D stream kernel.
+struct AdArgs {
+    const void* A;       // FP64 / FP32 matrix, or the BF16 "hi" plane; column-major, lda
+    const void* A_lo;    // BF16 "lo" plane (bf16x2 only)
+    int64_t lda;         // leading dimension in elements
+    int n;               // system size
+    int n_pad;           // padded row count of the vector blocks
+    int nks;             // column splits (workgroups per row tile)
+    int kc;              // columns per split
+    int ntiles;          // row tiles
+    int product_only;    // 1: only form Y = A.V (residual); 0: also Gram + alpha
+    const void* V;       // operand block (n_pad x P row-major, vector type)
+    void* part;          // nks x n_pad x P partial products (accumulator type)
+    void* AD;            // n_pad x P result (vector type)
+    double* gpart;       // ntiles x P x P Gram partials
+    unsigned* cnt_tile;  // ntiles tickets
+    DevState* st;
+};
+
+struct UpdArgs {
+    int n_pad;
+    int nblk;            // workgroups
+    void* X;             // n_pad x P (vector type)
+    void* R;
+    const void* D;
+    const void* AD;
+    double* upart;       // nblk x 3 x P x P partials
+    DevState* st;
+};
+
+struct DirArgs {
+    int n_pad;
+    const void* R;
+    void* D;
+    const DevState* st;
+};
+
+// Residual epilogue: T = B - Y, with B = b in every column (FP64).
+enum ResMode : int { RES_INIT = 0, RES_CONFIRM = 1, RES_FINAL = 2 };
+
+struct ResArgs {
+    int n_pad;
+    int nblk;
+    int p;               // true agent count (columns >= p ignored)
+    int mode;            // ResMode
+    int set_nb;          // 1: also set st->nb = ||b||
+    const double* b;     // n_pad (zero padded)
+    const double* Y;     // n_pad x P: A X
+    double* R;           // n_pad x P (written in INIT / CONFIRM)
+    double* D;
+    double* rpart;       // nblk x (P x P + 1) partials of T^T T and b^T b
+    DevState* st;
+};
+
+}  // namespace ccg

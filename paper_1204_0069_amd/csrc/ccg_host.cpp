@@ -1,0 +1,600 @@
+// Host driver and C interface (include/ccg.h) of the cooperative CG library.
+//
+// The driver owns one workspace per context, sized for the largest solve so far.
+// A solve is: pack X0 into the row-major agent block, form R0 = B - A X0 (an A
+// stream plus the residual epilogue), then repeat groups of block steps
+// (k_ad, k_upd, k_dir) -- captured once into a HIP graph and replayed -- polling
+// the device state between groups.  When the recurrence residual passes the test,
+// the explicit FP64 residual confirms it or restarts the agents from it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ccg.h"
+#include "ccg_device.h"
+
+namespace ccg {
+hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s);
+hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s);
+hipError_t launch_dir(int prec, int P, const DirArgs& a, hipStream_t s);
+hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
+hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,
+                       hipStream_t s);
+hipError_t launch_unpack(int n, int p, int P, const double* Xr, double* X, int64_t ldx,
+                         hipStream_t s);
+hipError_t launch_pad_vec(int n, int n_pad, const double* b, double* bp, hipStream_t s);
+int ad_tile_rows(int prec);
+}  // namespace ccg
+
+using namespace ccg;
+
+namespace {
+
+struct CcgError {
+    ccg_status st;
+    std::string msg;
+};
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw CcgError{CCG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+int pad_agents(int p) {
+    int P = 1;
+    while (P < p) P <<= 1;
+    return P;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Geometry of the A.D launch for one (n, precision).
+struct AdGeom {
+    int tm, ntiles, nks, kc;
+};
+
+AdGeom ad_geometry(int n, int prec, int target_wgs) {
+    AdGeom g;
+    g.tm = ad_tile_rows(prec);
+    g.ntiles = (int)((n + g.tm - 1) / g.tm);
+    int nks = std::max(1, (target_wgs + g.ntiles - 1) / g.ntiles);
+    nks = std::min(nks, std::max(1, n / 64));           // at least ~16 columns per wave
+    g.kc = (int)round_up((n + nks - 1) / nks, 4);
+    g.nks = (n + g.kc - 1) / g.kc;
+    return g;
+}
+
+struct Workspace {
+    int n = 0, n_pad = 0, P = 0, nks = 0, ntiles = 0;
+    size_t bytes = 0;
+    void* base = nullptr;            // one allocation, carved
+    double* Xr = nullptr;            // n_pad x P (FP64 agents)
+    double* bp = nullptr;            // n_pad
+    double* R = nullptr;             // n_pad x P
+    double* D = nullptr;
+    double* AD = nullptr;
+    void* part = nullptr;            // nks x n_pad x P (FP64)
+    double* gpart = nullptr;         // ntiles x P x P
+    double* upart = nullptr;         // nblk_upd x 3 P^2
+    double* rpart = nullptr;         // nblk_res x (P^2 + 1)
+    unsigned* cnt_tile = nullptr;    // ntiles
+    DevState* st = nullptr;
+};
+
+struct Carver {
+    char* p;
+    size_t off = 0;
+    template <class T> T* take(size_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* r = reinterpret_cast<T*>(p ? p + off : nullptr);
+        off += count * sizeof(T);
+        return r;
+    }
+};
+
+}  // namespace
+
+struct ccg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    std::string err;
+    Workspace ws;
+    DevState* st_host = nullptr;     // pinned mirror of the device state
+    // A.D timing (CCG_PROFILE)
+    double prof_ms = 0.0;
+    long long prof_launches = 0;
+    std::vector<hipEvent_t> ev_pool;
+    // captured block-step graph
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    int64_t graph_key[7] = {0, 0, 0, 0, 0, 0, 0};
+    bool graph_events_ok = true;     // runtime captures event records into graphs
+};
+
+namespace {
+
+void free_workspace(ccg_ctx* c) {
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    if (c->ws.base) (void)hipFree(c->ws.base);
+    c->ws = Workspace();
+}
+
+// Lay out (or only size, when base == nullptr) the workspace.
+size_t carve(Workspace& w, char* base, int n_pad, int P, int nks, int ntiles) {
+    Carver cv{base};
+    const int nblk_upd = n_pad / (P <= 8 ? kWG : kWG / 2);
+    w.Xr = cv.take<double>((size_t)n_pad * P);
+    w.bp = cv.take<double>((size_t)n_pad);
+    w.R = cv.take<double>((size_t)n_pad * P);
+    w.D = cv.take<double>((size_t)n_pad * P);
+    w.AD = cv.take<double>((size_t)n_pad * P);
+    w.part = cv.take<double>((size_t)nks * n_pad * P);
+    w.gpart = cv.take<double>((size_t)ntiles * P * P);
+    w.upart = cv.take<double>((size_t)nblk_upd * 3 * P * P);
+    w.rpart = cv.take<double>((size_t)nblk_upd * (P * P + 1));
+    w.cnt_tile = cv.take<unsigned>((size_t)ntiles);
+    w.st = cv.take<DevState>(1);
+    return cv.off;
+}
+
+void ensure_workspace(ccg_ctx* c, int n, int P, const AdGeom& g) {
+    const int n_pad = (int)round_up(n, kRowAlign);
+    Workspace& w = c->ws;
+    if (w.base && w.n_pad == n_pad && w.P == P && w.nks == g.nks && w.ntiles == g.ntiles) {
+        w.n = n;
+        return;
+    }
+    free_workspace(c);
+    Workspace nw;
+    const size_t bytes = carve(nw, nullptr, n_pad, P, g.nks, g.ntiles);
+    if (c->budget && bytes > c->budget)
+        throw CcgError{CCG_ERR_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget"};
+    void* base = nullptr;
+    if (hipMalloc(&base, bytes) != hipSuccess)
+        throw CcgError{CCG_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    HIP_OK(hipMemsetAsync(base, 0, bytes, c->stream));
+    carve(nw, static_cast<char*>(base), n_pad, P, g.nks, g.ntiles);
+    nw.base = base;
+    nw.bytes = bytes;
+    nw.n = n;
+    nw.n_pad = n_pad;
+    nw.P = P;
+    nw.nks = g.nks;
+    nw.ntiles = g.ntiles;
+    w = nw;
+}
+
+struct Solve {
+    ccg_ctx* c;
+    int n, p, P, prec;
+    const void* A;
+    const void* A_lo;
+    int64_t lda;
+    AdGeom g;
+    bool profile;
+};
+
+AdArgs ad_args(const Solve& s, const void* V, bool product_only) {
+    const Workspace& w = s.c->ws;
+    AdArgs a;
+    a.A = s.A;
+    a.A_lo = s.A_lo;
+    a.lda = s.lda;
+    a.n = s.n;
+    a.n_pad = w.n_pad;
+    a.nks = s.g.nks;
+    a.kc = s.g.kc;
+    a.ntiles = s.g.ntiles;
+    a.product_only = product_only ? 1 : 0;
+    a.V = V;
+    a.part = w.part;
+    a.AD = w.AD;
+    a.gpart = w.gpart;
+    a.cnt_tile = w.cnt_tile;
+    a.st = w.st;
+    return a;
+}
+
+void enqueue_residual(const Solve& s, int mode, int set_nb) {
+    Workspace& w = s.c->ws;
+    // Y = A X in FP64 (the residual is always FP64)
+    Solve s64 = s;
+    s64.prec = PREC_F64;
+    HIP_OK(launch_ad(PREC_F64, s.P, ad_args(s64, w.Xr, true), s.c->stream));
+    ResArgs r;
+    r.n_pad = w.n_pad;
+    r.nblk = w.n_pad / (s.P <= 8 ? kWG : kWG / 2);
+    r.p = s.p;
+    r.mode = mode;
+    r.set_nb = set_nb;
+    r.b = w.bp;
+    r.Y = w.AD;
+    r.R = w.R;
+    r.D = w.D;
+    r.rpart = w.rpart;
+    r.st = w.st;
+    HIP_OK(launch_res(s.P, r, s.c->stream));
+}
+
+hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
+    while (c->ev_pool.size() <= i) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[i];
+}
+
+// One block step: A.D (+ Gram, rank step, alpha), update (+ beta), direction.
+void enqueue_step(const Solve& s, size_t ev_slot) {
+    Workspace& w = s.c->ws;
+    if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot), s.c->stream));
+    HIP_OK(launch_ad(s.prec, s.P, ad_args(s, w.D, false), s.c->stream));
+    if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot + 1), s.c->stream));
+    UpdArgs u;
+    u.n_pad = w.n_pad;
+    u.nblk = w.n_pad / (s.P <= 8 ? kWG : kWG / 2);
+    u.X = w.Xr;
+    u.R = w.R;
+    u.D = w.D;
+    u.AD = w.AD;
+    u.upart = w.upart;
+    u.st = w.st;
+    HIP_OK(launch_upd(s.prec, s.P, u, s.c->stream));
+    DirArgs d;
+    d.n_pad = w.n_pad;
+    d.R = w.R;
+    d.D = w.D;
+    d.st = w.st;
+    HIP_OK(launch_dir(s.prec, s.P, d, s.c->stream));
+}
+
+void read_state(ccg_ctx* c) {
+    HIP_OK(hipMemcpyAsync(c->st_host, c->ws.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+}
+
+void write_state(ccg_ctx* c) {
+    HIP_OK(hipMemcpyAsync(c->ws.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+}
+
+void collect_profile(ccg_ctx* c, int steps) {
+    for (int i = 0; i < steps; ++i) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+    }
+}
+
+// Capture `steps` block steps into c->graph.  With profiling, an event pair
+// brackets every A.D launch inside the graph.  Returns false (and leaves no graph)
+// if the runtime refuses to capture the event records.
+bool capture_steps(Solve& s, int steps) {
+    ccg_ctx* c = s.c;
+    if (s.profile) (void)pooled_event(c, 2 * (size_t)steps - 1);   // create before capture
+    hipGraph_t gr = nullptr;
+    HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    bool ok = true;
+    try {
+        for (int i = 0; i < steps; ++i) enqueue_step(s, s.profile ? (size_t)i : 0);
+    } catch (const CcgError&) {
+        ok = false;
+    }
+    const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (!ok || e != hipSuccess || !gr) {
+        (void)hipGetLastError();
+        if (gr) (void)hipGraphDestroy(gr);
+        if (!s.profile) throw CcgError{CCG_ERR_DEVICE, "stream capture of the block step failed"};
+        return false;
+    }
+    HIP_OK(hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0));
+    HIP_OK(hipGraphDestroy(gr));
+    return true;
+}
+
+// Run `steps` block steps, through a captured graph when allowed.
+void run_steps(Solve& s, int steps, bool use_graph) {
+    ccg_ctx* c = s.c;
+    if (!use_graph || (s.profile && !c->graph_events_ok)) {
+        for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i);
+        return;
+    }
+    const int64_t key[7] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
+                            s.lda, s.profile ? 1 : 0};
+    const bool same = c->graph && c->graph_k == steps && std::equal(key, key + 7, c->graph_key);
+    if (!same) {
+        if (c->graph) { HIP_OK(hipGraphExecDestroy(c->graph)); c->graph = nullptr; }
+        if (!capture_steps(s, steps)) {
+            c->graph_events_ok = false;
+            for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i);
+            return;
+        }
+        c->graph_k = steps;
+        std::copy(key, key + 7, c->graph_key);
+    }
+    HIP_OK(hipGraphLaunch(c->graph, c->stream));
+}
+
+void check_common(int n, int p, const void* A, int64_t lda, const void* b, const void* X, int64_t ldx) {
+    if (n < 1 || p < 1 || p > kMaxP || p > n)
+        throw CcgError{CCG_ERR_ARG, "need 1 <= p <= min(n, 16)"};
+    if (!A || !b || !X) throw CcgError{CCG_ERR_ARG, "null pointer argument"};
+    if (lda < n || ldx < n) throw CcgError{CCG_ERR_ARG, "leading dimension smaller than n"};
+}
+
+// Host-pointer staging (CCG_HOST_PTRS): device copies of A, b, X.
+struct Staged {
+    double *A = nullptr, *b = nullptr, *X = nullptr;
+    ~Staged() {
+        if (A) (void)hipFree(A);
+        if (b) (void)hipFree(b);
+        if (X) (void)hipFree(X);
+    }
+};
+
+void stage_in(ccg_ctx* c, Staged& sg, int n, int p, const double*& A, int64_t& lda, const double*& b,
+              double*& X, int64_t& ldx) {
+    HIP_OK(hipMalloc(&sg.A, sizeof(double) * (size_t)n * n));
+    HIP_OK(hipMalloc(&sg.b, sizeof(double) * (size_t)n));
+    HIP_OK(hipMalloc(&sg.X, sizeof(double) * (size_t)n * p));
+    HIP_OK(hipMemcpy2DAsync(sg.A, sizeof(double) * n, A, sizeof(double) * lda, sizeof(double) * n, n,
+                            hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(sg.b, b, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpy2DAsync(sg.X, sizeof(double) * n, X, sizeof(double) * ldx, sizeof(double) * n, p,
+                            hipMemcpyHostToDevice, c->stream));
+    A = sg.A;
+    lda = n;
+    b = sg.b;
+    X = sg.X;
+    ldx = n;
+}
+
+// Plain FP64 cCG on device buffers; fills info.
+ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+                      double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
+    const int P = pad_agents(p);
+    Solve s{c, n, p, P, PREC_F64, A, nullptr, lda, ad_geometry(n, PREC_F64, 1024),
+            (o.flags & CCG_PROFILE) != 0};
+    ensure_workspace(c, n, P, s.g);
+    Workspace& w = c->ws;
+    HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
+    HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
+    DevState& h = *c->st_host;
+    std::memset(&h, 0, sizeof(DevState));
+    h.done = RUNNING;
+    h.m = p;
+    h.mask = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
+    for (int j = 0; j < p; ++j) h.keep[j] = j;
+    h.maxit = maxit;
+    h.tol = tol;
+    h.tau = o.rank_tau;
+    h.nb = 1.0;
+    write_state(c);
+    enqueue_residual(s, RES_INIT, 1);
+    read_state(c);
+    const double bytes_iter = (double)n * n * sizeof(double);
+    double bytes = bytes_iter;   // the initial residual
+    const bool use_graph = !(o.flags & CCG_NO_GRAPH);
+    const int gk = o.graph_k > 0 ? o.graph_k : 16;
+    while (h.done == RUNNING || h.done == RECUR_CONV) {
+        if (h.done == RUNNING) {
+            const int left = maxit - h.iter;
+            const int k = std::min(gk, std::max(left, 1));
+            const int it0 = h.iter;
+            run_steps(s, k, use_graph);
+            read_state(c);
+            if (s.profile) collect_profile(c, h.iter - it0);
+            bytes += bytes_iter * (h.iter - it0);
+        }
+        if (h.done == RECUR_CONV) {
+            enqueue_residual(s, RES_CONFIRM, 0);
+            read_state(c);
+            bytes += bytes_iter;
+        }
+    }
+    if (h.done == MAXIT) {
+        enqueue_residual(s, RES_FINAL, 0);
+        read_state(c);
+        bytes += bytes_iter;
+    }
+    HIP_OK(launch_unpack(n, p, P, w.Xr, X, ldx, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    ccg_status st = CCG_OK;
+    if (h.done == FAILED) st = (ccg_status)h.status;
+    else if (h.done == MAXIT) st = CCG_NOT_CONVERGED;
+    info.status = st;
+    info.iters = h.iter;
+    info.refinements = 0;
+    info.restarts = h.restarts;
+    info.p_final = h.m;
+    info.deflations = h.deflations;
+    double mn = INFINITY, mx = 0.0;
+    int best = -1;
+    for (int j = 0; j < p; ++j) {
+        const double r = h.norms[j] / h.nb;
+        if (r < mn) { mn = r; best = j; }
+        if (r > mx) mx = r;
+    }
+    info.best_agent = best;
+    info.rel_res = mn;
+    info.rel_res_max = mx;
+    info.bytes_A = bytes;
+    return st;
+}
+
+ccg_opts fill_defaults(const ccg_opts* in) {
+    ccg_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (in) o = *in;
+    if (o.inner_tol <= 0.0) o.inner_tol = 1e-4;
+    if (o.inner_maxit <= 0) o.inner_maxit = 500;
+    if (o.max_refine <= 0) o.max_refine = 60;
+    if (o.rank_tau <= 0.0) o.rank_tau = 1e-14;
+    if (o.graph_k <= 0) o.graph_k = 16;
+    return o;
+}
+
+template <class F>
+ccg_status guarded(ccg_ctx* c, F&& f) {
+    if (!c) return CCG_ERR_ARG;
+    try {
+        HIP_OK(hipSetDevice(c->device));
+        c->err.clear();
+        return f();
+    } catch (const CcgError& e) {
+        c->err = e.msg;
+        if (e.st == CCG_ERR_DEVICE) {
+            // leave the stream usable for the next call where possible
+            (void)hipStreamSynchronize(c->stream);
+        }
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        c->err = "host allocation failed";
+        return CCG_ERR_NOMEM;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+ccg_status ccg_create(ccg_ctx** ctx, int device, size_t hbm_budget_bytes, void* hip_stream) {
+    if (!ctx) return CCG_ERR_ARG;
+    *ctx = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CCG_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return CCG_ERR_DEVICE;
+    ccg_ctx* c = new ccg_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return CCG_ERR_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return CCG_ERR_DEVICE;
+    }
+    std::memset(c->st_host, 0, sizeof(DevState));
+    *ctx = c;
+    return CCG_OK;
+}
+
+ccg_status ccg_destroy(ccg_ctx* c) {
+    if (!c) return CCG_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_workspace(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return CCG_OK;
+}
+
+const char* ccg_last_error(const ccg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b, double* X,
+                     int64_t ldx, double tol, int maxit, const ccg_opts* opts, ccg_info* info) {
+    ccg_info local;
+    std::memset(&local, 0, sizeof local);
+    local.best_agent = -1;
+    ccg_status st = guarded(c, [&]() -> ccg_status {
+        check_common(n, p, A, lda, b, X, ldx);
+        if (!(tol > 0.0)) throw CcgError{CCG_ERR_ARG, "tol must be > 0"};
+        if (maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
+        const ccg_opts o = fill_defaults(opts);
+        if (o.prec != CCG_FP64) throw CcgError{CCG_ERR_ARG, "precision mode not available"};
+        const auto t0 = std::chrono::steady_clock::now();
+        Staged sg;
+        double* Xd = X;
+        int64_t ldxd = ldx;
+        if (o.flags & CCG_HOST_PTRS) stage_in(c, sg, n, p, A, lda, b, Xd, ldxd);
+        ccg_status r = solve_fp64(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local);
+        if (o.flags & CCG_HOST_PTRS) {
+            HIP_OK(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xd, sizeof(double) * n, sizeof(double) * n, p,
+                                    hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+        }
+        local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return r;
+    });
+    local.status = st;
+    if (info) *info = local;
+    return st;
+}
+
+ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+                          double* X, int64_t ldx, int ksteps, const ccg_opts* opts, double* alphas,
+                          double* betas, double* R, double* D) {
+    return guarded(c, [&]() -> ccg_status {
+        check_common(n, p, A, lda, b, X, ldx);
+        if (ksteps < 0) throw CcgError{CCG_ERR_ARG, "ksteps must be >= 0"};
+        const ccg_opts o = fill_defaults(opts);
+        const int P = pad_agents(p);
+        Solve s{c, n, p, P, PREC_F64, A, nullptr, lda, ad_geometry(n, PREC_F64, 1024), false};
+        ensure_workspace(c, n, P, s.g);
+        Workspace& w = c->ws;
+        HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
+        HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
+        DevState& h = *c->st_host;
+        std::memset(&h, 0, sizeof(DevState));
+        h.done = RUNNING;
+        h.m = p;
+        h.mask = (1u << p) - 1u;
+        for (int j = 0; j < p; ++j) h.keep[j] = j;
+        h.maxit = ksteps + 1;   // never reached: every step runs to the end
+        h.tol = -1.0;           // no stop test
+        h.tau = o.rank_tau;
+        h.nb = 1.0;
+        write_state(c);
+        enqueue_residual(s, RES_INIT, 1);
+        read_state(c);
+        for (int k = 0; k < ksteps && h.done == RUNNING; ++k) {
+            enqueue_step(s, 0);
+            read_state(c);
+            for (int cc = 0; cc < p; ++cc)
+                for (int r = 0; r < p; ++r) {
+                    if (alphas) alphas[(size_t)k * p * p + r + cc * p] = h.alpha[r * kMaxP + cc];
+                    if (betas) betas[(size_t)k * p * p + r + cc * p] = h.beta[r * kMaxP + cc];
+                }
+        }
+        HIP_OK(launch_unpack(n, p, P, w.Xr, X, ldx, c->stream));
+        if (R) HIP_OK(launch_unpack(n, p, P, w.R, R, n, c->stream));
+        if (D) HIP_OK(launch_unpack(n, p, P, w.D, D, n, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        if (h.done == FAILED) return (ccg_status)h.status;
+        return CCG_OK;
+    });
+}
+
+ccg_status ccg_kernel_time(ccg_ctx* c, double* ms, long long* launches, int reset) {
+    if (!c) return CCG_ERR_ARG;
+    if (ms) *ms = c->prof_ms;
+    if (launches) *launches = c->prof_launches;
+    if (reset) {
+        c->prof_ms = 0.0;
+        c->prof_launches = 0;
+    }
+    return CCG_OK;
+}
+
+}  // extern "C"
