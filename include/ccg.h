@@ -61,7 +61,8 @@ typedef enum {
 
 #define CCG_HOST_PTRS 0x1u   /* A, b, X are host pointers */
 #define CCG_NO_GRAPH  0x2u   /* launch every kernel directly (no captured graph) */
-#define CCG_PROFILE   0x4u   /* time every A.D launch with HIP events (ccg_kernel_time) */
+#define CCG_PROFILE   0x4u   /* time every A.D launch with HIP events (ccg_kernel_time);
+                                 block steps are then launched directly, not as a graph */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {

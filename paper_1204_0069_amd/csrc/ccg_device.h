@@ -1,7 +1,7 @@
 // Internal device-side definitions shared by the HIP kernels and the host driver.
 //
-// Vectors X, R, D, AD live on the device as n_pad x P row-major blocks ("agent
-// interleaved": the P values of one row are contiguous), with P the agent count p
+// Vectors X, R, D, AD live on the device as n_pad x P blocks stored agent-major
+// (column j = agent j is contiguous: V[j * n_pad + i]), with P the agent count p
 // rounded up to 1, 2, 4, 8 or 16 and n_pad = n rounded up to a multiple of 512.
 // Rows >= n and columns >= p are kept at zero, so elementwise kernels need no
 // guards and sums over padded rows only add exact zeros.
@@ -14,7 +14,9 @@ namespace ccg {
 
 constexpr int kMaxP = 16;       // largest padded agent count
 constexpr int kWG = 256;        // threads per workgroup for every kernel
-constexpr int kRowAlign = 512;  // n_pad granularity (largest row tile)
+constexpr int kRowAlign = 512;  // n_pad granularity
+constexpr int kAdCols = 16;     // A columns (= AD rows) per A.D workgroup: 4 waves x 4
+constexpr int kGroup = 16;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 
@@ -41,39 +43,36 @@ struct DevState {
     double beta[kMaxP * kMaxP];          // beta[l*kMaxP + j]:  D[:,j] = R[:,j] + D[:,l] beta[l][j]
     double S[kMaxP * kMaxP];             // D^T R for the next alpha (full P x P, zeros off J)
     double Lc[kMaxP * kMaxP];            // Cholesky factor of G restricted to keep[], compact m x m
-    unsigned cnt_all;                    // last-workgroup tickets (reset by the last one)
-    unsigned cnt_upd;
-    unsigned cnt_res;
-    unsigned pad_;
+};
+
+// Scratch of one fixed-order grid reduction (see grid_reduce in the kernels).
+struct RedBuf {
+    double* l1;          // nwg x ne partials
+    double* l2;          // ngroups x ne group sums
+    unsigned* cnt;       // ngroups + 1 tickets, zero between launches
 };
 
 // Arguments of the A.D stream kernel.
 struct AdArgs {
     const void* A;       // FP64 / FP32 matrix, or the BF16 "hi" plane; column-major, lda
     const void* A_lo;    // BF16 "lo" plane (bf16x2 only)
-    int64_t lda;         // leading dimension in elements
+    int64_t lda;         // leading dimension in elements (lda * element size % 16 == 0)
     int n;               // system size
     int n_pad;           // padded row count of the vector blocks
-    int nks;             // column splits (workgroups per row tile)
-    int kc;              // columns per split
-    int ntiles;          // row tiles
     int product_only;    // 1: only form Y = A.V (residual); 0: also Gram + alpha
-    const void* V;       // operand block (n_pad x P row-major, vector type)
-    void* part;          // nks x n_pad x P partial products (accumulator type)
-    void* AD;            // n_pad x P result (vector type)
-    double* gpart;       // ntiles x P x P Gram partials
-    unsigned* cnt_tile;  // ntiles tickets
+    const void* V;       // operand block (agent-major, vector type)
+    void* AD;            // result block (agent-major, vector type)
+    RedBuf red;          // Gram reduction scratch (ne = P*P)
     DevState* st;
 };
 
 struct UpdArgs {
     int n_pad;
-    int nblk;            // workgroups
-    void* X;             // n_pad x P (vector type)
+    void* X;             // agent-major blocks (vector type)
     void* R;
     const void* D;
     const void* AD;
-    double* upart;       // nblk x 3 x P x P partials
+    RedBuf red;          // ne = 3*P*P
     DevState* st;
 };
 
@@ -88,16 +87,16 @@ struct DirArgs {
 enum ResMode : int { RES_INIT = 0, RES_CONFIRM = 1, RES_FINAL = 2 };
 
 struct ResArgs {
+    int n;
     int n_pad;
-    int nblk;
     int p;               // true agent count (columns >= p ignored)
     int mode;            // ResMode
     int set_nb;          // 1: also set st->nb = ||b||
     const double* b;     // n_pad (zero padded)
-    const double* Y;     // n_pad x P: A X
-    double* R;           // n_pad x P (written in INIT / CONFIRM)
+    const double* Y;     // agent-major A X
+    double* R;           // written in INIT / CONFIRM
     double* D;
-    double* rpart;       // nblk x (P x P + 1) partials of T^T T and b^T b
+    RedBuf red;          // ne = P*P + 1
     DevState* st;
 };
 

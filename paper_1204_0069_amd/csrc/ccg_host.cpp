@@ -27,10 +27,12 @@ hipError_t launch_dir(int prec, int P, const DirArgs& a, hipStream_t s);
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
 hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,
                        hipStream_t s);
-hipError_t launch_unpack(int n, int p, int P, const double* Xr, double* X, int64_t ldx,
+hipError_t launch_unpack(int n, int n_pad, int p, const double* Xr, double* X, int64_t ldx,
                          hipStream_t s);
 hipError_t launch_pad_vec(int n, int n_pad, const double* b, double* bp, hipStream_t s);
-int ad_tile_rows(int prec);
+hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int64_t ldb, hipStream_t s);
+int ad_workgroups(int n);
+int row_workgroups(int n_pad, int P);
 }  // namespace ccg
 
 using namespace ccg;
@@ -57,36 +59,16 @@ int pad_agents(int p) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Geometry of the A.D launch for one (n, precision).
-struct AdGeom {
-    int tm, ntiles, nks, kc;
-};
-
-AdGeom ad_geometry(int n, int prec, int target_wgs) {
-    AdGeom g;
-    g.tm = ad_tile_rows(prec);
-    g.ntiles = (int)((n + g.tm - 1) / g.tm);
-    int nks = std::max(1, (target_wgs + g.ntiles - 1) / g.ntiles);
-    nks = std::min(nks, std::max(1, n / 64));           // at least ~16 columns per wave
-    g.kc = (int)round_up((n + nks - 1) / nks, 4);
-    g.nks = (n + g.kc - 1) / g.kc;
-    return g;
-}
-
 struct Workspace {
-    int n = 0, n_pad = 0, P = 0, nks = 0, ntiles = 0;
+    int n = 0, n_pad = 0, P = 0;
     size_t bytes = 0;
     void* base = nullptr;            // one allocation, carved
-    double* Xr = nullptr;            // n_pad x P (FP64 agents)
+    double* Xr = nullptr;            // agent-major n_pad x P (FP64 agents)
     double* bp = nullptr;            // n_pad
-    double* R = nullptr;             // n_pad x P
+    double* R = nullptr;             // agent-major n_pad x P
     double* D = nullptr;
     double* AD = nullptr;
-    void* part = nullptr;            // nks x n_pad x P (FP64)
-    double* gpart = nullptr;         // ntiles x P x P
-    double* upart = nullptr;         // nblk_upd x 3 P^2
-    double* rpart = nullptr;         // nblk_res x (P^2 + 1)
-    unsigned* cnt_tile = nullptr;    // ntiles
+    RedBuf red_ad{}, red_upd{}, red_res{};
     DevState* st = nullptr;
 };
 
@@ -100,6 +82,15 @@ struct Carver {
         return r;
     }
 };
+
+RedBuf carve_red(Carver& cv, int nwg, int ne) {
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    RedBuf r;
+    r.l1 = cv.take<double>((size_t)nwg * ne);
+    r.l2 = cv.take<double>((size_t)ngroups * ne);
+    r.cnt = cv.take<unsigned>((size_t)ngroups + 1);
+    return r;
+}
 
 }  // namespace
 
@@ -118,8 +109,10 @@ struct ccg_ctx {
     // captured block-step graph
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
-    int64_t graph_key[7] = {0, 0, 0, 0, 0, 0, 0};
-    bool graph_events_ok = true;     // runtime captures event records into graphs
+    int64_t graph_key[6] = {0, 0, 0, 0, 0, 0};
+    // aligned copy of a caller matrix with unaligned columns
+    void* acopy = nullptr;
+    size_t acopy_bytes = 0;
 };
 
 namespace {
@@ -131,47 +124,47 @@ void free_workspace(ccg_ctx* c) {
 }
 
 // Lay out (or only size, when base == nullptr) the workspace.
-size_t carve(Workspace& w, char* base, int n_pad, int P, int nks, int ntiles) {
+size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
     Carver cv{base};
-    const int nblk_upd = n_pad / (P <= 8 ? kWG : kWG / 2);
-    w.Xr = cv.take<double>((size_t)n_pad * P);
+    const size_t blk = (size_t)n_pad * P;
+    w.Xr = cv.take<double>(blk);
     w.bp = cv.take<double>((size_t)n_pad);
-    w.R = cv.take<double>((size_t)n_pad * P);
-    w.D = cv.take<double>((size_t)n_pad * P);
-    w.AD = cv.take<double>((size_t)n_pad * P);
-    w.part = cv.take<double>((size_t)nks * n_pad * P);
-    w.gpart = cv.take<double>((size_t)ntiles * P * P);
-    w.upart = cv.take<double>((size_t)nblk_upd * 3 * P * P);
-    w.rpart = cv.take<double>((size_t)nblk_upd * (P * P + 1));
-    w.cnt_tile = cv.take<unsigned>((size_t)ntiles);
+    w.R = cv.take<double>(blk);
+    w.D = cv.take<double>(blk);
+    w.AD = cv.take<double>(blk);
+    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * P);
+    w.red_upd = carve_red(cv, row_workgroups(n_pad, P), 3 * P * P);
+    w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
     return cv.off;
 }
 
-void ensure_workspace(ccg_ctx* c, int n, int P, const AdGeom& g) {
+// The workspace depends only on (n_pad, P); the reduction scratch is sized for n_pad
+// rows, which covers every n with the same padded size.
+void ensure_workspace(ccg_ctx* c, int n, int P) {
     const int n_pad = (int)round_up(n, kRowAlign);
     Workspace& w = c->ws;
-    if (w.base && w.n_pad == n_pad && w.P == P && w.nks == g.nks && w.ntiles == g.ntiles) {
+    if (w.base && w.n_pad == n_pad && w.P == P) {
+        // rows n..n_pad of AD must read as zero (the A.D kernel stores rows < n only)
+        if (w.n != n) HIP_OK(hipMemsetAsync(w.AD, 0, sizeof(double) * (size_t)n_pad * P, c->stream));
         w.n = n;
         return;
     }
     free_workspace(c);
     Workspace nw;
-    const size_t bytes = carve(nw, nullptr, n_pad, P, g.nks, g.ntiles);
+    const size_t bytes = carve(nw, nullptr, n, n_pad, P);
     if (c->budget && bytes > c->budget)
         throw CcgError{CCG_ERR_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget"};
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess)
         throw CcgError{CCG_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     HIP_OK(hipMemsetAsync(base, 0, bytes, c->stream));
-    carve(nw, static_cast<char*>(base), n_pad, P, g.nks, g.ntiles);
+    carve(nw, static_cast<char*>(base), n, n_pad, P);
     nw.base = base;
     nw.bytes = bytes;
     nw.n = n;
     nw.n_pad = n_pad;
     nw.P = P;
-    nw.nks = g.nks;
-    nw.ntiles = g.ntiles;
     w = nw;
 }
 
@@ -181,7 +174,6 @@ struct Solve {
     const void* A;
     const void* A_lo;
     int64_t lda;
-    AdGeom g;
     bool profile;
 };
 
@@ -193,15 +185,10 @@ AdArgs ad_args(const Solve& s, const void* V, bool product_only) {
     a.lda = s.lda;
     a.n = s.n;
     a.n_pad = w.n_pad;
-    a.nks = s.g.nks;
-    a.kc = s.g.kc;
-    a.ntiles = s.g.ntiles;
     a.product_only = product_only ? 1 : 0;
     a.V = V;
-    a.part = w.part;
     a.AD = w.AD;
-    a.gpart = w.gpart;
-    a.cnt_tile = w.cnt_tile;
+    a.red = w.red_ad;
     a.st = w.st;
     return a;
 }
@@ -213,8 +200,8 @@ void enqueue_residual(const Solve& s, int mode, int set_nb) {
     s64.prec = PREC_F64;
     HIP_OK(launch_ad(PREC_F64, s.P, ad_args(s64, w.Xr, true), s.c->stream));
     ResArgs r;
+    r.n = s.n;
     r.n_pad = w.n_pad;
-    r.nblk = w.n_pad / (s.P <= 8 ? kWG : kWG / 2);
     r.p = s.p;
     r.mode = mode;
     r.set_nb = set_nb;
@@ -222,7 +209,7 @@ void enqueue_residual(const Solve& s, int mode, int set_nb) {
     r.Y = w.AD;
     r.R = w.R;
     r.D = w.D;
-    r.rpart = w.rpart;
+    r.red = w.red_res;
     r.st = w.st;
     HIP_OK(launch_res(s.P, r, s.c->stream));
 }
@@ -244,12 +231,11 @@ void enqueue_step(const Solve& s, size_t ev_slot) {
     if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot + 1), s.c->stream));
     UpdArgs u;
     u.n_pad = w.n_pad;
-    u.nblk = w.n_pad / (s.P <= 8 ? kWG : kWG / 2);
     u.X = w.Xr;
     u.R = w.R;
     u.D = w.D;
     u.AD = w.AD;
-    u.upart = w.upart;
+    u.red = w.red_upd;
     u.st = w.st;
     HIP_OK(launch_upd(s.prec, s.P, u, s.c->stream));
     DirArgs d;
@@ -278,17 +264,14 @@ void collect_profile(ccg_ctx* c, int steps) {
     }
 }
 
-// Capture `steps` block steps into c->graph.  With profiling, an event pair
-// brackets every A.D launch inside the graph.  Returns false (and leaves no graph)
-// if the runtime refuses to capture the event records.
-bool capture_steps(Solve& s, int steps) {
+// Capture `steps` block steps into c->graph.
+void capture_steps(Solve& s, int steps) {
     ccg_ctx* c = s.c;
-    if (s.profile) (void)pooled_event(c, 2 * (size_t)steps - 1);   // create before capture
     hipGraph_t gr = nullptr;
     HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
     try {
-        for (int i = 0; i < steps; ++i) enqueue_step(s, s.profile ? (size_t)i : 0);
+        for (int i = 0; i < steps; ++i) enqueue_step(s, 0);
     } catch (const CcgError&) {
         ok = false;
     }
@@ -296,35 +279,53 @@ bool capture_steps(Solve& s, int steps) {
     if (!ok || e != hipSuccess || !gr) {
         (void)hipGetLastError();
         if (gr) (void)hipGraphDestroy(gr);
-        if (!s.profile) throw CcgError{CCG_ERR_DEVICE, "stream capture of the block step failed"};
-        return false;
+        throw CcgError{CCG_ERR_DEVICE, "stream capture of the block step failed"};
     }
     HIP_OK(hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0));
     HIP_OK(hipGraphDestroy(gr));
-    return true;
 }
 
-// Run `steps` block steps, through a captured graph when allowed.
+// Run `steps` block steps, through a captured graph when allowed.  While profiling,
+// steps are launched directly: the runtime does not time events recorded inside a
+// graph, so each A.D launch is bracketed by its own event pair on the stream.
 void run_steps(Solve& s, int steps, bool use_graph) {
     ccg_ctx* c = s.c;
-    if (!use_graph || (s.profile && !c->graph_events_ok)) {
+    if (!use_graph || s.profile) {
         for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i);
         return;
     }
-    const int64_t key[7] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
-                            s.lda, s.profile ? 1 : 0};
-    const bool same = c->graph && c->graph_k == steps && std::equal(key, key + 7, c->graph_key);
+    const int64_t key[6] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
+                            s.lda};
+    const bool same = c->graph && c->graph_k == steps && std::equal(key, key + 6, c->graph_key);
     if (!same) {
         if (c->graph) { HIP_OK(hipGraphExecDestroy(c->graph)); c->graph = nullptr; }
-        if (!capture_steps(s, steps)) {
-            c->graph_events_ok = false;
-            for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i);
-            return;
-        }
+        capture_steps(s, steps);
         c->graph_k = steps;
-        std::copy(key, key + 7, c->graph_key);
+        std::copy(key, key + 6, c->graph_key);
     }
     HIP_OK(hipGraphLaunch(c->graph, c->stream));
+}
+
+// The A.D kernel reads columns with 16-byte loads.  A caller matrix whose columns
+// are not 16-byte aligned is copied once into a context-owned aligned buffer (lda
+// is then updated by the caller from acopy_ld).
+const double* aligned_matrix(ccg_ctx* c, int n, const double* A, int64_t& lda) {
+    if (reinterpret_cast<uintptr_t>(A) % 16 == 0 && (lda * sizeof(double)) % 16 == 0) return A;
+    const int64_t ldb = round_up(n, 2);
+    const size_t bytes = sizeof(double) * (size_t)ldb * n;
+    if (c->acopy_bytes < bytes) {
+        if (c->acopy) (void)hipFree(c->acopy);
+        c->acopy = nullptr;
+        c->acopy_bytes = 0;
+        if (c->budget && bytes + c->ws.bytes > c->budget)
+            throw CcgError{CCG_ERR_NOMEM, "aligned copy of A exceeds the HBM budget"};
+        if (hipMalloc(&c->acopy, bytes) != hipSuccess)
+            throw CcgError{CCG_ERR_NOMEM, "hipMalloc for the aligned copy of A failed"};
+        c->acopy_bytes = bytes;
+    }
+    HIP_OK(launch_copy_cols(n, A, lda, static_cast<double*>(c->acopy), ldb, c->stream));
+    lda = ldb;
+    return static_cast<const double*>(c->acopy);
 }
 
 void check_common(int n, int p, const void* A, int64_t lda, const void* b, const void* X, int64_t ldx) {
@@ -365,9 +366,9 @@ void stage_in(ccg_ctx* c, Staged& sg, int n, int p, const double*& A, int64_t& l
 ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
-    Solve s{c, n, p, P, PREC_F64, A, nullptr, lda, ad_geometry(n, PREC_F64, 1024),
-            (o.flags & CCG_PROFILE) != 0};
-    ensure_workspace(c, n, P, s.g);
+    const double* Ause = aligned_matrix(c, n, A, lda);
+    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, (o.flags & CCG_PROFILE) != 0};
+    ensure_workspace(c, n, P);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -409,7 +410,7 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
         read_state(c);
         bytes += bytes_iter;
     }
-    HIP_OK(launch_unpack(n, p, P, w.Xr, X, ldx, c->stream));
+    HIP_OK(launch_unpack(n, w.n_pad, p, w.Xr, X, ldx, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     ccg_status st = CCG_OK;
     if (h.done == FAILED) st = (ccg_status)h.status;
@@ -503,6 +504,7 @@ ccg_status ccg_destroy(ccg_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     free_workspace(c);
+    if (c->acopy) (void)hipFree(c->acopy);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -550,8 +552,9 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         if (ksteps < 0) throw CcgError{CCG_ERR_ARG, "ksteps must be >= 0"};
         const ccg_opts o = fill_defaults(opts);
         const int P = pad_agents(p);
-        Solve s{c, n, p, P, PREC_F64, A, nullptr, lda, ad_geometry(n, PREC_F64, 1024), false};
-        ensure_workspace(c, n, P, s.g);
+        const double* Ause = aligned_matrix(c, n, A, lda);
+        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, false};
+        ensure_workspace(c, n, P);
         Workspace& w = c->ws;
         HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
         HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -577,9 +580,9 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
                     if (betas) betas[(size_t)k * p * p + r + cc * p] = h.beta[r * kMaxP + cc];
                 }
         }
-        HIP_OK(launch_unpack(n, p, P, w.Xr, X, ldx, c->stream));
-        if (R) HIP_OK(launch_unpack(n, p, P, w.R, R, n, c->stream));
-        if (D) HIP_OK(launch_unpack(n, p, P, w.D, D, n, c->stream));
+        HIP_OK(launch_unpack(n, w.n_pad, p, w.Xr, X, ldx, c->stream));
+        if (R) HIP_OK(launch_unpack(n, w.n_pad, p, w.R, R, n, c->stream));
+        if (D) HIP_OK(launch_unpack(n, w.n_pad, p, w.D, D, n, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
         if (h.done == FAILED) return (ccg_status)h.status;
         return CCG_OK;

@@ -3,21 +3,24 @@
 // One block step (Alg. 2 of the paper, sign convention R = B - A X, residual by
 // the Table 1 recurrence) is three launches:
 //
-//   k_ad   : AD = A D, streamed once over A.  A is column-major, so column k of A
-//            times row k of D is an outer-product update of a tile of AD rows;
-//            the D row is wave-uniform and arrives by scalar loads.  Partial tiles
-//            per column split are summed in a fixed order by the last workgroup of
-//            each row tile, which also forms that tile's share of G = D^T A D.  The
-//            last tile sums the Gram shares (fixed order), runs the rank test of
-//            Alg. 3 and solves G alpha = S (Cholesky, FP64).
+//   k_ad   : AD = A D, streaming A once.  A is symmetric, so column i of A (which is
+//            contiguous in the column-major layout) is row i: each wave streams
+//            four whole columns with 16-byte loads, its lanes splitting the
+//            contraction index k, and multiplies them with D rows staged in LDS
+//            (double buffered).  Lane sums are folded by a fixed xor butterfly, so
+//            every AD row is complete inside one wave: no split-K partials.  Each
+//            workgroup adds its rows' share of G = D^T A D; a two-level fixed-order
+//            reduction across workgroups ends in the last workgroup, which runs the
+//            rank step of Alg. 3 and solves G alpha = S (Cholesky, FP64).
 //   k_upd  : X += D alpha, R -= AD alpha, and the reductions (AD)^T R, R^T R and
 //            D^T R; the last workgroup solves G beta = -(AD)^T R with the cached
 //            factor, forms the next S = D_new^T R = R^T R + beta^T (D^T R), the
 //            residual norms and the stop test.
 //   k_dir  : D = R + D beta (masked to the active agents).
 //
-// Every reduction is a fixed-order tree over fixed-size tiles, so results depend
-// only on (n, p, precision, tile shape), never on timing.
+// Cross-workgroup sums are written and read with agent-scope atomic stores and
+// loads (coherent across the XCDs without flushing L2) and summed in a fixed
+// order, so every result depends only on (n, p, precision, tile shape).
 #include "ccg_device.h"
 
 #include <math.h>
@@ -32,37 +35,39 @@ template <> struct PT<PREC_F64> {
     using TV = double;   // vector element (X, R, D, AD)
     using TACC = double; // accumulator of A.D
     static constexpr int E = 2;   // elements per 16-byte load
-    static constexpr int V = 2;   // 16-byte loads per lane per column
 };
 template <> struct PT<PREC_F32> {
     using TA = float;
     using TV = float;
     using TACC = float;
     static constexpr int E = 4;
-    static constexpr int V = 1;
 };
 template <> struct PT<PREC_BF16X2> {
     using TA = uint16_t;
     using TV = float;
     using TACC = float;
     static constexpr int E = 8;
-    static constexpr int V = 1;
 };
 
-template <int PREC> constexpr int tile_rows() { return 64 * PT<PREC>::E * PT<PREC>::V; }
+constexpr int kCW = 4;   // A columns per wave
+constexpr int kNW = 4;   // waves per A.D workgroup (kCW * kNW == kAdCols)
+static_assert(kCW * kNW == kAdCols, "A.D tile shape");
 
-// Columns per unrolled step: keep the uniform D rows of one step within ~64 SGPRs.
-template <int PREC, int P> constexpr int unroll() {
-    return (sizeof(typename PT<PREC>::TV) * P * 4 <= 256) ? 4 : 2;
+// Contraction elements per D chunk staged in LDS: a multiple of one wave step
+// (64 * E) keeping the two chunk buffers near 32 KiB.
+template <int PREC, int P> constexpr int chunk_k() {
+    constexpr int step = 64 * PT<PREC>::E;
+    constexpr int fit = 32768 / (2 * P * (int)sizeof(typename PT<PREC>::TV));
+    return fit >= step ? (fit / step) * step : step;
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float(((uint32_t)h) << 16);
 }
 
-// Load the E elements of one 16-byte chunk of column data, converted to TACC.
-// hi points into the FP64 / FP32 matrix or the BF16 "hi" plane, lo into the BF16
-// "lo" plane (same offsets).
+// Load the E elements of one 16-byte chunk of a column, converted to TACC.  hi
+// points into the FP64 / FP32 matrix or the BF16 "hi" plane, lo into the BF16 "lo"
+// plane at the same offset.
 template <int PREC> struct Loader;
 
 template <> struct Loader<PREC_F64> {
@@ -98,22 +103,65 @@ template <> struct Loader<PREC_BF16X2> {
     }
 };
 
-// ----------------------------------------------------------- last-workgroup tickets
+// ------------------------------------------------------ cross-workgroup reduction
 
-// Returns true in every thread of the workgroup that arrives last at *counter
-// (expected arrivals: total).  Publishes this workgroup's global writes before the
-// ticket and makes every other workgroup's writes visible after it.
-__device__ __forceinline__ bool last_arrival(unsigned* counter, unsigned total, int* s_flag) {
-    __threadfence();
+__device__ __forceinline__ void st_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ticket(unsigned* c) {
+    return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void reset_ticket(unsigned* c) {
+    __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory operation this thread issued is acknowledged.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Sum `ne` values per workgroup (mine[], LDS) over the whole grid, in workgroup
+// order within groups of kGroup and in group order across groups.  Returns true
+// in the one workgroup that ends up holding the totals in out[] (LDS).  Tickets
+// are reset by their last taker, so the scratch is ready for the next launch.
+__device__ bool grid_reduce(const double* mine, int ne, const RedBuf& rb, double* out, int* s_flag) {
+    const int tid = threadIdx.x;
+    const int nwg = gridDim.x;
+    const int bid = blockIdx.x;
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    const int grp = bid / kGroup;
+    const int gsize = min(kGroup, nwg - grp * kGroup);
+    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
+    stores_done();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(counter, 1u);
-        *s_flag = (t == total - 1) ? 1 : 0;
+    if (tid == 0) *s_flag = (ticket(&rb.cnt[grp]) == (unsigned)gsize - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid == 0) reset_ticket(&rb.cnt[grp]);
+    const int64_t g0 = (int64_t)grp * kGroup;
+    for (int e = tid; e < ne; e += kWG) {
+        double s = ld_agent(&rb.l1[g0 * ne + e]);
+        for (int q = 1; q < gsize; ++q) s += ld_agent(&rb.l1[(g0 + q) * ne + e]);
+        if (ngroups == 1) out[e] = s;
+        else st_agent(&rb.l2[(int64_t)grp * ne + e], s);
+    }
+    if (ngroups == 1) {
+        __syncthreads();
+        return true;
+    }
+    stores_done();
+    __syncthreads();
+    if (tid == 0) *s_flag = (ticket(&rb.cnt[ngroups]) == (unsigned)ngroups - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
+    for (int e = tid; e < ne; e += kWG) {
+        double s = ld_agent(&rb.l2[e]);
+        for (int g = 1; g < ngroups; ++g) s += ld_agent(&rb.l2[(int64_t)g * ne + e]);
+        out[e] = s;
     }
     __syncthreads();
-    const bool last = *s_flag != 0;
-    if (last) __threadfence();
-    return last;
+    return true;
 }
 
 // ------------------------------------------------------------ small p x p algebra
@@ -125,8 +173,7 @@ __device__ __forceinline__ bool last_arrival(unsigned* counter, unsigned total, 
 // taken compact indices, ascending, to keep[]; returns their count, or -1 when a
 // diagonal entry is negative, -2 on a non-finite entry.  Columns with G_ii == 0 are
 // never taken.  Same rule as the oracle's rank step.
-__device__ int wg_rank_select(const double* G, int m, double tau, int* keep, double* H,
-                              int* sh) {
+__device__ int wg_rank_select(const double* G, int m, double tau, int* keep, double* H, int* sh) {
     const int tid = threadIdx.x;
     // sh[0]: status, sh[1]: ncand, sh[2]: ntaken, sh[3]: pivot (or -1 to stop)
     // sh[8..8+m): candidate list, sh[32..32+m): taken list
@@ -255,223 +302,206 @@ __device__ __forceinline__ void fail_state(DevState* st, int code) {
     st->status = code;
 }
 
-// ============================================================== k_ad: AD = A D
-//
-// Workgroup (it, ks) covers rows [it*TM, it*TM+TM) and columns [ks*kc, ks*kc+kc);
-// its four waves take contiguous quarters of the column range and are summed in
-// wave order through LDS.  Lane l owns rows it*TM + v*64*E + l*E + e.
+// Fold M = 2^q values held by every lane of a wave into sums over the 64 lanes:
+// each xor round with offset o keeps one half of the live values and adds the
+// partner's copy of it, until one value per lane remains, then plain xor adds.
+// Returns the index (0..M-1) of the total this lane holds in v[0].
+template <int M, class T>
+__device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
+    int idx = 0;
+    int m = M;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        if (m > 1) {
+            const bool up = (lane & o) != 0;
+            const int h = m >> 1;
+#pragma unroll
+            for (int q = 0; q < M / 2; ++q) {
+                if (q < h) {
+                    const T send = up ? v[q] : v[q + h];
+                    const T keep = up ? v[q + h] : v[q];
+                    v[q] = keep + __shfl_xor(send, o);
+                }
+            }
+            if (up) idx += h;
+            m = h;
+        } else {
+            v[0] += __shfl_xor(v[0], o);
+        }
+    }
+    return idx;
+}
 
-template <int PREC, int P, bool TAIL>
-__device__ __forceinline__ void ad_stream(const AdArgs& a, int it, int ks,
-                                          typename PT<PREC>::TACC (&acc)[PT<PREC>::V][PT<PREC>::E][P]) {
+// ============================================================== k_ad: AD = A D
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
     using TA = typename PT<PREC>::TA;
     using TV = typename PT<PREC>::TV;
     using TACC = typename PT<PREC>::TACC;
     constexpr int E = PT<PREC>::E;
-    constexpr int V = PT<PREC>::V;
-    constexpr int TM = tile_rows<PREC>();
-    constexpr int U = unroll<PREC, P>();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int kb0 = ks * a.kc;
-    const int ke0 = min(a.n, kb0 + a.kc);
-    const int per = (ke0 - kb0 + 3) >> 2;
-    const int kb = kb0 + wave * per;
-    const int ke = min(ke0, kb + per);
-    const int64_t lda = a.lda;
-    // wave-uniform column pointers (tile base) and D row pointer
-    const TA* chi = static_cast<const TA*>(a.A) + (int64_t)kb * lda + (int64_t)it * TM;
-    const TA* clo = (PREC == PREC_BF16X2)
-                        ? static_cast<const TA*>(a.A_lo) + (int64_t)kb * lda + (int64_t)it * TM
-                        : chi;
-    const TV* dp = static_cast<const TV*>(a.V) + (int64_t)kb * P;
-    const int loff = lane * E;      // per-lane element offset inside a column tile
+    constexpr int KSTEP = 64 * E;
+    constexpr int KC = chunk_k<PREC, P>();
+    constexpr int SPC = KC / KSTEP;           // wave steps per chunk
+    constexpr int NV = kCW * P;               // lane sums per wave
+    constexpr int PER = P * KC / kWG;         // staged D values per thread per chunk
+    static_assert(P * KC % kWG == 0, "chunk staging must split evenly");
+    static_assert(NV <= 64, "lane sums per wave");
 
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-#pragma unroll
-            for (int j = 0; j < P; ++j) acc[v][e][j] = TACC(0);
-
-    int k = kb;
-    if (!TAIL) {
-        for (; k + U <= ke; k += U) {
-            TACC av[U][V][E];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    Loader<PREC>::load(chi + u * lda + loff + v * 64 * E, clo + u * lda + loff + v * 64 * E,
-                                       av[u][v]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                TACC d[P];
-#pragma unroll
-                for (int j = 0; j < P; ++j) d[j] = TACC(dp[u * P + j]);
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-#pragma unroll
-                        for (int j = 0; j < P; ++j) acc[v][e][j] = fma(av[u][v][e], d[j], acc[v][e][j]);
-            }
-            chi += U * lda;
-            clo += U * lda;
-            dp += U * P;
-        }
-    }
-    const int row_lane = it * TM + loff;
-    for (; k < ke; ++k) {
-        TACC av[V][E];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            if (!TAIL) {
-                Loader<PREC>::load(chi + loff + v * 64 * E, clo + loff + v * 64 * E, av[v]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int off = loff + v * 64 * E + e;
-                    av[v][e] = (row_lane + v * 64 * E + e < a.n) ? Loader<PREC>::load1(chi + off, clo + off)
-                                                                 : TACC(0);
-                }
-            }
-        }
-        TACC d[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) d[j] = TACC(dp[j]);
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-                for (int j = 0; j < P; ++j) acc[v][e][j] = fma(av[v][e], d[j], acc[v][e][j]);
-        chi += lda;
-        clo += lda;
-        dp += P;
-    }
-}
-
-template <int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
-    using TV = typename PT<PREC>::TV;
-    using TACC = typename PT<PREC>::TACC;
-    constexpr int E = PT<PREC>::E;
-    constexpr int V = PT<PREC>::V;
-    constexpr int TM = tile_rows<PREC>();
-    __shared__ TACC red[TM * P];           // wave sums; then the reduced AD tile
-    __shared__ TV dtile[TM * P];           // D rows of the tile (Gram epilogue)
-    __shared__ double gsh[kWG];            // Gram sub-sums / final Gram
-    __shared__ double sm[5 * kMaxP * kMaxP];
+    __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
+    __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
+    __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
+    __shared__ double sm[6 * kMaxP * kMaxP];
     __shared__ int ish[128];
 
     if (!a.product_only && a.st->done != RUNNING) return;
-    const int it = blockIdx.x / a.nks;
-    const int ks = blockIdx.x - it * a.nks;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n;
+    const int i0 = blockIdx.x * kAdCols;                  // first AD row of the workgroup
+    const int iw = i0 + wave * kCW;                       // first row of this wave
+    const TV* __restrict__ V = static_cast<const TV*>(a.V);
+    const int64_t lda = a.lda;
+    const TA* colhi[kCW];
+    const TA* collo[kCW];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c) {
+        const int i = min(iw + c, n - 1);                 // rows >= n compute a copy, never stored
+        colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
+        collo[c] = (PREC == PREC_BF16X2) ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
+    }
 
-    TACC acc[V][E][P];
-    const bool tail = (it + 1) * TM > a.n;
-    if (tail) ad_stream<PREC, P, true>(a, it, ks, acc);
-    else ad_stream<PREC, P, false>(a, it, ks, acc);
+    TACC acc[kCW][P];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
 
-    // ---- fixed-order sum of the four waves: ((w0 + w1) + w2) + w3
-    for (int w = 1; w < 4; ++w) {
-        if (wave == w) {
+    const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
+    TV pre[PER];
 #pragma unroll
-            for (int v = 0; v < V; ++v)
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * kWG;
+        const int j = idx / KC, kk = idx - (idx / KC) * KC;
+        pre[q] = V[(int64_t)j * a.n_pad + kk];
+    }
 #pragma unroll
-                for (int e = 0; e < E; ++e)
+    for (int q = 0; q < PER; ++q) dch[0][tid + q * kWG] = pre[q];
+    __syncthreads();
+
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const int k0 = ch * KC;
+        const bool more = ch + 1 < nch;
+        if (more) {
 #pragma unroll
-                    for (int j = 0; j < P; ++j) red[(v * 64 * E + lane * E + e) * P + j] = acc[v][e][j];
+            for (int q = 0; q < PER; ++q) {
+                const int idx = tid + q * kWG;
+                const int j = idx / KC, kk = idx - (idx / KC) * KC;
+                pre[q] = V[(int64_t)j * a.n_pad + k0 + KC + kk];
+            }
         }
-        __syncthreads();
-        if (wave == 0) {
+        const TV* dc = dch[buf];
+        if (k0 + KC <= n) {
 #pragma unroll
-            for (int v = 0; v < V; ++v)
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
 #pragma unroll
-                for (int e = 0; e < E; ++e)
+                for (int c = 0; c < kCW; ++c) Loader<PREC>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
 #pragma unroll
-                    for (int j = 0; j < P; ++j) acc[v][e][j] += red[(v * 64 * E + lane * E + e) * P + j];
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        } else {
+            // last, partial chunk: element loads guarded by k < n
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
+#pragma unroll
+                for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
+                                                     : TACC(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) dch[buf ^ 1][tid + q * kWG] = pre[q];
         }
         __syncthreads();
     }
-    // ---- partial tile for this column split
-    TACC* part = static_cast<TACC*>(a.part) + ((int64_t)ks * a.n_pad + (int64_t)it * TM) * P;
-    if (wave == 0) {
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-                for (int j = 0; j < P; ++j) part[(v * 64 * E + lane * E + e) * P + j] = acc[v][e][j];
-    }
-    if (!last_arrival(&a.cnt_tile[it], (unsigned)a.nks, &ish[0])) return;
-    if (tid == 0) a.cnt_tile[it] = 0u;
 
-    // ---- last workgroup of the tile: AD tile = sum over splits in split order
-    {
-        const TACC* p0 = static_cast<const TACC*>(a.part) + (int64_t)it * TM * P;
-        TV* ad = static_cast<TV*>(a.AD) + (int64_t)it * TM * P;
-        const TV* dv = static_cast<const TV*>(a.V) + (int64_t)it * TM * P;
-        for (int idx = tid; idx < TM * P; idx += kWG) {
-            TACC s = p0[idx];
-            for (int q = 1; q < a.nks; ++q) s += p0[(int64_t)q * a.n_pad * P + idx];
-            ad[idx] = TV(s);
-            red[idx] = TACC(TV(s));
-            dtile[idx] = dv[idx];
-        }
+    // ---- lane sums -> complete AD rows (fixed butterfly order)
+    TACC v[NV];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
+    const int idx = wave_fold<NV>(v, lane);
+    constexpr int REP = 64 / NV;             // lanes holding the same total
+    if (lane % REP == 0) {
+        const int c = idx / P, j = idx - (idx / P) * P;
+        const int i = iw + c;
+        const TV y = TV(v[0]);
+        if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
+        adt[(wave * kCW + c) * kMaxP + j] = double(y);
     }
     if (a.product_only) return;
-    __syncthreads();
 
-    // ---- Gram share of this tile: G_t[x][y] = sum_r D[r][x] * AD[r][y]
-    {
-        constexpr int NE = P * P;
-        constexpr int TPE = (kWG / NE) > 0 ? (kWG / NE) : 1;   // threads per entry
-        const int e = tid / TPE, sub = tid - (tid / TPE) * TPE;
-        double s = 0.0;
-        if (e < NE) {
-            const int x = e / P, y = e - (e / P) * P;
-            for (int r = sub; r < TM; r += TPE)
-                s = fma((double)dtile[r * P + x], (double)red[r * P + y], s);
-        }
-        gsh[tid] = s;
-        __syncthreads();
-        if (sub == 0 && e < NE) {
-            double t = gsh[tid];
-            for (int q = 1; q < TPE; ++q) t += gsh[tid + q];
-            a.gpart[(int64_t)it * NE + e] = t;
-        }
+    // ---- Gram share of the workgroup's rows: G_w[x][y] = sum_r D[r][x] AD[r][y]
+    if (tid < kAdCols * P) {
+        const int r = tid / P, j = tid - (tid / P) * P;
+        const int i = i0 + r;
+        drw[r * kMaxP + j] = (i < n) ? double(V[(int64_t)j * a.n_pad + i]) : 0.0;
     }
-    if (!last_arrival(&a.st->cnt_all, (unsigned)a.ntiles, &ish[0])) return;
-
-    // ---- last tile: G = sum of shares (tile order), rank step, alpha = G^{-1} S
-    DevState* st = a.st;
-    if (tid == 0) st->cnt_all = 0u;
-    double* Gf = gsh;                       // P x P full Gram
+    __syncthreads();
+    double* gmine = sm;                       // P*P
+    double* gtot = sm + kMaxP * kMaxP;        // P*P
     if (tid < P * P) {
-        double t = a.gpart[tid];
-        for (int q = 1; q < a.ntiles; ++q) t += a.gpart[(int64_t)q * P * P + tid];
-        Gf[tid] = t;
+        const int x = tid / P, y = tid - (tid / P) * P;
+        double s = 0.0;
+        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], adt[r * kMaxP + y], s);
+        gmine[tid] = s;
     }
     __syncthreads();
+    if (!grid_reduce(gmine, P * P, a.red, gtot, &ish[0])) return;
+
+    // ---- last workgroup: rank step, alpha = G^{-1} S
+    DevState* st = a.st;
     int* act = &ish[64];    // active agents (global indices), ascending
     int m = st->m;
     if (tid < m) act[tid] = st->keep[tid];
     __syncthreads();
-    double* Gc = sm;                         // compact m x m
-    double* H = sm + kMaxP * kMaxP;
-    double* Lc = sm + 2 * kMaxP * kMaxP;
-    double* Sc = sm + 3 * kMaxP * kMaxP;
-    double* Zc = sm + 4 * kMaxP * kMaxP;
+    double* Gc = sm + 2 * kMaxP * kMaxP;      // compact m x m
+    double* H = sm + 3 * kMaxP * kMaxP;
+    double* Lc = sm + 4 * kMaxP * kMaxP;
+    double* Sc = sm + 5 * kMaxP * kMaxP;
+    double* Zc = gmine;                        // free again
     if (tid < m * m) {
         const int i = tid / m, j = tid - (tid / m) * m;
-        // G is symmetric in exact arithmetic; use the lower triangle of the sum
+        // G is symmetric in exact arithmetic; use one triangle of the sum
         const int gi = max(act[i], act[j]), gj = min(act[i], act[j]);
-        Gc[tid] = Gf[gi * P + gj];
+        Gc[tid] = gtot[gi * P + gj];
     }
     __syncthreads();
     int* kp = &ish[96];
@@ -500,7 +530,7 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         }
         m = r;
         if (m == 0) {
-            if (tid == 0) { st->done = FINISHED; }
+            if (tid == 0) st->done = FINISHED;
             return;
         }
     }
@@ -514,7 +544,6 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
     }
     __syncthreads();
     wg_chol_solve(Lc, m, m, Sc, Zc);
-    // publish alpha (full, zeros off the active block) and the factor
     if (tid < kMaxP * kMaxP) st->alpha[tid] = 0.0;
     __syncthreads();
     if (tid < m * m) {
@@ -525,79 +554,60 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
 }
 
 // ============================================ k_upd: X += D alpha, R -= AD alpha
+//
+// Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     using TV = typename PT<PREC>::TV;
-    constexpr int RB = (P <= 8) ? kWG : kWG / 2;      // rows per workgroup
+    constexpr int RB = kWG / P;
+    constexpr int NE = 3 * P * P;
     __shared__ double al[P * P];
-    __shared__ double rs[RB * P], ads[RB * P], ds[RB * P];
-    __shared__ double sm[5 * kMaxP * kMaxP];
+    __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
+    __shared__ double mine[NE];
+    __shared__ double tot[NE];
+    __shared__ double Lc[kMaxP * kMaxP], Wc[kMaxP * kMaxP], Bc[kMaxP * kMaxP];
     __shared__ int ish[128];
     DevState* st = a.st;
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)blockIdx.x * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
     if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
-    __syncthreads();
-
     TV* X = static_cast<TV*>(a.X);
     TV* R = static_cast<TV*>(a.R);
-    const TV* D = static_cast<const TV*>(a.D);
-    const TV* AD = static_cast<const TV*>(a.AD);
-    const int64_t row0 = (int64_t)blockIdx.x * RB;
-    if (tid < RB) {
-        const int64_t i = row0 + tid;
-        double x[P], rr[P], d[P], ad[P];
+    const double x0 = X[o];
+    const double r0 = R[o];
+    dt[r * P + j] = static_cast<const TV*>(a.D)[o];
+    adt[r * P + j] = static_cast<const TV*>(a.AD)[o];
+    __syncthreads();
+    double sx = 0.0, sr = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            x[j] = X[i * P + j];
-            rr[j] = R[i * P + j];
-            d[j] = D[i * P + j];
-            ad[j] = AD[i * P + j];
-        }
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            double sx = 0.0, sr = 0.0;
-#pragma unroll
-            for (int l = 0; l < P; ++l) {
-                sx = fma(d[l], al[l * P + j], sx);
-                sr = fma(ad[l], al[l * P + j], sr);
-            }
-            x[j] += sx;
-            rr[j] -= sr;
-        }
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            X[i * P + j] = TV(x[j]);
-            R[i * P + j] = TV(rr[j]);
-            rs[tid * P + j] = double(TV(rr[j]));
-            ads[tid * P + j] = ad[j];
-            ds[tid * P + j] = d[j];
-        }
+    for (int l = 0; l < P; ++l) {
+        sx = fma(dt[r * P + l], al[l * P + j], sx);
+        sr = fma(adt[r * P + l], al[l * P + j], sr);
     }
+    const TV xn = TV(x0 + sx);
+    const TV rn = TV(r0 - sr);
+    X[o] = xn;
+    R[o] = rn;
+    rt[r * P + j] = double(rn);
     __syncthreads();
     // partial sums over this workgroup's rows: W = AD^T R, Q = R^T R, F = D^T R
-    constexpr int NE = 3 * P * P;
     for (int e = tid; e < NE; e += kWG) {
         const int which = e / (P * P);
         const int xy = e - which * P * P;
         const int x = xy / P, y = xy - (xy / P) * P;
-        const double* U = which == 0 ? ads : (which == 1 ? rs : ds);
+        const double* U = which == 0 ? adt : (which == 1 ? rt : dt);
         double s = 0.0;
-        for (int r = 0; r < RB; ++r) s = fma(U[r * P + x], rs[r * P + y], s);
-        a.upart[(int64_t)blockIdx.x * NE + e] = s;
-    }
-    if (!last_arrival(&st->cnt_upd, (unsigned)a.nblk, &ish[0])) return;
-
-    // ---- last workgroup: totals in block order, beta, next S, norms, stop test
-    if (tid == 0) st->cnt_upd = 0u;
-    double* tot = sm;   // 3 x P x P  (fits: 3*256 <= 5*256)
-    for (int e = tid; e < NE; e += kWG) {
-        double t = a.upart[e];
-        for (int q = 1; q < a.nblk; ++q) t += a.upart[(int64_t)q * NE + e];
-        tot[e] = t;
+        for (int q = 0; q < RB; ++q) s = fma(U[q * P + x], rt[q * P + y], s);
+        mine[e] = s;
     }
     __syncthreads();
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0])) return;
+
+    // ---- last workgroup: beta, next S, norms, stop test
     const double* W = tot;
     const double* Q = tot + P * P;
     const double* F = tot + 2 * P * P;
@@ -605,11 +615,10 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     int* act = &ish[64];
     if (tid < m) act[tid] = st->keep[tid];
     __syncthreads();
-    __shared__ double Lc[kMaxP * kMaxP], Wc[kMaxP * kMaxP], Bc[kMaxP * kMaxP];
     if (tid < m * m) {
-        const int i = tid / m, j = tid - (tid / m) * m;
+        const int ii = tid / m, jj = tid - (tid / m) * m;
         Lc[tid] = st->Lc[tid];
-        Wc[tid] = -W[act[i] * P + act[j]];
+        Wc[tid] = -W[act[ii] * P + act[jj]];
     }
     __syncthreads();
     wg_chol_solve(Lc, m, m, Wc, Bc);       // beta = -G^{-1} (AD)^T R
@@ -619,20 +628,20 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     }
     __syncthreads();
     if (tid < m * m) {
-        const int i = tid / m, j = tid - (tid / m) * m;
-        st->beta[act[i] * kMaxP + act[j]] = Bc[tid];
+        const int ii = tid / m, jj = tid - (tid / m) * m;
+        st->beta[act[ii] * kMaxP + act[jj]] = Bc[tid];
         // S_next = R^T R + beta^T (D^T R), restricted to the active agents
-        double s = Q[act[i] * P + act[j]];
-        for (int l = 0; l < m; ++l) s = fma(Bc[l * m + i], F[act[l] * P + act[j]], s);
-        st->S[act[i] * kMaxP + act[j]] = s;
+        double s = Q[act[ii] * P + act[jj]];
+        for (int l = 0; l < m; ++l) s = fma(Bc[l * m + ii], F[act[l] * P + act[jj]], s);
+        st->S[act[ii] * kMaxP + act[jj]] = s;
     }
     if (tid == 0) {
         double mn = INFINITY;
         bool bad = false;
         for (int q = 0; q < m; ++q) {
-            const int j = act[q];
-            const double nr = sqrt(Q[j * P + j]);
-            st->norms[j] = nr;
+            const int jj = act[q];
+            const double nr = sqrt(Q[jj * P + jj]);
+            st->norms[jj] = nr;
             if (!isfinite(nr)) bad = true;
             mn = fmin(mn, nr / st->nb);
         }
@@ -649,86 +658,73 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir(DirArgs a) {
     using TV = typename PT<PREC>::TV;
+    constexpr int RB = kWG / P;
     __shared__ double be[P * P];
-    __shared__ unsigned msk;
+    __shared__ double dt[RB * P];
     const DevState* st = a.st;
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t o = (int64_t)j * a.n_pad + (int64_t)blockIdx.x * RB + r;
     if (tid < P * P) be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
-    if (tid == 0) msk = st->mask;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kWG + tid;
-    if (i >= a.n_pad) return;
-    const TV* R = static_cast<const TV*>(a.R);
     TV* D = static_cast<TV*>(a.D);
-    double d[P];
+    dt[r * P + j] = D[o];
+    const unsigned msk = st->mask;
+    const double rr = static_cast<const TV*>(a.R)[o];
+    __syncthreads();
+    double s = rr;
 #pragma unroll
-    for (int j = 0; j < P; ++j) d[j] = D[i * P + j];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double s = R[i * P + j];
-#pragma unroll
-        for (int l = 0; l < P; ++l) s = fma(d[l], be[l * P + j], s);
-        D[i * P + j] = ((msk >> j) & 1u) ? TV(s) : TV(0);
-    }
+    for (int l = 0; l < P; ++l) s = fma(dt[r * P + l], be[l * P + j], s);
+    D[o] = ((msk >> j) & 1u) ? TV(s) : TV(0);
 }
 
 // ============================================ k_res: T = B - Y, norms, restart
 
 template <int P>
 __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
-    constexpr int RB = (P <= 8) ? kWG : kWG / 2;
+    constexpr int RB = kWG / P;
     constexpr int NE = P * P + 1;      // T^T T entries, then b^T b
     __shared__ double ts[RB * P];
     __shared__ double bs[RB];
+    __shared__ double mine[NE];
     __shared__ double tot[NE];
     __shared__ int ish[8];
     DevState* st = a.st;
     const int tid = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.x * RB;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)blockIdx.x * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
     const unsigned msk = st->mask;
-    if (tid < RB) {
-        const int64_t i = row0 + tid;
-        const double bi = a.b[i];
-        bs[tid] = bi;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const double t = (j < a.p) ? bi - a.Y[i * P + j] : 0.0;
-            ts[tid * P + j] = t;
-            if (a.mode != RES_FINAL) {
-                a.R[i * P + j] = t;
-                a.D[i * P + j] = ((msk >> j) & 1u) ? t : 0.0;
-            }
-        }
+    const double bi = a.b[i];
+    if (j == 0) bs[r] = bi;
+    const double t = (j < a.p && i < a.n) ? bi - a.Y[o] : 0.0;
+    ts[r * P + j] = t;
+    if (a.mode != RES_FINAL) {
+        a.R[o] = t;
+        a.D[o] = ((msk >> j) & 1u) ? t : 0.0;
     }
     __syncthreads();
     for (int e = tid; e < NE; e += kWG) {
         double s = 0.0;
         if (e < P * P) {
             const int x = e / P, y = e - (e / P) * P;
-            for (int r = 0; r < RB; ++r) s = fma(ts[r * P + x], ts[r * P + y], s);
+            for (int q = 0; q < RB; ++q) s = fma(ts[q * P + x], ts[q * P + y], s);
         } else {
-            for (int r = 0; r < RB; ++r) s = fma(bs[r], bs[r], s);
+            for (int q = 0; q < RB; ++q) s = fma(bs[q], bs[q], s);
         }
-        a.rpart[(int64_t)blockIdx.x * NE + e] = s;
-    }
-    if (!last_arrival(&st->cnt_res, (unsigned)a.nblk, &ish[0])) return;
-    if (tid == 0) st->cnt_res = 0u;
-    for (int e = tid; e < NE; e += kWG) {
-        double t = a.rpart[e];
-        for (int q = 1; q < a.nblk; ++q) t += a.rpart[(int64_t)q * NE + e];
-        tot[e] = t;
+        mine[e] = s;
     }
     __syncthreads();
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0])) return;
     if (tid == 0) {
         if (a.set_nb) st->nb = sqrt(tot[P * P]);
         double mn = INFINITY;
         bool bad = !isfinite(st->nb);
-        for (int j = 0; j < a.p; ++j) {
-            const double nr = sqrt(tot[j * P + j]);
-            st->norms[j] = nr;
+        for (int jj = 0; jj < a.p; ++jj) {
+            const double nr = sqrt(tot[jj * P + jj]);
+            st->norms[jj] = nr;
             if (!isfinite(nr)) bad = true;
-            if ((msk >> j) & 1u) mn = fmin(mn, nr / st->nb);
+            if ((msk >> jj) & 1u) mn = fmin(mn, nr / st->nb);
         }
         st->minres = mn;
         if (a.mode != RES_FINAL) {
@@ -751,21 +747,21 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
 
 // ======================================================== layout conversions
 
-// Xr (n_pad x P row-major, zero padded) <- X (n x p column-major, ldx)
+// Xr (agent-major n_pad x P, zero padded) <- X (n x p column-major, ldx)
 __global__ void k_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_pad * P) return;
-    const int64_t i = idx / P;
-    const int j = (int)(idx - i * P);
+    const int j = (int)(idx / n_pad);
+    const int64_t i = idx - (int64_t)j * n_pad;
     Xr[idx] = (i < n && j < p) ? X[i + j * ldx] : 0.0;
 }
 
-__global__ void k_unpack(int n, int p, int P, const double* Xr, double* X, int64_t ldx) {
+__global__ void k_unpack(int n, int n_pad, int p, const double* Xr, double* X, int64_t ldx) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n * p) return;
-    const int64_t i = idx % n;
     const int j = (int)(idx / n);
-    X[i + j * ldx] = Xr[i * P + j];
+    const int64_t i = idx - (int64_t)j * n;
+    X[i + j * ldx] = Xr[(int64_t)j * n_pad + i];
 }
 
 __global__ void k_pad_vec(int n, int n_pad, const double* b, double* bp) {
@@ -773,26 +769,35 @@ __global__ void k_pad_vec(int n, int n_pad, const double* b, double* bp) {
     if (i < n_pad) bp[i] = (i < n) ? b[i] : 0.0;
 }
 
+// Copy a column-major matrix into one whose leading dimension keeps every column
+// 16-byte aligned.
+__global__ void k_copy_cols(int n, const double* A, int64_t lda, double* B, int64_t ldb) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int64_t c = idx / n, r = idx - c * n;
+    B[c * ldb + r] = A[c * lda + r];
+}
+
 // ================================================================== launchers
 
 template <int PREC, int P>
 static hipError_t launch_ad_t(const AdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_ad<PREC, P>), dim3(a.ntiles * a.nks), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_ad<PREC, P>), dim3((a.n + kAdCols - 1) / kAdCols), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(a.nblk), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int PREC, int P>
 static hipError_t launch_dir_t(const DirArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_dir<PREC, P>), dim3((a.n_pad + kWG - 1) / kWG), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int P>
 static hipError_t launch_res_t(const ResArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_res<P>), dim3(a.nblk), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_res<P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -861,11 +866,11 @@ hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_unpack(int n, int p, int P, const double* Xr, double* X, int64_t ldx,
+hipError_t launch_unpack(int n, int n_pad, int p, const double* Xr, double* X, int64_t ldx,
                          hipStream_t s) {
     const int64_t tot = (int64_t)n * p;
-    hipLaunchKernelGGL(k_unpack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, p, P, Xr,
-                       X, ldx);
+    hipLaunchKernelGGL(k_unpack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, n_pad, p,
+                       Xr, X, ldx);
     return hipGetLastError();
 }
 
@@ -874,12 +879,15 @@ hipError_t launch_pad_vec(int n, int n_pad, const double* b, double* bp, hipStre
     return hipGetLastError();
 }
 
-int ad_tile_rows(int prec) {
-    switch (prec) {
-        case PREC_F64: return tile_rows<PREC_F64>();
-        case PREC_F32: return tile_rows<PREC_F32>();
-        default: return tile_rows<PREC_BF16X2>();
-    }
+hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int64_t ldb, hipStream_t s) {
+    const int64_t tot = (int64_t)n * n;
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, A, lda, B,
+                       ldb);
+    return hipGetLastError();
 }
+
+// Number of workgroups of each launch (the host sizes reduction scratch with it).
+int ad_workgroups(int n) { return (n + kAdCols - 1) / kAdCols; }
+int row_workgroups(int n_pad, int P) { return n_pad / (kWG / P); }
 
 }  // namespace ccg

@@ -252,3 +252,15 @@ def test_full_size_solve_properties(gpu_ctx, big_system):
     xs = torch.linalg.solve(A, b)
     err = (torch.linalg.norm(X[:, info["best_agent"]] - xs) / torch.linalg.norm(xs)).item()
     assert err <= 1e4 * tol
+
+
+def test_small_solve_after_larger_one_in_same_workspace(gpu_ctx):
+    """Regression: rows n..n_pad of the workspace must not carry values from an
+    earlier, larger solve that used the same padded size."""
+    A1, b1, X1 = ci.system(500, 3, 1e2, seed=31)
+    gpu_ctx.solve(_t(A1), _t(b1), _t(X1), 1e-10, 2000)
+    A, b, X0 = ci.system(13, 3, 10.0, seed=21)
+    orc = oracle.ccg(A, b, X0, tol=1e-12, maxit=50)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-12, 50)
+    assert info["status"] == 0 and info["iters"] == orc["iters"]
+    assert info["deflations"] == orc["deflations"]
