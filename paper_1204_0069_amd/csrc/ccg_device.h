@@ -42,7 +42,7 @@ struct DevState {
     double alpha[kMaxP * kMaxP];         // alpha[l*kMaxP + j]: X[:,j] += D[:,l] alpha[l][j]
     double beta[kMaxP * kMaxP];          // beta[l*kMaxP + j]:  D[:,j] = R[:,j] + D[:,l] beta[l][j]
     double S[kMaxP * kMaxP];             // D^T R for the next alpha (full P x P, zeros off J)
-    double Lc[kMaxP * kMaxP];            // Cholesky factor of G restricted to keep[], compact m x m
+    double L[kMaxP * kMaxP];             // Cholesky factor of G (inactive agents: identity)
 };
 
 // Scratch of one fixed-order grid reduction (see grid_reduce in the kernels).

@@ -120,11 +120,53 @@ __device__ __forceinline__ void reset_ticket(unsigned* c) {
 // Wait until every memory operation this thread issued is acknowledged.
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Sum, for entry e, the rows m0 .. m0+cnt-1 of src (row stride ne) in row order.
+// Loads are issued in unrolled batches of 16 so that their latencies overlap.
+__device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int m0, int cnt) {
+    double s = 0.0;
+    for (int base = 0; base < cnt; base += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = (base + q < cnt) ? ld_agent(&src[(int64_t)(m0 + base + q) * ne + e]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (base + q < cnt) s += v[q];
+    }
+    return s;
+}
+
+// out[e] = sum over rows 0..cnt-1 of src (row stride ne), for every e < ne, with the
+// rows of each entry split into contiguous slices over spare threads and the slice
+// sums added in slice order (a fixed tree).  scratch: kWG doubles of LDS.
+__device__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
+    const int tid = threadIdx.x;
+    const int tpe = ne >= kWG ? 1 : kWG / ne;          // threads per entry
+    const int slice = (cnt + tpe - 1) / tpe;
+    for (int e0 = 0; e0 < ne; e0 += kWG / tpe) {
+        const int e = e0 + tid / tpe, sub = tid % tpe;
+        double s = 0.0;
+        if (e < ne && tid / tpe < kWG / tpe) {
+            const int m0 = sub * slice;
+            s = sum_rows(src, ne, e, m0, max(0, min(slice, cnt - m0)));
+        }
+        scratch[tid] = s;
+        __syncthreads();
+        if (sub == 0 && e < ne && tid / tpe < kWG / tpe) {
+            double t = scratch[tid];
+            for (int q = 1; q < tpe; ++q) t += scratch[tid + q];
+            out[e] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // Sum `ne` values per workgroup (mine[], LDS) over the whole grid, in workgroup
 // order within groups of kGroup and in group order across groups.  Returns true
 // in the one workgroup that ends up holding the totals in out[] (LDS).  Tickets
 // are reset by their last taker, so the scratch is ready for the next launch.
-__device__ bool grid_reduce(const double* mine, int ne, const RedBuf& rb, double* out, int* s_flag) {
+__device__ bool grid_reduce(const double* mine, int ne, const RedBuf& rb, double* out, int* s_flag,
+                            double* scratch) {
     const int tid = threadIdx.x;
     const int nwg = gridDim.x;
     const int bid = blockIdx.x;
@@ -138,29 +180,20 @@ __device__ bool grid_reduce(const double* mine, int ne, const RedBuf& rb, double
     __syncthreads();
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[grp]);
-    const int64_t g0 = (int64_t)grp * kGroup;
-    for (int e = tid; e < ne; e += kWG) {
-        double s = ld_agent(&rb.l1[g0 * ne + e]);
-        for (int q = 1; q < gsize; ++q) s += ld_agent(&rb.l1[(g0 + q) * ne + e]);
-        if (ngroups == 1) out[e] = s;
-        else st_agent(&rb.l2[(int64_t)grp * ne + e], s);
-    }
     if (ngroups == 1) {
-        __syncthreads();
+        sum_table(rb.l1, ne, gsize, out, scratch);
         return true;
     }
+    // group sum -> level-2 row of this group
+    sum_table(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
     stores_done();
     __syncthreads();
     if (tid == 0) *s_flag = (ticket(&rb.cnt[ngroups]) == (unsigned)ngroups - 1) ? 1 : 0;
     __syncthreads();
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
-    for (int e = tid; e < ne; e += kWG) {
-        double s = ld_agent(&rb.l2[e]);
-        for (int g = 1; g < ngroups; ++g) s += ld_agent(&rb.l2[(int64_t)g * ne + e]);
-        out[e] = s;
-    }
-    __syncthreads();
+    sum_table(rb.l2, ne, ngroups, out, scratch);
     return true;
 }
 
@@ -252,54 +285,119 @@ __device__ int wg_rank_select(const double* G, int m, double tau, int* keep, dou
     return sh[2];
 }
 
-// Cholesky G = L L^T (m x m compact, natural order).  Returns 0, or -1 when a pivot
-// is not positive.
-__device__ int wg_cholesky(const double* G, int m, double* L, int* sh) {
-    const int tid = threadIdx.x;
-    if (tid < m * m) L[tid] = 0.0;
-    __syncthreads();
-    for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            double d = G[j * m + j];
-            for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
-            if (d > 0.0) { L[j * m + j] = sqrt(d); sh[0] = 0; }
-            else sh[0] = -1;
-        }
-        __syncthreads();
-        if (sh[0] != 0) return -1;
-        const int i = j + 1 + tid;
-        if (i < m) {
-            double s = G[i * m + j];
-            for (int k = 0; k < j; ++k) s -= L[i * m + k] * L[j * m + k];
-            L[i * m + j] = s / L[j * m + j];
-        }
-        __syncthreads();
-    }
-    return 0;
-}
-
-// Z = (L L^T)^{-1} B for q right-hand-side columns (B, Z m x q row-major, stride q).
-// One thread per column.
-__device__ void wg_chol_solve(const double* L, int m, int q, const double* B, double* Z) {
-    const int c = threadIdx.x;
-    if (c < q) {
-        for (int i = 0; i < m; ++i) {
-            double s = B[i * q + c];
-            for (int k = 0; k < i; ++k) s -= L[i * m + k] * Z[k * q + c];
-            Z[i * q + c] = s / L[i * m + i];
-        }
-        for (int i = m - 1; i >= 0; --i) {
-            double s = Z[i * q + c];
-            for (int k = i + 1; k < m; ++k) s -= L[k * m + i] * Z[k * q + c];
-            Z[i * q + c] = s / L[i * m + i];
-        }
-    }
-    __syncthreads();
-}
-
 __device__ __forceinline__ void fail_state(DevState* st, int code) {
     st->done = FAILED;
     st->status = code;
+}
+
+// ----------------------------------------------- wave-distributed p x p algebra
+//
+// A P x P matrix lives in the registers of one wave: entry e = a*P + b sits in lane
+// e % 64, slot e / 64.  Inactive agents are padded as identity rows and columns, so
+// every loop runs over the compile-time P and the active block gets exactly the
+// result of its own factorisation (natural order).  Run by all 64 lanes of a wave.
+
+template <int P> struct WM {
+    static constexpr int NE = P * P;
+    static constexpr int NQ = (NE + 63) / 64;
+};
+
+template <int NQ>
+__device__ __forceinline__ double wget(const double (&h)[NQ], int e) {
+    if (NQ == 1) return __shfl(h[0], e & 63);
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double t = __shfl(h[q], e & 63);
+        if ((e >> 6) == q) r = t;
+    }
+    return r;
+}
+
+// In-place Cholesky G = L L^T (right-looking, natural order); the lower triangle of
+// h becomes L, the strict upper triangle zero.  Returns false on a pivot <= 0 or
+// NaN.  Each L entry is formed from the same products, in the same order, as the
+// plain left-looking recurrence.
+template <int P>
+__device__ bool wave_cholesky(double (&h)[WM<P>::NQ], int lane) {
+    constexpr int NQ = WM<P>::NQ;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const double djj = wget<NQ>(h, j * P + j);
+        if (!(djj > 0.0)) return false;
+        const double ljj = sqrt(djj);
+        double nh[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = lane + 64 * q;
+            const int ea = e < WM<P>::NE ? e : 0;
+            const int x = ea / P, y = ea - (ea / P) * P;
+            const double lx = wget<NQ>(h, x * P + j) / ljj;
+            const double ly = wget<NQ>(h, y * P + j) / ljj;
+            double v = h[q];
+            if (x > j && y > j) v = h[q] - lx * ly;
+            else if (x > j && y == j) v = lx;
+            else if (x == j && y == j) v = ljj;
+            else if (x == j && y > j) v = 0.0;
+            nh[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) h[q] = nh[q];
+    }
+    return true;
+}
+
+// y <- (L L^T)^{-1} y for the P right-hand-side columns held in y (entry (i, c)).
+template <int P>
+__device__ void wave_chol_solve(const double (&h)[WM<P>::NQ], double (&y)[WM<P>::NQ], int lane) {
+    constexpr int NQ = WM<P>::NQ;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {            // L z = y
+        const double lkk = wget<NQ>(h, k * P + k);
+        double ny[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = lane + 64 * q;
+            const int ea = e < WM<P>::NE ? e : 0;
+            const int i = ea / P, c = ea - (ea / P) * P;
+            const double zk = wget<NQ>(y, k * P + c) / lkk;
+            const double lik = wget<NQ>(h, i * P + k);
+            ny[q] = (i == k) ? zk : (i > k ? y[q] - lik * zk : y[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) y[q] = ny[q];
+    }
+#pragma unroll
+    for (int k = P - 1; k >= 0; --k) {       // L^T x = z
+        const double lkk = wget<NQ>(h, k * P + k);
+        double ny[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = lane + 64 * q;
+            const int ea = e < WM<P>::NE ? e : 0;
+            const int i = ea / P, c = ea - (ea / P) * P;
+            const double xk = wget<NQ>(y, k * P + c) / lkk;
+            const double lki = wget<NQ>(h, k * P + i);
+            ny[q] = (i == k) ? xk : (i < k ? y[q] - lki * xk : y[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) y[q] = ny[q];
+    }
+}
+
+// Load a P x P matrix from src[a*lds + b] into wave registers, replacing inactive
+// rows / columns (bit clear in mask) by the identity (diag) or zero (off-diag).
+template <int P>
+__device__ __forceinline__ void wave_load(double (&h)[WM<P>::NQ], const double* src, int lds,
+                                          unsigned mask, bool identity, int lane) {
+#pragma unroll
+    for (int q = 0; q < WM<P>::NQ; ++q) {
+        const int e = lane + 64 * q;
+        const int ea = e < WM<P>::NE ? e : 0;
+        const int x = ea / P, y = ea - (ea / P) * P;
+        const bool on = ((mask >> x) & 1u) && ((mask >> y) & 1u);
+        h[q] = on ? src[x * lds + y] : ((identity && x == y) ? 1.0 : 0.0);
+    }
 }
 
 // Fold M = 2^q values held by every lane of a wave into sums over the 64 lanes:
@@ -352,6 +450,7 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
     __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
     __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
     __shared__ double sm[6 * kMaxP * kMaxP];
+    __shared__ double gscr[kWG];
     __shared__ int ish[128];
 
     if (!a.product_only && a.st->done != RUNNING) return;
@@ -484,72 +583,88 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         gmine[tid] = s;
     }
     __syncthreads();
-    if (!grid_reduce(gmine, P * P, a.red, gtot, &ish[0])) return;
+    if (!grid_reduce(gmine, P * P, a.red, gtot, &ish[0], gscr)) return;
 
-    // ---- last workgroup: rank step, alpha = G^{-1} S
+    // ---- last workgroup: rank step (Alg. 3), alpha = G^{-1} S
     DevState* st = a.st;
-    int* act = &ish[64];    // active agents (global indices), ascending
-    int m = st->m;
-    if (tid < m) act[tid] = st->keep[tid];
-    __syncthreads();
-    double* Gc = sm + 2 * kMaxP * kMaxP;      // compact m x m
-    double* H = sm + 3 * kMaxP * kMaxP;
-    double* Lc = sm + 4 * kMaxP * kMaxP;
-    double* Sc = sm + 5 * kMaxP * kMaxP;
-    double* Zc = gmine;                        // free again
-    if (tid < m * m) {
-        const int i = tid / m, j = tid - (tid / m) * m;
-        // G is symmetric in exact arithmetic; use one triangle of the sum
-        const int gi = max(act[i], act[j]), gj = min(act[i], act[j]);
-        Gc[tid] = gtot[gi * P + gj];
+    constexpr int NQ = WM<P>::NQ;
+    // G is symmetric in exact arithmetic: use the lower triangle of the sum
+    double* Gs = sm + 2 * kMaxP * kMaxP;       // full symmetric P x P
+    if (tid < P * P) {
+        const int x = tid / P, y = tid - (tid / P) * P;
+        Gs[tid] = gtot[max(x, y) * P + min(x, y)];
     }
     __syncthreads();
-    int* kp = &ish[96];
-    const int r = wg_rank_select(Gc, m, st->tau, kp, H, &ish[0]);
-    if (r < 0) {
-        if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
-        return;
-    }
-    if (r < m) {
-        // deflation: restrict to the kept agents (compact indices kp[0..r))
-        double g2 = 0.0;
-        int na = 0;
-        if (tid < r * r) g2 = Gc[kp[tid / r] * m + kp[tid - (tid / r) * r]];
-        if (tid < r) na = act[kp[tid]];
-        __syncthreads();
-        if (tid < r * r) Gc[tid] = g2;
-        if (tid < r) act[tid] = na;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned mask = 0u;
-            for (int q = 0; q < r; ++q) mask |= 1u << act[q];
-            st->mask = mask;
-            st->m = r;
-            st->deflations += 1;
-            for (int q = 0; q < r; ++q) st->keep[q] = act[q];
+    unsigned mask = st->mask;
+    // Fast path: when det of the diagonally scaled G exceeds 2 tau, every pivot of
+    // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
+    // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
+    // keeps every agent; the slow path below runs the greedy rule itself.
+    if (wave == 0) {
+        double h[NQ];
+        wave_load<P>(h, Gs, P, mask, true, lane);
+        const bool ok = wave_cholesky<P>(h, lane);
+        double det = ok ? 1.0 : 0.0;
+        if (ok) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                if ((mask >> j) & 1u) {
+                    const double l = wget<NQ>(h, j * P + j);
+                    det *= (l * l) / Gs[j * P + j];
+                }
+            }
         }
-        m = r;
-        if (m == 0) {
-            if (tid == 0) st->done = FINISHED;
+        if (lane == 0) ish[120] = (ok && det > 2.0 * st->tau) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!ish[120]) {
+        int* act = &ish[64];    // active agents (global indices), ascending
+        const int m = st->m;
+        if (tid < m) act[tid] = st->keep[tid];
+        __syncthreads();
+        double* Gc = sm + 3 * kMaxP * kMaxP;   // compact m x m
+        double* H = sm + 4 * kMaxP * kMaxP;
+        if (tid < m * m) Gc[tid] = Gs[act[tid / m] * P + act[tid % m]];
+        __syncthreads();
+        int* kp = &ish[96];
+        const int r = wg_rank_select(Gc, m, st->tau, kp, H, &ish[0]);
+        if (r < 0) {
+            if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
             return;
         }
+        if (r < m) {
+            if (tid == 0) {
+                unsigned nm = 0u;
+                for (int q = 0; q < r; ++q) nm |= 1u << act[kp[q]];
+                for (int q = 0; q < r; ++q) st->keep[q] = act[kp[q]];
+                st->mask = nm;
+                st->m = r;
+                st->deflations += 1;
+                if (r == 0) st->done = FINISHED;
+                ish[121] = (int)nm;
+            }
+            __syncthreads();
+            mask = (unsigned)ish[121];
+            if (r == 0) return;
+        }
     }
-    if (wg_cholesky(Gc, m, Lc, &ish[0]) != 0) {
-        if (tid == 0) fail_state(st, -3);
+    if (wave != 0) return;
+    double h[NQ], y[NQ];
+    wave_load<P>(h, Gs, P, mask, true, lane);
+    if (!wave_cholesky<P>(h, lane)) {
+        if (lane == 0) fail_state(st, -3);
         return;
     }
-    if (tid < m * m) {
-        const int i = tid / m, j = tid - (tid / m) * m;
-        Sc[tid] = st->S[act[i] * kMaxP + act[j]];
-    }
-    __syncthreads();
-    wg_chol_solve(Lc, m, m, Sc, Zc);
-    if (tid < kMaxP * kMaxP) st->alpha[tid] = 0.0;
-    __syncthreads();
-    if (tid < m * m) {
-        const int i = tid / m, j = tid - (tid / m) * m;
-        st->alpha[act[i] * kMaxP + act[j]] = Zc[tid];
-        st->Lc[tid] = Lc[tid];
+    wave_load<P>(y, st->S, kMaxP, mask, false, lane);
+    wave_chol_solve<P>(h, y, lane);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = lane + 64 * q;
+        if (e < WM<P>::NE) {
+            const int x = e / P, yy = e - (e / P) * P;
+            st->alpha[x * kMaxP + yy] = y[q];
+            st->L[x * kMaxP + yy] = h[q];
+        }
     }
 }
 
@@ -566,7 +681,7 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
     __shared__ double mine[NE];
     __shared__ double tot[NE];
-    __shared__ double Lc[kMaxP * kMaxP], Wc[kMaxP * kMaxP], Bc[kMaxP * kMaxP];
+    __shared__ double gscr[kWG];
     __shared__ int ish[128];
     DevState* st = a.st;
     if (st->done != RUNNING) return;
@@ -605,41 +720,42 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(mine, NE, a.red, tot, &ish[0])) return;
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr)) return;
 
-    // ---- last workgroup: beta, next S, norms, stop test
+    // ---- last workgroup: beta = -G^{-1} (AD)^T R, next S, norms, stop test
+    if ((tid >> 6) != 0) return;
+    const int lane = tid & 63;
+    constexpr int NQ = WM<P>::NQ;
     const double* W = tot;
     const double* Q = tot + P * P;
     const double* F = tot + 2 * P * P;
-    const int m = st->m;
-    int* act = &ish[64];
-    if (tid < m) act[tid] = st->keep[tid];
-    __syncthreads();
-    if (tid < m * m) {
-        const int ii = tid / m, jj = tid - (tid / m) * m;
-        Lc[tid] = st->Lc[tid];
-        Wc[tid] = -W[act[ii] * P + act[jj]];
-    }
-    __syncthreads();
-    wg_chol_solve(Lc, m, m, Wc, Bc);       // beta = -G^{-1} (AD)^T R
-    if (tid < kMaxP * kMaxP) {
-        st->beta[tid] = 0.0;
-        st->S[tid] = 0.0;
-    }
-    __syncthreads();
-    if (tid < m * m) {
-        const int ii = tid / m, jj = tid - (tid / m) * m;
-        st->beta[act[ii] * kMaxP + act[jj]] = Bc[tid];
+    const unsigned mask = st->mask;
+    double h[NQ], y[NQ];
+    wave_load<P>(h, st->L, kMaxP, mask, true, lane);
+    wave_load<P>(y, W, P, mask, false, lane);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] = -y[q];
+    wave_chol_solve<P>(h, y, lane);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = lane + 64 * q;
+        const int ea = e < WM<P>::NE ? e : 0;
+        const int i = ea / P, jj = ea - (ea / P) * P;
+        const bool on = ((mask >> i) & 1u) && ((mask >> jj) & 1u);
         // S_next = R^T R + beta^T (D^T R), restricted to the active agents
-        double s = Q[act[ii] * P + act[jj]];
-        for (int l = 0; l < m; ++l) s = fma(Bc[l * m + ii], F[act[l] * P + act[jj]], s);
-        st->S[act[ii] * kMaxP + act[jj]] = s;
+        double sv = Q[i * P + jj];
+#pragma unroll
+        for (int l = 0; l < P; ++l) sv = fma(wget<NQ>(y, l * P + i), F[l * P + jj], sv);
+        if (e < WM<P>::NE) {
+            st->beta[i * kMaxP + jj] = on ? y[q] : 0.0;
+            st->S[i * kMaxP + jj] = on ? sv : 0.0;
+        }
     }
-    if (tid == 0) {
+    if (lane == 0) {
         double mn = INFINITY;
         bool bad = false;
-        for (int q = 0; q < m; ++q) {
-            const int jj = act[q];
+        for (int jj = 0; jj < P; ++jj) {
+            if (!((mask >> jj) & 1u)) continue;
             const double nr = sqrt(Q[jj * P + jj]);
             st->norms[jj] = nr;
             if (!isfinite(nr)) bad = true;
@@ -688,6 +804,7 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
     __shared__ double bs[RB];
     __shared__ double mine[NE];
     __shared__ double tot[NE];
+    __shared__ double gscr[kWG];
     __shared__ int ish[8];
     DevState* st = a.st;
     const int tid = threadIdx.x;
@@ -715,7 +832,7 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(mine, NE, a.red, tot, &ish[0])) return;
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr)) return;
     if (tid == 0) {
         if (a.set_nb) st->nb = sqrt(tot[P * P]);
         double mn = INFINITY;
