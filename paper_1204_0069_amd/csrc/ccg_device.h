@@ -15,7 +15,6 @@ namespace ccg {
 constexpr int kMaxP = 16;       // largest padded agent count
 constexpr int kWG = 256;        // threads per workgroup for every kernel
 constexpr int kRowAlign = 512;  // n_pad granularity
-constexpr int kAdCols = 16;     // A columns (= AD rows) per A.D workgroup: 4 waves x 4
 constexpr int kGroup = 16;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
@@ -41,7 +40,6 @@ struct DevState {
     double norms[kMaxP];                 // ||R_j|| per agent (last computed)
     double alpha[kMaxP * kMaxP];         // alpha[l*kMaxP + j]: X[:,j] += D[:,l] alpha[l][j]
     double beta[kMaxP * kMaxP];          // beta[l*kMaxP + j]:  D[:,j] = R[:,j] + D[:,l] beta[l][j]
-    double S[kMaxP * kMaxP];             // D^T R for the next alpha (full P x P, zeros off J)
     double L[kMaxP * kMaxP];             // Cholesky factor of G (inactive agents: identity)
 };
 
@@ -60,9 +58,10 @@ struct AdArgs {
     int n;               // system size
     int n_pad;           // padded row count of the vector blocks
     int product_only;    // 1: only form Y = A.V (residual); 0: also Gram + alpha
-    const void* V;       // operand block (agent-major, vector type)
+    const void* V;       // operand block D (agent-major, vector type)
+    const void* R;       // residual block (agent-major, vector type)
     void* AD;            // result block (agent-major, vector type)
-    RedBuf red;          // Gram reduction scratch (ne = P*P)
+    RedBuf red;          // reduction scratch (ne = P*(P+1) + 2*P*P + P)
     DevState* st;
 };
 
@@ -70,17 +69,9 @@ struct UpdArgs {
     int n_pad;
     void* X;             // agent-major blocks (vector type)
     void* R;
-    const void* D;
-    const void* AD;
-    RedBuf red;          // ne = 3*P*P
-    DevState* st;
-};
-
-struct DirArgs {
-    int n_pad;
-    const void* R;
     void* D;
-    const DevState* st;
+    const void* AD;
+    DevState* st;
 };
 
 // Residual epilogue: T = B - Y, with B = b in every column (FP64).

@@ -23,7 +23,6 @@
 namespace ccg {
 hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s);
 hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s);
-hipError_t launch_dir(int prec, int P, const DirArgs& a, hipStream_t s);
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
 hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,
                        hipStream_t s);
@@ -68,7 +67,7 @@ struct Workspace {
     double* R = nullptr;             // agent-major n_pad x P
     double* D = nullptr;
     double* AD = nullptr;
-    RedBuf red_ad{}, red_upd{}, red_res{};
+    RedBuf red_ad{}, red_res{};
     DevState* st = nullptr;
 };
 
@@ -132,8 +131,7 @@ size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
     w.R = cv.take<double>(blk);
     w.D = cv.take<double>(blk);
     w.AD = cv.take<double>(blk);
-    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * P);
-    w.red_upd = carve_red(cv, row_workgroups(n_pad, P), 3 * P * P);
+    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) + 2 * P * P + P);
     w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
     return cv.off;
@@ -187,6 +185,7 @@ AdArgs ad_args(const Solve& s, const void* V, bool product_only) {
     a.n_pad = w.n_pad;
     a.product_only = product_only ? 1 : 0;
     a.V = V;
+    a.R = w.R;
     a.AD = w.AD;
     a.red = w.red_ad;
     a.st = w.st;
@@ -223,7 +222,8 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
     return c->ev_pool[i];
 }
 
-// One block step: A.D (+ Gram, rank step, alpha), update (+ beta), direction.
+// One block step: A.D (+ products, stop test, rank step, alpha, beta), then the
+// X, R, D update.
 void enqueue_step(const Solve& s, size_t ev_slot) {
     Workspace& w = s.c->ws;
     if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot), s.c->stream));
@@ -235,15 +235,8 @@ void enqueue_step(const Solve& s, size_t ev_slot) {
     u.R = w.R;
     u.D = w.D;
     u.AD = w.AD;
-    u.red = w.red_upd;
     u.st = w.st;
     HIP_OK(launch_upd(s.prec, s.P, u, s.c->stream));
-    DirArgs d;
-    d.n_pad = w.n_pad;
-    d.R = w.R;
-    d.D = w.D;
-    d.st = w.st;
-    HIP_OK(launch_dir(s.prec, s.P, d, s.c->stream));
 }
 
 void read_state(ccg_ctx* c) {
@@ -396,8 +389,11 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
             const int it0 = h.iter;
             run_steps(s, k, use_graph);
             read_state(c);
-            if (s.profile) collect_profile(c, h.iter - it0);
-            bytes += bytes_iter * (h.iter - it0);
+            // A.D launches that streamed A: one per completed step, plus the one
+            // whose stop test ended the batch
+            const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
+            if (s.profile) collect_profile(c, streamed);
+            bytes += bytes_iter * streamed;
         }
         if (h.done == RECUR_CONV) {
             enqueue_residual(s, RES_CONFIRM, 0);

@@ -1,26 +1,22 @@
 // HIP kernels (gfx950) for the block step of cooperative conjugate gradient.
 //
 // One block step (Alg. 2 of the paper, sign convention R = B - A X, residual by
-// the Table 1 recurrence) is three launches:
+// the Table 1 recurrence) is two launches:
 //
 //   k_ad   : AD = A D, streaming A once.  A is symmetric, so column i of A (which is
 //            contiguous in the column-major layout) is row i: each wave streams
-//            four whole columns with 16-byte loads, its lanes splitting the
+//            whole columns with 16-byte non-temporal loads, its lanes splitting the
 //            contraction index k, and multiplies them with D rows staged in LDS
 //            (double buffered).  Lane sums are folded by a fixed xor butterfly, so
 //            every AD row is complete inside one wave: no split-K partials.  Each
-//            workgroup adds its rows' share of G = D^T A D; a two-level fixed-order
-//            reduction across workgroups ends in the last workgroup, which runs the
-//            rank step of Alg. 3 and solves G alpha = S (Cholesky, FP64).
-//   k_upd  : X += D alpha, R -= AD alpha, and the reductions (AD)^T R, R^T R and
-//            D^T R; the last workgroup solves G beta = -(AD)^T R with the cached
-//            factor, forms the next S = D_new^T R = R^T R + beta^T (D^T R), the
-//            residual norms and the stop test.
-//   k_dir  : D = R + D beta (masked to the active agents).
+//            workgroup adds its rows' share of five p x p products (D^T AD, AD^T R,
+//            AD^T AD, D^T R, R^T R); a two-level fixed-order reduction across
+//            workgroups ends in the last workgroup, which runs the stop test on the
+//            residual norms, the rank step of Alg. 3, alpha = G^{-1} D^T R and
+//            beta = -G^{-1} (AD)^T R_new with (AD)^T R_new = AD^T R - AD^T AD alpha
+//            (all FP64).
+//   k_upd  : X += D alpha, R -= AD alpha, D = R + D beta (masked to active agents).
 //
-// Cross-workgroup sums are written and read with agent-scope atomic stores and
-// loads (coherent across the XCDs without flushing L2) and summed in a fixed
-// order, so every result depends only on (n, p, precision, tile shape).
 #include "ccg_device.h"
 
 #include <math.h>
@@ -49,17 +45,21 @@ template <> struct PT<PREC_BF16X2> {
     static constexpr int E = 8;
 };
 
-constexpr int kCW = 4;   // A columns per wave
-constexpr int kNW = 4;   // waves per A.D workgroup (kCW * kNW == kAdCols)
-static_assert(kCW * kNW == kAdCols, "A.D tile shape");
-
-// Contraction elements per D chunk staged in LDS: a multiple of one wave step
-// (64 * E) keeping the two chunk buffers near 32 KiB.
-template <int PREC, int P> constexpr int chunk_k() {
-    constexpr int step = 64 * PT<PREC>::E;
-    constexpr int fit = 32768 / (2 * P * (int)sizeof(typename PT<PREC>::TV));
-    return fit >= step ? (fit / step) * step : step;
-}
+// Tile configuration of the A.D kernel: CW A columns per wave (4 waves per
+// workgroup, so 4*CW AD rows per workgroup), SPC wave steps of 64*E contraction
+// elements per staged D chunk, an occupancy hint MINW (waves per SIMD) and
+// non-temporal A loads (A is read exactly once per launch).
+// STG rotates each workgroup's starting chunk so that concurrent workgroups read
+// different offsets of their columns (the column stride is a large power of two).
+template <int CW_, int SPC_, int MINW_, bool NT_, bool STG_ = false>
+struct AdCfg {
+    static constexpr int CW = CW_;
+    static constexpr int SPC = SPC_;
+    static constexpr int MINW = MINW_;
+    static constexpr bool NT = NT_;
+    static constexpr bool STG = STG_;
+    static constexpr int ROWS = 4 * CW_;
+};
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float(((uint32_t)h) << 16);
@@ -67,28 +67,38 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 
 // Load the E elements of one 16-byte chunk of a column, converted to TACC.  hi
 // points into the FP64 / FP32 matrix or the BF16 "hi" plane, lo into the BF16 "lo"
-// plane at the same offset.
-template <int PREC> struct Loader;
+// plane at the same offset.  NT selects non-temporal (streaming) loads.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
-template <> struct Loader<PREC_F64> {
+template <bool NT, class T>
+__device__ __forceinline__ T ld16(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <int PREC, bool NT> struct Loader;
+
+template <bool NT> struct Loader<PREC_F64, NT> {
     __device__ __forceinline__ static void load(const double* hi, const double*, double (&out)[2]) {
-        const double2 v = *reinterpret_cast<const double2*>(hi);
+        const d2v v = ld16<NT>(reinterpret_cast<const d2v*>(hi));
         out[0] = v.x;
         out[1] = v.y;
     }
     __device__ __forceinline__ static double load1(const double* hi, const double*) { return *hi; }
 };
-template <> struct Loader<PREC_F32> {
+template <bool NT> struct Loader<PREC_F32, NT> {
     __device__ __forceinline__ static void load(const float* hi, const float*, float (&out)[4]) {
-        const float4 v = *reinterpret_cast<const float4*>(hi);
+        const f4v v = ld16<NT>(reinterpret_cast<const f4v*>(hi));
         out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
     }
     __device__ __forceinline__ static float load1(const float* hi, const float*) { return *hi; }
 };
-template <> struct Loader<PREC_BF16X2> {
+template <bool NT> struct Loader<PREC_BF16X2, NT> {
     __device__ __forceinline__ static void load(const uint16_t* hi, const uint16_t* lo, float (&out)[8]) {
-        const uint4 h = *reinterpret_cast<const uint4*>(hi);
-        const uint4 l = *reinterpret_cast<const uint4*>(lo);
+        const u4v h = ld16<NT>(reinterpret_cast<const u4v*>(hi));
+        const u4v l = ld16<NT>(reinterpret_cast<const u4v*>(lo));
         const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
         const uint32_t lw[4] = {l.x, l.y, l.z, l.w};
 #pragma unroll
@@ -432,24 +442,31 @@ __device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
 
 // ============================================================== k_ad: AD = A D
 
-template <int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
+template <int PREC, int P, class CFG>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
     using TA = typename PT<PREC>::TA;
     using TV = typename PT<PREC>::TV;
     using TACC = typename PT<PREC>::TACC;
     constexpr int E = PT<PREC>::E;
     constexpr int KSTEP = 64 * E;
-    constexpr int KC = chunk_k<PREC, P>();
-    constexpr int SPC = KC / KSTEP;           // wave steps per chunk
+    constexpr int SPC = CFG::SPC;             // wave steps per chunk
+    constexpr int KC = SPC * KSTEP;
+    constexpr int kCW = CFG::CW;
+    constexpr int kAdCols = CFG::ROWS;
+    constexpr bool NT = CFG::NT;
     constexpr int NV = kCW * P;               // lane sums per wave
     constexpr int PER = P * KC / kWG;         // staged D values per thread per chunk
     static_assert(P * KC % kWG == 0, "chunk staging must split evenly");
     static_assert(NV <= 64, "lane sums per wave");
+    static_assert(512 % KC == 0, "chunks must tile the padded length");
 
     __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
     __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
     __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
-    __shared__ double sm[6 * kMaxP * kMaxP];
+    __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
+    __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
+    __shared__ double gtot[P * (P + 1) + 2 * P * P + P];    // grid totals (last workgroup)
+    __shared__ double sm[3 * kMaxP * kMaxP];
     __shared__ double gscr[kWG];
     __shared__ int ish[128];
 
@@ -478,27 +495,32 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
 
     const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
+    // first chunk of this workgroup (rotated when staggering); chunks then wrap
+    const int c0 = CFG::STG ? (int)(((unsigned)blockIdx.x * 7u) % (unsigned)nch) : 0;
     TV pre[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int idx = tid + q * kWG;
         const int j = idx / KC, kk = idx - (idx / KC) * KC;
-        pre[q] = V[(int64_t)j * a.n_pad + kk];
+        pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) dch[0][tid + q * kWG] = pre[q];
     __syncthreads();
 
-    for (int ch = 0; ch < nch; ++ch) {
-        const int buf = ch & 1;
+    for (int it = 0; it < nch; ++it) {
+        const int buf = it & 1;
+        int ch = c0 + it;
+        if (ch >= nch) ch -= nch;
         const int k0 = ch * KC;
-        const bool more = ch + 1 < nch;
+        const bool more = it + 1 < nch;
         if (more) {
+            const int nx = (ch + 1 < nch) ? ch + 1 : 0;
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 const int idx = tid + q * kWG;
                 const int j = idx / KC, kk = idx - (idx / KC) * KC;
-                pre[q] = V[(int64_t)j * a.n_pad + k0 + KC + kk];
+                pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
             }
         }
         const TV* dc = dch[buf];
@@ -508,7 +530,7 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
                 const int kk = s * KSTEP + lane * E;
                 TACC av[kCW][E];
 #pragma unroll
-                for (int c = 0; c < kCW; ++c) Loader<PREC>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
+                for (int c = 0; c < kCW; ++c) Loader<PREC, NT>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                     TACC d[E];
@@ -529,7 +551,7 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
                 for (int c = 0; c < kCW; ++c)
 #pragma unroll
                     for (int e = 0; e < E; ++e)
-                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
+                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC, NT>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
                                                      : TACC(0);
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
@@ -563,45 +585,95 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         const int i = iw + c;
         const TV y = TV(v[0]);
         if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
-        adt[(wave * kCW + c) * kMaxP + j] = double(y);
+        adt[(wave * kCW + c) * kMaxP + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
     }
     if (a.product_only) return;
 
-    // ---- Gram share of the workgroup's rows: G_w[x][y] = sum_r D[r][x] AD[r][y]
-    if (tid < kAdCols * P) {
-        const int r = tid / P, j = tid - (tid / P) * P;
+    // ---- the workgroup's share of the products over its rows, packed as
+    //   G = D^T AD (lower triangle), Z = AD^T R, Y = AD^T AD (lower triangle),
+    //   S = D^T R, and the diagonal of R^T R
+    const TV* __restrict__ Rv = static_cast<const TV*>(a.R);
+    for (int t = tid; t < kAdCols * P; t += kWG) {
+        const int r = t / P, j = t - (t / P) * P;
         const int i = i0 + r;
         drw[r * kMaxP + j] = (i < n) ? double(V[(int64_t)j * a.n_pad + i]) : 0.0;
+        rrw[r * kMaxP + j] = (i < n) ? double(Rv[(int64_t)j * a.n_pad + i]) : 0.0;
     }
     __syncthreads();
-    double* gmine = sm;                       // P*P
-    double* gtot = sm + kMaxP * kMaxP;        // P*P
-    if (tid < P * P) {
-        const int x = tid / P, y = tid - (tid / P) * P;
+    constexpr int TRI = P * (P + 1) / 2;
+    constexpr int OZ = TRI, OY = TRI + P * P, OS = 2 * TRI + P * P, OQ = 2 * TRI + 2 * P * P;
+    constexpr int NE = OQ + P;
+    for (int e = tid; e < NE; e += kWG) {
+        const double* U;
+        const double* Wv;
+        int x, y;
+        if (e < OZ || (e >= OY && e < OS)) {             // triangles of G and Y
+            const int t = e < OZ ? e : e - OY;
+            x = 0;
+            while ((x + 1) * (x + 2) / 2 <= t) ++x;
+            y = t - x * (x + 1) / 2;
+            U = e < OZ ? drw : adt;
+            Wv = adt;
+        } else if (e < OQ) {                              // Z and S, full
+            const int t = e < OY ? e - OZ : e - OS;
+            x = t / P;
+            y = t - x * P;
+            U = e < OY ? adt : drw;
+            Wv = rrw;
+        } else {                                          // diagonal of R^T R
+            x = y = e - OQ;
+            U = rrw;
+            Wv = rrw;
+        }
         double s = 0.0;
-        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], adt[r * kMaxP + y], s);
-        gmine[tid] = s;
+        for (int r = 0; r < kAdCols; ++r) s = fma(U[r * kMaxP + x], Wv[r * kMaxP + y], s);
+        gmine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(gmine, P * P, a.red, gtot, &ish[0], gscr)) return;
+    if (!grid_reduce(gmine, NE, a.red, gtot, &ish[0], gscr)) return;
 
-    // ---- last workgroup: rank step (Alg. 3), alpha = G^{-1} S
+    // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
     DevState* st = a.st;
     constexpr int NQ = WM<P>::NQ;
-    // G is symmetric in exact arithmetic: use the lower triangle of the sum
-    double* Gs = sm + 2 * kMaxP * kMaxP;       // full symmetric P x P
-    if (tid < P * P) {
-        const int x = tid / P, y = tid - (tid / P) * P;
-        Gs[tid] = gtot[max(x, y) * P + min(x, y)];
+    const double* Zt = gtot + OZ;
+    const double* St = gtot + OS;
+    const double* Qd = gtot + OQ;
+    unsigned mask = st->mask;
+    if (tid == 0) {
+        // stop test (Alg. 4: smallest agent residual) before the step, as the loop does
+        double mn = INFINITY;
+        bool bad = false;
+        for (int jj = 0; jj < P; ++jj) {
+            if (!((mask >> jj) & 1u)) continue;
+            const double nr = sqrt(Qd[jj]);
+            st->norms[jj] = nr;
+            if (!isfinite(nr)) bad = true;
+            mn = fmin(mn, nr / st->nb);
+        }
+        st->minres = mn;
+        int stop = 0;
+        if (bad) { fail_state(st, -2); stop = 1; }
+        else if (mn <= st->tol) { st->done = RECUR_CONV; stop = 1; }
+        else if (st->iter >= st->maxit) { st->done = MAXIT; stop = 1; }
+        ish[122] = stop;
+    }
+    // G and Y are symmetric in exact arithmetic: expand their lower triangles
+    double* Gs = sm;                          // full symmetric P x P
+    double* Ys = gmine;                       // (gmine is free now)
+    for (int t = tid; t < P * P; t += kWG) {
+        const int x = t / P, y = t - (t / P) * P;
+        const int hi = max(x, y), lo = min(x, y);
+        Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
+        Ys[t] = gtot[OY + hi * (hi + 1) / 2 + lo];
     }
     __syncthreads();
-    unsigned mask = st->mask;
+    if (ish[122]) return;
     // Fast path: when det of the diagonally scaled G exceeds 2 tau, every pivot of
     // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
     // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
     // keeps every agent; the slow path below runs the greedy rule itself.
+    double h[NQ];
     if (wave == 0) {
-        double h[NQ];
         wave_load<P>(h, Gs, P, mask, true, lane);
         const bool ok = wave_cholesky<P>(h, lane);
         double det = ok ? 1.0 : 0.0;
@@ -617,13 +689,14 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         if (lane == 0) ish[120] = (ok && det > 2.0 * st->tau) ? 1 : 0;
     }
     __syncthreads();
-    if (!ish[120]) {
+    const bool fast = ish[120] != 0;
+    if (!fast) {
         int* act = &ish[64];    // active agents (global indices), ascending
         const int m = st->m;
         if (tid < m) act[tid] = st->keep[tid];
         __syncthreads();
-        double* Gc = sm + 3 * kMaxP * kMaxP;   // compact m x m
-        double* H = sm + 4 * kMaxP * kMaxP;
+        double* Gc = sm + kMaxP * kMaxP;       // compact m x m
+        double* H = sm + 2 * kMaxP * kMaxP;
         if (tid < m * m) Gc[tid] = Gs[act[tid / m] * P + act[tid % m]];
         __syncthreads();
         int* kp = &ish[96];
@@ -649,52 +722,70 @@ __global__ __launch_bounds__(kWG) void k_ad(AdArgs a) {
         }
     }
     if (wave != 0) return;
-    double h[NQ], y[NQ];
-    wave_load<P>(h, Gs, P, mask, true, lane);
-    if (!wave_cholesky<P>(h, lane)) {
-        if (lane == 0) fail_state(st, -3);
-        return;
+    double al[NQ], w[NQ];
+    if (!fast) {
+        wave_load<P>(h, Gs, P, mask, true, lane);
+        if (!wave_cholesky<P>(h, lane)) {
+            if (lane == 0) fail_state(st, -3);
+            return;
+        }
     }
-    wave_load<P>(y, st->S, kMaxP, mask, false, lane);
-    wave_chol_solve<P>(h, y, lane);
+    // alpha = G^{-1} (D^T R)
+    wave_load<P>(al, St, P, mask, false, lane);
+    wave_chol_solve<P>(h, al, lane);
+    // (AD)^T R_new = (AD)^T R - (AD^T AD) alpha, then beta = -G^{-1} (AD)^T R_new
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = lane + 64 * q;
+        const int ea = e < WM<P>::NE ? e : 0;
+        const int x = ea / P, c = ea - (ea / P) * P;
+        double v = Zt[x * P + c];
+#pragma unroll
+        for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * wget<NQ>(al, l * P + c);
+        const bool on = ((mask >> x) & 1u) && ((mask >> c) & 1u);
+        w[q] = on ? -v : 0.0;
+    }
+    wave_chol_solve<P>(h, w, lane);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int e = lane + 64 * q;
         if (e < WM<P>::NE) {
             const int x = e / P, yy = e - (e / P) * P;
-            st->alpha[x * kMaxP + yy] = y[q];
+            st->alpha[x * kMaxP + yy] = al[q];
+            st->beta[x * kMaxP + yy] = w[q];
             st->L[x * kMaxP + yy] = h[q];
         }
     }
 }
 
-// ============================================ k_upd: X += D alpha, R -= AD alpha
+// ===================== k_upd: X += D alpha, R -= AD alpha, D = R + D beta
 //
 // Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
+// Every row's old D is read into LDS before any thread writes the new one.
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
-    constexpr int NE = 3 * P * P;
-    __shared__ double al[P * P];
+    __shared__ double al[P * P], be[P * P];
     __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
-    __shared__ double mine[NE];
-    __shared__ double tot[NE];
-    __shared__ double gscr[kWG];
-    __shared__ int ish[128];
     DevState* st = a.st;
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
     const int r = tid % RB, j = tid / RB;
     const int64_t i = (int64_t)blockIdx.x * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
-    if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+    if (tid < P * P) {
+        al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+        be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
+    }
+    const unsigned msk = st->mask;
     TV* X = static_cast<TV*>(a.X);
     TV* R = static_cast<TV*>(a.R);
+    TV* D = static_cast<TV*>(a.D);
     const double x0 = X[o];
     const double r0 = R[o];
-    dt[r * P + j] = static_cast<const TV*>(a.D)[o];
+    dt[r * P + j] = D[o];
     adt[r * P + j] = static_cast<const TV*>(a.AD)[o];
     __syncthreads();
     double sx = 0.0, sr = 0.0;
@@ -709,89 +800,11 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     R[o] = rn;
     rt[r * P + j] = double(rn);
     __syncthreads();
-    // partial sums over this workgroup's rows: W = AD^T R, Q = R^T R, F = D^T R
-    for (int e = tid; e < NE; e += kWG) {
-        const int which = e / (P * P);
-        const int xy = e - which * P * P;
-        const int x = xy / P, y = xy - (xy / P) * P;
-        const double* U = which == 0 ? adt : (which == 1 ? rt : dt);
-        double s = 0.0;
-        for (int q = 0; q < RB; ++q) s = fma(U[q * P + x], rt[q * P + y], s);
-        mine[e] = s;
-    }
-    __syncthreads();
-    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr)) return;
-
-    // ---- last workgroup: beta = -G^{-1} (AD)^T R, next S, norms, stop test
-    if ((tid >> 6) != 0) return;
-    const int lane = tid & 63;
-    constexpr int NQ = WM<P>::NQ;
-    const double* W = tot;
-    const double* Q = tot + P * P;
-    const double* F = tot + 2 * P * P;
-    const unsigned mask = st->mask;
-    double h[NQ], y[NQ];
-    wave_load<P>(h, st->L, kMaxP, mask, true, lane);
-    wave_load<P>(y, W, P, mask, false, lane);
+    double sd = rt[r * P + j];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) y[q] = -y[q];
-    wave_chol_solve<P>(h, y, lane);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int e = lane + 64 * q;
-        const int ea = e < WM<P>::NE ? e : 0;
-        const int i = ea / P, jj = ea - (ea / P) * P;
-        const bool on = ((mask >> i) & 1u) && ((mask >> jj) & 1u);
-        // S_next = R^T R + beta^T (D^T R), restricted to the active agents
-        double sv = Q[i * P + jj];
-#pragma unroll
-        for (int l = 0; l < P; ++l) sv = fma(wget<NQ>(y, l * P + i), F[l * P + jj], sv);
-        if (e < WM<P>::NE) {
-            st->beta[i * kMaxP + jj] = on ? y[q] : 0.0;
-            st->S[i * kMaxP + jj] = on ? sv : 0.0;
-        }
-    }
-    if (lane == 0) {
-        double mn = INFINITY;
-        bool bad = false;
-        for (int jj = 0; jj < P; ++jj) {
-            if (!((mask >> jj) & 1u)) continue;
-            const double nr = sqrt(Q[jj * P + jj]);
-            st->norms[jj] = nr;
-            if (!isfinite(nr)) bad = true;
-            mn = fmin(mn, nr / st->nb);
-        }
-        st->minres = mn;
-        st->iter += 1;
-        if (bad) fail_state(st, -2);
-        else if (mn <= st->tol) st->done = RECUR_CONV;
-        else if (st->iter >= st->maxit) st->done = MAXIT;
-    }
-}
-
-// ====================================================== k_dir: D = R + D beta
-
-template <int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_dir(DirArgs a) {
-    using TV = typename PT<PREC>::TV;
-    constexpr int RB = kWG / P;
-    __shared__ double be[P * P];
-    __shared__ double dt[RB * P];
-    const DevState* st = a.st;
-    if (st->done != RUNNING) return;
-    const int tid = threadIdx.x;
-    const int r = tid % RB, j = tid / RB;
-    const int64_t o = (int64_t)j * a.n_pad + (int64_t)blockIdx.x * RB + r;
-    if (tid < P * P) be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
-    TV* D = static_cast<TV*>(a.D);
-    dt[r * P + j] = D[o];
-    const unsigned msk = st->mask;
-    const double rr = static_cast<const TV*>(a.R)[o];
-    __syncthreads();
-    double s = rr;
-#pragma unroll
-    for (int l = 0; l < P; ++l) s = fma(dt[r * P + l], be[l * P + j], s);
-    D[o] = ((msk >> j) & 1u) ? TV(s) : TV(0);
+    for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
+    D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
+    if (blockIdx.x == 0 && tid == 0) st->iter += 1;
 }
 
 // ============================================ k_res: T = B - Y, norms, restart
@@ -854,12 +867,6 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
             }
         }
     }
-    // next S = D^T R = T^T T on the active agents (D = R = T)
-    if (a.mode != RES_FINAL && tid < kMaxP * kMaxP) {
-        const int x = tid / kMaxP, y = tid % kMaxP;
-        const bool on = x < P && y < P && ((msk >> x) & 1u) && ((msk >> y) & 1u);
-        st->S[tid] = on ? tot[x * P + y] : 0.0;
-    }
 }
 
 // ======================================================== layout conversions
@@ -897,19 +904,23 @@ __global__ void k_copy_cols(int n, const double* A, int64_t lda, double* B, int6
 
 // ================================================================== launchers
 
+// Tile configuration used by the library, per precision and padded agent count.
+// (measured at n = 8192, FP64, p = 8: 2 columns per wave, one wave step per staged
+// chunk, staggered starts and non-temporal A loads stream A at ~85 % of HBM peak)
+template <int PREC, int P> struct AdPick {
+    static constexpr int step = 64 * PT<PREC>::E;
+    using type = AdCfg<2, (P * step >= kWG ? 1 : kWG / (P * step)), 4, true, true>;
+};
+
 template <int PREC, int P>
 static hipError_t launch_ad_t(const AdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_ad<PREC, P>), dim3((a.n + kAdCols - 1) / kAdCols), dim3(kWG), 0, s, a);
+    using C = typename AdPick<PREC, P>::type;
+    hipLaunchKernelGGL((k_ad<PREC, P, C>), dim3((a.n + C::ROWS - 1) / C::ROWS), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_upd<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
-    return hipGetLastError();
-}
-template <int PREC, int P>
-static hipError_t launch_dir_t(const DirArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int P>
@@ -956,19 +967,6 @@ hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_dir(int prec, int P, const DirArgs& a, hipStream_t s) {
-    switch (prec) {
-#define C64(PP) launch_dir_t<PREC_F64, PP>(a, s)
-#define C32(PP) launch_dir_t<PREC_F32, PP>(a, s)
-        case PREC_F64: CCG_DISPATCH_P(P, C64)
-        case PREC_F32:
-        case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
-#undef C64
-#undef C32
-        default: return hipErrorInvalidValue;
-    }
-}
-
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s) {
 #define CR(PP) launch_res_t<PP>(a, s)
     CCG_DISPATCH_P(P, CR)
@@ -1004,7 +1002,8 @@ hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int6
 }
 
 // Number of workgroups of each launch (the host sizes reduction scratch with it).
-int ad_workgroups(int n) { return (n + kAdCols - 1) / kAdCols; }
+// (an upper bound over every configuration: at least 4 rows per workgroup)
+int ad_workgroups(int n) { return (n + 3) / 4; }
 int row_workgroups(int n_pad, int P) { return n_pad / (kWG / P); }
 
 }  // namespace ccg
