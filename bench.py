@@ -40,7 +40,44 @@ def parse():
                     help="block steps of the oracle timed on the host (0: skip)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (3 times) and exit: the "
+                         "known-size kernel that scales hardware byte counters")
     return ap.parse_args()
+
+
+def recorded_traffic(n: int, p: int, prec: str):
+    """HBM bytes per A.D launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    (profiles/), or None when no run covers this workload or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", f"k_ad_{prec}_n{n}_p{p}_traffic.md")
+    src = os.path.join(HERE, "paper_1204_0069_amd", "csrc", "ccg_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "*", "`", " ")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in rec:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
+def copy_calibration(mib: int):
+    """A plain device copy of known size, for reading FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
 def main():
@@ -51,6 +88,10 @@ def main():
                                    "multi-GPU path (see DESIGN.md for how it would shard)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -112,7 +153,8 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "kernel": "k_ad",
+                    "traffic": recorded_traffic(n, p, args.prec), "traffic_unit": "B/launch",
+                    "kernel": "k_ad",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
                     "bytes_per_launch": bytes_per_launch}
 
