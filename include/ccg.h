@@ -70,7 +70,8 @@ typedef struct {
     double inner_tol;    /* low-precision modes: inner relative tolerance (default 1e-4) */
     int inner_maxit;     /* low-precision modes: block steps per refinement (default 500) */
     int max_refine;      /* low-precision modes: outer refinement steps (default 60) */
-    double rank_tau;     /* rank threshold on scaled pivots (default 1e-14) */
+    double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
+                            low-precision modes, whose vectors carry FP32 rounding) */
     int graph_k;         /* block steps per captured graph / per host poll (default 16) */
     unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE */
 } ccg_opts;
@@ -107,7 +108,23 @@ const char *ccg_last_error(const ccg_ctx *ctx);
 
 /* Solve A x = b with p cooperating agents (Alg. 2 + Alg. 3, stop test of Alg. 4).
  * X: in, the p starting points X0; out, the final p agents.  tol > 0 is relative
- * to ||b||; maxit bounds the block steps.  opts and info may be NULL. */
+ * to ||b||; maxit bounds the block steps.  opts and info may be NULL.
+ *
+ * opts->prec selects how A is streamed:
+ *  - CCG_FP64: plain cCG on the FP64 matrix and FP64 agents.
+ *  - CCG_FP32 / CCG_BF16X2 (not in the paper; mixed-precision iterative refinement
+ *    around the paper's iteration): A is converted on every call to FP32 (nearest
+ *    even) or to two BF16 planes hi = bf16(A), lo = bf16(A - hi).  Each outer step
+ *    forms the explicit FP64 residual T = B - A X, runs cCG on A E = T (columns of T
+ *    scaled to unit norm) with FP32 vectors and FP32 accumulation of A.D, FP64 Gram
+ *    products, alpha and beta, until min_j of the inner relative residual is below
+ *    inner_tol or inner_maxit steps, then sets X += E (FP64).  The result is
+ *    converged when the FP64 residual meets tol, as in CCG_FP64.  Returns
+ *    CCG_ERR_BREAKDOWN when three outer steps in a row fail to lower the best FP64
+ *    residual (e.g. when cond(A) times the rounding of the low-precision copy is
+ *    near 1), CCG_NOT_CONVERGED after max_refine outer steps or maxit block steps
+ *    in total.  The library holds the low-precision copy (4 n^2 bytes) until
+ *    ccg_destroy. */
 ccg_status ccg_solve(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
                      const double *b, double *X, int64_t ldx, double tol, int maxit,
                      const ccg_opts *opts, ccg_info *info);
@@ -121,6 +138,16 @@ ccg_status ccg_debug_step(ccg_ctx *ctx, int n, int p, const double *A, int64_t l
                           const double *b, double *X, int64_t ldx, int ksteps,
                           const ccg_opts *opts, double *alphas, double *betas,
                           double *R, double *D);
+
+/* The low-precision copy of A that a CCG_FP32 or CCG_BF16X2 solve streams, written
+ * to caller buffers (device pointers, n x n column-major with leading dimension n):
+ *  - CCG_FP32: hi receives float values, A rounded to nearest even; lo is unused.
+ *  - CCG_BF16X2: hi and lo receive uint16 BF16 bit patterns, hi = A rounded to the
+ *    nearest BF16 (ties to even, one rounding from the double), lo = A - hi (exact
+ *    in FP64) rounded the same way.
+ * For inspecting the conversion; ccg_solve converts by itself. */
+ccg_status ccg_convert_matrix(ccg_ctx *ctx, int n, const double *A, int64_t lda, int prec,
+                              void *hi, void *lo);
 
 /* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
  * block steps run with CCG_PROFILE since the last reset; reset != 0 clears them. */

@@ -54,7 +54,7 @@ _lib = None
 
 # Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
 EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
-           "ccg_kernel_time")
+           "ccg_convert_matrix", "ccg_kernel_time")
 
 
 def load_library(path: str = LIB_PATH):
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_debug_step.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64,
                                    ctypes.c_int, ctypes.POINTER(Opts), dp, dp, dp, dp]
     lib.ccg_debug_step.restype = ctypes.c_int
+    lib.ccg_convert_matrix.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp]
+    lib.ccg_convert_matrix.restype = ctypes.c_int
     lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     lib.ccg_kernel_time.restype = ctypes.c_int
     if path == LIB_PATH:
@@ -181,6 +183,27 @@ class Context:
         bb = np.frombuffer(be, dtype=np.float64)[: ksteps * p * p].reshape(ksteps, p, p)
         return {"X": Xt.t().cpu(), "R": R.t().cpu(), "D": D.t().cpu(),
                 "alphas": a.transpose(0, 2, 1).copy(), "betas": bb.transpose(0, 2, 1).copy()}
+
+    def convert_matrix(self, A: torch.Tensor, prec: str):
+        """The low-precision copy of A streamed by a ``prec`` solve: a float32 n x n
+        tensor (fp32), or the (hi, lo) BF16 planes as int16 bit patterns (bf16x2).
+        The result keeps A's element order when A is row-major contiguous (the
+        library reads such a tensor as the column-major matrix A^T)."""
+        aptr, lda, keep = _colmajor_matrix(A)
+        n = A.shape[0]
+        if prec == "fp32":
+            hi = torch.empty(n, n, dtype=torch.float32, device=A.device)
+            lo = None
+        else:
+            hi = torch.empty(n, n, dtype=torch.int16, device=A.device)
+            lo = torch.empty(n, n, dtype=torch.int16, device=A.device)
+        torch.cuda.synchronize(A.device)
+        st = self.lib.ccg_convert_matrix(self.h, n, aptr, lda, PREC[prec], hi.data_ptr(),
+                                         None if lo is None else lo.data_ptr())
+        if st < 0:
+            raise self._err(st)
+        del keep
+        return hi if lo is None else (hi, lo)
 
     def kernel_time(self, reset: bool = False):
         ms = ctypes.c_double()

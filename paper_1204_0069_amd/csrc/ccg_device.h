@@ -75,7 +75,11 @@ struct UpdArgs {
 };
 
 // Residual epilogue: T = B - Y, with B = b in every column (FP64).
-enum ResMode : int { RES_INIT = 0, RES_CONFIRM = 1, RES_FINAL = 2 };
+//   RES_INIT    R = D = T, the start of a solve
+//   RES_CONFIRM R = D = T; a failed confirmation restarts the agents from T
+//   RES_FINAL   norms only (the report after maxit)
+//   RES_REFINE  R = T only: the FP64 residual of an outer refinement step
+enum ResMode : int { RES_INIT = 0, RES_CONFIRM = 1, RES_FINAL = 2, RES_REFINE = 3 };
 
 struct ResArgs {
     int n;
@@ -89,6 +93,20 @@ struct ResArgs {
     double* D;
     RedBuf red;          // ne = P*P + 1
     DevState* st;
+};
+
+// One outer step of the mixed-precision refinement (FP32 / BF16x2 modes).  The
+// inner solve works on A E = T with every column of T scaled to unit norm, in the
+// low-precision vector blocks; the FP64 agents then take X += E * scale.
+struct RefArgs {
+    int n_pad;
+    int P;
+    const double* T;          // FP64 residual block (agent-major)
+    double* X;                // FP64 agents (agent-major)
+    void* E;                  // inner iterate (FP32)
+    void* R;                  // inner residual (FP32)
+    void* D;                  // inner direction (FP32)
+    double scale[kMaxP];      // ||T_j|| (0: agent j sits out of the inner solve)
 };
 
 }  // namespace ccg

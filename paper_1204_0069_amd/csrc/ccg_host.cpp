@@ -30,6 +30,10 @@ hipError_t launch_unpack(int n, int n_pad, int p, const double* Xr, double* X, i
                          hipStream_t s);
 hipError_t launch_pad_vec(int n, int n_pad, const double* b, double* bp, hipStream_t s);
 hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int64_t ldb, hipStream_t s);
+hipError_t launch_convert(int prec, int n, const double* A, int64_t lda, void* hi, void* lo, int64_t ldb,
+                          hipStream_t s);
+hipError_t launch_inner_init(const RefArgs& a, hipStream_t s);
+hipError_t launch_refine_add(const RefArgs& a, hipStream_t s);
 int ad_workgroups(int n);
 int row_workgroups(int n_pad, int P);
 }  // namespace ccg
@@ -67,6 +71,11 @@ struct Workspace {
     double* R = nullptr;             // agent-major n_pad x P
     double* D = nullptr;
     double* AD = nullptr;
+    // low-precision inner solve of the refinement modes (FP32 blocks, agent-major)
+    float* E = nullptr;
+    float* Rl = nullptr;
+    float* Dl = nullptr;
+    float* ADl = nullptr;
     RedBuf red_ad{}, red_res{};
     DevState* st = nullptr;
 };
@@ -112,6 +121,9 @@ struct ccg_ctx {
     // aligned copy of a caller matrix with unaligned columns
     void* acopy = nullptr;
     size_t acopy_bytes = 0;
+    // low-precision copy of A (FP32, or the BF16 hi plane followed by the lo plane)
+    void* lowA = nullptr;
+    size_t lowA_bytes = 0;
 };
 
 namespace {
@@ -131,6 +143,10 @@ size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
     w.R = cv.take<double>(blk);
     w.D = cv.take<double>(blk);
     w.AD = cv.take<double>(blk);
+    w.E = cv.take<float>(blk);
+    w.Rl = cv.take<float>(blk);
+    w.Dl = cv.take<float>(blk);
+    w.ADl = cv.take<float>(blk);
     w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) + 2 * P * P + P);
     w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
@@ -144,14 +160,17 @@ void ensure_workspace(ccg_ctx* c, int n, int P) {
     Workspace& w = c->ws;
     if (w.base && w.n_pad == n_pad && w.P == P) {
         // rows n..n_pad of AD must read as zero (the A.D kernel stores rows < n only)
-        if (w.n != n) HIP_OK(hipMemsetAsync(w.AD, 0, sizeof(double) * (size_t)n_pad * P, c->stream));
+        if (w.n != n) {
+            HIP_OK(hipMemsetAsync(w.AD, 0, sizeof(double) * (size_t)n_pad * P, c->stream));
+            HIP_OK(hipMemsetAsync(w.ADl, 0, sizeof(float) * (size_t)n_pad * P, c->stream));
+        }
         w.n = n;
         return;
     }
     free_workspace(c);
     Workspace nw;
     const size_t bytes = carve(nw, nullptr, n, n_pad, P);
-    if (c->budget && bytes > c->budget)
+    if (c->budget && bytes + c->acopy_bytes + c->lowA_bytes > c->budget)
         throw CcgError{CCG_ERR_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget"};
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess)
@@ -169,24 +188,47 @@ void ensure_workspace(ccg_ctx* c, int n, int P) {
 struct Solve {
     ccg_ctx* c;
     int n, p, P, prec;
-    const void* A;
-    const void* A_lo;
-    int64_t lda;
+    const void* A;         // matrix the block steps stream (prec)
+    const void* A_lo;      // BF16 lo plane (BF16x2)
+    int64_t lda;           // its leading dimension in elements
+    const double* A64;     // FP64 matrix of the explicit residual
+    int64_t lda64;
     bool profile;
 };
 
-AdArgs ad_args(const Solve& s, const void* V, bool product_only) {
+// Vector blocks of the block steps: FP64 for plain cCG, FP32 for the inner solve of
+// the refinement modes.
+struct Blocks {
+    void *X, *R, *D, *AD;
+};
+Blocks blocks(const Solve& s) {
+    const Workspace& w = s.c->ws;
+    if (s.prec == PREC_F64) return Blocks{w.Xr, w.R, w.D, w.AD};
+    return Blocks{w.E, w.Rl, w.Dl, w.ADl};
+}
+
+AdArgs ad_args(const Solve& s, bool product_only) {
     const Workspace& w = s.c->ws;
     AdArgs a;
-    a.A = s.A;
-    a.A_lo = s.A_lo;
-    a.lda = s.lda;
     a.n = s.n;
     a.n_pad = w.n_pad;
     a.product_only = product_only ? 1 : 0;
-    a.V = V;
-    a.R = w.R;
-    a.AD = w.AD;
+    if (product_only) {          // Y = A X in FP64, into the FP64 AD block
+        a.A = s.A64;
+        a.A_lo = nullptr;
+        a.lda = s.lda64;
+        a.V = w.Xr;
+        a.R = w.R;
+        a.AD = w.AD;
+    } else {
+        const Blocks b = blocks(s);
+        a.A = s.A;
+        a.A_lo = s.A_lo;
+        a.lda = s.lda;
+        a.V = b.D;
+        a.R = b.R;
+        a.AD = b.AD;
+    }
     a.red = w.red_ad;
     a.st = w.st;
     return a;
@@ -195,9 +237,7 @@ AdArgs ad_args(const Solve& s, const void* V, bool product_only) {
 void enqueue_residual(const Solve& s, int mode, int set_nb) {
     Workspace& w = s.c->ws;
     // Y = A X in FP64 (the residual is always FP64)
-    Solve s64 = s;
-    s64.prec = PREC_F64;
-    HIP_OK(launch_ad(PREC_F64, s.P, ad_args(s64, w.Xr, true), s.c->stream));
+    HIP_OK(launch_ad(PREC_F64, s.P, ad_args(s, true), s.c->stream));
     ResArgs r;
     r.n = s.n;
     r.n_pad = w.n_pad;
@@ -227,14 +267,15 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
 void enqueue_step(const Solve& s, size_t ev_slot) {
     Workspace& w = s.c->ws;
     if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot), s.c->stream));
-    HIP_OK(launch_ad(s.prec, s.P, ad_args(s, w.D, false), s.c->stream));
+    HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream));
     if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot + 1), s.c->stream));
+    const Blocks b = blocks(s);
     UpdArgs u;
     u.n_pad = w.n_pad;
-    u.X = w.Xr;
-    u.R = w.R;
-    u.D = w.D;
-    u.AD = w.AD;
+    u.X = b.X;
+    u.R = b.R;
+    u.D = b.D;
+    u.AD = b.AD;
     u.st = w.st;
     HIP_OK(launch_upd(s.prec, s.P, u, s.c->stream));
 }
@@ -360,7 +401,7 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
     const double* Ause = aligned_matrix(c, n, A, lda);
-    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, (o.flags & CCG_PROFILE) != 0};
+    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, (o.flags & CCG_PROFILE) != 0};
     ensure_workspace(c, n, P);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
@@ -385,7 +426,7 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
     while (h.done == RUNNING || h.done == RECUR_CONV) {
         if (h.done == RUNNING) {
             const int left = maxit - h.iter;
-            const int k = std::min(gk, std::max(left, 1));
+            const int k = left > 0 ? gk : 1;   // steps past maxit are no-ops: keep one graph
             const int it0 = h.iter;
             run_steps(s, k, use_graph);
             read_state(c);
@@ -431,6 +472,164 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
     return st;
 }
 
+// Low-precision copy of A for the FP32 / BF16x2 modes, converted on every solve (the
+// caller may change A between calls).  Returns the streamed planes and their
+// leading dimension (16-byte aligned columns).
+struct LowCopy {
+    const void* hi;
+    const void* lo;
+    int64_t ld;
+    double bytes;     // algorithmic bytes of the conversion pass
+};
+
+LowCopy low_copy(ccg_ctx* c, int n, const double* A, int64_t lda, int prec) {
+    const int64_t ld = round_up(n, prec == PREC_F32 ? 4 : 8);
+    const size_t plane = (size_t)ld * n * (prec == PREC_F32 ? sizeof(float) : sizeof(uint16_t));
+    const size_t need = prec == PREC_F32 ? plane : 2 * round_up((int64_t)plane, 256);
+    if (c->lowA_bytes < need) {
+        if (c->lowA) (void)hipFree(c->lowA);
+        c->lowA = nullptr;
+        c->lowA_bytes = 0;
+        if (c->budget && need + c->ws.bytes + c->acopy_bytes > c->budget)
+            throw CcgError{CCG_ERR_NOMEM, "low-precision copy of A exceeds the HBM budget"};
+        if (hipMalloc(&c->lowA, need) != hipSuccess)
+            throw CcgError{CCG_ERR_NOMEM, "hipMalloc for the low-precision copy of A failed"};
+        c->lowA_bytes = need;
+    }
+    char* base = static_cast<char*>(c->lowA);
+    void* hi = base;
+    void* lo = prec == PREC_F32 ? nullptr : base + round_up((int64_t)plane, 256);
+    HIP_OK(launch_convert(prec, n, A, lda, hi, lo, ld, c->stream));
+    const double elem = prec == PREC_F32 ? 4.0 : 4.0;   // FP32, or two BF16 planes
+    return LowCopy{hi, lo, ld, (double)n * n * (8.0 + elem)};
+}
+
+void set_all_agents(DevState& h, int p) {
+    h.m = p;
+    h.mask = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
+    for (int j = 0; j < p; ++j) h.keep[j] = j;
+}
+
+// Mixed precision (FP32 or BF16x2 A): FP64 iterative refinement around a low-
+// precision cCG inner solve.  Each outer step forms the explicit FP64 residual
+// T = B - A X, scales its columns to unit norm, runs cCG on A E = T in the low-
+// precision blocks (FP32 vectors and A.D accumulation; FP64 products, alpha and
+// beta) until the best agent's relative residual is below inner_tol (relaxed to
+// 0.1 tol / minres in the last steps, where less suffices), and adds E * scale to
+// the FP64 agents.  Stops when min_j ||b - A x_j|| / ||b|| <= tol.
+ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
+    const int P = pad_agents(p);
+    const int prec = o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2;
+    const double* A64 = aligned_matrix(c, n, A, lda);
+    ensure_workspace(c, n, P);
+    const LowCopy lc = low_copy(c, n, A64, lda, prec);
+    Solve s{c, n, p, P, prec, lc.hi, lc.lo, lc.ld, A64, lda, (o.flags & CCG_PROFILE) != 0};
+    Workspace& w = c->ws;
+    HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
+    HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
+    DevState& h = *c->st_host;
+    std::memset(&h, 0, sizeof(DevState));
+    h.done = RUNNING;
+    set_all_agents(h, p);
+    h.maxit = maxit;
+    h.tol = tol;
+    h.tau = o.rank_tau;
+    h.nb = 1.0;
+    write_state(c);
+    enqueue_residual(s, RES_REFINE, 1);
+    read_state(c);
+    const double nb = h.nb;     // ||b||; the inner solves use 1 (unit columns)
+    const double s_low = 4.0;   // bytes per streamed A element (FP32, or BF16 hi + lo)
+    double bytes = lc.bytes + 8.0 * n * n;
+    const bool use_graph = !(o.flags & CCG_NO_GRAPH);
+    const int gk = o.graph_k > 0 ? o.graph_k : 16;
+    int iters = 0, refinements = 0, stall = 0;
+    double best = h.minres;
+    ccg_status st = CCG_OK;
+    RefArgs ra{};
+    ra.n_pad = w.n_pad;
+    ra.P = P;
+    ra.T = w.R;
+    ra.X = w.Xr;
+    ra.E = w.E;
+    ra.R = w.Rl;
+    ra.D = w.Dl;
+    while (h.done == RUNNING) {
+        if (refinements >= o.max_refine || iters >= maxit) { st = CCG_NOT_CONVERGED; break; }
+        // inner solve on A E = T (unit columns)
+        unsigned mask = 0u;
+        int m = 0;
+        for (int j = 0; j < kMaxP; ++j) {
+            const double sc = (j < p && std::isfinite(h.norms[j])) ? h.norms[j] : 0.0;
+            ra.scale[j] = sc;
+            if (sc > 0.0) { mask |= 1u << j; h.keep[m++] = j; }
+        }
+        HIP_OK(launch_inner_init(ra, c->stream));
+        h.done = RUNNING;
+        h.iter = 0;
+        h.m = m;
+        h.mask = mask;
+        // no need to solve the correction more accurately than the outer target:
+        // the best agent's residual after this step is about (inner tol) x minres
+        h.tol = std::min(0.5, std::max(o.inner_tol, 0.1 * tol / h.minres));
+        h.nb = 1.0;
+        h.maxit = std::min(o.inner_maxit, maxit - iters);
+        write_state(c);
+        while (h.done == RUNNING) {
+            const int k = gk;   // steps past maxit are no-ops: keep one graph
+            const int it0 = h.iter;
+            run_steps(s, k, use_graph);
+            read_state(c);
+            const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
+            if (s.profile) collect_profile(c, streamed);
+            bytes += s_low * n * n * streamed;
+        }
+        iters += h.iter;
+        if (h.done == FAILED) { st = (ccg_status)h.status; break; }
+        HIP_OK(launch_refine_add(ra, c->stream));
+        ++refinements;
+        // outer FP64 residual
+        h.done = RUNNING;
+        h.tol = tol;
+        h.nb = nb;
+        set_all_agents(h, p);
+        write_state(c);
+        enqueue_residual(s, RES_REFINE, 0);
+        read_state(c);
+        bytes += 8.0 * n * n;
+        if (h.done == FAILED) { st = (ccg_status)h.status; break; }
+        if (h.minres >= best) {
+            if (++stall >= 3) { st = CCG_ERR_BREAKDOWN; break; }
+        } else {
+            stall = 0;
+        }
+        best = std::min(best, h.minres);
+    }
+    if (h.done == FAILED && st == CCG_OK) st = (ccg_status)h.status;
+    HIP_OK(launch_unpack(n, w.n_pad, p, w.Xr, X, ldx, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (st == CCG_ERR_BREAKDOWN) c->err = "refinement made no progress over three outer steps";
+    info.status = st;
+    info.iters = iters;
+    info.refinements = refinements;
+    info.restarts = 0;
+    info.p_final = p;
+    info.deflations = h.deflations;
+    double mn = INFINITY, mx = 0.0;
+    int bestj = -1;
+    for (int j = 0; j < p; ++j) {
+        const double r = h.norms[j] / h.nb;
+        if (r < mn) { mn = r; bestj = j; }
+        if (r > mx) mx = r;
+    }
+    info.best_agent = bestj;
+    info.rel_res = mn;
+    info.rel_res_max = mx;
+    info.bytes_A = bytes;
+    return st;
+}
+
 ccg_opts fill_defaults(const ccg_opts* in) {
     ccg_opts o;
     std::memset(&o, 0, sizeof o);
@@ -438,7 +637,7 @@ ccg_opts fill_defaults(const ccg_opts* in) {
     if (o.inner_tol <= 0.0) o.inner_tol = 1e-4;
     if (o.inner_maxit <= 0) o.inner_maxit = 500;
     if (o.max_refine <= 0) o.max_refine = 60;
-    if (o.rank_tau <= 0.0) o.rank_tau = 1e-14;
+    if (o.rank_tau <= 0.0) o.rank_tau = o.prec == CCG_FP64 ? 1e-14 : 1e-12;
     if (o.graph_k <= 0) o.graph_k = 16;
     return o;
 }
@@ -501,6 +700,7 @@ ccg_status ccg_destroy(ccg_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     free_workspace(c);
     if (c->acopy) (void)hipFree(c->acopy);
+    if (c->lowA) (void)hipFree(c->lowA);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -520,13 +720,15 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
         if (!(tol > 0.0)) throw CcgError{CCG_ERR_ARG, "tol must be > 0"};
         if (maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
         const ccg_opts o = fill_defaults(opts);
-        if (o.prec != CCG_FP64) throw CcgError{CCG_ERR_ARG, "precision mode not available"};
+        if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)
+            throw CcgError{CCG_ERR_ARG, "unknown precision mode"};
         const auto t0 = std::chrono::steady_clock::now();
         Staged sg;
         double* Xd = X;
         int64_t ldxd = ldx;
         if (o.flags & CCG_HOST_PTRS) stage_in(c, sg, n, p, A, lda, b, Xd, ldxd);
-        ccg_status r = solve_fp64(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local);
+        ccg_status r = o.prec == CCG_FP64 ? solve_fp64(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local)
+                                          : solve_mixed(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local);
         if (o.flags & CCG_HOST_PTRS) {
             HIP_OK(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xd, sizeof(double) * n, sizeof(double) * n, p,
                                     hipMemcpyDeviceToHost, c->stream));
@@ -549,7 +751,7 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         const ccg_opts o = fill_defaults(opts);
         const int P = pad_agents(p);
         const double* Ause = aligned_matrix(c, n, A, lda);
-        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, false};
+        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, false};
         ensure_workspace(c, n, P);
         Workspace& w = c->ws;
         HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
@@ -581,6 +783,17 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         if (D) HIP_OK(launch_unpack(n, w.n_pad, p, w.D, D, n, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
         if (h.done == FAILED) return (ccg_status)h.status;
+        return CCG_OK;
+    });
+}
+
+ccg_status ccg_convert_matrix(ccg_ctx* c, int n, const double* A, int64_t lda, int prec, void* hi, void* lo) {
+    return guarded(c, [&]() -> ccg_status {
+        if (n < 1 || !A || !hi || lda < n) throw CcgError{CCG_ERR_ARG, "bad matrix argument"};
+        if (prec != CCG_FP32 && prec != CCG_BF16X2) throw CcgError{CCG_ERR_ARG, "prec must be FP32 or BF16X2"};
+        if (prec == CCG_BF16X2 && !lo) throw CcgError{CCG_ERR_ARG, "BF16X2 needs the lo plane"};
+        HIP_OK(launch_convert(prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2, n, A, lda, hi, lo, n, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
         return CCG_OK;
     });
 }

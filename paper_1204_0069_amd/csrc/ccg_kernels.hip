@@ -21,6 +21,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ccg {
 
 // ----------------------------------------------------------------- precision traits
@@ -829,10 +831,8 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
     if (j == 0) bs[r] = bi;
     const double t = (j < a.p && i < a.n) ? bi - a.Y[o] : 0.0;
     ts[r * P + j] = t;
-    if (a.mode != RES_FINAL) {
-        a.R[o] = t;
-        a.D[o] = ((msk >> j) & 1u) ? t : 0.0;
-    }
+    if (a.mode != RES_FINAL) a.R[o] = t;
+    if (a.mode == RES_INIT || a.mode == RES_CONFIRM) a.D[o] = ((msk >> j) & 1u) ? t : 0.0;
     __syncthreads();
     for (int e = tid; e < NE; e += kWG) {
         double s = 0.0;
@@ -861,6 +861,7 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
             if (bad) fail_state(st, -2);
             else if (st->nb == 0.0) fail_state(st, -1);
             else if (mn <= st->tol) st->done = FINISHED;
+            else if (a.mode == RES_REFINE) st->done = RUNNING;
             else {
                 if (a.mode == RES_CONFIRM) st->restarts += 1;
                 st->done = (st->iter >= st->maxit) ? MAXIT : RUNNING;
@@ -900,6 +901,77 @@ __global__ void k_copy_cols(int n, const double* A, int64_t lda, double* B, int6
     if (idx >= (int64_t)n * n) return;
     const int64_t c = idx / n, r = idx - c * n;
     B[c * ldb + r] = A[c * lda + r];
+}
+
+// ============================================== low-precision copies of A
+//
+// The FP32 mode streams A32 = A rounded to nearest (ties to even).  The BF16x2 mode
+// streams two BF16 planes, hi = A rounded to nearest-even BF16 and lo = (A - hi)
+// rounded the same way (A - hi is exact in FP64), so that hi + lo carries 16
+// significant bits.  Columns are written with leading dimension ldb (>= n; rows
+// n..ldb-1 are zero-filled so 16-byte loads of a column tail read zeros).
+
+// Nearest-even BF16 of a double, rounding once: the double is first cut to FP32
+// toward zero with a sticky bit in the last place (round to odd), which keeps the
+// information a single rounding needs, then rounded to 8 significant bits.
+__device__ __forceinline__ uint16_t bf16_rne(double a) {
+    const float f = __double2float_rz(a);
+    uint32_t u = __float_as_uint(f);
+    if ((double)f != a) u |= 1u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_to_f32(int n, const double* A, int64_t lda, float* B, int64_t ldb) {
+    const int64_t tot = (int64_t)n * ldb;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = idx / ldb, r = idx - c * ldb;
+        B[idx] = r < n ? (float)A[c * lda + r] : 0.0f;
+    }
+}
+
+__global__ void k_to_bf16x2(int n, const double* A, int64_t lda, uint16_t* H, uint16_t* L, int64_t ldb) {
+    const int64_t tot = (int64_t)n * ldb;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = idx / ldb, r = idx - c * ldb;
+        uint16_t h = 0, l = 0;
+        if (r < n) {
+            const double a = A[c * lda + r];
+            h = bf16_rne(a);
+            const double hv = (double)__uint_as_float((uint32_t)h << 16);
+            l = bf16_rne(a - hv);
+        }
+        H[idx] = h;
+        L[idx] = l;
+    }
+}
+
+// ============================== refinement: start an inner solve / apply it
+//
+// k_inner_init: R = T_j / scale_j (rounded to FP32), D = R, E = 0 for every element
+// of the padded block (agents with scale 0 get zero columns).
+// k_refine_add: X += E_j * scale_j in FP64.
+__global__ void k_inner_init(RefArgs a) {
+    const int64_t tot = (int64_t)a.n_pad * a.P;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int j = (int)(idx / a.n_pad);
+    const double s = a.scale[j];
+    const float r = s > 0.0 ? (float)(a.T[idx] / s) : 0.0f;
+    static_cast<float*>(a.R)[idx] = r;
+    static_cast<float*>(a.D)[idx] = r;
+    static_cast<float*>(a.E)[idx] = 0.0f;
+}
+
+__global__ void k_refine_add(RefArgs a) {
+    const int64_t tot = (int64_t)a.n_pad * a.P;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int j = (int)(idx / a.n_pad);
+    const double s = a.scale[j];
+    if (s > 0.0) a.X[idx] = fma((double)static_cast<const float*>(a.E)[idx], s, a.X[idx]);
 }
 
 // ================================================================== launchers
@@ -998,6 +1070,33 @@ hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int6
     const int64_t tot = (int64_t)n * n;
     hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, A, lda, B,
                        ldb);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int prec, int n, const double* A, int64_t lda, void* hi, void* lo, int64_t ldb,
+                          hipStream_t s) {
+    const int64_t tot = (int64_t)n * ldb;
+    const unsigned grid = (unsigned)std::min<int64_t>((tot + 255) / 256, 8192);
+    if (prec == PREC_F32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(256), 0, s, n, A, lda, static_cast<float*>(hi), ldb);
+    } else if (prec == PREC_BF16X2) {
+        hipLaunchKernelGGL(k_to_bf16x2, dim3(grid), dim3(256), 0, s, n, A, lda, static_cast<uint16_t*>(hi),
+                           static_cast<uint16_t*>(lo), ldb);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_init(const RefArgs& a, hipStream_t s) {
+    const int64_t tot = (int64_t)a.n_pad * a.P;
+    hipLaunchKernelGGL(k_inner_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_add(const RefArgs& a, hipStream_t s) {
+    const int64_t tot = (int64_t)a.n_pad * a.P;
+    hipLaunchKernelGGL(k_refine_add, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

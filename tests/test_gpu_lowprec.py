@@ -1,0 +1,144 @@
+"""GPU tests of the mixed-precision modes (FP32 / BF16x2 A in FP64 refinement).
+
+* The low-precision copies of A are integer-exact work: compared bit for bit with
+  the conversion oracle (oracle/lowprec.py) through ccg_convert_matrix.
+* A refined solve has no oracle trajectory (its iterates differ from any FP64 run
+  by design), so it is held to what fixes the answer: the explicit FP64 residual of
+  the best agent, recomputed by the oracle, is <= tol, and that agent is within
+  2 * cond(A) * tol of the direct solution (relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import ccg_inputs as ci
+import oracle
+from oracle import lowprec as lp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def _wide_matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n)) * np.exp(rng.uniform(-30, 30, (n, n)))
+    M[0, 0] = 0.0
+    M[1 % n, 0] = 1.0 + 0.5 / 128.0          # a BF16 tie
+    return M
+
+
+@pytest.mark.parametrize("n", [1, 37, 256, 1000])
+def test_fp32_copy_is_bit_exact(gpu_ctx, n):
+    print(f"case convert fp32 n={n}", flush=True)
+    M = _wide_matrix(n, n)
+    got = gpu_ctx.convert_matrix(_t(M), "fp32").cpu().numpy()
+    want = lp.to_f32(M)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [1, 37, 256, 1000])
+def test_bf16x2_copy_is_bit_exact(gpu_ctx, n):
+    print(f"case convert bf16x2 n={n}", flush=True)
+    M = _wide_matrix(n, 100 + n)
+    hi, lo = gpu_ctx.convert_matrix(_t(M), "bf16x2")
+    whi, wlo = lp.to_bf16x2(M)
+    assert np.array_equal(hi.cpu().numpy().view(np.uint16), lp.bf16_bits(whi))
+    assert np.array_equal(lo.cpu().numpy().view(np.uint16), lp.bf16_bits(wlo))
+
+
+def _residual_noise(A, b, x):
+    """Bound on the rounding of a computed relative residual ||b - A x|| / ||b||:
+    each entry of b - A x carries at most n * eps * (|b| + |A| |x|) (standard
+    summation bound), for either summation order."""
+    n = A.shape[0]
+    scale = np.abs(b) + np.abs(A) @ np.abs(x)
+    return 2.0 * n * 1.11e-16 * np.linalg.norm(scale) / np.linalg.norm(b)
+
+
+def _check_refined(A, b, X, info, tol, kappa):
+    Xg = X.cpu().numpy()
+    T = oracle.residual(A, b, Xg)
+    rel = np.linalg.norm(T, axis=0) / np.linalg.norm(b)
+    assert info["status"] == 0, info
+    assert rel.min() <= tol, (rel.min(), info)
+    j = info["best_agent"]
+    noise = _residual_noise(A, b, Xg[:, j])
+    # the library's explicit residual and the oracle's agree up to rounding; the
+    # best agent is a true argmin up to the same rounding
+    assert abs(info["rel_res"] - rel[j]) <= 1e-3 * rel[j] + noise, (info["rel_res"], rel[j], noise)
+    assert rel[j] <= rel.min() + 2 * noise
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(Xg[:, j] - xs) <= 2 * kappa * tol * np.linalg.norm(xs)
+    assert info["refinements"] >= 1 and info["iters"] >= 1
+
+
+FP32_CASES = [(256, 3, 1e3), (1000, 4, 1e3), (777, 2, 1e2), (640, 16, 1e2), (300, 1, 1e3),
+              (2085, 8, 1e4)]
+BF16_CASES = [(256, 3, 1e3), (1000, 4, 1e3), (777, 2, 1e2), (640, 16, 1e2), (300, 1, 1e2)]
+
+
+@pytest.mark.parametrize("n,p,kappa", FP32_CASES)
+def test_fp32_refined_solve(gpu_ctx, n, p, kappa):
+    print(f"case solve fp32 n={n} p={p} kappa={kappa}", flush=True)
+    A, b, X0 = ci.system(n, p, kappa, seed=303)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32")
+    _check_refined(A, b, X, info, 1e-10, kappa)
+
+
+@pytest.mark.parametrize("n,p,kappa", BF16_CASES)
+def test_bf16x2_refined_solve(gpu_ctx, n, p, kappa):
+    print(f"case solve bf16x2 n={n} p={p} kappa={kappa}", flush=True)
+    A, b, X0 = ci.system(n, p, kappa, seed=404)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="bf16x2")
+    _check_refined(A, b, X, info, 1e-10, kappa)
+
+
+def test_refined_solve_is_deterministic(gpu_ctx):
+    A, b, X0 = ci.system(900, 4, 1e3, seed=9)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32")
+    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32")
+    assert i1["iters"] == i2["iters"] and i1["refinements"] == i2["refinements"]
+    assert torch.equal(X1, X2)
+
+
+def test_refined_graph_and_direct_launch_agree(gpu_ctx):
+    from paper_1204_0069_amd import CCG_NO_GRAPH
+    A, b, X0 = ci.system(700, 8, 1e3, seed=10)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="bf16x2")
+    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="bf16x2", flags=CCG_NO_GRAPH)
+    assert i1["iters"] == i2["iters"]
+    assert torch.equal(X1, X2)
+
+
+def test_refinement_limits(gpu_ctx):
+    A, b, X0 = ci.system(500, 4, 1e3, seed=12)
+    # one outer step cannot reach 1e-10 with an inner tolerance of 1e-4
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32", max_refine=1,
+                            raise_on_error=False)
+    assert info["status"] == 1 and info["refinements"] == 1
+    # a total step budget stops the refinement too
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 30, prec="fp32", raise_on_error=False)
+    assert info["status"] == 1 and info["iters"] <= 30
+
+
+def test_full_size_fp32_solve(gpu_ctx):
+    n, p, kappa = 8192, 8, 1e4
+    print("case full-size fp32 n=8192 p=8", flush=True)
+    A = ci.spd_spectrum(n, kappa, ci.item_seed("A", ci.BASE_SEED, base=n), device=DEV)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", ci.BASE_SEED, base=n)), device=DEV)
+    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", ci.BASE_SEED, base=n)), device=DEV)
+    X, info = gpu_ctx.solve(A, b, X0, 1e-10, 100000, prec="fp32")
+    assert info["status"] == 0, info
+    # explicit residual of every agent with torch's own product (rocBLAS)
+    T = b[:, None] - A @ X
+    rel = (torch.linalg.norm(T, dim=0) / torch.linalg.norm(b)).cpu().numpy()
+    assert rel.min() <= 1e-10
+    j = info["best_agent"]
+    x = X[:, j]
+    noise = float(2.0 * n * 1.11e-16 * torch.linalg.norm(b.abs() + A.abs() @ x.abs()) / torch.linalg.norm(b))
+    assert abs(info["rel_res"] - rel[j]) <= 1e-3 * rel[j] + noise
