@@ -139,6 +139,52 @@ ccg_status ccg_debug_step(ccg_ctx *ctx, int n, int p, const double *A, int64_t l
                           const ccg_opts *opts, double *alphas, double *betas,
                           double *R, double *D);
 
+/* One system of a batched or served solve: the arguments of ccg_solve. */
+typedef struct {
+    int n, p;
+    const double *A;
+    int64_t lda;
+    const double *b;
+    double *X;           /* in: X0; out: the final agents */
+    int64_t ldx;
+    double tol;
+    int maxit;
+    ccg_opts opts;       /* per system (precision, CCG_HOST_PTRS, ...); zero = defaults */
+} ccg_problem;
+
+/* Solve `count` independent systems together (not in the paper: many cCG solves
+ * share each launch).  Every block step is one batched A.D launch and one batched
+ * update launch per (precision, padded agent count) class, whose workgroups are
+ * (system, row tile) work items of all systems still running; systems that finish
+ * leave the work lists, and systems still waiting are admitted as the HBM budget
+ * frees up.  Each system gets exactly the result ccg_solve would give it.
+ * infos[i] (may be NULL) receives system i's report.  Returns CCG_OK when every
+ * system converged, else the first error status met, else CCG_NOT_CONVERGED.  A
+ * system too large for the HBM budget on its own gets CCG_ERR_NOMEM. */
+ccg_status ccg_solve_batched(ccg_ctx *ctx, int count, const ccg_problem *probs, ccg_info *infos);
+
+/* Served mode (not in the paper): continuous batching.  ccg_submit queues a system
+ * and returns at once with a ticket; a service thread of the context admits queued
+ * systems in arrival order while their device memory fits the context's HBM budget,
+ * advances every resident system with the batched launches of ccg_solve_batched on
+ * a stream of its own, and retires each system as soon as it finishes.  The
+ * problem's buffers must stay valid until ccg_poll / ccg_wait report a final status.
+ * With CCG_HOST_PTRS, A, b and X are uploaded at admission, inside the latency.
+ * info->seconds is the latency from ccg_submit to completion. */
+ccg_status ccg_submit(ccg_ctx *ctx, const ccg_problem *prob, uint64_t *ticket);
+
+/* Final status and report of a ticket (the ticket is then released), or
+ * CCG_PENDING while it is queued or running.  Unknown tickets give CCG_ERR_ARG. */
+ccg_status ccg_poll(ccg_ctx *ctx, uint64_t ticket, ccg_info *info);
+
+/* Block until the ticket finishes; then as ccg_poll. */
+ccg_status ccg_wait(ccg_ctx *ctx, uint64_t ticket, ccg_info *info);
+
+/* Ask for a ticket to stop.  A queued system is dropped; a running one stops at the
+ * next host round with its current agents in X.  Its final status is CCG_CANCELLED
+ * (or its real status if it finished first). */
+ccg_status ccg_cancel(ccg_ctx *ctx, uint64_t ticket);
+
 /* The low-precision copy of A that a CCG_FP32 or CCG_BF16X2 solve streams, written
  * to caller buffers (device pointers, n x n column-major with leading dimension n):
  *  - CCG_FP32: hi receives float values, A rounded to nearest even; lo is unused.

@@ -50,10 +50,18 @@ class Info(ctypes.Structure):
         return d
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("b", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("opts", Opts)]
+
+
 _lib = None
 
 # Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
 EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
+           "ccg_solve_batched", "ccg_submit", "ccg_poll", "ccg_wait", "ccg_cancel",
            "ccg_convert_matrix", "ccg_kernel_time")
 
 
@@ -80,6 +88,16 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_debug_step.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64,
                                    ctypes.c_int, ctypes.POINTER(Opts), dp, dp, dp, dp]
     lib.ccg_debug_step.restype = ctypes.c_int
+    lib.ccg_solve_batched.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(Info)]
+    lib.ccg_solve_batched.restype = ctypes.c_int
+    lib.ccg_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_uint64)]
+    lib.ccg_submit.restype = ctypes.c_int
+    lib.ccg_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Info)]
+    lib.ccg_poll.restype = ctypes.c_int
+    lib.ccg_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Info)]
+    lib.ccg_wait.restype = ctypes.c_int
+    lib.ccg_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.ccg_cancel.restype = ctypes.c_int
     lib.ccg_convert_matrix.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp]
     lib.ccg_convert_matrix.restype = ctypes.c_int
     lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
@@ -112,6 +130,22 @@ def make_opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_refine=0, rank_tau=
                 int(inner_maxit), int(max_refine), float(rank_tau), int(graph_k), int(flags))
 
 
+def _problem(A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, tol: float, maxit: int, opts: dict):
+    """(Problem, X, keep-alive list).  Tensors on the CPU are passed as host pointers
+    (CCG_HOST_PTRS); X is the n x p result view."""
+    host = A.device.type == "cpu"
+    aptr, lda, Ak = _colmajor_matrix(A)
+    n = A.shape[0]
+    bb = b.reshape(-1).to(device=A.device, dtype=torch.float64).contiguous()
+    Xt = X0.to(device=A.device, dtype=torch.float64).t().clone(memory_format=torch.contiguous_format)   # p x n = col-major n x p
+    o = dict(opts)
+    if host:
+        o["flags"] = int(o.get("flags", 0)) | CCG_HOST_PTRS
+    pr = Problem(n, Xt.shape[0], aptr, lda, bb.data_ptr(), Xt.data_ptr(), n, float(tol), int(maxit),
+                 make_opts(**o))
+    return pr, Xt.t(), [Ak, bb, Xt]
+
+
 class Context:
     """A library context on one GPU (its own HIP stream, default priority)."""
 
@@ -123,6 +157,72 @@ class Context:
         if st != 0:
             raise CcgError(st, "ccg_create failed")
         self.h = h
+        self._pending = {}
+
+    def solve_batched(self, systems, raise_on_error: bool = False):
+        """Solve many systems in shared launches.  systems: iterable of dicts with keys
+        A, b, X0, tol, maxit and optional solver options.  Returns a list of (X, info)."""
+        probs, outs, keep = [], [], []
+        for sy in systems:
+            sy = dict(sy)
+            A, b, X0 = sy.pop("A"), sy.pop("b"), sy.pop("X0")
+            tol, maxit = sy.pop("tol"), sy.pop("maxit")
+            pr, X, k = _problem(A, b, X0, tol, maxit, sy)
+            probs.append(pr)
+            outs.append(X)
+            keep.append(k)
+        arr = (Problem * max(1, len(probs)))(*probs)
+        infos = (Info * max(1, len(probs)))()
+        torch.cuda.synchronize()
+        st = self.lib.ccg_solve_batched(self.h, len(probs), arr, infos)
+        if st < 0 and raise_on_error:
+            raise self._err(st)
+        del keep
+        return [(outs[i], infos[i].as_dict()) for i in range(len(probs))]
+
+    def submit(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, tol: float, maxit: int,
+               **opts) -> int:
+        """Queue a system on the context's service; returns its ticket.  Its buffers are
+        kept alive here until the ticket is polled or waited for."""
+        pr, X, keep = _problem(A, b, X0, tol, maxit, opts)
+        if A.device.type != "cpu":
+            torch.cuda.synchronize(A.device)
+        t = ctypes.c_uint64()
+        st = self.lib.ccg_submit(self.h, ctypes.byref(pr), ctypes.byref(t))
+        if st != 0:
+            raise self._err(st)
+        self._pending[t.value] = (X, keep)
+        return t.value
+
+    def _finish(self, ticket, st, info):
+        X, _ = self._pending.pop(ticket, (None, None))
+        d = info.as_dict()
+        d["status"] = st
+        d["status_name"] = STATUS.get(st, str(st))
+        return X, d
+
+    def poll(self, ticket: int):
+        """(X, info) when the ticket has finished, else None."""
+        info = Info()
+        st = self.lib.ccg_poll(self.h, ticket, ctypes.byref(info))
+        if st == -7:
+            return None
+        if st == -1 and ticket not in self._pending:
+            raise self._err(st)
+        return self._finish(ticket, st, info)
+
+    def wait(self, ticket: int):
+        """Block until the ticket finishes; returns (X, info)."""
+        info = Info()
+        st = self.lib.ccg_wait(self.h, ticket, ctypes.byref(info))
+        if st == -1 and ticket not in self._pending:
+            raise self._err(st)
+        return self._finish(ticket, st, info)
+
+    def cancel(self, ticket: int) -> None:
+        st = self.lib.ccg_cancel(self.h, ticket)
+        if st != 0:
+            raise self._err(st)
 
     def close(self):
         if getattr(self, "h", None):
@@ -144,7 +244,7 @@ class Context:
         aptr, lda, keep = _colmajor_matrix(A)
         n = A.shape[0]
         b = b.reshape(-1).to(device=A.device, dtype=torch.float64).contiguous()
-        Xt = X0.to(device=A.device, dtype=torch.float64).t().contiguous()   # p x n = col-major n x p
+        Xt = X0.to(device=A.device, dtype=torch.float64).t().clone(memory_format=torch.contiguous_format)   # p x n = col-major n x p
         p = Xt.shape[0]
         o = make_opts(**opts)
         info = Info()
@@ -163,7 +263,7 @@ class Context:
         aptr, lda, keep = _colmajor_matrix(A)
         n = A.shape[0]
         b = b.reshape(-1).to(device=A.device, dtype=torch.float64).contiguous()
-        Xt = X0.to(device=A.device, dtype=torch.float64).t().contiguous()
+        Xt = X0.to(device=A.device, dtype=torch.float64).t().clone(memory_format=torch.contiguous_format)
         p = Xt.shape[0]
         R = torch.zeros(p, n, dtype=torch.float64, device=A.device)
         D = torch.zeros(p, n, dtype=torch.float64, device=A.device)

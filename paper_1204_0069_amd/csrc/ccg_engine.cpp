@@ -1,0 +1,1033 @@
+// Multi-system engine: many independent cCG solves advanced together by batched
+// launches (ccg_solve_batched), and the continuous-batching service built on it
+// (ccg_submit / ccg_poll / ccg_wait / ccg_cancel).
+//
+// Every resident system owns a slot: its device state (one DevState array for all
+// slots, so one strided copy reads or writes every state header), its argument
+// records for the batched kernels (AdArgs / UpdArgs / ResArgs arrays indexed by
+// slot) and its vectors in an arena of device memory.  One host round launches:
+//   1. the refinement corrections X += E * scale due this round (per system),
+//   2. one batched explicit-residual pass (FP64 A.X, then the residual epilogue)
+//      over every system that needs one, per padded agent count,
+//   3. the starts of refinement inner solves (per system),
+//   4. k block steps over every stepping system: one batched A.D launch and one
+//      batched update launch per (precision, padded agent count) class,
+// then reads every state header and moves each system through the same phases,
+// in the same order, as the single-system driver, so a system's result does not
+// depend on the systems it shares launches with.
+#include <chrono>
+#include <condition_variable>
+#include <cstddef>
+#include <cstdio>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "ccg_host.h"
+
+namespace ccg {
+namespace host {
+namespace {
+
+constexpr size_t kHeader = offsetof(DevState, alpha);   // state bytes exchanged per round
+constexpr int kSlots = 4096;                             // resident systems at most
+constexpr size_t kChunk = size_t(1) << 30;               // arena growth step
+constexpr size_t kHeadroom = size_t(2) << 30;            // device memory left to others
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over device memory chunks.  Chunks grow in kChunk steps up
+// to the cap (0: what the device reports free, less a headroom) and are returned
+// only when the arena is destroyed (hipFree synchronises the device).
+class Arena {
+  public:
+    explicit Arena(size_t cap) : cap_(cap) {}
+    ~Arena() {
+        for (auto& c : chunks_) (void)hipFree(c.base);
+    }
+    Arena(const Arena&) = delete;
+    Arena& operator=(const Arena&) = delete;
+
+    // nullptr when `bytes` does not fit now
+    char* alloc(size_t bytes) {
+        bytes = (size_t)round_up((int64_t)bytes, 256);
+        for (auto& c : chunks_) {
+            char* p = take(c, bytes);
+            if (p) return p;
+        }
+        size_t want = std::max(bytes, kChunk);
+        if (cap_) {
+            if (total_ + bytes > cap_) return nullptr;
+            want = std::min(want, cap_ - total_);
+        } else {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess || fr < bytes + kHeadroom) return nullptr;
+            want = std::min(want, fr - kHeadroom);
+        }
+        void* base = nullptr;
+        if (hipMalloc(&base, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        chunks_.push_back(Chunk{static_cast<char*>(base), want, {}});
+        chunks_.back().free[0] = want;
+        total_ += want;
+        return take(chunks_.back(), bytes);
+    }
+
+    void release(char* p) {
+        auto u = used_.find(p);
+        if (u == used_.end()) return;
+        const size_t bytes = u->second;
+        used_.erase(u);
+        for (auto& c : chunks_) {
+            if (p < c.base || p >= c.base + c.size) continue;
+            size_t off = (size_t)(p - c.base), size = bytes;
+            auto nx = c.free.lower_bound(off);
+            if (nx != c.free.end() && off + size == nx->first) {
+                size += nx->second;
+                nx = c.free.erase(nx);
+            }
+            if (nx != c.free.begin()) {
+                auto pv = std::prev(nx);
+                if (pv->first + pv->second == off) {
+                    pv->second += size;
+                    return;
+                }
+            }
+            c.free[off] = size;
+            return;
+        }
+    }
+
+    // Whether `bytes` could ever fit (the cap, or the device's total memory).
+    bool could_fit(size_t bytes) const {
+        if (cap_) return bytes <= cap_;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+        return bytes + kHeadroom <= tot;
+    }
+
+  private:
+    struct Chunk {
+        char* base;
+        size_t size;
+        std::map<size_t, size_t> free;   // offset -> size
+    };
+    char* take(Chunk& c, size_t bytes) {
+        for (auto it = c.free.begin(); it != c.free.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, size = it->second;
+            c.free.erase(it);
+            if (size > bytes) c.free[off + bytes] = size - bytes;
+            char* p = c.base + off;
+            used_[p] = bytes;
+            return p;
+        }
+        return nullptr;
+    }
+    size_t cap_;
+    size_t total_ = 0;
+    std::vector<Chunk> chunks_;
+    std::unordered_map<char*, size_t> used_;
+};
+
+enum Phase : int {
+    PH_INIT_RES,     // waiting for / past the first explicit residual
+    PH_STEP,         // FP64 block steps
+    PH_CONFIRM,      // FP64 confirmation of the recurrence stop test
+    PH_FINAL,        // FP64 report residual after maxit
+    PH_INNER,        // low-precision inner solve
+    PH_OUTER_RES,    // FP64 residual after a refinement correction
+};
+
+struct Sys {
+    uint64_t tag = 0;
+    int slot = -1;
+    // problem
+    int n = 0, p = 0, P = 0, prec = PREC_F64;
+    double tol = 0.0;
+    int maxit = 0;
+    ccg_opts o{};
+    double* X_out = nullptr;    // caller's X (device, or host with CCG_HOST_PTRS)
+    int64_t ldx = 0;
+    bool host = false;
+    // device memory
+    char* mem = nullptr;
+    Workspace w;
+    const double* A64 = nullptr;
+    int64_t lda64 = 0;
+    const void* lowhi = nullptr;
+    const void* lowlo = nullptr;
+    int64_t ldlow = 0;
+    double* Xdev = nullptr;     // device X buffer of a host-pointer system
+    // phase machine
+    Phase ph = PH_INIT_RES;
+    bool res_due = true;        // an explicit residual is launched this round
+    int res_mode = RES_INIT;
+    int res_set_nb = 1;
+    bool refine_due = false;    // X += E * scale this round
+    bool inner_start_due = false;
+    bool stepping = false;
+    int iter_before = 0;
+    bool running_before = false;
+    // low-precision outer loop
+    double nb = 1.0, best = 0.0;
+    int iters = 0, refinements = 0, stall = 0;
+    RefArgs ra{};
+    // report
+    double bytes = 0.0;
+    Clock::time_point t0;
+    ccg_status status = CCG_OK;
+    bool cancel = false;
+};
+
+struct Finished {
+    uint64_t tag;
+    ccg_status status;
+    ccg_info info;
+};
+
+class Engine {
+  public:
+    Engine(int device, hipStream_t stream, size_t budget) : device_(device), s_(stream), arena_(budget) {
+        HIP_OK(hipMalloc(&states_, sizeof(DevState) * kSlots));
+        HIP_OK(hipMalloc(&d_ad_, sizeof(AdArgs) * kSlots));
+        HIP_OK(hipMalloc(&d_res_ad_, sizeof(AdArgs) * kSlots));
+        HIP_OK(hipMalloc(&d_upd_, sizeof(UpdArgs) * kSlots));
+        HIP_OK(hipMalloc(&d_res_, sizeof(ResArgs) * kSlots));
+        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&h_states_), sizeof(DevState) * kSlots,
+                             hipHostMallocDefault));
+        std::memset(h_states_, 0, sizeof(DevState) * kSlots);
+        for (int i = kSlots - 1; i >= 0; --i) free_slots_.push_back(i);
+    }
+    ~Engine() {
+        (void)hipStreamSynchronize(s_);
+        (void)hipFree(states_);
+        (void)hipFree(d_ad_);
+        (void)hipFree(d_res_ad_);
+        (void)hipFree(d_upd_);
+        (void)hipFree(d_res_);
+        if (d_items_) (void)hipFree(d_items_);
+        if (h_items_) (void)hipHostFree(h_items_);
+        (void)hipHostFree(h_states_);
+    }
+
+    bool idle() const { return live_.empty(); }
+    size_t live() const { return live_.size(); }
+
+    // Device bytes a problem needs while resident.
+    static size_t footprint(const ccg_problem& pr, const ccg_opts& o) {
+        const int P = pad_agents(pr.p);
+        const int n_pad = (int)round_up(pr.n, kRowAlign);
+        Workspace tmp;
+        size_t b = round_up((int64_t)carve(tmp, nullptr, pr.n, n_pad, P), 256);
+        const bool host = (o.flags & CCG_HOST_PTRS) != 0;
+        const bool aligned = !host && reinterpret_cast<uintptr_t>(pr.A) % 16 == 0 && (pr.lda * 8) % 16 == 0;
+        if (!aligned) b += round_up((int64_t)sizeof(double) * round_up(pr.n, 2) * pr.n, 256);
+        if (host) b += round_up((int64_t)sizeof(double) * pr.n, 256) + round_up((int64_t)sizeof(double) * pr.n * pr.p, 256);
+        if (o.prec == CCG_FP32) b += round_up((int64_t)sizeof(float) * round_up(pr.n, 4) * pr.n, 256);
+        if (o.prec == CCG_BF16X2) b += 2 * round_up((int64_t)sizeof(uint16_t) * round_up(pr.n, 8) * pr.n, 256);
+        return b;
+    }
+
+    bool could_fit(size_t bytes) const { return arena_.could_fit(bytes); }
+
+    // Make a problem resident and enqueue its set-up.  Returns false (nothing done)
+    // when there is no slot or no memory for it right now.  Throws CcgError on an
+    // invalid problem.
+    bool admit(const ccg_problem& pr, uint64_t tag) {
+        const ccg_opts o = fill_defaults(&pr.opts);
+        check_common(pr.n, pr.p, pr.A, pr.lda, pr.b, pr.X, pr.ldx);
+        if (!(pr.tol > 0.0)) throw CcgError{CCG_ERR_ARG, "tol must be > 0"};
+        if (pr.maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
+        if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)
+            throw CcgError{CCG_ERR_ARG, "unknown precision mode"};
+        if (free_slots_.empty()) return false;
+        const size_t need = footprint(pr, o);
+        char* mem = arena_.alloc(need);
+        if (!mem) return false;
+        Sys sy;
+        sy.tag = tag;
+        sy.slot = free_slots_.back();
+        free_slots_.pop_back();
+        sy.n = pr.n;
+        sy.p = pr.p;
+        sy.P = pad_agents(pr.p);
+        sy.prec = o.prec == CCG_FP64 ? PREC_F64 : (o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
+        sy.tol = pr.tol;
+        sy.maxit = pr.maxit;
+        sy.o = o;
+        sy.X_out = pr.X;
+        sy.ldx = pr.ldx;
+        sy.host = (o.flags & CCG_HOST_PTRS) != 0;
+        sy.mem = mem;
+        sy.t0 = Clock::now();
+        const int n = sy.n, p = sy.p, P = sy.P;
+        const int n_pad = (int)round_up(n, kRowAlign);
+        Carver cv{mem};
+        const size_t wsb = carve(sy.w, mem, n, n_pad, P);
+        sy.w.base = mem;
+        sy.w.bytes = wsb;
+        sy.w.n = n;
+        sy.w.n_pad = n_pad;
+        sy.w.P = P;
+        cv.off = wsb;
+        HIP_OK(hipMemsetAsync(mem, 0, wsb, s_));
+        // FP64 matrix (uploaded, or the caller's, copied when its columns are unaligned)
+        const double* A = pr.A;
+        int64_t lda = pr.lda;
+        const double* b = pr.b;
+        const double* X0 = pr.X;
+        int64_t ldx0 = pr.ldx;
+        const bool aligned = !sy.host && reinterpret_cast<uintptr_t>(A) % 16 == 0 && (lda * 8) % 16 == 0;
+        if (!aligned) {
+            const int64_t ldb = round_up(n, 2);
+            double* Ac = cv.take<double>((size_t)ldb * n);
+            if (sy.host) {
+                HIP_OK(hipMemcpy2DAsync(Ac, sizeof(double) * ldb, A, sizeof(double) * lda, sizeof(double) * n, n,
+                                        hipMemcpyHostToDevice, s_));
+            } else {
+                HIP_OK(launch_copy_cols(n, A, lda, Ac, ldb, s_));
+            }
+            A = Ac;
+            lda = ldb;
+        }
+        if (sy.host) {
+            double* bd = cv.take<double>((size_t)n);
+            double* Xd = cv.take<double>((size_t)n * p);
+            HIP_OK(hipMemcpyAsync(bd, b, sizeof(double) * n, hipMemcpyHostToDevice, s_));
+            HIP_OK(hipMemcpy2DAsync(Xd, sizeof(double) * n, X0, sizeof(double) * ldx0, sizeof(double) * n, p,
+                                    hipMemcpyHostToDevice, s_));
+            b = bd;
+            X0 = Xd;
+            ldx0 = n;
+            sy.Xdev = Xd;
+        }
+        sy.A64 = A;
+        sy.lda64 = lda;
+        if (sy.prec != PREC_F64) {
+            const int64_t ld = round_up(n, sy.prec == PREC_F32 ? 4 : 8);
+            if (sy.prec == PREC_F32) {
+                float* hi = cv.take<float>((size_t)ld * n);
+                HIP_OK(launch_convert(PREC_F32, n, A, lda, hi, nullptr, ld, s_));
+                sy.lowhi = hi;
+            } else {
+                uint16_t* hi = cv.take<uint16_t>((size_t)ld * n);
+                uint16_t* lo = cv.take<uint16_t>((size_t)ld * n);
+                HIP_OK(launch_convert(PREC_BF16X2, n, A, lda, hi, lo, ld, s_));
+                sy.lowhi = hi;
+                sy.lowlo = lo;
+            }
+            sy.ldlow = ld;
+            sy.bytes += (double)n * n * (8.0 + 4.0);
+        }
+        HIP_OK(launch_pack(n, n_pad, p, P, X0, ldx0, sy.w.Xr, s_));
+        HIP_OK(launch_pad_vec(n, n_pad, b, sy.w.bp, s_));
+        // argument records of the batched kernels
+        DevState* st = states_ + sy.slot;
+        AdArgs ad{};
+        ad.n = n;
+        ad.n_pad = n_pad;
+        ad.product_only = 0;
+        ad.red = sy.w.red_ad;
+        ad.st = st;
+        if (sy.prec == PREC_F64) {
+            ad.A = A;
+            ad.A_lo = nullptr;
+            ad.lda = lda;
+            ad.V = sy.w.D;
+            ad.R = sy.w.R;
+            ad.AD = sy.w.AD;
+        } else {
+            ad.A = sy.lowhi;
+            ad.A_lo = sy.lowlo;
+            ad.lda = sy.ldlow;
+            ad.V = sy.w.Dl;
+            ad.R = sy.w.Rl;
+            ad.AD = sy.w.ADl;
+        }
+        AdArgs ra = ad;
+        ra.product_only = 1;
+        ra.A = A;
+        ra.A_lo = nullptr;
+        ra.lda = lda;
+        ra.V = sy.w.Xr;
+        ra.R = sy.w.R;
+        ra.AD = sy.w.AD;
+        UpdArgs u{};
+        u.n_pad = n_pad;
+        if (sy.prec == PREC_F64) {
+            u.X = sy.w.Xr; u.R = sy.w.R; u.D = sy.w.D; u.AD = sy.w.AD;
+        } else {
+            u.X = sy.w.E; u.R = sy.w.Rl; u.D = sy.w.Dl; u.AD = sy.w.ADl;
+        }
+        u.st = st;
+        ResArgs r{};
+        r.n = n;
+        r.n_pad = n_pad;
+        r.p = p;
+        r.mode = RES_INIT;
+        r.set_nb = 1;
+        r.b = sy.w.bp;
+        r.Y = sy.w.AD;
+        r.R = sy.w.R;
+        r.D = sy.w.D;
+        r.red = sy.w.red_res;
+        r.st = st;
+        HIP_OK(hipMemcpyAsync(d_ad_ + sy.slot, &ad, sizeof ad, hipMemcpyHostToDevice, s_));
+        HIP_OK(hipMemcpyAsync(d_res_ad_ + sy.slot, &ra, sizeof ra, hipMemcpyHostToDevice, s_));
+        HIP_OK(hipMemcpyAsync(d_upd_ + sy.slot, &u, sizeof u, hipMemcpyHostToDevice, s_));
+        HIP_OK(hipMemcpyAsync(d_res_ + sy.slot, &r, sizeof r, hipMemcpyHostToDevice, s_));
+        // initial state (written with every header at the start of the next round)
+        DevState& h = h_states_[sy.slot];
+        std::memset(&h, 0, kHeader);
+        h.done = RUNNING;
+        set_all_agents(h, p);
+        h.maxit = sy.maxit;
+        h.tol = sy.tol;
+        h.tau = o.rank_tau;
+        h.nb = 1.0;
+        sy.ph = PH_INIT_RES;
+        sy.res_due = true;
+        sy.res_mode = sy.prec == PREC_F64 ? RES_INIT : RES_REFINE;
+        sy.res_set_nb = 1;
+        sy.ra.n_pad = n_pad;
+        sy.ra.P = P;
+        sy.ra.T = sy.w.R;
+        sy.ra.X = sy.w.Xr;
+        sy.ra.E = sy.w.E;
+        sy.ra.R = sy.w.Rl;
+        sy.ra.D = sy.w.Dl;
+        if (sy.slot + 1 > hi_slot_) hi_slot_ = sy.slot + 1;
+        live_.push_back(sy);
+        return true;
+    }
+
+    void cancel(uint64_t tag) {
+        for (auto& sy : live_)
+            if (sy.tag == tag) sy.cancel = true;
+    }
+
+    // One host round (see the file comment); k block steps for stepping systems.
+    void round(int k) {
+        if (live_.empty()) return;
+        // cancelled systems leave before any launch
+        for (auto& sy : live_)
+            if (sy.cancel) retire(sy, CCG_CANCELLED);
+        finish_retired();
+        if (live_.empty()) return;
+        // --- work lists
+        items_.clear();
+        struct Range { int prec, P; size_t ad_off, ad_n, up_off, up_n; };
+        std::vector<Range> res_ranges, step_ranges;
+        for (int P : {1, 2, 4, 8, 16}) {
+            Range rr{PREC_F64, P, items_.size(), 0, 0, 0};
+            for (auto& sy : live_) {
+                if (!sy.res_due || sy.P != P) continue;
+                const int t = (sy.n + ad_tile_rows(PREC_F64, P) - 1) / ad_tile_rows(PREC_F64, P);
+                for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+            }
+            rr.ad_n = items_.size() - rr.ad_off;
+            rr.up_off = items_.size();
+            for (auto& sy : live_) {
+                if (!sy.res_due || sy.P != P) continue;
+                const int t = sy.w.n_pad / (kWG / P);
+                for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, sy.res_mode, sy.res_set_nb});
+            }
+            rr.up_n = items_.size() - rr.up_off;
+            if (rr.ad_n) res_ranges.push_back(rr);
+        }
+        for (int prec : {PREC_F64, PREC_F32, PREC_BF16X2}) {
+            for (int P : {1, 2, 4, 8, 16}) {
+                Range sr{prec, P, items_.size(), 0, 0, 0};
+                for (auto& sy : live_) {
+                    if (!sy.stepping || sy.prec != prec || sy.P != P) continue;
+                    const int t = (sy.n + ad_tile_rows(prec, P) - 1) / ad_tile_rows(prec, P);
+                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+                }
+                sr.ad_n = items_.size() - sr.ad_off;
+                sr.up_off = items_.size();
+                for (auto& sy : live_) {
+                    if (!sy.stepping || sy.prec != prec || sy.P != P) continue;
+                    const int t = sy.w.n_pad / (kWG / P);
+                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+                }
+                sr.up_n = items_.size() - sr.up_off;
+                if (sr.ad_n) step_ranges.push_back(sr);
+            }
+        }
+        upload_items();
+        // --- state headers (host decisions of the previous round)
+        for (auto& sy : live_) {
+            sy.iter_before = h_states_[sy.slot].iter;
+            sy.running_before = h_states_[sy.slot].done == RUNNING;
+        }
+        HIP_OK(hipMemcpy2DAsync(states_, sizeof(DevState), h_states_, sizeof(DevState), kHeader, hi_slot_,
+                                hipMemcpyHostToDevice, s_));
+        // 1. refinement corrections
+        for (auto& sy : live_)
+            if (sy.refine_due) HIP_OK(launch_refine_add(sy.ra, s_));
+        // 2. explicit residuals
+        for (const Range& r : res_ranges) {
+            HIP_OK(launch_ad_batch(PREC_F64, r.P, d_res_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
+            HIP_OK(launch_res_batch(r.P, d_res_, d_items_ + r.up_off, (int)r.up_n, s_));
+        }
+        // 3. inner-solve starts
+        for (auto& sy : live_)
+            if (sy.inner_start_due) HIP_OK(launch_inner_init(sy.ra, s_));
+        // 4. block steps
+        if (!step_ranges.empty()) {
+            for (int it = 0; it < k; ++it) {
+                for (const Range& r : step_ranges) {
+                    HIP_OK(launch_ad_batch(r.prec, r.P, d_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
+                    HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_items_ + r.up_off, (int)r.up_n, s_));
+                }
+            }
+        }
+        HIP_OK(hipMemcpy2DAsync(h_states_, sizeof(DevState), states_, sizeof(DevState), kHeader, hi_slot_,
+                                hipMemcpyDeviceToHost, s_));
+        HIP_OK(hipStreamSynchronize(s_));
+        // --- advance every system
+#ifdef CCG_ENGINE_TRACE
+        for (auto& sy : live_) {
+            const DevState& h = h_states_[sy.slot];
+            fprintf(stderr, "round slot %d n %d P %d ph %d res %d/%d step %d | done %d iter %d minres %.3e nb %.3e mask %x\n",
+                    sy.slot, sy.n, sy.P, (int)sy.ph, (int)sy.res_due, sy.res_mode, (int)sy.stepping, h.done, h.iter,
+                    h.minres, h.nb, h.mask);
+        }
+#endif
+        for (auto& sy : live_) advance(sy);
+        finish_retired();
+    }
+
+    std::vector<Finished> take_finished() {
+        std::vector<Finished> f;
+        f.swap(finished_);
+        return f;
+    }
+
+  private:
+    void advance(Sys& sy) {
+        DevState& h = h_states_[sy.slot];
+        const double nn = (double)sy.n * sy.n;
+        const double s_step = sy.prec == PREC_F64 ? 8.0 : 4.0;
+        if (sy.stepping) {
+            const int streamed = (h.iter - sy.iter_before) + (sy.running_before && h.done != RUNNING ? 1 : 0);
+            sy.bytes += s_step * nn * streamed;
+        }
+        if (sy.res_due) sy.bytes += 8.0 * nn;
+        const bool had_res = sy.res_due;
+        sy.res_due = false;
+        sy.refine_due = false;
+        sy.inner_start_due = false;
+        sy.stepping = false;
+        if (sy.prec == PREC_F64) {
+            switch (sy.ph) {
+                case PH_INIT_RES:
+                case PH_CONFIRM:
+                case PH_STEP:
+                    if (h.done == RUNNING) {
+                        sy.ph = PH_STEP;
+                        sy.stepping = true;
+                    } else if (h.done == RECUR_CONV) {
+                        sy.ph = PH_CONFIRM;
+                        due_res(sy, RES_CONFIRM, 0);
+                    } else if (h.done == MAXIT) {
+                        sy.ph = PH_FINAL;
+                        due_res(sy, RES_FINAL, 0);
+                    } else {
+                        retire(sy, h.done == FAILED ? (ccg_status)h.status : CCG_OK);
+                    }
+                    break;
+                case PH_FINAL:
+                    retire(sy, h.done == FAILED ? (ccg_status)h.status : CCG_NOT_CONVERGED);
+                    break;
+                default:
+                    retire(sy, CCG_ERR_DEVICE);
+            }
+            return;
+        }
+        // refinement modes
+        switch (sy.ph) {
+            case PH_INIT_RES:
+                sy.nb = h.nb;
+                sy.best = h.minres;
+                decide(sy);
+                break;
+            case PH_INNER:
+                if (h.done == RUNNING) {
+                    sy.stepping = true;
+                    break;
+                }
+                sy.iters += h.iter;
+                if (h.done == FAILED) {
+                    retire(sy, (ccg_status)h.status);
+                    break;
+                }
+                sy.refine_due = true;
+                ++sy.refinements;
+                h.done = RUNNING;
+                h.tol = sy.tol;
+                h.nb = sy.nb;
+                set_all_agents(h, sy.p);
+                sy.ph = PH_OUTER_RES;
+                due_res(sy, RES_REFINE, 0);
+                break;
+            case PH_OUTER_RES:
+                if (!had_res) break;
+                if (h.done == FAILED) {
+                    retire(sy, (ccg_status)h.status);
+                    break;
+                }
+                if (h.minres >= sy.best) {
+                    if (++sy.stall >= 3) {
+                        retire(sy, CCG_ERR_BREAKDOWN);
+                        break;
+                    }
+                } else {
+                    sy.stall = 0;
+                }
+                sy.best = std::min(sy.best, h.minres);
+                decide(sy);
+                break;
+            default:
+                retire(sy, CCG_ERR_DEVICE);
+        }
+    }
+
+    // Refinement: finished, out of budget, or start the next inner solve.
+    void decide(Sys& sy) {
+        DevState& h = h_states_[sy.slot];
+        if (h.done == FAILED) { retire(sy, (ccg_status)h.status); return; }
+        if (h.done != RUNNING) { retire(sy, CCG_OK); return; }
+        if (sy.refinements >= sy.o.max_refine || sy.iters >= sy.maxit) {
+            retire(sy, CCG_NOT_CONVERGED);
+            return;
+        }
+        unsigned mask = 0u;
+        int m = 0;
+        for (int j = 0; j < kMaxP; ++j) {
+            const double sc = (j < sy.p && std::isfinite(h.norms[j])) ? h.norms[j] : 0.0;
+            sy.ra.scale[j] = sc;
+            if (sc > 0.0) { mask |= 1u << j; h.keep[m++] = j; }
+        }
+        h.done = RUNNING;
+        h.iter = 0;
+        h.m = m;
+        h.mask = mask;
+        h.tol = std::min(0.5, std::max(sy.o.inner_tol, 0.1 * sy.tol / h.minres));
+        h.nb = 1.0;
+        h.maxit = std::min(sy.o.inner_maxit, sy.maxit - sy.iters);
+        sy.inner_start_due = true;
+        sy.stepping = true;
+        sy.ph = PH_INNER;
+    }
+
+    void due_res(Sys& sy, int mode, int set_nb) {
+        sy.res_due = true;
+        sy.res_mode = mode;
+        sy.res_set_nb = set_nb;
+    }
+
+    // Report a system and copy its agents out (completed in finish_retired).
+    void retire(Sys& sy, ccg_status st) {
+        if (sy.slot < 0) return;
+        DevState& h = h_states_[sy.slot];
+        ccg_info info;
+        std::memset(&info, 0, sizeof info);
+        info.status = st;
+        if (sy.prec == PREC_F64) {
+            info.iters = h.iter;
+            info.refinements = 0;
+            info.restarts = h.restarts;
+            info.p_final = h.m;
+        } else {
+            info.iters = sy.iters;
+            info.refinements = sy.refinements;
+            info.restarts = 0;
+            info.p_final = sy.p;
+        }
+        info.deflations = h.deflations;
+        double mn = INFINITY, mx = 0.0;
+        int best = -1;
+        for (int j = 0; j < sy.p; ++j) {
+            const double r = h.norms[j] / h.nb;
+            if (r < mn) { mn = r; best = j; }
+            if (r > mx) mx = r;
+        }
+        info.best_agent = best;
+        info.rel_res = mn;
+        info.rel_res_max = mx;
+        info.bytes_A = sy.bytes;
+        double* dst = sy.host ? sy.Xdev : sy.X_out;
+        const int64_t ldd = sy.host ? sy.n : sy.ldx;
+        HIP_OK(launch_unpack(sy.n, sy.w.n_pad, sy.p, sy.w.Xr, dst, ldd, s_));
+        if (sy.host)
+            HIP_OK(hipMemcpy2DAsync(sy.X_out, sizeof(double) * sy.ldx, sy.Xdev, sizeof(double) * sy.n,
+                                    sizeof(double) * sy.n, sy.p, hipMemcpyDeviceToHost, s_));
+        retiring_.push_back(Finished{sy.tag, st, info});
+        retiring_mem_.push_back(sy.mem);
+        free_slots_.push_back(sy.slot);
+        sy.slot = -1;
+    }
+
+    void finish_retired() {
+        if (retiring_.empty()) return;
+        HIP_OK(hipStreamSynchronize(s_));
+        const auto now = Clock::now();
+        for (size_t i = 0; i < retiring_.size(); ++i) {
+            for (auto& sy : live_)
+                if (sy.tag == retiring_[i].tag && sy.slot < 0)
+                    retiring_[i].info.seconds = std::chrono::duration<double>(now - sy.t0).count();
+            finished_.push_back(retiring_[i]);
+        }
+        for (char* m : retiring_mem_) arena_.release(m);
+        retiring_.clear();
+        retiring_mem_.clear();
+        live_.erase(std::remove_if(live_.begin(), live_.end(), [](const Sys& s) { return s.slot < 0; }),
+                    live_.end());
+        hi_slot_ = 0;
+        for (auto& sy : live_) hi_slot_ = std::max(hi_slot_, sy.slot + 1);
+    }
+
+    void upload_items() {
+        const size_t n = std::max<size_t>(items_.size(), 1);
+        if (n > items_cap_) {
+            if (d_items_) (void)hipFree(d_items_);
+            if (h_items_) (void)hipHostFree(h_items_);
+            d_items_ = nullptr;
+            h_items_ = nullptr;
+            items_cap_ = 0;
+            const size_t cap = std::max<size_t>(n * 2, 1 << 16);
+            HIP_OK(hipMalloc(&d_items_, sizeof(int4) * cap));
+            HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&h_items_), sizeof(int4) * cap, hipHostMallocDefault));
+            items_cap_ = cap;
+        }
+        if (items_.empty()) return;
+        std::memcpy(h_items_, items_.data(), sizeof(int4) * items_.size());
+        HIP_OK(hipMemcpyAsync(d_items_, h_items_, sizeof(int4) * items_.size(), hipMemcpyHostToDevice, s_));
+    }
+
+    int device_;
+    hipStream_t s_;
+    Arena arena_;
+    DevState* states_ = nullptr;
+    DevState* h_states_ = nullptr;
+    AdArgs* d_ad_ = nullptr;
+    AdArgs* d_res_ad_ = nullptr;
+    UpdArgs* d_upd_ = nullptr;
+    ResArgs* d_res_ = nullptr;
+    int4* d_items_ = nullptr;
+    int4* h_items_ = nullptr;
+    size_t items_cap_ = 0;
+    std::vector<int4> items_;
+    std::vector<int> free_slots_;
+    int hi_slot_ = 0;
+    std::vector<Sys> live_;
+    std::vector<Finished> retiring_;
+    std::vector<char*> retiring_mem_;
+    std::vector<Finished> finished_;
+};
+
+// ------------------------------------------------------------------ service
+
+struct Request {
+    uint64_t ticket;
+    ccg_problem prob;
+    Clock::time_point t_submit;
+};
+
+struct Result {
+    bool done = false;
+    ccg_status status = CCG_PENDING;
+    ccg_info info{};
+    Clock::time_point t_submit;
+};
+
+}  // namespace
+
+struct Server {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable wake;      // to the service thread
+    std::condition_variable done_cv;   // to waiters
+    std::deque<Request> queue;
+    std::map<uint64_t, Result> results;
+    std::vector<uint64_t> cancels;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::string fatal;                 // a device error that ended the service
+};
+
+namespace {
+
+// Service loop: admit in arrival order while memory allows, advance, retire.
+void serve(ccg_ctx* c, Server* sv) {
+    (void)hipSetDevice(c->device);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->fatal = "service stream creation failed";
+        sv->done_cv.notify_all();
+        return;
+    }
+    try {
+        Engine eng(c->device, s, c->budget);
+        std::map<uint64_t, Clock::time_point> submitted;
+        for (;;) {
+            std::vector<Request> admit;
+            {
+                std::unique_lock<std::mutex> lk(sv->mu);
+                if (eng.idle())
+                    sv->wake.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->cancels.empty(); });
+                if (sv->stop) break;
+                for (uint64_t t : sv->cancels) {
+                    bool queued = false;
+                    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+                        if (it->ticket != t) continue;
+                        Result& r = sv->results[t];
+                        r.done = true;
+                        r.status = CCG_CANCELLED;
+                        r.info.status = CCG_CANCELLED;
+                        sv->queue.erase(it);
+                        queued = true;
+                        break;
+                    }
+                    if (!queued) eng.cancel(t);
+                }
+                sv->cancels.clear();
+                sv->done_cv.notify_all();
+                while (!sv->queue.empty()) {
+                    admit.push_back(sv->queue.front());
+                    sv->queue.pop_front();
+                }
+            }
+            // admission in arrival order; what does not fit goes back to the front
+            size_t taken = 0;
+            for (; taken < admit.size(); ++taken) {
+                const Request& rq = admit[taken];
+                const ccg_opts o = fill_defaults(&rq.prob.opts);
+                bool ok = false;
+                ccg_status err = CCG_OK;
+                std::string msg;
+                try {
+                    if (!eng.could_fit(Engine::footprint(rq.prob, o))) {
+                        err = CCG_ERR_NOMEM;
+                        msg = "system exceeds the HBM budget";
+                    } else {
+                        ok = eng.admit(rq.prob, rq.ticket);
+                    }
+                } catch (const CcgError& e) {
+                    err = e.st;
+                    msg = e.msg;
+                }
+                if (err != CCG_OK) {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    Result& r = sv->results[rq.ticket];
+                    r.done = true;
+                    r.status = err;
+                    r.info.status = err;
+                    sv->done_cv.notify_all();
+                    continue;
+                }
+                if (!ok) break;
+                submitted[rq.ticket] = rq.t_submit;
+            }
+            if (taken < admit.size()) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                for (size_t i = admit.size(); i-- > taken;) sv->queue.push_front(admit[i]);
+            }
+            eng.round(8);
+            auto fin = eng.take_finished();
+            if (!fin.empty()) {
+                const auto now = Clock::now();
+                std::lock_guard<std::mutex> lk(sv->mu);
+                for (auto& f : fin) {
+                    Result& r = sv->results[f.tag];
+                    r.done = true;
+                    r.status = f.status;
+                    r.info = f.info;
+                    auto it = submitted.find(f.tag);
+                    if (it != submitted.end()) {
+                        r.info.seconds = std::chrono::duration<double>(now - it->second).count();
+                        submitted.erase(it);
+                    }
+                }
+                sv->done_cv.notify_all();
+            }
+        }
+    } catch (const CcgError& e) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->fatal = e.msg;
+    } catch (const std::bad_alloc&) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->fatal = "host allocation failed";
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->fatal.empty()) {
+        for (auto& kv : sv->results)
+            if (!kv.second.done) {
+                kv.second.done = true;
+                kv.second.status = CCG_ERR_DEVICE;
+                kv.second.info.status = CCG_ERR_DEVICE;
+            }
+    }
+    sv->done_cv.notify_all();
+}
+
+}  // namespace
+
+void stop_server(ccg_ctx* c) {
+    Server* sv = c->server;
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->wake.notify_all();
+    if (sv->th.joinable()) sv->th.join();
+    delete sv;
+    c->server = nullptr;
+}
+
+}  // namespace host
+}  // namespace ccg
+
+using namespace ccg;
+using namespace ccg::host;
+
+extern "C" {
+
+ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, ccg_info* infos) {
+    if (!c) return CCG_ERR_ARG;
+    if (count < 0 || (count > 0 && !probs)) return CCG_ERR_ARG;
+    if (infos)
+        for (int i = 0; i < count; ++i) {
+            std::memset(&infos[i], 0, sizeof(ccg_info));
+            infos[i].best_agent = -1;
+            infos[i].status = CCG_PENDING;
+        }
+    ccg_status first_err = CCG_OK;
+    bool any_nc = false;
+    const ccg_status st = guarded(c, [&]() -> ccg_status {
+        Engine eng(c->device, c->stream, c->budget);
+        std::deque<int> queue;
+        for (int i = 0; i < count; ++i) queue.push_back(i);
+        auto record = [&](int i, ccg_status s, const ccg_info* inf) {
+            if (infos) {
+                if (inf) infos[i] = *inf;
+                infos[i].status = s;
+            }
+            if (s < 0 && first_err == CCG_OK) first_err = s;
+            if (s == CCG_NOT_CONVERGED) any_nc = true;
+        };
+        while (!queue.empty() || !eng.idle()) {
+            while (!queue.empty()) {
+                const int i = queue.front();
+                const ccg_opts o = fill_defaults(&probs[i].opts);
+                if (!eng.could_fit(Engine::footprint(probs[i], o))) {
+                    record(i, CCG_ERR_NOMEM, nullptr);
+                    queue.pop_front();
+                    continue;
+                }
+                bool ok = false;
+                try {
+                    ok = eng.admit(probs[i], (uint64_t)i);
+                } catch (const CcgError& e) {
+                    if (e.st == CCG_ERR_DEVICE) throw;
+                    record(i, e.st, nullptr);
+                    queue.pop_front();
+                    continue;
+                }
+                if (!ok) {
+                    if (eng.idle()) {   // nothing resident and still no room: never fits
+                        record(i, CCG_ERR_NOMEM, nullptr);
+                        queue.pop_front();
+                        continue;
+                    }
+                    break;
+                }
+                queue.pop_front();
+            }
+            eng.round(16);
+            for (auto& f : eng.take_finished()) record((int)f.tag, f.status, &f.info);
+        }
+        return CCG_OK;
+    });
+    if (st != CCG_OK) return st;
+    if (first_err != CCG_OK) return first_err;
+    return any_nc ? CCG_NOT_CONVERGED : CCG_OK;
+}
+
+ccg_status ccg_submit(ccg_ctx* c, const ccg_problem* prob, uint64_t* ticket) {
+    if (!c || !prob || !ticket) return CCG_ERR_ARG;
+    try {
+        if (!c->server) {
+            Server* sv = new Server();
+            c->server = sv;
+            sv->th = std::thread(serve, c, sv);
+        }
+        Server* sv = c->server;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (!sv->fatal.empty()) {
+            c->err = sv->fatal;
+            return CCG_ERR_DEVICE;
+        }
+        const uint64_t t = sv->next_ticket++;
+        Result r;
+        r.t_submit = Clock::now();
+        sv->results[t] = r;
+        sv->queue.push_back(Request{t, *prob, r.t_submit});
+        *ticket = t;
+    } catch (const std::bad_alloc&) {
+        return CCG_ERR_NOMEM;
+    } catch (const std::system_error&) {
+        c->err = "could not start the service thread";
+        return CCG_ERR_DEVICE;
+    }
+    c->server->wake.notify_all();
+    return CCG_OK;
+}
+
+static ccg_status take_result(Server* sv, uint64_t ticket, ccg_info* info, bool wait) {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->results.find(ticket);
+    if (it == sv->results.end()) return CCG_ERR_ARG;
+    if (wait) sv->done_cv.wait(lk, [&] { return it->second.done; });
+    if (!it->second.done) return CCG_PENDING;
+    const ccg_status st = it->second.status;
+    if (info) *info = it->second.info;
+    sv->results.erase(it);
+    return st;
+}
+
+ccg_status ccg_poll(ccg_ctx* c, uint64_t ticket, ccg_info* info) {
+    if (!c || !c->server) return CCG_ERR_ARG;
+    return take_result(c->server, ticket, info, false);
+}
+
+ccg_status ccg_wait(ccg_ctx* c, uint64_t ticket, ccg_info* info) {
+    if (!c || !c->server) return CCG_ERR_ARG;
+    return take_result(c->server, ticket, info, true);
+}
+
+ccg_status ccg_cancel(ccg_ctx* c, uint64_t ticket) {
+    if (!c || !c->server) return CCG_ERR_ARG;
+    Server* sv = c->server;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->results.find(ticket);
+        if (it == sv->results.end()) return CCG_ERR_ARG;
+        if (it->second.done) return CCG_OK;
+        sv->cancels.push_back(ticket);
+    }
+    sv->wake.notify_all();
+    return CCG_OK;
+}
+
+}  // extern "C"

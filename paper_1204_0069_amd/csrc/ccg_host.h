@@ -1,0 +1,205 @@
+// Internal host-side definitions shared by the single-solve driver (ccg_host.cpp)
+// and the multi-system engine (ccg_engine.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ccg.h"
+#include "ccg_device.h"
+
+namespace ccg {
+hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s);
+hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s);
+hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
+hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,
+                       hipStream_t s);
+hipError_t launch_unpack(int n, int n_pad, int p, const double* Xr, double* X, int64_t ldx,
+                         hipStream_t s);
+hipError_t launch_pad_vec(int n, int n_pad, const double* b, double* bp, hipStream_t s);
+hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int64_t ldb, hipStream_t s);
+hipError_t launch_convert(int prec, int n, const double* A, int64_t lda, void* hi, void* lo, int64_t ldb,
+                          hipStream_t s);
+hipError_t launch_inner_init(const RefArgs& a, hipStream_t s);
+hipError_t launch_refine_add(const RefArgs& a, hipStream_t s);
+hipError_t launch_ad_batch(int prec, int P, const AdArgs* sys, const int4* items, int nitems, hipStream_t s);
+hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);
+hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int nitems, hipStream_t s);
+int ad_tile_rows(int prec, int P);
+int ad_workgroups(int n);
+int row_workgroups(int n_pad, int P);
+
+namespace host {
+
+struct CcgError {
+    ccg_status st;
+    std::string msg;
+};
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw CcgError{CCG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+inline int pad_agents(int p) {
+    int P = 1;
+    while (P < p) P <<= 1;
+    return P;
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Workspace {
+    int n = 0, n_pad = 0, P = 0;
+    size_t bytes = 0;
+    void* base = nullptr;            // one allocation, carved
+    double* Xr = nullptr;            // agent-major n_pad x P (FP64 agents)
+    double* bp = nullptr;            // n_pad
+    double* R = nullptr;             // agent-major n_pad x P
+    double* D = nullptr;
+    double* AD = nullptr;
+    // low-precision inner solve of the refinement modes (FP32 blocks, agent-major)
+    float* E = nullptr;
+    float* Rl = nullptr;
+    float* Dl = nullptr;
+    float* ADl = nullptr;
+    RedBuf red_ad{}, red_res{};
+    DevState* st = nullptr;
+};
+
+struct Carver {
+    char* p;
+    size_t off = 0;
+    template <class T> T* take(size_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* r = reinterpret_cast<T*>(p ? p + off : nullptr);
+        off += count * sizeof(T);
+        return r;
+    }
+};
+
+inline RedBuf carve_red(Carver& cv, int nwg, int ne) {
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    RedBuf r;
+    r.l1 = cv.take<double>((size_t)nwg * ne);
+    r.l2 = cv.take<double>((size_t)ngroups * ne);
+    r.cnt = cv.take<unsigned>((size_t)ngroups + 1);
+    return r;
+}
+
+}  // namespace host
+}  // namespace ccg
+
+namespace ccg {
+namespace host {
+struct Server;
+}  // namespace host
+}  // namespace ccg
+
+struct ccg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    std::string err;
+    ccg::host::Workspace ws;
+    ccg::DevState* st_host = nullptr;     // pinned mirror of the device state
+    // A.D timing (CCG_PROFILE)
+    double prof_ms = 0.0;
+    long long prof_launches = 0;
+    std::vector<hipEvent_t> ev_pool;
+    // captured block-step graph
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    int64_t graph_key[6] = {0, 0, 0, 0, 0, 0};
+    // aligned copy of a caller matrix with unaligned columns
+    void* acopy = nullptr;
+    size_t acopy_bytes = 0;
+    // low-precision copy of A (FP32, or the BF16 hi plane followed by the lo plane)
+    void* lowA = nullptr;
+    size_t lowA_bytes = 0;
+    // continuous-batching service (ccg_submit), started on first use
+    ccg::host::Server* server = nullptr;
+};
+
+
+namespace ccg {
+namespace host {
+
+// Stop and join the service thread of a context (no-op without one).
+void stop_server(ccg_ctx* c);
+
+// Lay out (or only size, when base == nullptr) the workspace.
+inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
+    Carver cv{base};
+    const size_t blk = (size_t)n_pad * P;
+    w.Xr = cv.take<double>(blk);
+    w.bp = cv.take<double>((size_t)n_pad);
+    w.R = cv.take<double>(blk);
+    w.D = cv.take<double>(blk);
+    w.AD = cv.take<double>(blk);
+    w.E = cv.take<float>(blk);
+    w.Rl = cv.take<float>(blk);
+    w.Dl = cv.take<float>(blk);
+    w.ADl = cv.take<float>(blk);
+    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) + 2 * P * P + P);
+    w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
+    w.st = cv.take<DevState>(1);
+    return cv.off;
+}
+
+inline void check_common(int n, int p, const void* A, int64_t lda, const void* b, const void* X, int64_t ldx) {
+    if (n < 1 || p < 1 || p > kMaxP || p > n)
+        throw CcgError{CCG_ERR_ARG, "need 1 <= p <= min(n, 16)"};
+    if (!A || !b || !X) throw CcgError{CCG_ERR_ARG, "null pointer argument"};
+    if (lda < n || ldx < n) throw CcgError{CCG_ERR_ARG, "leading dimension smaller than n"};
+}
+
+inline void set_all_agents(DevState& h, int p) {
+    h.m = p;
+    h.mask = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
+    for (int j = 0; j < p; ++j) h.keep[j] = j;
+}
+
+inline ccg_opts fill_defaults(const ccg_opts* in) {
+    ccg_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (in) o = *in;
+    if (o.inner_tol <= 0.0) o.inner_tol = 1e-4;
+    if (o.inner_maxit <= 0) o.inner_maxit = 500;
+    if (o.max_refine <= 0) o.max_refine = 60;
+    if (o.rank_tau <= 0.0) o.rank_tau = o.prec == CCG_FP64 ? 1e-14 : 1e-12;
+    if (o.graph_k <= 0) o.graph_k = 16;
+    return o;
+}
+
+template <class F>
+inline ccg_status guarded(ccg_ctx* c, F&& f) {
+    if (!c) return CCG_ERR_ARG;
+    try {
+        HIP_OK(hipSetDevice(c->device));
+        c->err.clear();
+        return f();
+    } catch (const CcgError& e) {
+        c->err = e.msg;
+        if (e.st == CCG_ERR_DEVICE) {
+            // leave the stream usable for the next call where possible
+            (void)hipStreamSynchronize(c->stream);
+        }
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        c->err = "host allocation failed";
+        return CCG_ERR_NOMEM;
+    }
+}
+
+}  // namespace host
+}  // namespace ccg

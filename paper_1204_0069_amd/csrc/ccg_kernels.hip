@@ -151,7 +151,7 @@ __device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int
 // out[e] = sum over rows 0..cnt-1 of src (row stride ne), for every e < ne, with the
 // rows of each entry split into contiguous slices over spare threads and the slice
 // sums added in slice order (a fixed tree).  scratch: kWG doubles of LDS.
-__device__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
+__device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
     const int tid = threadIdx.x;
     const int tpe = ne >= kWG ? 1 : kWG / ne;          // threads per entry
     const int slice = (cnt + tpe - 1) / tpe;
@@ -173,15 +173,13 @@ __device__ void sum_table(const double* src, int ne, int cnt, double* out, doubl
     }
 }
 
-// Sum `ne` values per workgroup (mine[], LDS) over the whole grid, in workgroup
-// order within groups of kGroup and in group order across groups.  Returns true
-// in the one workgroup that ends up holding the totals in out[] (LDS).  Tickets
-// are reset by their last taker, so the scratch is ready for the next launch.
-__device__ bool grid_reduce(const double* mine, int ne, const RedBuf& rb, double* out, int* s_flag,
-                            double* scratch) {
+// Sum `ne` values per tile (mine[], LDS) over the nwg tiles of one system, in tile
+// order within groups of kGroup and in group order across groups.  Returns true in
+// the one workgroup that ends up holding the totals in out[] (LDS).  Tickets are
+// reset by their last taker, so the scratch is ready for the next launch.
+__device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const RedBuf rb, double* out,
+                                            int* s_flag, double* scratch, int bid, int nwg) {
     const int tid = threadIdx.x;
-    const int nwg = gridDim.x;
-    const int bid = blockIdx.x;
     const int ngroups = (nwg + kGroup - 1) / kGroup;
     const int grp = bid / kGroup;
     const int gsize = min(kGroup, nwg - grp * kGroup);
@@ -444,8 +442,9 @@ __device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
 
 // ============================================================== k_ad: AD = A D
 
+// One tile (4 * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
 template <int PREC, int P, class CFG>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
+__device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const int ntiles) {
     using TA = typename PT<PREC>::TA;
     using TV = typename PT<PREC>::TV;
     using TACC = typename PT<PREC>::TACC;
@@ -477,7 +476,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n;
-    const int i0 = blockIdx.x * kAdCols;                  // first AD row of the workgroup
+    const int i0 = tile * kAdCols;                        // first AD row of the workgroup
     const int iw = i0 + wave * kCW;                       // first row of this wave
     const TV* __restrict__ V = static_cast<const TV*>(a.V);
     const int64_t lda = a.lda;
@@ -498,7 +497,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))
 
     const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
     // first chunk of this workgroup (rotated when staggering); chunks then wrap
-    const int c0 = CFG::STG ? (int)(((unsigned)blockIdx.x * 7u) % (unsigned)nch) : 0;
+    const int c0 = CFG::STG ? (int)(((unsigned)tile * 7u) % (unsigned)nch) : 0;
     TV pre[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -632,7 +631,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))
         gmine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(gmine, NE, a.red, gtot, &ish[0], gscr)) return;
+    if (!grid_reduce(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
 
     // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
     DevState* st = a.st;
@@ -760,13 +759,30 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))
     }
 }
 
+template <class CFG>
+__host__ __device__ constexpr int ad_tiles(int n) { return (n + CFG::ROWS - 1) / CFG::ROWS; }
+
+template <int PREC, int P, class CFG>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
+    ad_tile<PREC, P, CFG>(a, blockIdx.x, gridDim.x);
+}
+
+// Many systems in one launch: workgroup w runs tile items[w].y of system items[w].x.
+template <int PREC, int P, class CFG>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW)))
+void k_ad_batch(const AdArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const AdArgs a = sys[it.x];
+    ad_tile<PREC, P, CFG>(a, it.y, ad_tiles<CFG>(a.n));
+}
+
 // ===================== k_upd: X += D alpha, R -= AD alpha, D = R + D beta
 //
 // Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
 // Every row's old D is read into LDS before any thread writes the new one.
 
 template <int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
+__device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile) {
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
     __shared__ double al[P * P], be[P * P];
@@ -775,7 +791,7 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
     const int r = tid % RB, j = tid / RB;
-    const int64_t i = (int64_t)blockIdx.x * RB + r;
+    const int64_t i = (int64_t)tile * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
     if (tid < P * P) {
         al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
@@ -806,13 +822,25 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
 #pragma unroll
     for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
     D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
-    if (blockIdx.x == 0 && tid == 0) st->iter += 1;
+    if (tile == 0 && tid == 0) st->iter += 1;
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
+    upd_tile<PREC, P>(a, blockIdx.x);
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const UpdArgs a = sys[it.x];
+    upd_tile<PREC, P>(a, it.y);
 }
 
 // ============================================ k_res: T = B - Y, norms, restart
 
 template <int P>
-__global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
+__device__ __forceinline__ void res_tile(const ResArgs& a, const int tile, const int ntiles) {
     constexpr int RB = kWG / P;
     constexpr int NE = P * P + 1;      // T^T T entries, then b^T b
     __shared__ double ts[RB * P];
@@ -824,7 +852,7 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
     DevState* st = a.st;
     const int tid = threadIdx.x;
     const int r = tid % RB, j = tid / RB;
-    const int64_t i = (int64_t)blockIdx.x * RB + r;
+    const int64_t i = (int64_t)tile * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
     const unsigned msk = st->mask;
     const double bi = a.b[i];
@@ -845,7 +873,7 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr)) return;
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
     if (tid == 0) {
         if (a.set_nb) st->nb = sqrt(tot[P * P]);
         double mn = INFINITY;
@@ -868,6 +896,22 @@ __global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
             }
         }
     }
+}
+
+template <int P>
+__global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
+    res_tile<P>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched residual: items[w] = (system, tile, mode, set_nb); the mode of each
+// system's pass travels with its items.
+template <int P>
+__global__ __launch_bounds__(kWG) void k_res_batch(const ResArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    ResArgs a = sys[it.x];
+    a.mode = it.z;
+    a.set_nb = it.w;
+    res_tile<P>(a, it.y, a.n_pad / (kWG / P));
 }
 
 // ======================================================== layout conversions
@@ -1036,6 +1080,81 @@ hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
 #undef C64
 #undef C32
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int P>
+static hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    using C = typename AdPick<PREC, P>::type;
+    hipLaunchKernelGGL((k_ad_batch<PREC, P, C>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    return hipGetLastError();
+}
+template <int PREC, int P>
+static hipError_t launch_upd_batch_t(const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_upd_batch<PREC, P>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    return hipGetLastError();
+}
+template <int P>
+static hipError_t launch_res_batch_t(const ResArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_res_batch<P>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_batch(int prec, int P, const AdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    switch (prec) {
+#define C64(PP) launch_ad_batch_t<PREC_F64, PP>(sys, items, nitems, s)
+#define C32(PP) launch_ad_batch_t<PREC_F32, PP>(sys, items, nitems, s)
+#define CBF(PP) launch_ad_batch_t<PREC_BF16X2, PP>(sys, items, nitems, s)
+        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F32: CCG_DISPATCH_P(P, C32)
+        case PREC_BF16X2: CCG_DISPATCH_P(P, CBF)
+#undef C64
+#undef C32
+#undef CBF
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    switch (prec) {
+#define C64(PP) launch_upd_batch_t<PREC_F64, PP>(sys, items, nitems, s)
+#define C32(PP) launch_upd_batch_t<PREC_F32, PP>(sys, items, nitems, s)
+        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F32:
+        case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
+#undef C64
+#undef C32
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+#define CR(PP) launch_res_batch_t<PP>(sys, items, nitems, s)
+    CCG_DISPATCH_P(P, CR)
+#undef CR
+}
+
+// AD rows per A.D tile for a precision and padded agent count (0: unsupported).
+template <int PREC>
+static int rows_for(int P) {
+    switch (P) {
+        case 1: return AdPick<PREC, 1>::type::ROWS;
+        case 2: return AdPick<PREC, 2>::type::ROWS;
+        case 4: return AdPick<PREC, 4>::type::ROWS;
+        case 8: return AdPick<PREC, 8>::type::ROWS;
+        case 16: return AdPick<PREC, 16>::type::ROWS;
+        default: return 0;
+    }
+}
+int ad_tile_rows(int prec, int P) {
+    switch (prec) {
+        case PREC_F64: return rows_for<PREC_F64>(P);
+        case PREC_F32: return rows_for<PREC_F32>(P);
+        case PREC_BF16X2: return rows_for<PREC_BF16X2>(P);
+        default: return 0;
     }
 }
 

@@ -264,3 +264,17 @@ def test_small_solve_after_larger_one_in_same_workspace(gpu_ctx):
     X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-12, 50)
     assert info["status"] == 0 and info["iters"] == orc["iters"]
     assert info["deflations"] == orc["deflations"]
+
+
+def test_inputs_are_not_modified(gpu_ctx):
+    """X0 (including a single column, whose transpose shares its storage), A and b
+    are read only."""
+    for p in (1, 3):
+        A, b, X0 = ci.system(200, p, 1e2, seed=31)
+        At, bt, Xt = _t(A), _t(b), _t(X0)
+        A0, b0, X00 = At.clone(), bt.clone(), Xt.clone()
+        X, info = gpu_ctx.solve(At, bt, Xt, 1e-10, 5000)
+        assert info["status"] == 0 and info["iters"] > 0
+        assert torch.equal(At, A0) and torch.equal(bt, b0) and torch.equal(Xt, X00)
+        g = gpu_ctx.debug_step(At, bt, Xt, 2)
+        assert torch.equal(Xt, X00)
