@@ -1,15 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark: cooperative CG solves per second on one MI355X.
 
-Workload (one "step" = one complete solve): dense SPD A = Q diag(lam) Q^T with
-n = 8192, lam log-uniform in [1, 1e4] (condition number 1e4 exactly), b and the
-p = 8 starting points N(0,1), seeded; stop when the best agent's explicit FP64
-relative residual is <= 1e-10.  Inputs are resident in HBM before timing starts.
+Default workload (--mode single; one "step" = one complete solve): dense SPD
+A = Q diag(lam) Q^T with n = 8192, lam log-uniform in [1, 1e4] (condition number
+1e4 exactly), b and the p = 8 starting points N(0,1), seeded; stop when the best
+agent's explicit FP64 relative residual is <= 1e-10.  Inputs are resident in HBM
+before timing starts.  --kind gram selects A = M^T M / n + sigma I instead, and
+--prec fp32 / bf16x2 the mixed-precision refinement modes.
 
 Printed: ONE JSON line with solves/s, ms per solve, p50/p99 solve latency, the
 A.D kernel's achieved HBM bandwidth against the 8 TB/s peak (HIP events around
 every A.D launch, on the library's stream, inside the timed region), and the
 oracle's throughput on the host cores on a bounded sample of the same workload.
+
+Other modes (their own JSON line each):
+  --mode batched  many independent systems in one ccg_solve_batched call (n
+                  log-uniform in [64, 4096], p in {2, 4, 8}, kappa log-uniform in
+                  [1e2, 1e5], FP32 A + FP64 refinement); one step = the whole batch.
+  --mode served   Poisson arrivals into the continuous-batching service (n
+                  log-uniform in [128, 16384], p = 4, kappa log-uniform in
+                  [1e2, 1e6], precision drawn from fp64 / fp32 / bf16x2, A in pinned
+                  host memory, upload inside the latency); reports p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -40,6 +51,16 @@ def parse():
                     help="block steps of the oracle timed on the host (0: skip)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
+    ap.add_argument("--kind", default="spectrum", choices=["spectrum", "gram"],
+                    help="single mode: Q diag(lam) Q^T, or M^T M / n + sigma I")
+    ap.add_argument("--count", type=int, default=1024, help="batched mode: systems per batch")
+    ap.add_argument("--requests", type=int, default=48, help="served mode: timed requests")
+    ap.add_argument("--pool", type=int, default=12, help="served mode: distinct matrices")
+    ap.add_argument("--n-hi", type=int, default=16384, help="served mode: largest n")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="served mode: arrivals per second (0: half the measured closed-loop rate)")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="served mode: HBM budget")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (3 times) and exit: the "
                          "known-size kernel that scales hardware byte counters")
@@ -93,6 +114,11 @@ def main():
         copy_calibration(args.copy_calibration)
         return
 
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "served":
+        return run_served(args)
+
     import numpy as np
     import torch
 
@@ -101,7 +127,10 @@ def main():
 
     dev = "cuda:0"
     n, p = args.n, args.p
-    A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", ci.BASE_SEED, base=n), device=dev)
+    if args.kind == "gram":
+        A = ci.spd_gram(n, args.kappa, ci.item_seed("G", ci.BASE_SEED, base=n), device=dev)
+    else:
+        A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", ci.BASE_SEED, base=n), device=dev)
     b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", ci.BASE_SEED, base=n)), device=dev)
     X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", ci.BASE_SEED, base=n)), device=dev)
     torch.cuda.synchronize()
@@ -189,9 +218,11 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x2": "bf16x2"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": f"dense SPD n={n}, kappa={args.kappa:g} (log-uniform spectrum), "
+        "config": {"workload": f"dense SPD n={n}, kappa={args.kappa:g} "
+                               f"({'log-uniform spectrum' if args.kind == 'spectrum' else 'M^T M/n + sigma I'}), "
                                f"p={p} agents, {args.prec.upper()} A, tol {args.tol:g}",
-                   "n": n, "p": p, "kappa": args.kappa, "tol": args.tol, "prec": args.prec},
+                   "n": n, "p": p, "kappa": args.kappa, "tol": args.tol, "prec": args.prec,
+                   "kind": args.kind},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3)},
         "solves_per_s_graph": None if graph_rate is None else round(graph_rate, 4),
@@ -201,6 +232,168 @@ def main():
         "status": infos[-1]["status_name"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def _oracle_rate(samples):
+    """Oracle seconds per block step per n^2, from a few (A, b, X0, steps) samples."""
+    import oracle
+    coef, spent = [], 0.0
+    for A, b, X0, k in samples:
+        c0 = time.perf_counter()
+        oracle.ccg(A, b, X0, tol=0.0, maxit=k)
+        dt = time.perf_counter() - c0
+        spent += dt
+        coef.append(dt / ((k + 1) * A.shape[0] ** 2))
+    return float(sum(coef) / len(coef)), spent
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import Context
+
+    dev = "cuda:0"
+    specs = ci.batch_specs(count=args.count, n_lo=64, n_hi=4096, p_choices=(2, 4, 8),
+                           k_lo=1e2, k_hi=1e5)
+    systems = []
+    for sp in specs:
+        A = ci.spd_spectrum(sp["n"], sp["kappa"], sp["seed"], device=dev)
+        b = torch.as_tensor(ci.normal_block(sp["n"], 0, ci.item_seed("bb", sp["seed"])), device=dev)
+        X0 = torch.as_tensor(ci.normal_block(sp["n"], sp["p"], ci.item_seed("bx", sp["seed"])), device=dev)
+        systems.append(dict(A=A, b=b, X0=X0, tol=args.tol, maxit=10 ** 6, prec=args.prec))
+    torch.cuda.synchronize()
+    ctx = Context(0)
+    for _ in range(args.warmup):
+        ctx.solve_batched(systems[: min(32, len(systems))])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.solve_batched(systems)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    infos = [r[1] for r in res]
+    ok = sum(1 for i in infos if i["status"] == 0)
+    bytes_a = sum(i["bytes_A"] for i in infos) * args.steps
+    eff = bytes_a / total / 1e9
+    n2 = np.array([sp["n"] ** 2 for sp in specs], dtype=np.float64)
+    cpu = None
+    if args.cpu_sample_steps > 0:
+        idx = np.argsort(n2)[:: max(1, len(specs) // 6)][:6]
+        samples = []
+        for i in idx:
+            sy = systems[i]
+            samples.append((sy["A"].cpu().numpy(), sy["b"].cpu().numpy(), sy["X0"].cpu().numpy(),
+                            args.cpu_sample_steps))
+        c, spent = _oracle_rate(samples)
+        steps_i = np.array([i["iters"] + 2 * (i["refinements"] + 1) for i in infos], dtype=np.float64)
+        t_cpu = float(c * (n2 * steps_i).sum())
+        cpu = {"value": round(len(specs) / t_cpu, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_sample_steps} FP64 block steps on each of {len(samples)} systems of "
+                         f"the batch ({spent:.1f} s); seconds per step per n^2 = {c:.3e}, scaled by "
+                         f"sum(n^2 x the GPU's steps per system)"}
+    out = {
+        "metric": METRIC, "value": round(len(specs) * args.steps / total, 4), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x2": "bf16x2"}[args.prec], "data": "synthetic",
+        "config": {"workload": f"batch of {len(specs)} dense SPD systems, n log-uniform in [64, 4096], "
+                               f"p in {{2, 4, 8}}, kappa log-uniform in [1e2, 1e5], {args.prec.upper()} A, "
+                               f"tol {args.tol:g}", "count": len(specs), "prec": args.prec},
+        "converged": ok, "iters_mean": float(np.mean([i["iters"] for i in infos])),
+        "iters_max": int(max(i["iters"] for i in infos)),
+        "rel_res_max": float(max(i["rel_res"] for i in infos)),
+        "roofline": {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kind": "effective: algorithmic A bytes of all systems / wall time"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def run_served(args):
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import Context
+
+    dev = "cuda:0"
+    rng = np.random.default_rng(ci.item_seed("served-pool", ci.BASE_SEED))
+    pool = []
+    for i in range(args.pool):
+        n = int(round(np.exp(rng.uniform(np.log(128), np.log(args.n_hi)))))
+        kappa = float(np.exp(rng.uniform(np.log(1e2), np.log(1e6))))
+        A = ci.spd_spectrum(n, kappa, ci.item_seed("served-A", i), device=dev)
+        pool.append((n, kappa, A.cpu().pin_memory()))
+        del A
+    torch.cuda.empty_cache()
+    precs = ("fp64", "fp32", "bf16x2")
+    total_req = args.requests + 8
+    reqs = []
+    for r in range(total_req):
+        k = int(rng.integers(0, len(pool)))
+        n = pool[k][0]
+        b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("served-b", r))).pin_memory()
+        X0 = torch.as_tensor(ci.normal_block(n, 4, ci.item_seed("served-x", r))).pin_memory()
+        reqs.append((k, b, X0, precs[int(rng.integers(0, 3))]))
+    ctx = Context(0, hbm_budget=int(args.budget_gib * (1 << 30)))
+
+    def submit(r):
+        k, b, X0, prec = reqs[r]
+        return ctx.submit(pool[k][2], b, X0, args.tol, 10 ** 6, prec=prec)
+
+    # closed loop on the first 8 requests: saturated rate (and warm-up)
+    c0 = time.perf_counter()
+    ts = [submit(r) for r in range(8)]
+    for t in ts:
+        ctx.wait(t)
+    closed = 8 / (time.perf_counter() - c0)
+    rate = args.rate if args.rate > 0 else 0.5 * closed
+    gaps = rng.exponential(1.0 / rate, args.requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    tickets = []
+    t0 = time.perf_counter()
+    for j in range(args.requests):
+        now = time.perf_counter() - t0
+        if arrivals[j] > now:
+            time.sleep(arrivals[j] - now)
+        tickets.append(submit(8 + j))
+    results = [ctx.wait(t) for t in tickets]
+    total = time.perf_counter() - t0
+    infos = [r[1] for r in results]
+    lat = np.array([i["seconds"] for i in infos]) * 1e3
+    st = {}
+    for i, j in zip(infos, range(args.requests)):
+        key = f"{reqs[8 + j][3]}:{i['status_name']}"
+        st[key] = st.get(key, 0) + 1
+    ok = [i for i in infos if i["status"] == 0]
+    bytes_a = sum(i["bytes_A"] for i in infos)
+    eff = bytes_a / total / 1e9
+    out = {
+        "metric": METRIC, "value": round(len(ok) / total, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": 8, "ms_per_step": round(total / args.requests * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
+        "data": "synthetic",
+        "config": {"workload": f"served stream: Poisson arrivals at {rate:.3f}/s (half the closed-loop "
+                               f"rate {closed:.3f}/s), n log-uniform in [128, {args.n_hi}], p=4, kappa "
+                               f"log-uniform in [1e2, 1e6], precision uniform over fp64/fp32/bf16x2, "
+                               f"{args.pool} pooled matrices in pinned host memory (upload in latency), "
+                               f"HBM budget {args.budget_gib:g} GiB", "requests": args.requests},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "statuses": st,
+        "rel_res_max_converged": float(max((i["rel_res"] for i in ok), default=float("nan"))),
+        "roofline": {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kind": "effective: algorithmic A bytes of all requests / wall time"},
+        "cpu_baseline": None,
     }
     print(json.dumps(out))
     ctx.close()
