@@ -300,113 +300,95 @@ __device__ __forceinline__ void fail_state(DevState* st, int code) {
     st->status = code;
 }
 
-// ----------------------------------------------- wave-distributed p x p algebra
+// ------------------------------------------------ one-wave p x p algebra
 //
-// A P x P matrix lives in the registers of one wave: entry e = a*P + b sits in lane
-// e % 64, slot e / 64.  Inactive agents are padded as identity rows and columns, so
-// every loop runs over the compile-time P and the active block gets exactly the
-// result of its own factorisation (natural order).  Run by all 64 lanes of a wave.
+// The Cholesky factor is formed with lane a holding row a of the matrix in
+// registers, the other lanes' values read with v_readlane (uniform, no LDS round
+// trip).  The triangular solves then run one right-hand side per lane, entirely in
+// that lane's registers, with the factor read from LDS (uniform addresses, so
+// every lane gets the same broadcast value).  Inactive agents are identity rows and
+// columns, so every loop runs over the compile-time P.
 
-template <int P> struct WM {
-    static constexpr int NE = P * P;
-    static constexpr int NQ = (NE + 63) / 64;
-};
-
-template <int NQ>
-__device__ __forceinline__ double wget(const double (&h)[NQ], int e) {
-    if (NQ == 1) return __shfl(h[0], e & 63);
-    double r = 0.0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double t = __shfl(h[q], e & 63);
-        if ((e >> 6) == q) r = t;
-    }
-    return r;
+__device__ __forceinline__ double bcast(double v, int src_lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src_lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src_lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// In-place Cholesky G = L L^T (right-looking, natural order); the lower triangle of
-// h becomes L, the strict upper triangle zero.  Returns false on a pivot <= 0 or
-// NaN.  Each L entry is formed from the same products, in the same order, as the
-// plain left-looking recurrence.
+// In-place Cholesky of the rows g (lane = row; lanes >= P hold padding): g becomes
+// row `lane` of L in its lower part.  Each L entry is formed from the same products,
+// in the same order, as the plain left-looking recurrence.  Returns false (uniform)
+// on a pivot <= 0 or NaN.
 template <int P>
-__device__ bool wave_cholesky(double (&h)[WM<P>::NQ], int lane) {
-    constexpr int NQ = WM<P>::NQ;
+__device__ __forceinline__ bool row_cholesky(double (&g)[P], int lane) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const double djj = wget<NQ>(h, j * P + j);
+        const double djj = bcast(g[j], j);
         if (!(djj > 0.0)) return false;
         const double ljj = sqrt(djj);
-        double nh[NQ];
+        if (lane > j) g[j] = g[j] / ljj;
+        else if (lane == j) g[j] = ljj;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int e = lane + 64 * q;
-            const int ea = e < WM<P>::NE ? e : 0;
-            const int x = ea / P, y = ea - (ea / P) * P;
-            const double lx = wget<NQ>(h, x * P + j) / ljj;
-            const double ly = wget<NQ>(h, y * P + j) / ljj;
-            double v = h[q];
-            if (x > j && y > j) v = h[q] - lx * ly;
-            else if (x > j && y == j) v = lx;
-            else if (x == j && y == j) v = ljj;
-            else if (x == j && y > j) v = 0.0;
-            nh[q] = v;
+        for (int b = j + 1; b < P; ++b) {
+            const double lbj = bcast(g[j], b);
+            if (lane > j) g[b] = g[b] - g[j] * lbj;
         }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) h[q] = nh[q];
     }
     return true;
 }
 
-// y <- (L L^T)^{-1} y for the P right-hand-side columns held in y (entry (i, c)).
+// Row `lane` of src (row stride lds) with inactive rows / columns replaced by the
+// identity (identity == true) or by zero.
 template <int P>
-__device__ void wave_chol_solve(const double (&h)[WM<P>::NQ], double (&y)[WM<P>::NQ], int lane) {
-    constexpr int NQ = WM<P>::NQ;
+__device__ __forceinline__ void row_load(double (&r)[P], const double* src, int lds, unsigned mask,
+                                         bool identity, int lane) {
+    const int a = lane < P ? lane : 0;
+    const bool ra = (mask >> a) & 1u;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {            // L z = y
-        const double lkk = wget<NQ>(h, k * P + k);
-        double ny[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int e = lane + 64 * q;
-            const int ea = e < WM<P>::NE ? e : 0;
-            const int i = ea / P, c = ea - (ea / P) * P;
-            const double zk = wget<NQ>(y, k * P + c) / lkk;
-            const double lik = wget<NQ>(h, i * P + k);
-            ny[q] = (i == k) ? zk : (i > k ? y[q] - lik * zk : y[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) y[q] = ny[q];
-    }
-#pragma unroll
-    for (int k = P - 1; k >= 0; --k) {       // L^T x = z
-        const double lkk = wget<NQ>(h, k * P + k);
-        double ny[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int e = lane + 64 * q;
-            const int ea = e < WM<P>::NE ? e : 0;
-            const int i = ea / P, c = ea - (ea / P) * P;
-            const double xk = wget<NQ>(y, k * P + c) / lkk;
-            const double lki = wget<NQ>(h, k * P + i);
-            ny[q] = (i == k) ? xk : (i < k ? y[q] - lki * xk : y[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) y[q] = ny[q];
+    for (int b = 0; b < P; ++b) {
+        const bool on = ra && ((mask >> b) & 1u);
+        r[b] = on ? src[a * lds + b] : ((identity && a == b) ? 1.0 : 0.0);
     }
 }
 
-// Load a P x P matrix from src[a*lds + b] into wave registers, replacing inactive
-// rows / columns (bit clear in mask) by the identity (diag) or zero (off-diag).
+// The same for a right-hand side kept in LDS (element i at Y[i * P + c], column c
+// owned by this lane), with rolled loops: the register-resident form does not fit
+// the register budget at P = 16.
 template <int P>
-__device__ __forceinline__ void wave_load(double (&h)[WM<P>::NQ], const double* src, int lds,
-                                          unsigned mask, bool identity, int lane) {
+__device__ __forceinline__ void col_chol_solve_lds(const double* L, const double* rinv, double* Y, int c) {
+#pragma unroll 1
+    for (int i = 0; i < P; ++i) {
+        double s = Y[i * P + c];
+        for (int k = 0; k < i; ++k) s -= L[i * P + k] * Y[k * P + c];
+        Y[i * P + c] = s * rinv[i];
+    }
+#pragma unroll 1
+    for (int i = P - 1; i >= 0; --i) {
+        double s = Y[i * P + c];
+        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * Y[k * P + c];
+        Y[i * P + c] = s * rinv[i];
+    }
+}
+
+// y <- (L L^T)^{-1} y for one right-hand side held by this lane.  L is row-major
+// (stride P) in LDS, rinv[i] = 1 / L[i][i].  Forward then backward substitution in
+// the textbook order; each pivot divides through its reciprocal.
+template <int P>
+__device__ __forceinline__ void col_chol_solve(const double* L, const double* rinv, double (&y)[P]) {
 #pragma unroll
-    for (int q = 0; q < WM<P>::NQ; ++q) {
-        const int e = lane + 64 * q;
-        const int ea = e < WM<P>::NE ? e : 0;
-        const int x = ea / P, y = ea - (ea / P) * P;
-        const bool on = ((mask >> x) & 1u) && ((mask >> y) & 1u);
-        h[q] = on ? src[x * lds + y] : ((identity && x == y) ? 1.0 : 0.0);
+    for (int i = 0; i < P; ++i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
+        y[i] = s * rinv[i];
+    }
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * y[k];
+        y[i] = s * rinv[i];
     }
 }
 
@@ -414,29 +396,35 @@ __device__ __forceinline__ void wave_load(double (&h)[WM<P>::NQ], const double* 
 // each xor round with offset o keeps one half of the live values and adds the
 // partner's copy of it, until one value per lane remains, then plain xor adds.
 // Returns the index (0..M-1) of the total this lane holds in v[0].
+// (the halving is unrolled by recursion over compile-time counts, so every array
+// index is a constant and v stays in registers)
+template <int M, int O, class T>
+struct Fold {
+    __device__ static __forceinline__ void run(T* v, int lane, int& idx) {
+        if constexpr (O >= 1) {
+            if constexpr (M > 1) {
+                constexpr int h = M / 2;
+                const bool up = (lane & O) != 0;
+#pragma unroll
+                for (int q = 0; q < h; ++q) {
+                    const T send = up ? v[q] : v[q + h];
+                    const T keep = up ? v[q + h] : v[q];
+                    v[q] = keep + __shfl_xor(send, O);
+                }
+                if (up) idx += h;
+                Fold<h, O / 2, T>::run(v, lane, idx);
+            } else {
+                v[0] += __shfl_xor(v[0], O);
+                Fold<1, O / 2, T>::run(v, lane, idx);
+            }
+        }
+    }
+};
+
 template <int M, class T>
 __device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
     int idx = 0;
-    int m = M;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        if (m > 1) {
-            const bool up = (lane & o) != 0;
-            const int h = m >> 1;
-#pragma unroll
-            for (int q = 0; q < M / 2; ++q) {
-                if (q < h) {
-                    const T send = up ? v[q] : v[q + h];
-                    const T keep = up ? v[q + h] : v[q];
-                    v[q] = keep + __shfl_xor(send, o);
-                }
-            }
-            if (up) idx += h;
-            m = h;
-        } else {
-            v[0] += __shfl_xor(v[0], o);
-        }
-    }
+    Fold<M, 32, T>::run(v, lane, idx);
     return idx;
 }
 
@@ -467,11 +455,16 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
     __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
     __shared__ double gtot[P * (P + 1) + 2 * P * P + P];    // grid totals (last workgroup)
-    __shared__ double sm[3 * kMaxP * kMaxP];
+    __shared__ double sm[4 * kMaxP * kMaxP];
     __shared__ double gscr[kWG];
     __shared__ int ish[128];
 
     if (!a.product_only && a.st->done != RUNNING) return;
+    // state the last workgroup needs, read now so that its latency hides under the
+    // stream (the previous launches have finished writing it)
+    const unsigned mask0 = a.st->mask;
+    const double nb0 = a.st->nb, tol0 = a.st->tol, tau0 = a.st->tau;
+    const int iter0 = a.st->iter, maxit0 = a.st->maxit, m0 = a.st->m;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -635,37 +628,53 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
 
     // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
     DevState* st = a.st;
-    constexpr int NQ = WM<P>::NQ;
     const double* Zt = gtot + OZ;
     const double* St = gtot + OS;
     const double* Qd = gtot + OQ;
-    unsigned mask = st->mask;
-    if (tid == 0) {
-        // stop test (Alg. 4: smallest agent residual) before the step, as the loop does
-        double mn = INFINITY;
-        bool bad = false;
-        for (int jj = 0; jj < P; ++jj) {
-            if (!((mask >> jj) & 1u)) continue;
-            const double nr = sqrt(Qd[jj]);
-            st->norms[jj] = nr;
-            if (!isfinite(nr)) bad = true;
-            mn = fmin(mn, nr / st->nb);
-        }
-        st->minres = mn;
-        int stop = 0;
-        if (bad) { fail_state(st, -2); stop = 1; }
-        else if (mn <= st->tol) { st->done = RECUR_CONV; stop = 1; }
-        else if (st->iter >= st->maxit) { st->done = MAXIT; stop = 1; }
-        ish[122] = stop;
-    }
-    // G and Y are symmetric in exact arithmetic: expand their lower triangles
+    unsigned mask = mask0;
     double* Gs = sm;                          // full symmetric P x P
     double* Ys = gmine;                       // (gmine is free now)
+    double* Lsh = sm + kMaxP * kMaxP;         // Cholesky factor, row-major stride P
+    double* rinv = sm + 2 * kMaxP * kMaxP;    // 1 / L[i][i]
+    double* lred = gscr;                      // per-lane values reduced by lane 0
+    // G and Y are symmetric in exact arithmetic: expand their lower triangles
     for (int t = tid; t < P * P; t += kWG) {
         const int x = t / P, y = t - (t / P) * P;
         const int hi = max(x, y), lo = min(x, y);
         Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
         Ys[t] = gtot[OY + hi * (hi + 1) / 2 + lo];
+    }
+    // stop test (Alg. 4: smallest agent residual) before the step, as the loop does
+    if (wave == 0) {
+        double q = INFINITY;
+        double bad = 0.0;
+        if (lane < P && ((mask >> lane) & 1u)) {
+            const double nr = sqrt(Qd[lane]);
+            st->norms[lane] = nr;
+            if (!isfinite(nr)) bad = 1.0;
+            q = nr / nb0;
+        }
+        if (lane < P) {
+            lred[lane] = q;
+            lred[32 + lane] = bad;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            double mn = INFINITY, anybad = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P; ++jj) {
+                mn = fmin(mn, lred[jj]);
+                anybad += lred[32 + jj];
+            }
+            st->minres = mn;
+            int stop = 0;
+            if (anybad > 0.0) { fail_state(st, -2); stop = 1; }
+            else if (mn <= tol0) { st->done = RECUR_CONV; stop = 1; }
+            else if (iter0 >= maxit0) { st->done = MAXIT; stop = 1; }
+            ish[122] = stop;
+        }
     }
     __syncthreads();
     if (ish[122]) return;
@@ -673,35 +682,45 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
     // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
     // keeps every agent; the slow path below runs the greedy rule itself.
-    double h[NQ];
     if (wave == 0) {
-        wave_load<P>(h, Gs, P, mask, true, lane);
-        const bool ok = wave_cholesky<P>(h, lane);
-        double det = ok ? 1.0 : 0.0;
-        if (ok) {
+        double g[P];
+        row_load<P>(g, Gs, P, mask, true, lane);
+        const bool ok = row_cholesky<P>(g, lane);
+        double ratio = 1.0;
+        if (lane < P) {
+            double dg = 1.0;
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                if ((mask >> j) & 1u) {
-                    const double l = wget<NQ>(h, j * P + j);
-                    det *= (l * l) / Gs[j * P + j];
-                }
+            for (int b = 0; b < P; ++b) {
+                Lsh[lane * P + b] = b <= lane ? g[b] : 0.0;
+                if (b == lane) dg = g[b];
             }
+            rinv[lane] = 1.0 / dg;
+            if (ok && ((mask >> lane) & 1u)) ratio = (dg * dg) / Gs[lane * P + lane];
+            lred[lane] = ratio;
         }
-        if (lane == 0) ish[120] = (ok && det > 2.0 * st->tau) ? 1 : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            double det = ok ? 1.0 : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P; ++jj) det *= lred[jj];
+            ish[120] = (ok && det > 2.0 * tau0) ? 1 : 0;
+        }
     }
     __syncthreads();
     const bool fast = ish[120] != 0;
     if (!fast) {
         int* act = &ish[64];    // active agents (global indices), ascending
-        const int m = st->m;
+        const int m = m0;
         if (tid < m) act[tid] = st->keep[tid];
         __syncthreads();
-        double* Gc = sm + kMaxP * kMaxP;       // compact m x m
-        double* H = sm + 2 * kMaxP * kMaxP;
+        double* Gc = sm + 3 * kMaxP * kMaxP;   // compact m x m (below: H)
+        double* H = gscr;
         if (tid < m * m) Gc[tid] = Gs[act[tid / m] * P + act[tid % m]];
         __syncthreads();
         int* kp = &ish[96];
-        const int r = wg_rank_select(Gc, m, st->tau, kp, H, &ish[0]);
+        const int r = wg_rank_select(Gc, m, tau0, kp, H, &ish[0]);
         if (r < 0) {
             if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
             return;
@@ -721,40 +740,71 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
             mask = (unsigned)ish[121];
             if (r == 0) return;
         }
-    }
-    if (wave != 0) return;
-    double al[NQ], w[NQ];
-    if (!fast) {
-        wave_load<P>(h, Gs, P, mask, true, lane);
-        if (!wave_cholesky<P>(h, lane)) {
-            if (lane == 0) fail_state(st, -3);
+        if (wave == 0) {
+            double g[P];
+            row_load<P>(g, Gs, P, mask, true, lane);
+            const bool ok = row_cholesky<P>(g, lane);
+            if (lane < P) {
+                double dg = 1.0;
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    Lsh[lane * P + b] = b <= lane ? g[b] : 0.0;
+                    if (b == lane) dg = g[b];
+                }
+                rinv[lane] = 1.0 / dg;
+            }
+            if (lane == 0) ish[123] = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (ish[123]) {
+            if (tid == 0) fail_state(st, -3);
             return;
         }
     }
-    // alpha = G^{-1} (D^T R)
-    wave_load<P>(al, St, P, mask, false, lane);
-    wave_chol_solve<P>(h, al, lane);
-    // (AD)^T R_new = (AD)^T R - (AD^T AD) alpha, then beta = -G^{-1} (AD)^T R_new
+    if (wave != 0 || lane >= P) return;
+    // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c]; then (AD)^T R_new = (AD)^T R - (AD^T AD)
+    // alpha and beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c], all in this lane's registers
+    const int c = lane;
+    const bool ac = (mask >> c) & 1u;
+    // (registers up to P = 8; LDS beyond)
+    if constexpr (P <= 8) {
+        double y[P];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int e = lane + 64 * q;
-        const int ea = e < WM<P>::NE ? e : 0;
-        const int x = ea / P, c = ea - (ea / P) * P;
-        double v = Zt[x * P + c];
+        for (int x = 0; x < P; ++x) y[x] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, y);
+        double w[P];
 #pragma unroll
-        for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * wget<NQ>(al, l * P + c);
-        const bool on = ((mask >> x) & 1u) && ((mask >> c) & 1u);
-        w[q] = on ? -v : 0.0;
-    }
-    wave_chol_solve<P>(h, w, lane);
+        for (int x = 0; x < P; ++x) {
+            double v = Zt[x * P + c];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int e = lane + 64 * q;
-        if (e < WM<P>::NE) {
-            const int x = e / P, yy = e - (e / P) * P;
-            st->alpha[x * kMaxP + yy] = al[q];
-            st->beta[x * kMaxP + yy] = w[q];
-            st->L[x * kMaxP + yy] = h[q];
+            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * y[l];
+            w[x] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
+        }
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+            st->alpha[x * kMaxP + c] = y[x];
+            st->beta[x * kMaxP + c] = w[x];
+            st->L[x * kMaxP + c] = Lsh[x * P + c];
+        }
+    } else {
+        double* Yc = sm + 3 * kMaxP * kMaxP;   // column c of alpha at Yc[x * P + c]
+        double* Wc = gscr;                     // column c of beta
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) Yc[x * P + c] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
+        col_chol_solve_lds<P>(Lsh, rinv, Yc, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) {
+            double v = Zt[x * P + c];
+            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * Yc[l * P + c];
+            Wc[x * P + c] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
+        }
+        col_chol_solve_lds<P>(Lsh, rinv, Wc, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) {
+            st->alpha[x * kMaxP + c] = Yc[x * P + c];
+            st->beta[x * kMaxP + c] = Wc[x * P + c];
+            st->L[x * kMaxP + c] = Lsh[x * P + c];
         }
     }
 }
@@ -1023,9 +1073,11 @@ __global__ void k_refine_add(RefArgs a) {
 // Tile configuration used by the library, per precision and padded agent count.
 // (measured at n = 8192, FP64, p = 8: 2 columns per wave, one wave step per staged
 // chunk, staggered starts and non-temporal A loads stream A at ~85 % of HBM peak)
+// (P = 16: one column per wave keeps the 16 accumulators and the p x p algebra
+// within the register budget of 4 waves per SIMD)
 template <int PREC, int P> struct AdPick {
     static constexpr int step = 64 * PT<PREC>::E;
-    using type = AdCfg<2, (P * step >= kWG ? 1 : kWG / (P * step)), 4, true, true>;
+    using type = AdCfg<(P >= 16 ? 1 : 2), (P * step >= kWG ? 1 : kWG / (P * step)), 4, true, true>;
 };
 
 template <int PREC, int P>
