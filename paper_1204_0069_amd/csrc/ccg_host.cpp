@@ -146,9 +146,12 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
 // X, R, D update.
 void enqueue_step(const Solve& s, size_t ev_slot) {
     Workspace& w = s.c->ws;
-    if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot), s.c->stream));
-    HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream));
-    if (s.profile) HIP_OK(hipEventRecord(pooled_event(s.c, 2 * ev_slot + 1), s.c->stream));
+    if (s.profile) {
+        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, pooled_event(s.c, 2 * ev_slot),
+                         pooled_event(s.c, 2 * ev_slot + 1)));
+    } else {
+        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream));
+    }
     const Blocks b = blocks(s);
     UpdArgs u;
     u.n_pad = w.n_pad;

@@ -15,7 +15,8 @@
 #include "ccg_device.h"
 
 namespace ccg {
-hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s);
+hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                     hipEvent_t e1 = nullptr);
 hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s);
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
 hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,

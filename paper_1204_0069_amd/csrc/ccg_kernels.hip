@@ -19,6 +19,8 @@
 //
 #include "ccg_device.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #include <algorithm>
@@ -1080,10 +1082,17 @@ template <int PREC, int P> struct AdPick {
     using type = AdCfg<(P >= 16 ? 1 : 2), (P * step >= kWG ? 1 : kWG / (P * step)), 4, true, true>;
 };
 
+// With a start / stop event pair the launch records them itself (the kernel's own
+// begin and end), with no separate marker packets around it.
 template <int PREC, int P>
-static hipError_t launch_ad_t(const AdArgs& a, hipStream_t s) {
+static hipError_t launch_ad_t(const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using C = typename AdPick<PREC, P>::type;
-    hipLaunchKernelGGL((k_ad<PREC, P, C>), dim3((a.n + C::ROWS - 1) / C::ROWS), dim3(kWG), 0, s, a);
+    const dim3 grid((a.n + C::ROWS - 1) / C::ROWS);
+    if (e0) {
+        hipExtLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, e0, e1, 0, a);
+    } else {
+        hipLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, a);
+    }
     return hipGetLastError();
 }
 template <int PREC, int P>
@@ -1107,11 +1116,11 @@ static hipError_t launch_res_t(const ResArgs& a, hipStream_t s) {
         default: return hipErrorInvalidValue;                          \
     }
 
-hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s) {
+hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (prec) {
-#define C64(PP) launch_ad_t<PREC_F64, PP>(a, s)
-#define C32(PP) launch_ad_t<PREC_F32, PP>(a, s)
-#define CBF(PP) launch_ad_t<PREC_BF16X2, PP>(a, s)
+#define C64(PP) launch_ad_t<PREC_F64, PP>(a, s, e0, e1)
+#define C32(PP) launch_ad_t<PREC_F32, PP>(a, s, e0, e1)
+#define CBF(PP) launch_ad_t<PREC_BF16X2, PP>(a, s, e0, e1)
         case PREC_F64: CCG_DISPATCH_P(P, C64)
         case PREC_F32: CCG_DISPATCH_P(P, C32)
         case PREC_BF16X2: CCG_DISPATCH_P(P, CBF)
