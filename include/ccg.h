@@ -195,6 +195,15 @@ ccg_status ccg_cancel(ccg_ctx *ctx, uint64_t ticket);
 ccg_status ccg_convert_matrix(ccg_ctx *ctx, int n, const double *A, int64_t lda, int prec,
                               void *hi, void *lo);
 
+/* Average duration in microseconds of one A.D launch (the block step's stream of A,
+ * products, stop test and p x p solves; not in the paper) with tile width `cw` (A
+ * columns per wave: 1, 2 or 4; a width beyond the register budget runs at the
+ * nearest one that fits) on a synthetic symmetric diagonally dominant system of
+ * size n with p agents in precision `prec`, over `reps` launches after 2 warm-up
+ * launches.  Uses and overwrites the context's workspace.  For the autotuner that
+ * writes the library's table of tile widths (paper_1204_0069_amd/tune.py). */
+ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int reps, double *us);
+
 /* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
  * block steps run with CCG_PROFILE since the last reset; reset != 0 clears them. */
 ccg_status ccg_kernel_time(ccg_ctx *ctx, double *ms, long long *launches, int reset);

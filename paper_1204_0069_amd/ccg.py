@@ -62,7 +62,7 @@ _lib = None
 # Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
 EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
            "ccg_solve_batched", "ccg_submit", "ccg_poll", "ccg_wait", "ccg_cancel",
-           "ccg_convert_matrix", "ccg_kernel_time")
+           "ccg_convert_matrix", "ccg_tune_ad", "ccg_kernel_time")
 
 
 def load_library(path: str = LIB_PATH):
@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_cancel.restype = ctypes.c_int
     lib.ccg_convert_matrix.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp]
     lib.ccg_convert_matrix.restype = ctypes.c_int
+    lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.ccg_tune_ad.restype = ctypes.c_int
     lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     lib.ccg_kernel_time.restype = ctypes.c_int
     if path == LIB_PATH:
@@ -304,6 +306,14 @@ class Context:
             raise self._err(st)
         del keep
         return hi if lo is None else (hi, lo)
+
+    def tune_ad(self, prec: str, p: int, n: int, cw: int, reps: int = 10) -> float:
+        """Microseconds per A.D launch with tile width cw (see ccg_tune_ad)."""
+        us = ctypes.c_double()
+        st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, reps, ctypes.byref(us))
+        if st != 0:
+            raise self._err(st)
+        return us.value
 
     def kernel_time(self, reset: bool = False):
         ms = ctypes.c_double()

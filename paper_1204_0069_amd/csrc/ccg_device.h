@@ -21,7 +21,9 @@ enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 
 // Device iteration state, one per solve.  Written only by "last workgroup"
 // epilogues and by the residual kernel; read by every kernel at entry.
-enum Done : int { RUNNING = 0, RECUR_CONV = 1, FINISHED = 2, MAXIT = 3, FAILED = 4 };
+// OUTER: a refinement residual found the solve unfinished; the host starts the
+// next inner solve (block steps only run while done == RUNNING).
+enum Done : int { RUNNING = 0, RECUR_CONV = 1, FINISHED = 2, MAXIT = 3, FAILED = 4, OUTER = 5 };
 
 struct DevState {
     int done;          // Done code; kernels are no-ops while done != RUNNING

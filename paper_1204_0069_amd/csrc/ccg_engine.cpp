@@ -10,8 +10,10 @@
 //   2. one batched explicit-residual pass (FP64 A.X, then the residual epilogue)
 //      over every system that needs one, per padded agent count,
 //   3. the starts of refinement inner solves (per system),
-//   4. k block steps over every stepping system: one batched A.D launch and one
-//      batched update launch per (precision, padded agent count) class,
+//   4. k block steps over every resident system, replayed from a captured graph:
+//      one batched A.D launch and one batched update launch per (precision, padded
+//      agent count, tile width) class (a step is a no-op for a system that is not
+//      running),
 // then reads every state header and moves each system through the same phases,
 // in the same order, as the single-system driver, so a system's result does not
 // depend on the systems it shares launches with.
@@ -148,6 +150,7 @@ struct Sys {
     int slot = -1;
     // problem
     int n = 0, p = 0, P = 0, prec = PREC_F64;
+    int cw_step = 2, cw_res = 2;   // A.D tile widths of the block step and the residual
     double tol = 0.0;
     int maxit = 0;
     ccg_opts o{};
@@ -170,9 +173,7 @@ struct Sys {
     int res_set_nb = 1;
     bool refine_due = false;    // X += E * scale this round
     bool inner_start_due = false;
-    bool stepping = false;
     int iter_before = 0;
-    bool running_before = false;
     // low-precision outer loop
     double nb = 1.0, best = 0.0;
     int iters = 0, refinements = 0, stall = 0;
@@ -192,7 +193,8 @@ struct Finished {
 
 class Engine {
   public:
-    Engine(int device, hipStream_t stream, size_t budget) : device_(device), s_(stream), arena_(budget) {
+    Engine(int device, hipStream_t stream, size_t budget, bool use_graph = true)
+        : device_(device), s_(stream), arena_(budget), use_graph_(use_graph) {
         HIP_OK(hipMalloc(&states_, sizeof(DevState) * kSlots));
         HIP_OK(hipMalloc(&d_ad_, sizeof(AdArgs) * kSlots));
         HIP_OK(hipMalloc(&d_res_ad_, sizeof(AdArgs) * kSlots));
@@ -210,8 +212,14 @@ class Engine {
         (void)hipFree(d_res_ad_);
         (void)hipFree(d_upd_);
         (void)hipFree(d_res_);
+        if (graph_) (void)hipGraphExecDestroy(graph_);
+        for (hipStream_t cs : class_streams_) (void)hipStreamDestroy(cs);
+        for (hipEvent_t ev : class_events_) (void)hipEventDestroy(ev);
+        if (fork_) (void)hipEventDestroy(fork_);
         if (d_items_) (void)hipFree(d_items_);
         if (h_items_) (void)hipHostFree(h_items_);
+        if (d_step_) (void)hipFree(d_step_);
+        if (h_step_) (void)hipHostFree(h_step_);
         (void)hipHostFree(h_states_);
     }
 
@@ -257,6 +265,8 @@ class Engine {
         sy.p = pr.p;
         sy.P = pad_agents(pr.p);
         sy.prec = o.prec == CCG_FP64 ? PREC_F64 : (o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
+        sy.cw_step = ad_cw(sy.prec, sy.P, pr.n);
+        sy.cw_res = ad_cw(PREC_F64, sy.P, pr.n);
         sy.tol = pr.tol;
         sy.maxit = pr.maxit;
         sy.o = o;
@@ -403,6 +413,7 @@ class Engine {
         sy.ra.D = sy.w.Dl;
         if (sy.slot + 1 > hi_slot_) hi_slot_ = sy.slot + 1;
         live_.push_back(sy);
+        items_dirty_ = true;
         return true;
     }
 
@@ -411,7 +422,11 @@ class Engine {
             if (sy.tag == tag) sy.cancel = true;
     }
 
-    // One host round (see the file comment); k block steps for stepping systems.
+    // One host round (see the file comment); k block steps for every resident system.
+    // The step work list holds every resident system, whatever its phase: a block
+    // step is a no-op for a system whose state is not RUNNING, so the list (and the
+    // graph captured from it) only changes when systems are admitted, or when the
+    // retired systems' items become a large share of it.
     void round(int k) {
         if (live_.empty()) return;
         // cancelled systems leave before any launch
@@ -419,52 +434,33 @@ class Engine {
             if (sy.cancel) retire(sy, CCG_CANCELLED);
         finish_retired();
         if (live_.empty()) return;
-        // --- work lists
+        if (items_dirty_ || dead_items_ * 8 > step_items_total_ || graph_k_ != k) rebuild_steps(k);
+        // --- explicit-residual work list
         items_.clear();
-        struct Range { int prec, P; size_t ad_off, ad_n, up_off, up_n; };
-        std::vector<Range> res_ranges, step_ranges;
+        struct Range { int P, cw; size_t ad_off, ad_n, up_off, up_n; };
+        std::vector<Range> res_ranges;
         for (int P : {1, 2, 4, 8, 16}) {
-            Range rr{PREC_F64, P, items_.size(), 0, 0, 0};
-            for (auto& sy : live_) {
-                if (!sy.res_due || sy.P != P) continue;
-                const int t = (sy.n + ad_tile_rows(PREC_F64, P) - 1) / ad_tile_rows(PREC_F64, P);
-                for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
-            }
-            rr.ad_n = items_.size() - rr.ad_off;
-            rr.up_off = items_.size();
-            for (auto& sy : live_) {
-                if (!sy.res_due || sy.P != P) continue;
-                const int t = sy.w.n_pad / (kWG / P);
-                for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, sy.res_mode, sy.res_set_nb});
-            }
-            rr.up_n = items_.size() - rr.up_off;
-            if (rr.ad_n) res_ranges.push_back(rr);
-        }
-        for (int prec : {PREC_F64, PREC_F32, PREC_BF16X2}) {
-            for (int P : {1, 2, 4, 8, 16}) {
-                Range sr{prec, P, items_.size(), 0, 0, 0};
+            for (int cw : {1, 2, 4}) {
+                Range rr{P, cw, items_.size(), 0, 0, 0};
                 for (auto& sy : live_) {
-                    if (!sy.stepping || sy.prec != prec || sy.P != P) continue;
-                    const int t = (sy.n + ad_tile_rows(prec, P) - 1) / ad_tile_rows(prec, P);
+                    if (!sy.res_due || sy.P != P || sy.cw_res != cw) continue;
+                    const int t = (sy.n + 4 * cw - 1) / (4 * cw);
                     for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
                 }
-                sr.ad_n = items_.size() - sr.ad_off;
-                sr.up_off = items_.size();
+                rr.ad_n = items_.size() - rr.ad_off;
+                rr.up_off = items_.size();
                 for (auto& sy : live_) {
-                    if (!sy.stepping || sy.prec != prec || sy.P != P) continue;
+                    if (!sy.res_due || sy.P != P || sy.cw_res != cw) continue;
                     const int t = sy.w.n_pad / (kWG / P);
-                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, sy.res_mode, sy.res_set_nb});
                 }
-                sr.up_n = items_.size() - sr.up_off;
-                if (sr.ad_n) step_ranges.push_back(sr);
+                rr.up_n = items_.size() - rr.up_off;
+                if (rr.ad_n) res_ranges.push_back(rr);
             }
         }
         upload_items();
         // --- state headers (host decisions of the previous round)
-        for (auto& sy : live_) {
-            sy.iter_before = h_states_[sy.slot].iter;
-            sy.running_before = h_states_[sy.slot].done == RUNNING;
-        }
+        for (auto& sy : live_) sy.iter_before = h_states_[sy.slot].iter;
         HIP_OK(hipMemcpy2DAsync(states_, sizeof(DevState), h_states_, sizeof(DevState), kHeader, hi_slot_,
                                 hipMemcpyHostToDevice, s_));
         // 1. refinement corrections
@@ -472,20 +468,17 @@ class Engine {
             if (sy.refine_due) HIP_OK(launch_refine_add(sy.ra, s_));
         // 2. explicit residuals
         for (const Range& r : res_ranges) {
-            HIP_OK(launch_ad_batch(PREC_F64, r.P, d_res_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
+            HIP_OK(launch_ad_batch(PREC_F64, r.P, r.cw, d_res_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
             HIP_OK(launch_res_batch(r.P, d_res_, d_items_ + r.up_off, (int)r.up_n, s_));
         }
         // 3. inner-solve starts
         for (auto& sy : live_)
             if (sy.inner_start_due) HIP_OK(launch_inner_init(sy.ra, s_));
         // 4. block steps
-        if (!step_ranges.empty()) {
-            for (int it = 0; it < k; ++it) {
-                for (const Range& r : step_ranges) {
-                    HIP_OK(launch_ad_batch(r.prec, r.P, d_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
-                    HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_items_ + r.up_off, (int)r.up_n, s_));
-                }
-            }
+        if (graph_) {
+            HIP_OK(hipGraphLaunch(graph_, s_));
+        } else {
+            for (int it = 0; it < k; ++it) enqueue_step_ranges();
         }
         HIP_OK(hipMemcpy2DAsync(h_states_, sizeof(DevState), states_, sizeof(DevState), kHeader, hi_slot_,
                                 hipMemcpyDeviceToHost, s_));
@@ -494,9 +487,9 @@ class Engine {
 #ifdef CCG_ENGINE_TRACE
         for (auto& sy : live_) {
             const DevState& h = h_states_[sy.slot];
-            fprintf(stderr, "round slot %d n %d P %d ph %d res %d/%d step %d | done %d iter %d minres %.3e nb %.3e mask %x\n",
-                    sy.slot, sy.n, sy.P, (int)sy.ph, (int)sy.res_due, sy.res_mode, (int)sy.stepping, h.done, h.iter,
-                    h.minres, h.nb, h.mask);
+            fprintf(stderr, "round slot %d n %d P %d ph %d res %d/%d | done %d iter %d minres %.3e nb %.3e mask %x\n",
+                    sy.slot, sy.n, sy.P, (int)sy.ph, (int)sy.res_due, sy.res_mode, h.done, h.iter, h.minres, h.nb,
+                    h.mask);
         }
 #endif
         for (auto& sy : live_) advance(sy);
@@ -514,16 +507,15 @@ class Engine {
         DevState& h = h_states_[sy.slot];
         const double nn = (double)sy.n * sy.n;
         const double s_step = sy.prec == PREC_F64 ? 8.0 : 4.0;
-        if (sy.stepping) {
-            const int streamed = (h.iter - sy.iter_before) + (sy.running_before && h.done != RUNNING ? 1 : 0);
-            sy.bytes += s_step * nn * streamed;
-        }
+        // A.D launches that streamed A: one per completed step, plus the one whose
+        // stop test ended the steps
+        const bool stopped = h.done == RECUR_CONV || (h.done == MAXIT && h.iter > sy.iter_before);
+        sy.bytes += s_step * nn * ((h.iter - sy.iter_before) + (stopped ? 1 : 0));
         if (sy.res_due) sy.bytes += 8.0 * nn;
         const bool had_res = sy.res_due;
         sy.res_due = false;
         sy.refine_due = false;
         sy.inner_start_due = false;
-        sy.stepping = false;
         if (sy.prec == PREC_F64) {
             switch (sy.ph) {
                 case PH_INIT_RES:
@@ -531,7 +523,6 @@ class Engine {
                 case PH_STEP:
                     if (h.done == RUNNING) {
                         sy.ph = PH_STEP;
-                        sy.stepping = true;
                     } else if (h.done == RECUR_CONV) {
                         sy.ph = PH_CONFIRM;
                         due_res(sy, RES_CONFIRM, 0);
@@ -558,10 +549,7 @@ class Engine {
                 decide(sy);
                 break;
             case PH_INNER:
-                if (h.done == RUNNING) {
-                    sy.stepping = true;
-                    break;
-                }
+                if (h.done == RUNNING) break;
                 sy.iters += h.iter;
                 if (h.done == FAILED) {
                     retire(sy, (ccg_status)h.status);
@@ -602,7 +590,7 @@ class Engine {
     void decide(Sys& sy) {
         DevState& h = h_states_[sy.slot];
         if (h.done == FAILED) { retire(sy, (ccg_status)h.status); return; }
-        if (h.done != RUNNING) { retire(sy, CCG_OK); return; }
+        if (h.done != OUTER) { retire(sy, CCG_OK); return; }
         if (sy.refinements >= sy.o.max_refine || sy.iters >= sy.maxit) {
             retire(sy, CCG_NOT_CONVERGED);
             return;
@@ -622,7 +610,6 @@ class Engine {
         h.nb = 1.0;
         h.maxit = std::min(sy.o.inner_maxit, sy.maxit - sy.iters);
         sy.inner_start_due = true;
-        sy.stepping = true;
         sy.ph = PH_INNER;
     }
 
@@ -670,7 +657,11 @@ class Engine {
                                     sizeof(double) * sy.n, sy.p, hipMemcpyDeviceToHost, s_));
         retiring_.push_back(Finished{sy.tag, st, info});
         retiring_mem_.push_back(sy.mem);
-        free_slots_.push_back(sy.slot);
+        // the slot may still have items in the step work list: its steps must stay
+        // no-ops, and the slot is reused only after the list is rebuilt
+        h.done = FINISHED;
+        pending_slots_.push_back(sy.slot);
+        dead_items_ += (size_t)((sy.n + 4 * sy.cw_step - 1) / (4 * sy.cw_step));
         sy.slot = -1;
     }
 
@@ -691,6 +682,118 @@ class Engine {
                     live_.end());
         hi_slot_ = 0;
         for (auto& sy : live_) hi_slot_ = std::max(hi_slot_, sy.slot + 1);
+        for (int sl : pending_slots_) hi_slot_ = std::max(hi_slot_, sl + 1);
+    }
+
+    // Step work list of every resident system, by (precision, P, tile width) class;
+    // uploaded once and captured with k steps into a graph.
+    void rebuild_steps(int k) {
+        for (int sl : pending_slots_) free_slots_.push_back(sl);
+        pending_slots_.clear();
+        hi_slot_ = 0;
+        for (auto& sy : live_) hi_slot_ = std::max(hi_slot_, sy.slot + 1);
+        if (graph_) {
+            HIP_OK(hipGraphExecDestroy(graph_));
+            graph_ = nullptr;
+        }
+        std::vector<int4> st;
+        step_ranges_.clear();
+        step_items_total_ = 0;
+        for (int prec : {PREC_F64, PREC_F32, PREC_BF16X2}) {
+            for (int P : {1, 2, 4, 8, 16}) {
+                for (int cw : {1, 2, 4}) {
+                    StepRange r{prec, P, cw, st.size(), 0, 0, 0};
+                    for (auto& sy : live_) {
+                        if (sy.prec != prec || sy.P != P || sy.cw_step != cw) continue;
+                        const int t = (sy.n + 4 * cw - 1) / (4 * cw);
+                        for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
+                    }
+                    r.ad_n = st.size() - r.ad_off;
+                    r.up_off = st.size();
+                    for (auto& sy : live_) {
+                        if (sy.prec != prec || sy.P != P || sy.cw_step != cw) continue;
+                        const int t = sy.w.n_pad / (kWG / P);
+                        for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
+                    }
+                    r.up_n = st.size() - r.up_off;
+                    if (r.ad_n) {
+                        step_ranges_.push_back(r);
+                        step_items_total_ += r.ad_n;
+                    }
+                }
+            }
+        }
+        const size_t n = std::max<size_t>(st.size(), 1);
+        if (n > step_cap_) {
+            if (d_step_) (void)hipFree(d_step_);
+            if (h_step_) (void)hipHostFree(h_step_);
+            d_step_ = nullptr;
+            h_step_ = nullptr;
+            step_cap_ = 0;
+            const size_t cap = std::max<size_t>(n * 2, 1 << 16);
+            HIP_OK(hipMalloc(&d_step_, sizeof(int4) * cap));
+            HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&h_step_), sizeof(int4) * cap, hipHostMallocDefault));
+            step_cap_ = cap;
+        }
+        if (!st.empty()) {
+            std::memcpy(h_step_, st.data(), sizeof(int4) * st.size());
+            HIP_OK(hipMemcpyAsync(d_step_, h_step_, sizeof(int4) * st.size(), hipMemcpyHostToDevice, s_));
+        }
+        items_dirty_ = false;
+        dead_items_ = 0;
+        graph_k_ = k;
+        if (!use_graph_ || step_ranges_.empty()) return;
+        // Classes touch disjoint systems, so each class's k steps form an independent
+        // chain: the graph forks one branch per class (streams of default priority)
+        // and the branches run concurrently, overlapping one class's reduction tail
+        // with another's stream of A.
+        while (class_streams_.size() < step_ranges_.size()) {
+            hipStream_t cs = nullptr;
+            HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            class_streams_.push_back(cs);
+            hipEvent_t ev = nullptr;
+            HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            class_events_.push_back(ev);
+        }
+        if (!fork_) HIP_OK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+        hipGraph_t gr = nullptr;
+        HIP_OK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+        bool ok = true;
+        try {
+            HIP_OK(hipEventRecord(fork_, s_));
+            for (size_t c = 0; c < step_ranges_.size(); ++c) {
+                hipStream_t cs = class_streams_[c];
+                HIP_OK(hipStreamWaitEvent(cs, fork_, 0));
+                const StepRange& r = step_ranges_[c];
+                for (int it = 0; it < k; ++it) {
+                    HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
+                    HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
+                }
+                HIP_OK(hipEventRecord(class_events_[c], cs));
+                HIP_OK(hipStreamWaitEvent(s_, class_events_[c], 0));
+            }
+        } catch (const CcgError&) {
+            ok = false;
+        }
+        const hipError_t e = hipStreamEndCapture(s_, &gr);
+        if (!ok || e != hipSuccess || !gr) {
+            (void)hipGetLastError();
+            if (gr) (void)hipGraphDestroy(gr);
+            throw CcgError{CCG_ERR_DEVICE, "stream capture of the batched block steps failed"};
+        }
+        const hipError_t ei = hipGraphInstantiate(&graph_, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess) {
+            graph_ = nullptr;
+            throw CcgError{CCG_ERR_DEVICE, "instantiating the batched block-step graph failed"};
+        }
+    }
+
+    void enqueue_step_ranges() {
+        for (const StepRange& r : step_ranges_) {
+            HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, s_));
+            HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, s_));
+        }
     }
 
     void upload_items() {
@@ -724,6 +827,24 @@ class Engine {
     int4* h_items_ = nullptr;
     size_t items_cap_ = 0;
     std::vector<int4> items_;
+    struct StepRange {
+        int prec, P, cw;
+        size_t ad_off, ad_n, up_off, up_n;
+    };
+    std::vector<StepRange> step_ranges_;
+    int4* d_step_ = nullptr;
+    int4* h_step_ = nullptr;
+    size_t step_cap_ = 0;
+    bool use_graph_ = true;
+    hipGraphExec_t graph_ = nullptr;
+    int graph_k_ = 0;
+    std::vector<hipStream_t> class_streams_;
+    std::vector<hipEvent_t> class_events_;
+    hipEvent_t fork_ = nullptr;
+    bool items_dirty_ = true;
+    size_t dead_items_ = 0;
+    size_t step_items_total_ = 0;
+    std::vector<int> pending_slots_;
     std::vector<int> free_slots_;
     int hi_slot_ = 0;
     std::vector<Sys> live_;
@@ -915,7 +1036,8 @@ ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, cc
     ccg_status first_err = CCG_OK;
     bool any_nc = false;
     const ccg_status st = guarded(c, [&]() -> ccg_status {
-        Engine eng(c->device, c->stream, c->budget);
+        const bool graphs = !(count > 0 && (probs[0].opts.flags & CCG_NO_GRAPH));
+        Engine eng(c->device, c->stream, c->budget, graphs);
         std::deque<int> queue;
         for (int i = 0; i < count; ++i) queue.push_back(i);
         auto record = [&](int i, ccg_status s, const ccg_info* inf) {

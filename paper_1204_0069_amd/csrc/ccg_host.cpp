@@ -425,7 +425,7 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
     ra.E = w.E;
     ra.R = w.Rl;
     ra.D = w.Dl;
-    while (h.done == RUNNING) {
+    while (h.done == OUTER) {
         if (refinements >= o.max_refine || iters >= maxit) { st = CCG_NOT_CONVERGED; break; }
         // inner solve on A E = T (unit columns)
         unsigned mask = 0u;
@@ -633,6 +633,53 @@ ccg_status ccg_convert_matrix(ccg_ctx* c, int n, const double* A, int64_t lda, i
         if (prec == CCG_BF16X2 && !lo) throw CcgError{CCG_ERR_ARG, "BF16X2 needs the lo plane"};
         HIP_OK(launch_convert(prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2, n, A, lda, hi, lo, n, c->stream));
         HIP_OK(hipStreamSynchronize(c->stream));
+        return CCG_OK;
+    });
+}
+
+ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int reps, double* us) {
+    return guarded(c, [&]() -> ccg_status {
+        if (n < 1 || p < 1 || p > kMaxP || p > n || reps < 1 || !us || (cw != 1 && cw != 2 && cw != 4))
+            throw CcgError{CCG_ERR_ARG, "bad tuning argument"};
+        if (prec != CCG_FP64 && prec != CCG_FP32 && prec != CCG_BF16X2) throw CcgError{CCG_ERR_ARG, "bad precision"};
+        const int pr = prec == CCG_FP64 ? PREC_F64 : (prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
+        const int P = pad_agents(p);
+        const int64_t lda = round_up(n, 2);
+        double* A = nullptr;
+        if (hipMalloc(&A, sizeof(double) * (size_t)lda * n) != hipSuccess)
+            throw CcgError{CCG_ERR_NOMEM, "tuning matrix allocation failed"};
+        struct Free {
+            double* p;
+            ~Free() { (void)hipFree(p); }
+        } fa{A};
+        HIP_OK(launch_tune_matrix(n, A, lda, c->stream));
+        ensure_workspace(c, n, P);
+        Workspace& w = c->ws;
+        const int64_t blk = (int64_t)w.n_pad * P;
+        HIP_OK(launch_tune_vectors(blk, w.D, w.Dl, 1u, c->stream));
+        HIP_OK(launch_tune_vectors(blk, w.R, w.Rl, 2u, c->stream));
+        const LowCopy lc = pr == PREC_F64 ? LowCopy{A, nullptr, lda, 0.0} : low_copy(c, n, A, lda, pr);
+        Solve s{c, n, p, P, pr, lc.hi, lc.lo, lc.ld, A, lda, false};
+        DevState& h = *c->st_host;
+        std::memset(&h, 0, sizeof(DevState));
+        h.done = RUNNING;
+        set_all_agents(h, p);
+        h.maxit = 1 << 30;
+        h.tol = 0.0;           // the stop test never passes: every launch runs in full
+        h.tau = 1e-14;
+        h.nb = 1.0;
+        write_state(c);
+        hipEvent_t e0 = pooled_event(c, 0), e1 = pooled_event(c, 1);
+        const AdArgs a = ad_args(s, false);
+        double tot = 0.0;
+        for (int i = 0; i < reps + 2; ++i) {
+            HIP_OK(launch_ad_cw(pr, P, cw, a, c->stream, e0, e1));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (i >= 2) tot += ms;
+        }
+        *us = tot * 1e3 / reps;
         return CCG_OK;
     });
 }

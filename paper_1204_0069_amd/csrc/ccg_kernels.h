@@ -1,0 +1,1051 @@
+// Device templates of the block step, shared by the kernel translation units:
+// precision traits, the A.D tile (k_ad / k_ad_batch), the update (k_upd), the
+// residual epilogue (k_res) and their helpers.  The kernels are instantiated per
+// precision in ccg_ad_f64.hip, ccg_ad_f32.hip and ccg_ad_bf16.hip (A.D) and in
+// ccg_kernels.hip (the rest), which compile in parallel.
+#pragma once
+
+// HIP kernels (gfx950) for the block step of cooperative conjugate gradient.
+//
+// One block step (Alg. 2 of the paper, sign convention R = B - A X, residual by
+// the Table 1 recurrence) is two launches:
+//
+//   k_ad   : AD = A D, streaming A once.  A is symmetric, so column i of A (which is
+//            contiguous in the column-major layout) is row i: each wave streams
+//            whole columns with 16-byte non-temporal loads, its lanes splitting the
+//            contraction index k, and multiplies them with D rows staged in LDS
+//            (double buffered).  Lane sums are folded by a fixed xor butterfly, so
+//            every AD row is complete inside one wave: no split-K partials.  Each
+//            workgroup adds its rows' share of five p x p products (D^T AD, AD^T R,
+//            AD^T AD, D^T R, R^T R); a two-level fixed-order reduction across
+//            workgroups ends in the last workgroup, which runs the stop test on the
+//            residual norms, the rank step of Alg. 3, alpha = G^{-1} D^T R and
+//            beta = -G^{-1} (AD)^T R_new with (AD)^T R_new = AD^T R - AD^T AD alpha
+//            (all FP64).
+//   k_upd  : X += D alpha, R -= AD alpha, D = R + D beta (masked to active agents).
+//
+#include "ccg_device.h"
+
+#include <hip/hip_ext.h>
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace ccg {
+
+// ----------------------------------------------------------------- precision traits
+
+template <int PREC> struct PT;
+template <> struct PT<PREC_F64> {
+    using TA = double;   // stored A element
+    using TV = double;   // vector element (X, R, D, AD)
+    using TACC = double; // accumulator of A.D
+    static constexpr int E = 2;   // elements per 16-byte load
+};
+template <> struct PT<PREC_F32> {
+    using TA = float;
+    using TV = float;
+    using TACC = float;
+    static constexpr int E = 4;
+};
+template <> struct PT<PREC_BF16X2> {
+    using TA = uint16_t;
+    using TV = float;
+    using TACC = float;
+    static constexpr int E = 8;
+};
+
+// Tile configuration of the A.D kernel: CW A columns per wave (4 waves per
+// workgroup, so 4*CW AD rows per workgroup), SPC wave steps of 64*E contraction
+// elements per staged D chunk, an occupancy hint MINW (waves per SIMD) and
+// non-temporal A loads (A is read exactly once per launch).
+// STG rotates each workgroup's starting chunk so that concurrent workgroups read
+// different offsets of their columns (the column stride is a large power of two).
+template <int CW_, int SPC_, int MINW_, bool NT_, bool STG_ = false>
+struct AdCfg {
+    static constexpr int CW = CW_;
+    static constexpr int SPC = SPC_;
+    static constexpr int MINW = MINW_;
+    static constexpr bool NT = NT_;
+    static constexpr bool STG = STG_;
+    static constexpr int ROWS = 4 * CW_;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// Load the E elements of one 16-byte chunk of a column, converted to TACC.  hi
+// points into the FP64 / FP32 matrix or the BF16 "hi" plane, lo into the BF16 "lo"
+// plane at the same offset.  NT selects non-temporal (streaming) loads.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+template <bool NT, class T>
+__device__ __forceinline__ T ld16(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <int PREC, bool NT> struct Loader;
+
+template <bool NT> struct Loader<PREC_F64, NT> {
+    __device__ __forceinline__ static void load(const double* hi, const double*, double (&out)[2]) {
+        const d2v v = ld16<NT>(reinterpret_cast<const d2v*>(hi));
+        out[0] = v.x;
+        out[1] = v.y;
+    }
+    __device__ __forceinline__ static double load1(const double* hi, const double*) { return *hi; }
+};
+template <bool NT> struct Loader<PREC_F32, NT> {
+    __device__ __forceinline__ static void load(const float* hi, const float*, float (&out)[4]) {
+        const f4v v = ld16<NT>(reinterpret_cast<const f4v*>(hi));
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    }
+    __device__ __forceinline__ static float load1(const float* hi, const float*) { return *hi; }
+};
+template <bool NT> struct Loader<PREC_BF16X2, NT> {
+    __device__ __forceinline__ static void load(const uint16_t* hi, const uint16_t* lo, float (&out)[8]) {
+        const u4v h = ld16<NT>(reinterpret_cast<const u4v*>(hi));
+        const u4v l = ld16<NT>(reinterpret_cast<const u4v*>(lo));
+        const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+        const uint32_t lw[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            // hi + lo is exact in FP32: both carry 8 significant bits, lo below hi.
+            out[2 * q] = __uint_as_float(hw[q] << 16) + __uint_as_float(lw[q] << 16);
+            out[2 * q + 1] = __uint_as_float(hw[q] & 0xffff0000u) + __uint_as_float(lw[q] & 0xffff0000u);
+        }
+    }
+    __device__ __forceinline__ static float load1(const uint16_t* hi, const uint16_t* lo) {
+        return bf16_to_f32(*hi) + bf16_to_f32(*lo);
+    }
+};
+
+// ------------------------------------------------------ cross-workgroup reduction
+
+__device__ __forceinline__ void st_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ticket(unsigned* c) {
+    return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void reset_ticket(unsigned* c) {
+    __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory operation this thread issued is acknowledged.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Sum, for entry e, the rows m0 .. m0+cnt-1 of src (row stride ne) in row order.
+// Loads are issued in unrolled batches of 16 so that their latencies overlap.
+__device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int m0, int cnt) {
+    double s = 0.0;
+    for (int base = 0; base < cnt; base += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = (base + q < cnt) ? ld_agent(&src[(int64_t)(m0 + base + q) * ne + e]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (base + q < cnt) s += v[q];
+    }
+    return s;
+}
+
+// out[e] = sum over rows 0..cnt-1 of src (row stride ne), for every e < ne, with the
+// rows of each entry split into contiguous slices over spare threads and the slice
+// sums added in slice order (a fixed tree).  scratch: kWG doubles of LDS.
+__device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
+    const int tid = threadIdx.x;
+    const int tpe = ne >= kWG ? 1 : kWG / ne;          // threads per entry
+    const int slice = (cnt + tpe - 1) / tpe;
+    for (int e0 = 0; e0 < ne; e0 += kWG / tpe) {
+        const int e = e0 + tid / tpe, sub = tid % tpe;
+        double s = 0.0;
+        if (e < ne && tid / tpe < kWG / tpe) {
+            const int m0 = sub * slice;
+            s = sum_rows(src, ne, e, m0, max(0, min(slice, cnt - m0)));
+        }
+        scratch[tid] = s;
+        __syncthreads();
+        if (sub == 0 && e < ne && tid / tpe < kWG / tpe) {
+            double t = scratch[tid];
+            for (int q = 1; q < tpe; ++q) t += scratch[tid + q];
+            out[e] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Sum `ne` values per tile (mine[], LDS) over the nwg tiles of one system, in tile
+// order within groups of kGroup and in group order across groups.  Returns true in
+// the one workgroup that ends up holding the totals in out[] (LDS).  Tickets are
+// reset by their last taker, so the scratch is ready for the next launch.
+__device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const RedBuf rb, double* out,
+                                            int* s_flag, double* scratch, int bid, int nwg) {
+    const int tid = threadIdx.x;
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    const int grp = bid / kGroup;
+    const int gsize = min(kGroup, nwg - grp * kGroup);
+    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
+    stores_done();
+    __syncthreads();
+    if (tid == 0) *s_flag = (ticket(&rb.cnt[grp]) == (unsigned)gsize - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid == 0) reset_ticket(&rb.cnt[grp]);
+    if (ngroups == 1) {
+        sum_table(rb.l1, ne, gsize, out, scratch);
+        return true;
+    }
+    // group sum -> level-2 row of this group
+    sum_table(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
+    stores_done();
+    __syncthreads();
+    if (tid == 0) *s_flag = (ticket(&rb.cnt[ngroups]) == (unsigned)ngroups - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
+    sum_table(rb.l2, ne, ngroups, out, scratch);
+    return true;
+}
+
+// ------------------------------------------------------------ small p x p algebra
+//
+// Executed by all threads of one workgroup on LDS arrays (m <= 16), with barriers
+// between dependent phases.  Compact m x m matrices are row-major with stride m.
+
+// Greedy pivoted Cholesky of the diagonally scaled G (unit diagonal).  Writes the
+// taken compact indices, ascending, to keep[]; returns their count, or -1 when a
+// diagonal entry is negative, -2 on a non-finite entry.  Columns with G_ii == 0 are
+// never taken.  Same rule as the oracle's rank step.
+__device__ __forceinline__ int wg_rank_select(const double* G, int m, double tau, int* keep, double* H, int* sh) {
+    const int tid = threadIdx.x;
+    // sh[0]: status, sh[1]: ncand, sh[2]: ntaken, sh[3]: pivot (or -1 to stop)
+    // sh[8..8+m): candidate list, sh[32..32+m): taken list
+    if (tid == 0) {
+        int st = 0;
+        for (int i = 0; i < m && st == 0; ++i) {
+            const double g = G[i * m + i];
+            if (!isfinite(g)) st = -2;
+            else if (g < 0.0) st = -1;
+        }
+        for (int i = 0; i < m * m && st == 0; ++i)
+            if (!isfinite(G[i])) st = -2;
+        sh[0] = st;
+    }
+    __syncthreads();
+    if (sh[0] != 0) return sh[0];
+    if (tid < m * m) {
+        const int i = tid / m, j = tid % m;
+        const double si = sqrt(G[i * m + i]), sj = sqrt(G[j * m + j]);
+        H[tid] = (si > 0.0 && sj > 0.0) ? G[tid] / (si * sj) : 0.0;
+    }
+    if (tid == 0) {
+        int nc = 0;
+        for (int i = 0; i < m; ++i)
+            if (G[i * m + i] > 0.0) sh[8 + nc++] = i;
+        sh[1] = nc;
+        sh[2] = 0;
+    }
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) {
+            const int nc = sh[1];
+            int piv = -1;
+            if (nc > 0) {
+                int best = 0;
+                for (int c = 1; c < nc; ++c)
+                    if (H[sh[8 + c] * m + sh[8 + c]] > H[sh[8 + best] * m + sh[8 + best]]) best = c;
+                const int cand = sh[8 + best];
+                const double d = H[cand * m + cand];
+                if (d > tau) {
+                    piv = cand;
+                    sh[32 + sh[2]] = cand;
+                    sh[2] += 1;
+                    for (int c = best; c + 1 < nc; ++c) sh[8 + c] = sh[8 + c + 1];
+                    sh[1] = nc - 1;
+                }
+            }
+            sh[3] = piv;
+        }
+        __syncthreads();
+        const int piv = sh[3];
+        if (piv < 0) break;
+        const int nc = sh[1];
+        const double r = sqrt(H[piv * m + piv]);
+        double upd = 0.0;
+        int ia = -1, ic = -1;
+        if (tid < nc * nc) {
+            ia = sh[8 + tid / nc];
+            ic = sh[8 + tid % nc];
+            const double lc = H[ic * m + piv] / r;
+            const double la = H[ia * m + piv] / r;
+            upd = H[ic * m + ia] - lc * la;
+        }
+        __syncthreads();
+        if (ia >= 0) H[ic * m + ia] = upd;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int nt = sh[2];
+        for (int a = 0; a < nt; ++a)
+            for (int c = a + 1; c < nt; ++c)
+                if (sh[32 + c] < sh[32 + a]) { const int t = sh[32 + a]; sh[32 + a] = sh[32 + c]; sh[32 + c] = t; }
+        for (int a = 0; a < nt; ++a) keep[a] = sh[32 + a];
+    }
+    __syncthreads();
+    return sh[2];
+}
+
+__device__ __forceinline__ void fail_state(DevState* st, int code) {
+    st->done = FAILED;
+    st->status = code;
+}
+
+// ------------------------------------------------ one-wave p x p algebra
+//
+// The Cholesky factor is formed with lane a holding row a of the matrix in
+// registers, the other lanes' values read with v_readlane (uniform, no LDS round
+// trip).  The triangular solves then run one right-hand side per lane, entirely in
+// that lane's registers, with the factor read from LDS (uniform addresses, so
+// every lane gets the same broadcast value).  Inactive agents are identity rows and
+// columns, so every loop runs over the compile-time P.
+
+__device__ __forceinline__ double bcast(double v, int src_lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src_lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src_lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// In-place Cholesky of the rows g (lane = row; lanes >= P hold padding): g becomes
+// row `lane` of L in its lower part.  Each L entry is formed from the same products,
+// in the same order, as the plain left-looking recurrence.  Returns false (uniform)
+// on a pivot <= 0 or NaN.
+template <int P>
+__device__ __forceinline__ bool row_cholesky(double (&g)[P], int lane) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const double djj = bcast(g[j], j);
+        if (!(djj > 0.0)) return false;
+        const double ljj = sqrt(djj);
+        if (lane > j) g[j] = g[j] / ljj;
+        else if (lane == j) g[j] = ljj;
+#pragma unroll
+        for (int b = j + 1; b < P; ++b) {
+            const double lbj = bcast(g[j], b);
+            if (lane > j) g[b] = g[b] - g[j] * lbj;
+        }
+    }
+    return true;
+}
+
+// Row `lane` of src (row stride lds) with inactive rows / columns replaced by the
+// identity (identity == true) or by zero.
+template <int P>
+__device__ __forceinline__ void row_load(double (&r)[P], const double* src, int lds, unsigned mask,
+                                         bool identity, int lane) {
+    const int a = lane < P ? lane : 0;
+    const bool ra = (mask >> a) & 1u;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+        const bool on = ra && ((mask >> b) & 1u);
+        r[b] = on ? src[a * lds + b] : ((identity && a == b) ? 1.0 : 0.0);
+    }
+}
+
+// The same for a right-hand side kept in LDS (element i at Y[i * P + c], column c
+// owned by this lane), with rolled loops: the register-resident form does not fit
+// the register budget at P = 16.
+template <int P>
+__device__ __forceinline__ void col_chol_solve_lds(const double* L, const double* rinv, double* Y, int c) {
+#pragma unroll 1
+    for (int i = 0; i < P; ++i) {
+        double s = Y[i * P + c];
+        for (int k = 0; k < i; ++k) s -= L[i * P + k] * Y[k * P + c];
+        Y[i * P + c] = s * rinv[i];
+    }
+#pragma unroll 1
+    for (int i = P - 1; i >= 0; --i) {
+        double s = Y[i * P + c];
+        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * Y[k * P + c];
+        Y[i * P + c] = s * rinv[i];
+    }
+}
+
+// y <- (L L^T)^{-1} y for one right-hand side held by this lane.  L is row-major
+// (stride P) in LDS, rinv[i] = 1 / L[i][i].  Forward then backward substitution in
+// the textbook order; each pivot divides through its reciprocal.
+template <int P>
+__device__ __forceinline__ void col_chol_solve(const double* L, const double* rinv, double (&y)[P]) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
+        y[i] = s * rinv[i];
+    }
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * y[k];
+        y[i] = s * rinv[i];
+    }
+}
+
+// Fold M = 2^q values held by every lane of a wave into sums over the 64 lanes:
+// each xor round with offset o keeps one half of the live values and adds the
+// partner's copy of it, until one value per lane remains, then plain xor adds.
+// Returns the index (0..M-1) of the total this lane holds in v[0].
+// (the halving is unrolled by recursion over compile-time counts, so every array
+// index is a constant and v stays in registers)
+template <int M, int O, class T>
+struct Fold {
+    __device__ static __forceinline__ void run(T* v, int lane, int& idx) {
+        if constexpr (O >= 1) {
+            if constexpr (M > 1) {
+                constexpr int h = M / 2;
+                const bool up = (lane & O) != 0;
+#pragma unroll
+                for (int q = 0; q < h; ++q) {
+                    const T send = up ? v[q] : v[q + h];
+                    const T keep = up ? v[q + h] : v[q];
+                    v[q] = keep + __shfl_xor(send, O);
+                }
+                if (up) idx += h;
+                Fold<h, O / 2, T>::run(v, lane, idx);
+            } else {
+                v[0] += __shfl_xor(v[0], O);
+                Fold<1, O / 2, T>::run(v, lane, idx);
+            }
+        }
+    }
+};
+
+template <int M, class T>
+__device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
+    int idx = 0;
+    Fold<M, 32, T>::run(v, lane, idx);
+    return idx;
+}
+
+// ============================================================== k_ad: AD = A D
+
+// One tile (4 * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
+template <int PREC, int P, class CFG>
+__device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const int ntiles) {
+    using TA = typename PT<PREC>::TA;
+    using TV = typename PT<PREC>::TV;
+    using TACC = typename PT<PREC>::TACC;
+    constexpr int E = PT<PREC>::E;
+    constexpr int KSTEP = 64 * E;
+    constexpr int SPC = CFG::SPC;             // wave steps per chunk
+    constexpr int KC = SPC * KSTEP;
+    constexpr int kCW = CFG::CW;
+    constexpr int kAdCols = CFG::ROWS;
+    constexpr bool NT = CFG::NT;
+    constexpr int NV = kCW * P;               // lane sums per wave
+    constexpr int PER = P * KC / kWG;         // staged D values per thread per chunk
+    static_assert(P * KC % kWG == 0, "chunk staging must split evenly");
+    static_assert(NV <= 64, "lane sums per wave");
+    static_assert(512 % KC == 0, "chunks must tile the padded length");
+
+    __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
+    __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
+    __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
+    __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
+    __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
+    __shared__ double gtot[P * (P + 1) + 2 * P * P + P];    // grid totals (last workgroup)
+    __shared__ double sm[4 * kMaxP * kMaxP];
+    __shared__ double gscr[kWG];
+    __shared__ int ish[128];
+
+    if (!a.product_only && a.st->done != RUNNING) return;
+    // state the last workgroup needs, read now so that its latency hides under the
+    // stream (the previous launches have finished writing it)
+    const unsigned mask0 = a.st->mask;
+    const double nb0 = a.st->nb, tol0 = a.st->tol, tau0 = a.st->tau;
+    const int iter0 = a.st->iter, maxit0 = a.st->maxit, m0 = a.st->m;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n;
+    const int i0 = tile * kAdCols;                        // first AD row of the workgroup
+    const int iw = i0 + wave * kCW;                       // first row of this wave
+    const TV* __restrict__ V = static_cast<const TV*>(a.V);
+    const int64_t lda = a.lda;
+    const TA* colhi[kCW];
+    const TA* collo[kCW];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c) {
+        const int i = min(iw + c, n - 1);                 // rows >= n compute a copy, never stored
+        colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
+        collo[c] = (PREC == PREC_BF16X2) ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
+    }
+
+    TACC acc[kCW][P];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
+
+    const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
+    // first chunk of this workgroup (rotated when staggering); chunks then wrap
+    const int c0 = CFG::STG ? (int)(((unsigned)tile * 7u) % (unsigned)nch) : 0;
+    TV pre[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * kWG;
+        const int j = idx / KC, kk = idx - (idx / KC) * KC;
+        pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) dch[0][tid + q * kWG] = pre[q];
+    __syncthreads();
+
+    for (int it = 0; it < nch; ++it) {
+        const int buf = it & 1;
+        int ch = c0 + it;
+        if (ch >= nch) ch -= nch;
+        const int k0 = ch * KC;
+        const bool more = it + 1 < nch;
+        if (more) {
+            const int nx = (ch + 1 < nch) ? ch + 1 : 0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = tid + q * kWG;
+                const int j = idx / KC, kk = idx - (idx / KC) * KC;
+                pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
+            }
+        }
+        const TV* dc = dch[buf];
+        if (k0 + KC <= n) {
+#pragma unroll
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
+#pragma unroll
+                for (int c = 0; c < kCW; ++c) Loader<PREC, NT>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        } else {
+            // last, partial chunk: element loads guarded by k < n
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
+#pragma unroll
+                for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC, NT>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
+                                                     : TACC(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) dch[buf ^ 1][tid + q * kWG] = pre[q];
+        }
+        __syncthreads();
+    }
+
+    // ---- lane sums -> complete AD rows (fixed butterfly order)
+    TACC v[NV];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
+    const int idx = wave_fold<NV>(v, lane);
+    constexpr int REP = 64 / NV;             // lanes holding the same total
+    if (lane % REP == 0) {
+        const int c = idx / P, j = idx - (idx / P) * P;
+        const int i = iw + c;
+        const TV y = TV(v[0]);
+        if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
+        adt[(wave * kCW + c) * kMaxP + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
+    }
+    if (a.product_only) return;
+
+    // ---- the workgroup's share of the products over its rows, packed as
+    //   G = D^T AD (lower triangle), Z = AD^T R, Y = AD^T AD (lower triangle),
+    //   S = D^T R, and the diagonal of R^T R
+    const TV* __restrict__ Rv = static_cast<const TV*>(a.R);
+    for (int t = tid; t < kAdCols * P; t += kWG) {
+        const int r = t / P, j = t - (t / P) * P;
+        const int i = i0 + r;
+        drw[r * kMaxP + j] = (i < n) ? double(V[(int64_t)j * a.n_pad + i]) : 0.0;
+        rrw[r * kMaxP + j] = (i < n) ? double(Rv[(int64_t)j * a.n_pad + i]) : 0.0;
+    }
+    __syncthreads();
+    constexpr int TRI = P * (P + 1) / 2;
+    constexpr int OZ = TRI, OY = TRI + P * P, OS = 2 * TRI + P * P, OQ = 2 * TRI + 2 * P * P;
+    constexpr int NE = OQ + P;
+    for (int e = tid; e < NE; e += kWG) {
+        const double* U;
+        const double* Wv;
+        int x, y;
+        if (e < OZ || (e >= OY && e < OS)) {             // triangles of G and Y
+            const int t = e < OZ ? e : e - OY;
+            x = 0;
+            while ((x + 1) * (x + 2) / 2 <= t) ++x;
+            y = t - x * (x + 1) / 2;
+            U = e < OZ ? drw : adt;
+            Wv = adt;
+        } else if (e < OQ) {                              // Z and S, full
+            const int t = e < OY ? e - OZ : e - OS;
+            x = t / P;
+            y = t - x * P;
+            U = e < OY ? adt : drw;
+            Wv = rrw;
+        } else {                                          // diagonal of R^T R
+            x = y = e - OQ;
+            U = rrw;
+            Wv = rrw;
+        }
+        double s = 0.0;
+        for (int r = 0; r < kAdCols; ++r) s = fma(U[r * kMaxP + x], Wv[r * kMaxP + y], s);
+        gmine[e] = s;
+    }
+    __syncthreads();
+    if (!grid_reduce(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
+
+    // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
+    DevState* st = a.st;
+    const double* Zt = gtot + OZ;
+    const double* St = gtot + OS;
+    const double* Qd = gtot + OQ;
+    unsigned mask = mask0;
+    double* Gs = sm;                          // full symmetric P x P
+    double* Ys = gmine;                       // (gmine is free now)
+    double* Lsh = sm + kMaxP * kMaxP;         // Cholesky factor, row-major stride P
+    double* rinv = sm + 2 * kMaxP * kMaxP;    // 1 / L[i][i]
+    double* lred = gscr;                      // per-lane values reduced by lane 0
+    // G and Y are symmetric in exact arithmetic: expand their lower triangles
+    for (int t = tid; t < P * P; t += kWG) {
+        const int x = t / P, y = t - (t / P) * P;
+        const int hi = max(x, y), lo = min(x, y);
+        Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
+        Ys[t] = gtot[OY + hi * (hi + 1) / 2 + lo];
+    }
+    // stop test (Alg. 4: smallest agent residual) before the step, as the loop does
+    if (wave == 0) {
+        double q = INFINITY;
+        double bad = 0.0;
+        if (lane < P && ((mask >> lane) & 1u)) {
+            const double nr = sqrt(Qd[lane]);
+            st->norms[lane] = nr;
+            if (!isfinite(nr)) bad = 1.0;
+            q = nr / nb0;
+        }
+        if (lane < P) {
+            lred[lane] = q;
+            lred[32 + lane] = bad;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            double mn = INFINITY, anybad = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P; ++jj) {
+                mn = fmin(mn, lred[jj]);
+                anybad += lred[32 + jj];
+            }
+            st->minres = mn;
+            int stop = 0;
+            if (anybad > 0.0) { fail_state(st, -2); stop = 1; }
+            else if (mn <= tol0) { st->done = RECUR_CONV; stop = 1; }
+            else if (iter0 >= maxit0) { st->done = MAXIT; stop = 1; }
+            ish[122] = stop;
+        }
+    }
+    __syncthreads();
+    if (ish[122]) return;
+    // Fast path: when det of the diagonally scaled G exceeds 2 tau, every pivot of
+    // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
+    // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
+    // keeps every agent; the slow path below runs the greedy rule itself.
+    if (wave == 0) {
+        double g[P];
+        row_load<P>(g, Gs, P, mask, true, lane);
+        const bool ok = row_cholesky<P>(g, lane);
+        double ratio = 1.0;
+        if (lane < P) {
+            double dg = 1.0;
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                Lsh[lane * P + b] = b <= lane ? g[b] : 0.0;
+                if (b == lane) dg = g[b];
+            }
+            rinv[lane] = 1.0 / dg;
+            if (ok && ((mask >> lane) & 1u)) ratio = (dg * dg) / Gs[lane * P + lane];
+            lred[lane] = ratio;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            double det = ok ? 1.0 : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P; ++jj) det *= lred[jj];
+            ish[120] = (ok && det > 2.0 * tau0) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    const bool fast = ish[120] != 0;
+    if (!fast) {
+        int* act = &ish[64];    // active agents (global indices), ascending
+        const int m = m0;
+        if (tid < m) act[tid] = st->keep[tid];
+        __syncthreads();
+        double* Gc = sm + 3 * kMaxP * kMaxP;   // compact m x m (below: H)
+        double* H = gscr;
+        if (tid < m * m) Gc[tid] = Gs[act[tid / m] * P + act[tid % m]];
+        __syncthreads();
+        int* kp = &ish[96];
+        const int r = wg_rank_select(Gc, m, tau0, kp, H, &ish[0]);
+        if (r < 0) {
+            if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
+            return;
+        }
+        if (r < m) {
+            if (tid == 0) {
+                unsigned nm = 0u;
+                for (int q = 0; q < r; ++q) nm |= 1u << act[kp[q]];
+                for (int q = 0; q < r; ++q) st->keep[q] = act[kp[q]];
+                st->mask = nm;
+                st->m = r;
+                st->deflations += 1;
+                if (r == 0) st->done = FINISHED;
+                ish[121] = (int)nm;
+            }
+            __syncthreads();
+            mask = (unsigned)ish[121];
+            if (r == 0) return;
+        }
+        if (wave == 0) {
+            double g[P];
+            row_load<P>(g, Gs, P, mask, true, lane);
+            const bool ok = row_cholesky<P>(g, lane);
+            if (lane < P) {
+                double dg = 1.0;
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    Lsh[lane * P + b] = b <= lane ? g[b] : 0.0;
+                    if (b == lane) dg = g[b];
+                }
+                rinv[lane] = 1.0 / dg;
+            }
+            if (lane == 0) ish[123] = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (ish[123]) {
+            if (tid == 0) fail_state(st, -3);
+            return;
+        }
+    }
+    if (wave != 0 || lane >= P) return;
+    // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c]; then (AD)^T R_new = (AD)^T R - (AD^T AD)
+    // alpha and beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c], all in this lane's registers
+    const int c = lane;
+    const bool ac = (mask >> c) & 1u;
+    // (registers up to P = 8; LDS beyond)
+    if constexpr (P <= 8) {
+        double y[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) y[x] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, y);
+        double w[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+            double v = Zt[x * P + c];
+#pragma unroll
+            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * y[l];
+            w[x] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
+        }
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+            st->alpha[x * kMaxP + c] = y[x];
+            st->beta[x * kMaxP + c] = w[x];
+            st->L[x * kMaxP + c] = Lsh[x * P + c];
+        }
+    } else {
+        double* Yc = sm + 3 * kMaxP * kMaxP;   // column c of alpha at Yc[x * P + c]
+        double* Wc = gscr;                     // column c of beta
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) Yc[x * P + c] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
+        col_chol_solve_lds<P>(Lsh, rinv, Yc, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) {
+            double v = Zt[x * P + c];
+            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * Yc[l * P + c];
+            Wc[x * P + c] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
+        }
+        col_chol_solve_lds<P>(Lsh, rinv, Wc, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) {
+            st->alpha[x * kMaxP + c] = Yc[x * P + c];
+            st->beta[x * kMaxP + c] = Wc[x * P + c];
+            st->L[x * kMaxP + c] = Lsh[x * P + c];
+        }
+    }
+}
+
+template <class CFG>
+__host__ __device__ constexpr int ad_tiles(int n) { return (n + CFG::ROWS - 1) / CFG::ROWS; }
+
+template <int PREC, int P, class CFG>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
+    ad_tile<PREC, P, CFG>(a, blockIdx.x, gridDim.x);
+}
+
+// Many systems in one launch: workgroup w runs tile items[w].y of system items[w].x.
+template <int PREC, int P, class CFG>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW)))
+void k_ad_batch(const AdArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const AdArgs a = sys[it.x];
+    ad_tile<PREC, P, CFG>(a, it.y, ad_tiles<CFG>(a.n));
+}
+
+// ===================== k_upd: X += D alpha, R -= AD alpha, D = R + D beta
+//
+// Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
+// Every row's old D is read into LDS before any thread writes the new one.
+
+template <int PREC, int P>
+__device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile) {
+    using TV = typename PT<PREC>::TV;
+    constexpr int RB = kWG / P;
+    __shared__ double al[P * P], be[P * P];
+    __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
+    DevState* st = a.st;
+    if (st->done != RUNNING) return;
+    const int tid = threadIdx.x;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)tile * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
+    if (tid < P * P) {
+        al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+        be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
+    }
+    const unsigned msk = st->mask;
+    TV* X = static_cast<TV*>(a.X);
+    TV* R = static_cast<TV*>(a.R);
+    TV* D = static_cast<TV*>(a.D);
+    const double x0 = X[o];
+    const double r0 = R[o];
+    dt[r * P + j] = D[o];
+    adt[r * P + j] = static_cast<const TV*>(a.AD)[o];
+    __syncthreads();
+    double sx = 0.0, sr = 0.0;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        sx = fma(dt[r * P + l], al[l * P + j], sx);
+        sr = fma(adt[r * P + l], al[l * P + j], sr);
+    }
+    const TV xn = TV(x0 + sx);
+    const TV rn = TV(r0 - sr);
+    X[o] = xn;
+    R[o] = rn;
+    rt[r * P + j] = double(rn);
+    __syncthreads();
+    double sd = rt[r * P + j];
+#pragma unroll
+    for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
+    D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
+    if (tile == 0 && tid == 0) st->iter += 1;
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
+    upd_tile<PREC, P>(a, blockIdx.x);
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const UpdArgs a = sys[it.x];
+    upd_tile<PREC, P>(a, it.y);
+}
+
+// ============================================ k_res: T = B - Y, norms, restart
+
+template <int P>
+__device__ __forceinline__ void res_tile(const ResArgs& a, const int tile, const int ntiles) {
+    constexpr int RB = kWG / P;
+    constexpr int NE = P * P + 1;      // T^T T entries, then b^T b
+    __shared__ double ts[RB * P];
+    __shared__ double bs[RB];
+    __shared__ double mine[NE];
+    __shared__ double tot[NE];
+    __shared__ double gscr[kWG];
+    __shared__ int ish[8];
+    DevState* st = a.st;
+    const int tid = threadIdx.x;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)tile * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
+    const unsigned msk = st->mask;
+    const double bi = a.b[i];
+    if (j == 0) bs[r] = bi;
+    const double t = (j < a.p && i < a.n) ? bi - a.Y[o] : 0.0;
+    ts[r * P + j] = t;
+    if (a.mode != RES_FINAL) a.R[o] = t;
+    if (a.mode == RES_INIT || a.mode == RES_CONFIRM) a.D[o] = ((msk >> j) & 1u) ? t : 0.0;
+    __syncthreads();
+    for (int e = tid; e < NE; e += kWG) {
+        double s = 0.0;
+        if (e < P * P) {
+            const int x = e / P, y = e - (e / P) * P;
+            for (int q = 0; q < RB; ++q) s = fma(ts[q * P + x], ts[q * P + y], s);
+        } else {
+            for (int q = 0; q < RB; ++q) s = fma(bs[q], bs[q], s);
+        }
+        mine[e] = s;
+    }
+    __syncthreads();
+    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
+    if (tid == 0) {
+        if (a.set_nb) st->nb = sqrt(tot[P * P]);
+        double mn = INFINITY;
+        bool bad = !isfinite(st->nb);
+        for (int jj = 0; jj < a.p; ++jj) {
+            const double nr = sqrt(tot[jj * P + jj]);
+            st->norms[jj] = nr;
+            if (!isfinite(nr)) bad = true;
+            if ((msk >> jj) & 1u) mn = fmin(mn, nr / st->nb);
+        }
+        st->minres = mn;
+        if (a.mode != RES_FINAL) {
+            if (bad) fail_state(st, -2);
+            else if (st->nb == 0.0) fail_state(st, -1);
+            else if (mn <= st->tol) st->done = FINISHED;
+            else if (a.mode == RES_REFINE) st->done = OUTER;
+            else {
+                if (a.mode == RES_CONFIRM) st->restarts += 1;
+                st->done = (st->iter >= st->maxit) ? MAXIT : RUNNING;
+            }
+        }
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kWG) void k_res(ResArgs a) {
+    res_tile<P>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched residual: items[w] = (system, tile, mode, set_nb); the mode of each
+// system's pass travels with its items.
+template <int P>
+__global__ __launch_bounds__(kWG) void k_res_batch(const ResArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    ResArgs a = sys[it.x];
+    a.mode = it.z;
+    a.set_nb = it.w;
+    res_tile<P>(a, it.y, a.n_pad / (kWG / P));
+}
+
+
+// ================================================================ A.D launchers
+//
+// Tile configuration: CW A columns per wave (from the tuning table, or given), one
+// wave step per staged chunk unless P * E elements are fewer than a workgroup,
+// 4 waves per SIMD, non-temporal A loads and staggered chunk starts.
+template <int PREC, int P, int CW>
+using AdCfgOf = AdCfg<CW, (P * 64 * PT<PREC>::E >= kWG ? 1 : kWG / (P * 64 * PT<PREC>::E)), 4, true, true>;
+
+template <int PREC, int P, int CW>
+inline hipError_t launch_ad_t(const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    using C = AdCfgOf<PREC, P, CW>;
+    const dim3 grid((a.n + C::ROWS - 1) / C::ROWS);
+    // With an event pair the launch records them itself (the kernel's own begin
+    // and end), with no separate marker packets around it.
+    if (e0) {
+        hipExtLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, e0, e1, 0, a);
+    } else {
+        hipLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int PREC, int P, int CW>
+inline hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    using C = AdCfgOf<PREC, P, CW>;
+    hipLaunchKernelGGL((k_ad_batch<PREC, P, C>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    return hipGetLastError();
+}
+
+// Widths that fit the register budget: 4 columns per wave only where the
+// accumulators stay small (FP64 up to P = 4, FP32 / BF16 up to P = 8); P = 16 at
+// most 2.  ad_cw_fit gives the width a request runs at.
+__host__ __device__ constexpr bool ad_cw4_fits(int prec, int P) {
+    return P < 16 && (prec != PREC_F64 || P <= 4);
+}
+__host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw) {
+    return cw >= 4 ? (ad_cw4_fits(prec, P) ? 4 : 2) : (cw >= 2 ? 2 : 1);
+}
+
+template <int PREC, int P>
+inline hipError_t launch_ad_pc(int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int W4 = ad_cw4_fits(PREC, P) ? 4 : 2;
+    if (cw >= 4) {
+        return one ? launch_ad_t<PREC, P, W4>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, W4>(sys, items, nitems, s);
+    }
+    if (cw >= 2) {
+        return one ? launch_ad_t<PREC, P, 2>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, 2>(sys, items, nitems, s);
+    }
+    return one ? launch_ad_t<PREC, P, 1>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, 1>(sys, items, nitems, s);
+}
+
+// One system (one != nullptr) or a batch of (system, tile) items.
+template <int PREC>
+inline hipError_t launch_ad_prec(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                                 int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (P) {
+        case 1: return launch_ad_pc<PREC, 1>(cw, one, sys, items, nitems, s, e0, e1);
+        case 2: return launch_ad_pc<PREC, 2>(cw, one, sys, items, nitems, s, e0, e1);
+        case 4: return launch_ad_pc<PREC, 4>(cw, one, sys, items, nitems, s, e0, e1);
+        case 8: return launch_ad_pc<PREC, 8>(cw, one, sys, items, nitems, s, e0, e1);
+        case 16: return launch_ad_pc<PREC, 16>(cw, one, sys, items, nitems, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Entry points of the per-precision translation units.
+hipError_t launch_ad_f64(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_ad_f32(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_ad_bf16(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+
+}  // namespace ccg

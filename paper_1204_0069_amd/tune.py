@@ -1,0 +1,148 @@
+"""Autotuner of the A.D tile width (A columns per wave) on the GPU.
+
+    python -m paper_1204_0069_amd.tune [--reps 10] [--out csrc/ccg_tune_table.h]
+
+For every precision, padded agent count P and a ladder of system sizes n it times
+the full A.D launch of the block step (stream of A, Gram products, stop test and
+p x p solves) for each candidate width with ccg_tune_ad, keeps the fastest, merges
+neighbouring sizes with the same choice into n ranges and writes the table that
+the library compiles in (csrc/ccg_tune_table.h).  Rebuild the library afterwards
+(python -m paper_1204_0069_amd.build).
+
+The width changes the tile decomposition, hence the order in which the Gram
+partial sums are added; the table is fixed at build time, so results stay
+reproducible from run to run.
+"""
+from __future__ import annotations
+
+import argparse
+import datetime
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "csrc", "ccg_tune_table.h")
+
+PRECS = (("fp64", "PREC_F64"), ("fp32", "PREC_F32"), ("bf16x2", "PREC_BF16X2"))
+AGENTS = (1, 2, 4, 8, 16)
+SIZES = (128, 256, 512, 1024, 2048, 4096, 8192, 16384)
+WIDTHS = (1, 2, 4)
+
+
+def fits4(prec: str, P: int) -> bool:
+    """Mirror of the library's rule for 4 columns per wave (ad_cw4_fits)."""
+    return P < 16 and (prec != "fp64" or P <= 4)
+
+
+MARGIN = 0.03   # another width must beat the default (2) by 3 % to be chosen
+
+
+def choose(t: dict) -> int:
+    """Fastest width, keeping the default 2 unless another is clearly faster (short
+    launches differ by timing noise)."""
+    w = min(t, key=t.get)
+    if 2 in t and t[2] <= (1.0 + MARGIN) * t[w]:
+        return 2
+    return w
+
+
+def rows_from(best_by_class):
+    """Table rows from {(cname, P): [(n, width), ...]}: neighbouring sizes with the
+    same width merge, and a row covers sizes up to 1.5 x its largest timed n."""
+    rows = []
+    for (cname, P), best in best_by_class.items():
+        merged = []
+        for n, w in best:
+            if merged and merged[-1][1] == w:
+                merged[-1] = (n, w)
+            else:
+                merged.append((n, w))
+        for i, (n, w) in enumerate(merged):
+            last = i == len(merged) - 1
+            rows.append((cname, P, (1 << 30) if last else n + (n // 2), w))
+    return rows
+
+
+def tune(ctx, reps: int, log=print):
+    best_by_class = {}
+    for prec, cname in PRECS:
+        for P in AGENTS:
+            widths = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
+            if P >= 16:
+                widths = [w for w in widths if w <= 2]
+            best = []
+            for n in SIZES:
+                if P > n:
+                    continue
+                t = {w: ctx.tune_ad(prec, P, n, w, reps) for w in widths}
+                w = choose(t)
+                best.append((n, w))
+                log(f"{prec:7s} P={P:2d} n={n:6d} " + "  ".join(f"cw{k}:{v:9.2f}us" for k, v in t.items())
+                    + f"  -> {w}")
+            best_by_class[(cname, P)] = best
+    return rows_from(best_by_class)
+
+
+def rows_from_log(path: str):
+    """Re-tabulate the timings a previous run printed (no GPU needed)."""
+    import re
+    names = dict(PRECS)
+    best_by_class = {}
+    for line in open(path):
+        m = re.match(r"(\w+)\s+P=\s*(\d+) n=\s*(\d+) (.*)  -> \d", line)
+        if not m:
+            continue
+        prec, P, n = m.group(1), int(m.group(2)), int(m.group(3))
+        t = {int(k): float(v) for k, v in re.findall(r"cw(\d):\s*([\d.]+)us", m.group(4))}
+        best_by_class.setdefault((names[prec], P), []).append((n, choose(t)))
+    return rows_from(best_by_class)
+
+
+def write_table(rows, device: str, path: str = OUT):
+    lines = [
+        "// A.D tile widths (A columns per wave) by precision, padded agent count and",
+        "// system size.  Written by `python -m paper_1204_0069_amd.tune` from timings of",
+        "// every candidate width on the GPU; the first row whose (prec, P) match and whose",
+        "// n_max >= n applies, and a size no row covers uses 2.",
+        f"// Tuned on: {device}, {datetime.date.today().isoformat()}.",
+        "#pragma once",
+        "",
+        "namespace ccg {",
+        "",
+        "struct TuneRow {",
+        "    int prec;     // Prec",
+        "    int P;        // padded agent count",
+        "    int n_max;    // largest n of the row",
+        "    int cw;       // A columns per wave: 1, 2 or 4",
+        "};",
+        "",
+        "static const TuneRow kTuneTable[] = {",
+    ]
+    lines += [f"    {{{c}, {P}, {n_max}, {w}}}," for c, P, n_max, w in rows]
+    lines += ["};", "", "}  // namespace ccg", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--out", default=OUT)
+    ap.add_argument("--from-log", default=None, help="re-tabulate a saved tuner log")
+    ap.add_argument("--device", default="AMD Instinct MI355X", help="device name for --from-log")
+    args = ap.parse_args()
+    if args.from_log:
+        rows = rows_from_log(args.from_log)
+        write_table(rows, args.device + " (timings of " + os.path.basename(args.from_log) + ")", args.out)
+        print(f"wrote {len(rows)} rows to {args.out}")
+        return
+    import torch
+    from .ccg import Context
+    ctx = Context(0)
+    rows = tune(ctx, args.reps, log=lambda s: print(s, flush=True))
+    write_table(rows, torch.cuda.get_device_name(0), args.out)
+    print(f"wrote {len(rows)} rows to {args.out}")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
