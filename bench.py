@@ -67,13 +67,24 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_sha(prec: str) -> str:
+    """sha256 over the sources that decide the A.D kernel of a precision: the device
+    templates, the precision's translation unit and the tile-width table."""
+    import hashlib
+    csrc = os.path.join(HERE, "paper_1204_0069_amd", "csrc")
+    tag = {"fp64": "f64", "fp32": "f32", "bf16x2": "bf16"}[prec]
+    h = hashlib.sha256()
+    for name in ("ccg_kernels.h", f"ccg_ad_{tag}.hip", "ccg_tune_table.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def recorded_traffic(n: int, p: int, prec: str):
     """HBM bytes per A.D launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     (profiles/), or None when no run covers this workload or the kernel source has
     changed since the counters were taken."""
-    import hashlib
     path = os.path.join(HERE, "profiles", f"k_ad_{prec}_n{n}_p{p}_traffic.md")
-    src = os.path.join(HERE, "paper_1204_0069_amd", "csrc", "ccg_kernels.hip")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -81,8 +92,7 @@ def recorded_traffic(n: int, p: int, prec: str):
         if ":" in line and not line.startswith(("#", "*", "`", " ")):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    sha = kernel_source_sha(prec)
     if rec.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in rec:
         return None
     return int(rec["traffic_bytes_per_launch"])
