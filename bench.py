@@ -332,7 +332,7 @@ def run_served(args):
     import torch
 
     import ccg_inputs as ci
-    from paper_1204_0069_amd import Context
+    from paper_1204_0069_amd import CCG_ESCALATE, Context
 
     dev = "cuda:0"
     rng = np.random.default_rng(ci.item_seed("served-pool", ci.BASE_SEED))
@@ -357,7 +357,9 @@ def run_served(args):
 
     def submit(r):
         k, b, X0, prec = reqs[r]
-        return ctx.submit(pool[k][2], b, X0, args.tol, 10 ** 6, prec=prec)
+        # a refinement that breaks down (BF16x2 at the largest condition numbers)
+        # continues in FP32, then FP64
+        return ctx.submit(pool[k][2], b, X0, args.tol, 10 ** 6, prec=prec, flags=CCG_ESCALATE)
 
     # closed loop on the first 8 requests: saturated rate (and warm-up)
     c0 = time.perf_counter()
@@ -395,6 +397,7 @@ def run_served(args):
                                f"rate {closed:.3f}/s), n log-uniform in [128, {args.n_hi}], p=4, kappa "
                                f"log-uniform in [1e2, 1e6], precision uniform over fp64/fp32/bf16x2, "
                                f"{args.pool} pooled matrices in pinned host memory (upload in latency), "
+                               f"precision escalation on breakdown, "
                                f"HBM budget {args.budget_gib:g} GiB", "requests": args.requests},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},

@@ -63,6 +63,11 @@ typedef enum {
 #define CCG_NO_GRAPH  0x2u   /* launch every kernel directly (no captured graph) */
 #define CCG_PROFILE   0x4u   /* time every A.D launch with HIP events (ccg_kernel_time);
                                  block steps are then launched directly, not as a graph */
+#define CCG_ESCALATE  0x8u   /* CCG_FP32 / CCG_BF16X2: when the refinement breaks down
+                                 (CCG_ERR_BREAKDOWN, or an inner Gram matrix that is not
+                                 positive or not finite), continue from the current agents
+                                 in the next wider precision (BF16X2 -> FP32 -> FP64);
+                                 info then totals every stage */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
@@ -73,7 +78,7 @@ typedef struct {
     double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
                             low-precision modes, whose vectors carry FP32 rounding) */
     int graph_k;         /* block steps per captured graph / per host poll (default 16) */
-    unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE */
+    unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_ESCALATE */
 } ccg_opts;
 
 /* Per-solve report. */
@@ -85,7 +90,8 @@ typedef struct {
     int p_final;         /* agents still active at the end */
     int best_agent;      /* argmin_j of the explicit residual */
     int deflations;      /* rank-drop events (Alg. 3) */
-    int reserved;
+    int prec_final;      /* ccg_prec the solve ended in (differs from opts->prec only
+                            after CCG_ESCALATE moved it to a wider precision) */
     double rel_res;      /* min_j ||b - A x_j|| / ||b||, explicit FP64 */
     double rel_res_max;  /* max_j of the same */
     double seconds;      /* wall time of the solve inside the library */

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libccg.so")
 CCG_HOST_PTRS = 0x1
 CCG_NO_GRAPH = 0x2
 CCG_PROFILE = 0x4
+CCG_ESCALATE = 0x8
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 
@@ -40,12 +41,12 @@ class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
                 ("refinements", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("p_final", ctypes.c_int), ("best_agent", ctypes.c_int),
-                ("deflations", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("deflations", ctypes.c_int), ("prec_final", ctypes.c_int),
                 ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("bytes_A", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d
 

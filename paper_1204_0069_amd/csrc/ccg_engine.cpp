@@ -178,6 +178,9 @@ struct Sys {
     double nb = 1.0, best = 0.0;
     int iters = 0, refinements = 0, stall = 0;
     RefArgs ra{};
+    // totals of earlier precision stages (CCG_ESCALATE)
+    ccg_opts o_user{};
+    int iters_done = 0, refinements_done = 0, deflations_done = 0;
     // report
     double bytes = 0.0;
     Clock::time_point t0;
@@ -270,6 +273,7 @@ class Engine {
         sy.tol = pr.tol;
         sy.maxit = pr.maxit;
         sy.o = o;
+        sy.o_user = pr.opts;
         sy.X_out = pr.X;
         sy.ldx = pr.ldx;
         sy.host = (o.flags & CCG_HOST_PTRS) != 0;
@@ -336,7 +340,26 @@ class Engine {
         }
         HIP_OK(launch_pack(n, n_pad, p, P, X0, ldx0, sy.w.Xr, s_));
         HIP_OK(launch_pad_vec(n, n_pad, b, sy.w.bp, s_));
-        // argument records of the batched kernels
+        // argument records of the batched kernels, and the initial state (written with
+        // every header at the start of the next round)
+        write_records(sy);
+        start_stage(sy);
+        sy.ra.n_pad = n_pad;
+        sy.ra.P = P;
+        sy.ra.T = sy.w.R;
+        sy.ra.X = sy.w.Xr;
+        sy.ra.E = sy.w.E;
+        sy.ra.R = sy.w.Rl;
+        sy.ra.D = sy.w.Dl;
+        if (sy.slot + 1 > hi_slot_) hi_slot_ = sy.slot + 1;
+        live_.push_back(sy);
+        items_dirty_ = true;
+        return true;
+    }
+
+    // Argument records of a system's batched kernels (its current precision).
+    void write_records(const Sys& sy) {
+        const int n = sy.n, n_pad = sy.w.n_pad;
         DevState* st = states_ + sy.slot;
         AdArgs ad{};
         ad.n = n;
@@ -345,9 +368,9 @@ class Engine {
         ad.red = sy.w.red_ad;
         ad.st = st;
         if (sy.prec == PREC_F64) {
-            ad.A = A;
+            ad.A = sy.A64;
             ad.A_lo = nullptr;
-            ad.lda = lda;
+            ad.lda = sy.lda64;
             ad.V = sy.w.D;
             ad.R = sy.w.R;
             ad.AD = sy.w.AD;
@@ -361,9 +384,9 @@ class Engine {
         }
         AdArgs ra = ad;
         ra.product_only = 1;
-        ra.A = A;
+        ra.A = sy.A64;
         ra.A_lo = nullptr;
-        ra.lda = lda;
+        ra.lda = sy.lda64;
         ra.V = sy.w.Xr;
         ra.R = sy.w.R;
         ra.AD = sy.w.AD;
@@ -378,7 +401,7 @@ class Engine {
         ResArgs r{};
         r.n = n;
         r.n_pad = n_pad;
-        r.p = p;
+        r.p = sy.p;
         r.mode = RES_INIT;
         r.set_nb = 1;
         r.b = sy.w.bp;
@@ -391,28 +414,55 @@ class Engine {
         HIP_OK(hipMemcpyAsync(d_res_ad_ + sy.slot, &ra, sizeof ra, hipMemcpyHostToDevice, s_));
         HIP_OK(hipMemcpyAsync(d_upd_ + sy.slot, &u, sizeof u, hipMemcpyHostToDevice, s_));
         HIP_OK(hipMemcpyAsync(d_res_ + sy.slot, &r, sizeof r, hipMemcpyHostToDevice, s_));
-        // initial state (written with every header at the start of the next round)
+    }
+
+    // Initial state of a (new or escalated) stage: the first explicit residual is due.
+    void start_stage(Sys& sy) {
         DevState& h = h_states_[sy.slot];
         std::memset(&h, 0, kHeader);
         h.done = RUNNING;
-        set_all_agents(h, p);
-        h.maxit = sy.maxit;
+        set_all_agents(h, sy.p);
+        h.maxit = sy.maxit - sy.iters_done;
         h.tol = sy.tol;
-        h.tau = o.rank_tau;
+        h.tau = sy.o.rank_tau;
         h.nb = 1.0;
         sy.ph = PH_INIT_RES;
         sy.res_due = true;
         sy.res_mode = sy.prec == PREC_F64 ? RES_INIT : RES_REFINE;
         sy.res_set_nb = 1;
-        sy.ra.n_pad = n_pad;
-        sy.ra.P = P;
-        sy.ra.T = sy.w.R;
-        sy.ra.X = sy.w.Xr;
-        sy.ra.E = sy.w.E;
-        sy.ra.R = sy.w.Rl;
-        sy.ra.D = sy.w.Dl;
-        if (sy.slot + 1 > hi_slot_) hi_slot_ = sy.slot + 1;
-        live_.push_back(sy);
+        sy.iters = 0;
+        sy.refinements = 0;
+        sy.stall = 0;
+    }
+
+    // CCG_ESCALATE: the refinement broke down; the system goes on from its FP64 agents
+    // in the next wider precision, as the single driver does.
+    bool escalate(Sys& sy, ccg_status st) {
+        if (!(sy.o_user.flags & CCG_ESCALATE) || sy.prec == PREC_F64) return false;
+        if (st != CCG_ERR_BREAKDOWN && st != CCG_ERR_NOT_SPD && st != CCG_ERR_NONFINITE) return false;
+        const DevState& h = h_states_[sy.slot];
+        sy.iters_done += sy.iters;
+        sy.refinements_done += sy.refinements;
+        sy.deflations_done += h.deflations;
+        if (sy.maxit - sy.iters_done <= 0) return false;
+        ccg_opts u = sy.o_user;
+        u.prec = sy.prec == PREC_BF16X2 ? CCG_FP32 : CCG_FP64;
+        sy.o = fill_defaults(&u);
+        if (sy.prec == PREC_BF16X2) {
+            // the FP32 copy fits where the two BF16 planes were
+            const int64_t ld = round_up(sy.n, 4);
+            float* hi = reinterpret_cast<float*>(const_cast<void*>(sy.lowhi));
+            HIP_OK(launch_convert(PREC_F32, sy.n, sy.A64, sy.lda64, hi, nullptr, ld, s_));
+            sy.bytes += (double)sy.n * sy.n * 12.0;
+            sy.prec = PREC_F32;
+            sy.lowlo = nullptr;
+            sy.ldlow = ld;
+        } else {
+            sy.prec = PREC_F64;
+        }
+        sy.cw_step = ad_cw(sy.prec, sy.P, sy.n);
+        write_records(sy);
+        start_stage(sy);
         items_dirty_ = true;
         return true;
     }
@@ -591,7 +641,8 @@ class Engine {
         DevState& h = h_states_[sy.slot];
         if (h.done == FAILED) { retire(sy, (ccg_status)h.status); return; }
         if (h.done != OUTER) { retire(sy, CCG_OK); return; }
-        if (sy.refinements >= sy.o.max_refine || sy.iters >= sy.maxit) {
+        const int budget = sy.maxit - sy.iters_done;   // block steps left for this stage
+        if (sy.refinements >= sy.o.max_refine || sy.iters >= budget) {
             retire(sy, CCG_NOT_CONVERGED);
             return;
         }
@@ -608,7 +659,7 @@ class Engine {
         h.mask = mask;
         h.tol = std::min(0.5, std::max(sy.o.inner_tol, 0.1 * sy.tol / h.minres));
         h.nb = 1.0;
-        h.maxit = std::min(sy.o.inner_maxit, sy.maxit - sy.iters);
+        h.maxit = std::min(sy.o.inner_maxit, budget - sy.iters);
         sy.inner_start_due = true;
         sy.ph = PH_INNER;
     }
@@ -622,22 +673,24 @@ class Engine {
     // Report a system and copy its agents out (completed in finish_retired).
     void retire(Sys& sy, ccg_status st) {
         if (sy.slot < 0) return;
+        if (escalate(sy, st)) return;
         DevState& h = h_states_[sy.slot];
         ccg_info info;
         std::memset(&info, 0, sizeof info);
         info.status = st;
         if (sy.prec == PREC_F64) {
-            info.iters = h.iter;
-            info.refinements = 0;
+            info.iters = sy.iters_done + h.iter;
+            info.refinements = sy.refinements_done;
             info.restarts = h.restarts;
             info.p_final = h.m;
         } else {
-            info.iters = sy.iters;
-            info.refinements = sy.refinements;
+            info.iters = sy.iters_done + sy.iters;
+            info.refinements = sy.refinements_done + sy.refinements;
             info.restarts = 0;
             info.p_final = sy.p;
         }
-        info.deflations = h.deflations;
+        info.deflations = sy.deflations_done + h.deflations;
+        info.prec_final = sy.prec == PREC_F64 ? CCG_FP64 : (sy.prec == PREC_F32 ? CCG_FP32 : CCG_BF16X2);
         double mn = INFINITY, mx = 0.0;
         int best = -1;
         for (int j = 0; j < sy.p; ++j) {

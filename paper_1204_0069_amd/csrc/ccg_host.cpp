@@ -549,6 +549,30 @@ ccg_status ccg_destroy(ccg_ctx* c) {
 
 const char* ccg_last_error(const ccg_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+// Precision escalation (CCG_ESCALATE): a refinement that breaks down (no progress,
+// or a low-precision inner solve whose Gram matrix is not positive or not finite)
+// continues from its agents in the next wider precision.
+bool escalates(const ccg_opts& o, ccg_status r) {
+    return (o.flags & CCG_ESCALATE) && o.prec != CCG_FP64 &&
+           (r == CCG_ERR_BREAKDOWN || r == CCG_ERR_NOT_SPD || r == CCG_ERR_NONFINITE);
+}
+
+ccg_opts next_precision(const ccg_opts* user, const ccg_opts& cur) {
+    ccg_opts u;
+    std::memset(&u, 0, sizeof u);
+    if (user) u = *user;
+    u.prec = cur.prec == CCG_BF16X2 ? CCG_FP32 : CCG_FP64;
+    return fill_defaults(&u);
+}
+
+void accumulate_stage(ccg_info& acc, const ccg_info& stage) {
+    acc.iters += stage.iters;
+    acc.refinements += stage.refinements;
+    acc.restarts += stage.restarts;
+    acc.deflations += stage.deflations;
+    acc.bytes_A += stage.bytes_A;
+}
+
 ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b, double* X,
                      int64_t ldx, double tol, int maxit, const ccg_opts* opts, ccg_info* info) {
     ccg_info local;
@@ -566,8 +590,26 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
         double* Xd = X;
         int64_t ldxd = ldx;
         if (o.flags & CCG_HOST_PTRS) stage_in(c, sg, n, p, A, lda, b, Xd, ldxd);
-        ccg_status r = o.prec == CCG_FP64 ? solve_fp64(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local)
-                                          : solve_mixed(c, n, p, A, lda, b, Xd, ldxd, tol, maxit, o, local);
+        ccg_status r = CCG_OK;
+        ccg_opts oo = o;
+        ccg_info acc;
+        std::memset(&acc, 0, sizeof acc);
+        for (;;) {
+            const int left = maxit - acc.iters;
+            r = oo.prec == CCG_FP64 ? solve_fp64(c, n, p, A, lda, b, Xd, ldxd, tol, left, oo, local)
+                                    : solve_mixed(c, n, p, A, lda, b, Xd, ldxd, tol, left, oo, local);
+            accumulate_stage(acc, local);
+            if (!escalates(oo, r) || maxit - acc.iters <= 0) break;
+            // X holds the agents of the last completed outer step: go on from them in
+            // the next wider precision
+            oo = next_precision(opts, oo);
+        }
+        local.prec_final = oo.prec;
+        local.iters = acc.iters;
+        local.refinements = acc.refinements;
+        local.restarts = acc.restarts;
+        local.deflations = acc.deflations;
+        local.bytes_A = acc.bytes_A;
         if (o.flags & CCG_HOST_PTRS) {
             HIP_OK(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xd, sizeof(double) * n, sizeof(double) * n, p,
                                     hipMemcpyDeviceToHost, c->stream));

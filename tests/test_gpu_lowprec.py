@@ -142,3 +142,20 @@ def test_full_size_fp32_solve(gpu_ctx):
     x = X[:, j]
     noise = float(2.0 * n * 1.11e-16 * torch.linalg.norm(b.abs() + A.abs() @ x.abs()) / torch.linalg.norm(b))
     assert abs(info["rel_res"] - rel[j]) <= 1e-3 * rel[j] + noise
+
+
+def test_escalation_after_breakdown(gpu_ctx):
+    """At cond(A) = 1e10 the BF16x2 copy of A (about 2^-17 relative error per element)
+    is far from positive definite, so its refinement cannot progress; with
+    CCG_ESCALATE the solve goes on from its agents in a wider precision, meets the
+    target, reports the precision it ended in and totals over every stage."""
+    from paper_1204_0069_amd import CCG_ESCALATE
+    n, p, kappa, tol = 128, 4, 1e10, 1e-5
+    A, b, X0 = ci.system(n, p, kappa, seed=505)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 100000, prec="bf16x2", raise_on_error=False)
+    assert i1["status"] != 0 and i1["prec_final"] == 2, i1
+    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 100000, prec="bf16x2", flags=CCG_ESCALATE)
+    assert i2["status"] == 0 and i2["prec_final"] in (0, 1), i2
+    T = oracle.residual(A, b, X2.cpu().numpy())
+    assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() <= 1.01 * tol
+    assert i2["iters"] > i1["iters"] and i2["bytes_A"] > i1["bytes_A"]
