@@ -61,6 +61,12 @@ def parse():
     ap.add_argument("--rate", type=float, default=0.0,
                     help="served mode: arrivals per second (0: half the measured closed-loop rate)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served mode: HBM budget")
+    ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
+                    help="served mode: skip the plain FP64 comparison")
+    ap.add_argument("--dump", default=None, help="served mode: write per-request records (JSON) here")
+    ap.add_argument("--single-fp64", action="store_true",
+                    help="batched mode: time the plain FP64 baseline instead (every 8th system, one "
+                         "ccg_solve at a time)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (3 times) and exit: the "
                          "known-size kernel that scales hardware byte counters")
@@ -278,6 +284,8 @@ def run_batched(args):
         systems.append(dict(A=A, b=b, X0=X0, tol=args.tol, maxit=10 ** 6, prec=args.prec))
     torch.cuda.synchronize()
     ctx = Context(0)
+    if args.single_fp64:
+        return _batched_single_fp64(args, ctx, specs, systems)
     for _ in range(args.warmup):
         ctx.solve_batched(systems[: min(32, len(systems))])
     torch.cuda.synchronize()
@@ -322,6 +330,47 @@ def run_batched(args):
                      "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None,
                      "kind": "effective: algorithmic A bytes of all systems / wall time"},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def _batched_single_fp64(args, ctx, specs, systems):
+    """Plain FP64 baseline of the batched workload: every 8th system of the same batch
+    solved with one ccg_solve at a time (no batched engine in the process)."""
+    import numpy as np
+    import torch
+    sample = list(range(0, len(systems), 8))
+    for i in sample[: args.warmup]:
+        sy = systems[i]
+        ctx.solve(sy["A"], sy["b"], sy["X0"], sy["tol"], sy["maxit"], raise_on_error=False, prec="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in sample:
+        sy = systems[i]
+        infos.append(ctx.solve(sy["A"], sy["b"], sy["X0"], sy["tol"], sy["maxit"], raise_on_error=False,
+                               prec="fp64")[1])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    bytes_a = sum(i["bytes_A"] for i in infos)
+    eff = bytes_a / total / 1e9
+    out = {
+        "metric": METRIC, "value": round(len(sample) / total, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(sample), "warmup": args.warmup, "ms_per_step": round(total / len(sample) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"plain FP64 baseline of the batched workload: every 8th of the batch of "
+                               f"{len(specs)} dense SPD systems (n log-uniform in [64, 4096], p in {{2, 4, 8}}, "
+                               f"kappa log-uniform in [1e2, 1e5]), one ccg_solve at a time, FP64 A, "
+                               f"tol {args.tol:g}", "count": len(sample), "prec": "fp64",
+                   "mode": "single-fp64"},
+        "converged": sum(1 for i in infos if i["status"] == 0),
+        "iters_mean": float(np.mean([i["iters"] for i in infos])),
+        "rel_res_max": float(max(i["rel_res"] for i in infos)),
+        "roofline": {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kind": "effective: algorithmic A bytes of the sampled systems / wall time"},
+        "cpu_baseline": None,
     }
     print(json.dumps(out))
     ctx.close()
@@ -408,8 +457,65 @@ def run_served(args):
                      "kind": "effective: algorithmic A bytes of all requests / wall time"},
         "cpu_baseline": None,
     }
-    print(json.dumps(out))
+    if args.compare_fp64:
+        # the same requests submitted all at once: the service's saturated rate
+        c0 = time.perf_counter()
+        ts = [submit(8 + j) for j in range(args.requests)]
+        for t in ts:
+            ctx.wait(t)
+        out["closed_loop_solves_per_s"] = round(args.requests / (time.perf_counter() - c0), 4)
     ctx.close()
+    if args.compare_fp64:
+        base = Context(0)
+        out["plain_fp64"] = _served_fp64_comparison(base, pool, reqs[8:8 + args.requests], arrivals, args, lat)
+        service_ms = out["plain_fp64"].pop("service_ms")
+        base.close()
+    if args.dump:
+        recs = [{"n": pool[reqs[8 + j][0]][0], "kappa": pool[reqs[8 + j][0]][1], "prec": reqs[8 + j][3],
+                 "arrival_s": float(arrivals[j]), "latency_ms": float(lat[j]), "iters": infos[j]["iters"],
+                 "refinements": infos[j]["refinements"], "prec_final": infos[j]["prec_final"],
+                 "status": infos[j]["status_name"]} for j in range(args.requests)]
+        if args.compare_fp64:
+            for r, s_ in zip(recs, service_ms):
+                r["fp64_service_ms"] = s_
+        with open(args.dump, "w") as f:
+            json.dump(recs, f, indent=1)
+    print(json.dumps(out))
+
+
+def _served_fp64_comparison(ctx, pool, reqs, arrivals, args, lat_served):
+    """The same requests in plain FP64, one ccg_solve at a time (upload of A from pinned
+    host memory included in each service time), and the latencies a first-come
+    first-served queue of such solves would give on the same arrival times."""
+    import numpy as np
+    import torch
+    dev = "cuda:0"
+    service = []
+    ok = 0
+    for k, b, X0, _ in reqs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = pool[k][2].to(dev, non_blocking=True)
+        _, info = ctx.solve(A, b.to(dev, non_blocking=True), X0.to(dev, non_blocking=True), args.tol, 10 ** 6,
+                            raise_on_error=False, prec="fp64")
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        ok += info["status"] == 0
+        del A
+    finish = 0.0
+    lat = []
+    for a, s in zip(arrivals, service):
+        finish = max(finish, a) + s
+        lat.append((finish - a) * 1e3)
+    lat = np.array(lat)
+    return {"closed_loop_solves_per_s": round(len(service) / sum(service), 4), "converged": int(ok),
+            "service_ms": [round(x * 1e3, 3) for x in service],
+            "fifo_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                "p99": round(float(np.percentile(lat, 99)), 3)},
+            "fifo_note": "first-come first-served queue of one-at-a-time FP64 solves on the served "
+                         "stream's arrival times, from each request's measured FP64 service time",
+            "fifo_p50_over_served_p50": round(float(np.percentile(lat, 50) / np.percentile(lat_served, 50)), 3),
+            "fifo_p99_over_served_p99": round(float(np.percentile(lat, 99) / np.percentile(lat_served, 99)), 3)}
 
 
 if __name__ == "__main__":

@@ -10,15 +10,18 @@
 //   2. one batched explicit-residual pass (FP64 A.X, then the residual epilogue)
 //      over every system that needs one, per padded agent count,
 //   3. the starts of refinement inner solves (per system),
-//   4. k block steps over every resident system, replayed from a captured graph:
-//      one batched A.D launch and one batched update launch per (precision, padded
-//      agent count, tile width) class (a step is a no-op for a system that is not
-//      running),
+//   4. k block steps over every resident system: per (precision, padded agent
+//      count, tile width) class, k pairs of batched A.D and update launches on a
+//      stream of the class, replayed from a graph captured on that stream; the
+//      class streams fork from and join back into the engine stream (a step is a
+//      no-op for a system that is not running),
 // then reads every state header and moves each system through the same phases,
 // in the same order, as the single-system driver, so a system's result does not
 // depend on the systems it shares launches with.
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <exception>
 #include <cstddef>
 #include <cstdio>
 #include <deque>
@@ -42,7 +45,8 @@ using Clock = std::chrono::steady_clock;
 
 // First-fit allocator over device memory chunks.  Chunks grow in kChunk steps up
 // to the cap (0: what the device reports free, less a headroom) and are returned
-// only when the arena is destroyed (hipFree synchronises the device).
+// only when the arena is destroyed (hipFree synchronises the device).  The lanes
+// of one batched call or of one service share an arena, so it is locked.
 class Arena {
   public:
     explicit Arena(size_t cap) : cap_(cap) {}
@@ -54,6 +58,7 @@ class Arena {
 
     // nullptr when `bytes` does not fit now
     char* alloc(size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
         bytes = (size_t)round_up((int64_t)bytes, 256);
         for (auto& c : chunks_) {
             char* p = take(c, bytes);
@@ -80,6 +85,7 @@ class Arena {
     }
 
     void release(char* p) {
+        std::lock_guard<std::mutex> lk(mu_);
         auto u = used_.find(p);
         if (u == used_.end()) return;
         const size_t bytes = u->second;
@@ -102,6 +108,12 @@ class Arena {
             c.free[off] = size;
             return;
         }
+    }
+
+    // Nothing allocated: a request that does not fit now never will.
+    bool empty() const {
+        std::lock_guard<std::mutex> lk(mu_);
+        return used_.empty();
     }
 
     // Whether `bytes` could ever fit (the cap, or the device's total memory).
@@ -130,11 +142,19 @@ class Arena {
         }
         return nullptr;
     }
+    mutable std::mutex mu_;
     size_t cap_;
     size_t total_ = 0;
     std::vector<Chunk> chunks_;
     std::unordered_map<char*, size_t> used_;
 };
+
+// Systems run in lanes by size: each lane is an engine with its own stream and
+// host thread, so the rounds of small systems (a few microseconds per block step)
+// do not wait for the block steps of large ones, which take up to milliseconds.
+constexpr int kLanes = 2;
+constexpr int kLaneSplit = 4096;   // n at or above: the large-system lane
+inline int lane_of(int n) { return n >= kLaneSplit ? 1 : 0; }
 
 enum Phase : int {
     PH_INIT_RES,     // waiting for / past the first explicit residual
@@ -195,9 +215,15 @@ struct Finished {
 };
 
 class Engine {
+    // a step class's items: A.D tiles at ad_off, update tiles at up_off in the list
+    struct StepRange {
+        int prec, P, cw;
+        size_t ad_off, ad_n, up_off, up_n;
+    };
+
   public:
-    Engine(int device, hipStream_t stream, size_t budget, bool use_graph = true)
-        : device_(device), s_(stream), arena_(budget), use_graph_(use_graph) {
+    Engine(int device, hipStream_t stream, Arena& arena, bool use_graph = true)
+        : device_(device), s_(stream), arena_(arena), use_graph_(use_graph) {
         HIP_OK(hipMalloc(&states_, sizeof(DevState) * kSlots));
         HIP_OK(hipMalloc(&d_ad_, sizeof(AdArgs) * kSlots));
         HIP_OK(hipMalloc(&d_res_ad_, sizeof(AdArgs) * kSlots));
@@ -215,7 +241,7 @@ class Engine {
         (void)hipFree(d_res_ad_);
         (void)hipFree(d_upd_);
         (void)hipFree(d_res_);
-        if (graph_) (void)hipGraphExecDestroy(graph_);
+        for (hipGraphExec_t g : class_graphs_) (void)hipGraphExecDestroy(g);
         for (hipStream_t cs : class_streams_) (void)hipStreamDestroy(cs);
         for (hipEvent_t ev : class_events_) (void)hipEventDestroy(ev);
         if (fork_) (void)hipEventDestroy(fork_);
@@ -524,11 +550,21 @@ class Engine {
         // 3. inner-solve starts
         for (auto& sy : live_)
             if (sy.inner_start_due) HIP_OK(launch_inner_init(sy.ra, s_));
-        // 4. block steps
-        if (graph_) {
-            HIP_OK(hipGraphLaunch(graph_, s_));
-        } else {
-            for (int it = 0; it < k; ++it) enqueue_step_ranges();
+        // 4. block steps: each class's k steps on a stream of its own, forked from
+        //    and joined back into the engine stream
+        if (!step_ranges_.empty()) {
+            HIP_OK(hipEventRecord(fork_, s_));
+            for (size_t c = 0; c < step_ranges_.size(); ++c) {
+                hipStream_t cs = class_streams_[c];
+                HIP_OK(hipStreamWaitEvent(cs, fork_, 0));
+                if (use_graph_) {
+                    HIP_OK(hipGraphLaunch(class_graphs_[c], cs));
+                } else {
+                    for (int it = 0; it < k; ++it) enqueue_class_step(step_ranges_[c], cs);
+                }
+                HIP_OK(hipEventRecord(class_events_[c], cs));
+                HIP_OK(hipStreamWaitEvent(s_, class_events_[c], 0));
+            }
         }
         HIP_OK(hipMemcpy2DAsync(h_states_, sizeof(DevState), states_, sizeof(DevState), kHeader, hi_slot_,
                                 hipMemcpyDeviceToHost, s_));
@@ -739,16 +775,14 @@ class Engine {
     }
 
     // Step work list of every resident system, by (precision, P, tile width) class;
-    // uploaded once and captured with k steps into a graph.
+    // uploaded once, and each class's k steps captured into a graph of its own.
     void rebuild_steps(int k) {
         for (int sl : pending_slots_) free_slots_.push_back(sl);
         pending_slots_.clear();
         hi_slot_ = 0;
         for (auto& sy : live_) hi_slot_ = std::max(hi_slot_, sy.slot + 1);
-        if (graph_) {
-            HIP_OK(hipGraphExecDestroy(graph_));
-            graph_ = nullptr;
-        }
+        for (hipGraphExec_t g : class_graphs_) HIP_OK(hipGraphExecDestroy(g));
+        class_graphs_.clear();
         std::vector<int4> st;
         step_ranges_.clear();
         step_items_total_ = 0;
@@ -795,11 +829,10 @@ class Engine {
         items_dirty_ = false;
         dead_items_ = 0;
         graph_k_ = k;
-        if (!use_graph_ || step_ranges_.empty()) return;
         // Classes touch disjoint systems, so each class's k steps form an independent
-        // chain: the graph forks one branch per class (streams of default priority)
-        // and the branches run concurrently, overlapping one class's reduction tail
-        // with another's stream of A.
+        // chain on a stream of its own (default priority); the chains run
+        // concurrently, overlapping one class's reduction tail with another's
+        // stream of A.  Each chain is a linear graph captured on its class stream.
         while (class_streams_.size() < step_ranges_.size()) {
             hipStream_t cs = nullptr;
             HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -809,44 +842,35 @@ class Engine {
             class_events_.push_back(ev);
         }
         if (!fork_) HIP_OK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
-        hipGraph_t gr = nullptr;
-        HIP_OK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
-        bool ok = true;
-        try {
-            HIP_OK(hipEventRecord(fork_, s_));
-            for (size_t c = 0; c < step_ranges_.size(); ++c) {
-                hipStream_t cs = class_streams_[c];
-                HIP_OK(hipStreamWaitEvent(cs, fork_, 0));
-                const StepRange& r = step_ranges_[c];
-                for (int it = 0; it < k; ++it) {
-                    HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
-                    HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
-                }
-                HIP_OK(hipEventRecord(class_events_[c], cs));
-                HIP_OK(hipStreamWaitEvent(s_, class_events_[c], 0));
+        if (!use_graph_) return;
+        for (size_t c = 0; c < step_ranges_.size(); ++c) {
+            hipStream_t cs = class_streams_[c];
+            hipGraph_t gr = nullptr;
+            HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            bool ok = true;
+            try {
+                for (int it = 0; it < k; ++it) enqueue_class_step(step_ranges_[c], cs);
+            } catch (const CcgError&) {
+                ok = false;
             }
-        } catch (const CcgError&) {
-            ok = false;
-        }
-        const hipError_t e = hipStreamEndCapture(s_, &gr);
-        if (!ok || e != hipSuccess || !gr) {
-            (void)hipGetLastError();
-            if (gr) (void)hipGraphDestroy(gr);
-            throw CcgError{CCG_ERR_DEVICE, "stream capture of the batched block steps failed"};
-        }
-        const hipError_t ei = hipGraphInstantiate(&graph_, gr, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(gr);
-        if (ei != hipSuccess) {
-            graph_ = nullptr;
-            throw CcgError{CCG_ERR_DEVICE, "instantiating the batched block-step graph failed"};
+            const hipError_t e = hipStreamEndCapture(cs, &gr);
+            if (!ok || e != hipSuccess || !gr) {
+                (void)hipGetLastError();
+                if (gr) (void)hipGraphDestroy(gr);
+                throw CcgError{CCG_ERR_DEVICE, "stream capture of the batched block steps failed"};
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess || !ex)
+                throw CcgError{CCG_ERR_DEVICE, "instantiating the batched block-step graph failed"};
+            class_graphs_.push_back(ex);
         }
     }
 
-    void enqueue_step_ranges() {
-        for (const StepRange& r : step_ranges_) {
-            HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, s_));
-            HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, s_));
-        }
+    void enqueue_class_step(const StepRange& r, hipStream_t cs) {
+        HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
+        HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
     }
 
     void upload_items() {
@@ -869,7 +893,7 @@ class Engine {
 
     int device_;
     hipStream_t s_;
-    Arena arena_;
+    Arena& arena_;
     DevState* states_ = nullptr;
     DevState* h_states_ = nullptr;
     AdArgs* d_ad_ = nullptr;
@@ -880,16 +904,12 @@ class Engine {
     int4* h_items_ = nullptr;
     size_t items_cap_ = 0;
     std::vector<int4> items_;
-    struct StepRange {
-        int prec, P, cw;
-        size_t ad_off, ad_n, up_off, up_n;
-    };
     std::vector<StepRange> step_ranges_;
     int4* d_step_ = nullptr;
     int4* h_step_ = nullptr;
     size_t step_cap_ = 0;
     bool use_graph_ = true;
-    hipGraphExec_t graph_ = nullptr;
+    std::vector<hipGraphExec_t> class_graphs_;   // one per step class (use_graph_)
     int graph_k_ = 0;
     std::vector<hipStream_t> class_streams_;
     std::vector<hipEvent_t> class_events_;
@@ -923,60 +943,72 @@ struct Result {
 
 }  // namespace
 
-struct Server {
+// One lane of the service: its request queue, pending cancels and thread.
+struct ServiceLane {
     std::thread th;
-    std::mutex mu;
-    std::condition_variable wake;      // to the service thread
-    std::condition_variable done_cv;   // to waiters
+    std::condition_variable wake;      // to the lane's thread
     std::deque<Request> queue;
-    std::map<uint64_t, Result> results;
     std::vector<uint64_t> cancels;
+};
+
+struct Server {
+    explicit Server(size_t budget) : arena(budget) {}
+    std::mutex mu;
+    std::condition_variable done_cv;   // to waiters
+    ServiceLane lanes[kLanes];
+    std::map<uint64_t, Result> results;
     uint64_t next_ticket = 1;
     bool stop = false;
     std::string fatal;                 // a device error that ended the service
+    Arena arena;                       // device memory of every lane
 };
 
 namespace {
 
-// Service loop: admit in arrival order while memory allows, advance, retire.
-void serve(ccg_ctx* c, Server* sv) {
+// Service loop of one lane: admit in arrival order while memory allows, advance,
+// retire.
+void serve(ccg_ctx* c, Server* sv, int lane) {
+    ServiceLane& L = sv->lanes[lane];
     (void)hipSetDevice(c->device);
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->fatal = "service stream creation failed";
         sv->done_cv.notify_all();
+        for (auto& l : sv->lanes) l.wake.notify_all();
         return;
     }
     try {
-        Engine eng(c->device, s, c->budget);
+        Engine eng(c->device, s, sv->arena);
         std::map<uint64_t, Clock::time_point> submitted;
         for (;;) {
             std::vector<Request> admit;
             {
                 std::unique_lock<std::mutex> lk(sv->mu);
                 if (eng.idle())
-                    sv->wake.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->cancels.empty(); });
-                if (sv->stop) break;
-                for (uint64_t t : sv->cancels) {
+                    L.wake.wait(lk, [&] {
+                        return sv->stop || !sv->fatal.empty() || !L.queue.empty() || !L.cancels.empty();
+                    });
+                if (sv->stop || !sv->fatal.empty()) break;
+                for (uint64_t t : L.cancels) {
                     bool queued = false;
-                    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+                    for (auto it = L.queue.begin(); it != L.queue.end(); ++it) {
                         if (it->ticket != t) continue;
                         Result& r = sv->results[t];
                         r.done = true;
                         r.status = CCG_CANCELLED;
                         r.info.status = CCG_CANCELLED;
-                        sv->queue.erase(it);
+                        L.queue.erase(it);
                         queued = true;
                         break;
                     }
                     if (!queued) eng.cancel(t);
                 }
-                sv->cancels.clear();
+                L.cancels.clear();
                 sv->done_cv.notify_all();
-                while (!sv->queue.empty()) {
-                    admit.push_back(sv->queue.front());
-                    sv->queue.pop_front();
+                while (!L.queue.empty()) {
+                    admit.push_back(L.queue.front());
+                    L.queue.pop_front();
                 }
             }
             // admission in arrival order; what does not fit goes back to the front
@@ -993,6 +1025,11 @@ void serve(ccg_ctx* c, Server* sv) {
                         msg = "system exceeds the HBM budget";
                     } else {
                         ok = eng.admit(rq.prob, rq.ticket);
+                        // nothing resident in any lane and still no room: never fits
+                        if (!ok && eng.idle() && sv->arena.empty()) {
+                            err = CCG_ERR_NOMEM;
+                            msg = "no device memory for the system";
+                        }
                     }
                 } catch (const CcgError& e) {
                     err = e.st;
@@ -1012,8 +1049,10 @@ void serve(ccg_ctx* c, Server* sv) {
             }
             if (taken < admit.size()) {
                 std::lock_guard<std::mutex> lk(sv->mu);
-                for (size_t i = admit.size(); i-- > taken;) sv->queue.push_front(admit[i]);
+                for (size_t i = admit.size(); i-- > taken;) L.queue.push_front(admit[i]);
             }
+            // the other lane holds the memory this lane waits for
+            if (eng.idle() && taken < admit.size()) std::this_thread::sleep_for(std::chrono::microseconds(200));
             eng.round(8);
             auto fin = eng.take_finished();
             if (!fin.empty()) {
@@ -1050,6 +1089,7 @@ void serve(ccg_ctx* c, Server* sv) {
                 kv.second.status = CCG_ERR_DEVICE;
                 kv.second.info.status = CCG_ERR_DEVICE;
             }
+        for (auto& l : sv->lanes) l.wake.notify_all();
     }
     sv->done_cv.notify_all();
 }
@@ -1063,8 +1103,10 @@ void stop_server(ccg_ctx* c) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
     }
-    sv->wake.notify_all();
-    if (sv->th.joinable()) sv->th.join();
+    for (auto& l : sv->lanes) {
+        l.wake.notify_all();
+        if (l.th.joinable()) l.th.join();
+    }
     delete sv;
     c->server = nullptr;
 }
@@ -1088,50 +1130,96 @@ ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, cc
         }
     ccg_status first_err = CCG_OK;
     bool any_nc = false;
+    std::mutex rec_mu;
+    auto record = [&](int i, ccg_status s, const ccg_info* inf) {
+        std::lock_guard<std::mutex> lk(rec_mu);
+        if (infos) {
+            if (inf) infos[i] = *inf;
+            infos[i].status = s;
+        }
+        if (s < 0 && first_err == CCG_OK) first_err = s;
+        if (s == CCG_NOT_CONVERGED) any_nc = true;
+    };
     const ccg_status st = guarded(c, [&]() -> ccg_status {
         const bool graphs = !(count > 0 && (probs[0].opts.flags & CCG_NO_GRAPH));
-        Engine eng(c->device, c->stream, c->budget, graphs);
-        std::deque<int> queue;
-        for (int i = 0; i < count; ++i) queue.push_back(i);
-        auto record = [&](int i, ccg_status s, const ccg_info* inf) {
-            if (infos) {
-                if (inf) infos[i] = *inf;
-                infos[i].status = s;
-            }
-            if (s < 0 && first_err == CCG_OK) first_err = s;
-            if (s == CCG_NOT_CONVERGED) any_nc = true;
-        };
-        while (!queue.empty() || !eng.idle()) {
-            while (!queue.empty()) {
-                const int i = queue.front();
-                const ccg_opts o = fill_defaults(&probs[i].opts);
-                if (!eng.could_fit(Engine::footprint(probs[i], o))) {
-                    record(i, CCG_ERR_NOMEM, nullptr);
-                    queue.pop_front();
-                    continue;
-                }
-                bool ok = false;
-                try {
-                    ok = eng.admit(probs[i], (uint64_t)i);
-                } catch (const CcgError& e) {
-                    if (e.st == CCG_ERR_DEVICE) throw;
-                    record(i, e.st, nullptr);
-                    queue.pop_front();
-                    continue;
-                }
-                if (!ok) {
-                    if (eng.idle()) {   // nothing resident and still no room: never fits
+        Arena arena(c->budget);
+        std::deque<int> queues[kLanes];
+        for (int i = 0; i < count; ++i) queues[lane_of(probs[i].n)].push_back(i);
+        std::atomic<bool> abort_lanes{false};
+        // one lane: admit in order while memory allows, run rounds until its systems
+        // have all retired
+        auto run_lane = [&](int lane, hipStream_t s) {
+            Engine eng(c->device, s, arena, graphs);
+            std::deque<int>& queue = queues[lane];
+            while ((!queue.empty() || !eng.idle()) && !abort_lanes.load()) {
+                bool wait_memory = false;
+                while (!queue.empty()) {
+                    const int i = queue.front();
+                    const ccg_opts o = fill_defaults(&probs[i].opts);
+                    if (!eng.could_fit(Engine::footprint(probs[i], o))) {
                         record(i, CCG_ERR_NOMEM, nullptr);
                         queue.pop_front();
                         continue;
                     }
-                    break;
+                    bool ok = false;
+                    try {
+                        ok = eng.admit(probs[i], (uint64_t)i);
+                    } catch (const CcgError& e) {
+                        if (e.st == CCG_ERR_DEVICE) throw;
+                        record(i, e.st, nullptr);
+                        queue.pop_front();
+                        continue;
+                    }
+                    if (!ok) {
+                        if (eng.idle()) {
+                            if (arena.empty()) {   // nothing resident anywhere and still no room
+                                record(i, CCG_ERR_NOMEM, nullptr);
+                                queue.pop_front();
+                                continue;
+                            }
+                            wait_memory = true;    // the other lane holds the memory
+                        }
+                        break;
+                    }
+                    queue.pop_front();
                 }
-                queue.pop_front();
+                if (wait_memory) std::this_thread::sleep_for(std::chrono::microseconds(200));
+                eng.round(16);
+                for (auto& f : eng.take_finished()) record((int)f.tag, f.status, &f.info);
             }
-            eng.round(16);
-            for (auto& f : eng.take_finished()) record((int)f.tag, f.status, &f.info);
+        };
+        // the large-system lane runs on a thread and stream of its own
+        std::exception_ptr lane_err;
+        std::thread big;
+        hipStream_t s_big = nullptr;
+        if (!queues[1].empty()) {
+            HIP_OK(hipStreamCreateWithFlags(&s_big, hipStreamNonBlocking));
+            try {
+                big = std::thread([&] {
+                    try {
+                        (void)hipSetDevice(c->device);
+                        run_lane(1, s_big);
+                    } catch (...) {
+                        lane_err = std::current_exception();
+                        abort_lanes = true;
+                    }
+                });
+            } catch (const std::system_error&) {
+                (void)hipStreamDestroy(s_big);
+                throw CcgError{CCG_ERR_DEVICE, "could not start the large-system lane"};
+            }
         }
+        std::exception_ptr own_err;
+        try {
+            run_lane(0, c->stream);
+        } catch (...) {
+            own_err = std::current_exception();
+            abort_lanes = true;
+        }
+        if (big.joinable()) big.join();
+        if (s_big) (void)hipStreamDestroy(s_big);
+        if (own_err) std::rethrow_exception(own_err);
+        if (lane_err) std::rethrow_exception(lane_err);
         return CCG_OK;
     });
     if (st != CCG_OK) return st;
@@ -1141,11 +1229,12 @@ ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, cc
 
 ccg_status ccg_submit(ccg_ctx* c, const ccg_problem* prob, uint64_t* ticket) {
     if (!c || !prob || !ticket) return CCG_ERR_ARG;
+    int lane = 0;
     try {
         if (!c->server) {
-            Server* sv = new Server();
+            Server* sv = new Server(c->budget);
             c->server = sv;
-            sv->th = std::thread(serve, c, sv);
+            for (int l = 0; l < kLanes; ++l) sv->lanes[l].th = std::thread(serve, c, sv, l);
         }
         Server* sv = c->server;
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -1157,15 +1246,17 @@ ccg_status ccg_submit(ccg_ctx* c, const ccg_problem* prob, uint64_t* ticket) {
         Result r;
         r.t_submit = Clock::now();
         sv->results[t] = r;
-        sv->queue.push_back(Request{t, *prob, r.t_submit});
+        lane = lane_of(prob->n);
+        sv->lanes[lane].queue.push_back(Request{t, *prob, r.t_submit});
         *ticket = t;
     } catch (const std::bad_alloc&) {
         return CCG_ERR_NOMEM;
     } catch (const std::system_error&) {
-        c->err = "could not start the service thread";
+        c->err = "could not start the service threads";
+        stop_server(c);
         return CCG_ERR_DEVICE;
     }
-    c->server->wake.notify_all();
+    c->server->lanes[lane].wake.notify_all();
     return CCG_OK;
 }
 
@@ -1199,9 +1290,10 @@ ccg_status ccg_cancel(ccg_ctx* c, uint64_t ticket) {
         auto it = sv->results.find(ticket);
         if (it == sv->results.end()) return CCG_ERR_ARG;
         if (it->second.done) return CCG_OK;
-        sv->cancels.push_back(ticket);
+        // the lane that holds the request acts on it; the others find nothing
+        for (auto& l : sv->lanes) l.cancels.push_back(ticket);
     }
-    sv->wake.notify_all();
+    for (auto& l : sv->lanes) l.wake.notify_all();
     return CCG_OK;
 }
 
