@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served mode: HBM budget")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
                     help="served mode: skip the plain FP64 comparison")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="time read-only streams of the A.D traffic shape at --n (ccg_stream_probe)")
     ap.add_argument("--dump", default=None, help="served mode: write per-request records (JSON) here")
     ap.add_argument("--single-fp64", action="store_true",
                     help="batched mode: time the plain FP64 baseline instead (every 8th system, one "
@@ -129,6 +131,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.stream_ceiling:
+        return stream_ceiling(args)
 
     if args.mode == "batched":
         return run_batched(args)
@@ -264,6 +268,24 @@ def _oracle_rate(samples):
         spent += dt
         coef.append(dt / ((k + 1) * A.shape[0] ** 2))
     return float(sum(coef) / len(coef)), spent
+
+
+def stream_ceiling(args):
+    """Read-only streams of an n x n FP64 matrix in the A.D kernel's traffic shape:
+    whole columns per workgroup, with and without the per-workgroup re-read of an
+    n x p direction block.  One JSON line; GB/s counts the matrix bytes only."""
+    import torch  # noqa: F401  (loads the HIP runtime the library shares)
+    from paper_1204_0069_amd import Context
+    ctx = Context(0)
+    n = args.n
+    rows = []
+    for dcols in (0, args.p):
+        for cols in (4, 8, 16, 32):
+            us = ctx.stream_probe(n, cols, dcols, reps=20)
+            rows.append({"cols_per_workgroup": cols, "direction_cols": dcols, "median_us": round(us, 2),
+                         "GB_s": round(8.0 * n * n / (us * 1e-6) / 1e9, 1)})
+    ctx.close()
+    print(json.dumps({"probe": "ccg_stream_probe", "n": n, "matrix_bytes": 8 * n * n, "rows": rows}))
 
 
 def run_batched(args):

@@ -72,7 +72,8 @@ typedef enum {
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
     int prec;            /* ccg_prec; default CCG_FP64 */
-    double inner_tol;    /* low-precision modes: inner relative tolerance (default 1e-4) */
+    double inner_tol;    /* low-precision modes: inner relative tolerance of the first
+                            outer step and its lower bound (default 1e-4) */
     int inner_maxit;     /* low-precision modes: block steps per refinement (default 500) */
     int max_refine;      /* low-precision modes: outer refinement steps (default 60) */
     double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
@@ -124,7 +125,10 @@ const char *ccg_last_error(const ccg_ctx *ctx);
  *    forms the explicit FP64 residual T = B - A X, runs cCG on A E = T (columns of T
  *    scaled to unit norm) with FP32 vectors and FP32 accumulation of A.D, FP64 Gram
  *    products, alpha and beta, until min_j of the inner relative residual is below
- *    inner_tol or inner_maxit steps, then sets X += E (FP64).  The result is
+ *    the inner tolerance or inner_maxit steps, then sets X += E (FP64).  The inner
+ *    tolerance is inner_tol in the first outer step, then a quarter of the factor by
+ *    which the last outer step lowered the FP64 residual (within [inner_tol, 0.05]).
+ *    The result is
  *    converged when the FP64 residual meets tol, as in CCG_FP64.  Returns
  *    CCG_ERR_BREAKDOWN when three outer steps in a row fail to lower the best FP64
  *    residual (e.g. when cond(A) times the rounding of the low-precision copy is
@@ -209,6 +213,15 @@ ccg_status ccg_convert_matrix(ccg_ctx *ctx, int n, const double *A, int64_t lda,
  * launches.  Uses and overwrites the context's workspace.  For the autotuner that
  * writes the library's table of tile widths (paper_1204_0069_amd/tune.py). */
 ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int reps, double *us);
+
+/* Median duration in microseconds, over `reps` launches after 2 warm-up launches, of
+ * a kernel that only reads: an n x n FP64 matrix (column-major, lda = n; n even),
+ * `cols` whole columns per workgroup (cols divides n), with 16-byte non-temporal
+ * loads, and, when dcols > 0 (at most 16), also the whole of an n x dcols FP64 block
+ * in every workgroup, as the A.D tile kernel reads the direction block.  The
+ * floor that the memory system sets for that traffic, to set A.D timings against
+ * (not in the paper).  Allocates and frees its own n^2 + n dcols doubles. */
+ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int reps, double *us);
 
 /* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
  * block steps run with CCG_PROFILE since the last reset; reset != 0 clears them. */

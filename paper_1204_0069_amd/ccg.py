@@ -63,7 +63,7 @@ _lib = None
 # Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
 EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
            "ccg_solve_batched", "ccg_submit", "ccg_poll", "ccg_wait", "ccg_cancel",
-           "ccg_convert_matrix", "ccg_tune_ad", "ccg_kernel_time")
+           "ccg_convert_matrix", "ccg_tune_ad", "ccg_stream_probe", "ccg_kernel_time")
 
 
 def load_library(path: str = LIB_PATH):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_convert_matrix.restype = ctypes.c_int
     lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
     lib.ccg_tune_ad.restype = ctypes.c_int
+    lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.ccg_stream_probe.restype = ctypes.c_int
     lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     lib.ccg_kernel_time.restype = ctypes.c_int
     if path == LIB_PATH:
@@ -312,6 +314,15 @@ class Context:
         """Microseconds per A.D launch with tile width cw (see ccg_tune_ad)."""
         us = ctypes.c_double()
         st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, reps, ctypes.byref(us))
+        if st != 0:
+            raise self._err(st)
+        return us.value
+
+    def stream_probe(self, n: int, cols: int, dcols: int = 0, reps: int = 20) -> float:
+        """Median microseconds of the read-only stream of an n x n FP64 matrix, cols
+        columns per workgroup, plus an n x dcols block per workgroup (ccg_stream_probe)."""
+        us = ctypes.c_double()
+        st = self.lib.ccg_stream_probe(self.h, n, cols, dcols, reps, ctypes.byref(us))
         if st != 0:
             raise self._err(st)
         return us.value

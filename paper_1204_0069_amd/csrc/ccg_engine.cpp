@@ -197,6 +197,8 @@ struct Sys {
     // low-precision outer loop
     double nb = 1.0, best = 0.0;
     int iters = 0, refinements = 0, stall = 0;
+    double in_tol = 0.0;        // inner tolerance, following the outer contraction
+    double prev_minres = 0.0;   // FP64 residual before the current outer step
     RefArgs ra{};
     // totals of earlier precision stages (CCG_ESCALATE)
     ccg_opts o_user{};
@@ -459,6 +461,7 @@ class Engine {
         sy.iters = 0;
         sy.refinements = 0;
         sy.stall = 0;
+        sy.in_tol = sy.o.inner_tol;
     }
 
     // CCG_ESCALATE: the refinement broke down; the system goes on from its FP64 agents
@@ -665,6 +668,7 @@ class Engine {
                     sy.stall = 0;
                 }
                 sy.best = std::min(sy.best, h.minres);
+                sy.in_tol = next_inner_tol(sy.o.inner_tol, h.minres / sy.prev_minres);
                 decide(sy);
                 break;
             default:
@@ -693,7 +697,8 @@ class Engine {
         h.iter = 0;
         h.m = m;
         h.mask = mask;
-        h.tol = std::min(0.5, std::max(sy.o.inner_tol, 0.1 * sy.tol / h.minres));
+        sy.prev_minres = h.minres;
+        h.tol = std::min(0.5, std::max(sy.in_tol, 0.1 * sy.tol / h.minres));
         h.nb = 1.0;
         h.maxit = std::min(sy.o.inner_maxit, budget - sy.iters);
         sy.inner_start_due = true;

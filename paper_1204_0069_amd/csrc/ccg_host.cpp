@@ -384,9 +384,11 @@ LowCopy low_copy(ccg_ctx* c, int n, const double* A, int64_t lda, int prec) {
 // precision cCG inner solve.  Each outer step forms the explicit FP64 residual
 // T = B - A X, scales its columns to unit norm, runs cCG on A E = T in the low-
 // precision blocks (FP32 vectors and A.D accumulation; FP64 products, alpha and
-// beta) until the best agent's relative residual is below inner_tol (relaxed to
-// 0.1 tol / minres in the last steps, where less suffices), and adds E * scale to
-// the FP64 agents.  Stops when min_j ||b - A x_j|| / ||b|| <= tol.
+// beta) until the best agent's relative residual is below the inner tolerance, and
+// adds E * scale to the FP64 agents.  Stops when min_j ||b - A x_j|| / ||b|| <= tol.
+// The inner tolerance starts at inner_tol and then follows the contraction of the
+// FP64 residual that the last outer step reached (next_inner_tol).  In the last
+// steps it is relaxed to 0.1 tol / minres, where less suffices.
 ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
                        double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
@@ -416,6 +418,8 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
     const int gk = o.graph_k > 0 ? o.graph_k : 16;
     int iters = 0, refinements = 0, stall = 0;
     double best = h.minres;
+    double in_tol = o.inner_tol;   // inner tolerance (see above)
+    double prev = h.minres;        // FP64 residual before the current outer step
     ccg_status st = CCG_OK;
     RefArgs ra{};
     ra.n_pad = w.n_pad;
@@ -436,13 +440,14 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
             if (sc > 0.0) { mask |= 1u << j; h.keep[m++] = j; }
         }
         HIP_OK(launch_inner_init(ra, c->stream));
+        prev = h.minres;
         h.done = RUNNING;
         h.iter = 0;
         h.m = m;
         h.mask = mask;
         // no need to solve the correction more accurately than the outer target:
         // the best agent's residual after this step is about (inner tol) x minres
-        h.tol = std::min(0.5, std::max(o.inner_tol, 0.1 * tol / h.minres));
+        h.tol = std::min(0.5, std::max(in_tol, 0.1 * tol / h.minres));
         h.nb = 1.0;
         h.maxit = std::min(o.inner_maxit, maxit - iters);
         write_state(c);
@@ -475,6 +480,7 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
             stall = 0;
         }
         best = std::min(best, h.minres);
+        in_tol = next_inner_tol(o.inner_tol, h.minres / prev);
     }
     if (h.done == FAILED && st == CCG_OK) st = (ccg_status)h.status;
     HIP_OK(launch_unpack(n, w.n_pad, p, w.Xr, X, ldx, c->stream));

@@ -169,6 +169,16 @@ inline void check_common(int n, int p, const void* A, int64_t lda, const void* b
     if (lda < n || ldx < n) throw CcgError{CCG_ERR_ARG, "leading dimension smaller than n"};
 }
 
+// Inner tolerance of the next refinement step, from the factor rho by which the last
+// outer step lowered the FP64 residual.  When the rounding of the low-precision copy
+// limits an outer step to about rho*, solving the correction much more accurately
+// than rho* only adds block steps; a quarter of rho keeps the inner solve from
+// becoming the limit (the contraction then settles near 4/3 rho*), and the bound
+// 0.05 keeps every inner solve doing real work.  Never tighter than inner_tol.
+inline double next_inner_tol(double inner_tol, double rho) {
+    return std::min(0.05, std::max(inner_tol, 0.25 * rho));
+}
+
 inline void set_all_agents(DevState& h, int p) {
     h.m = p;
     h.mask = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
