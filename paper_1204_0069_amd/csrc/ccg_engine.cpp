@@ -10,11 +10,11 @@
 //   2. one batched explicit-residual pass (FP64 A.X, then the residual epilogue)
 //      over every system that needs one, per padded agent count,
 //   3. the starts of refinement inner solves (per system),
-//   4. k block steps over every resident system: per (precision, padded agent
-//      count, tile width) class, k pairs of batched A.D and update launches on a
-//      stream of the class, replayed from a graph captured on that stream; the
-//      class streams fork from and join back into the engine stream (a step is a
-//      no-op for a system that is not running),
+//   4. k block steps over every resident system (k by lane and mode, kRoundSteps):
+//      per (precision, padded agent count, tile width) class, k pairs of batched
+//      A.D and update launches on a stream of the class, replayed from a graph
+//      captured on that stream; the class streams fork from and join back into the
+//      engine stream (a step is a no-op for a system that is not running),
 // then reads every state header and moves each system through the same phases,
 // in the same order, as the single-system driver, so a system's result does not
 // depend on the systems it shares launches with.
@@ -155,6 +155,11 @@ class Arena {
 constexpr int kLanes = 2;
 constexpr int kLaneSplit = 4096;   // n at or above: the large-system lane
 inline int lane_of(int n) { return n >= kLaneSplit ? 1 : 0; }
+// Block steps per round: the small-system lane takes long rounds (its steps cost
+// microseconds, so the header exchange of a round would weigh on short ones); the
+// large-system lane shorter ones, so its phase changes wait less.
+constexpr int kRoundSteps[2][kLanes] = {{32, 16},    // batched
+                                        {32, 8}};    // served
 
 enum Phase : int {
     PH_INIT_RES,     // waiting for / past the first explicit residual
@@ -1058,7 +1063,7 @@ void serve(ccg_ctx* c, Server* sv, int lane) {
             }
             // the other lane holds the memory this lane waits for
             if (eng.idle() && taken < admit.size()) std::this_thread::sleep_for(std::chrono::microseconds(200));
-            eng.round(8);
+            eng.round(kRoundSteps[1][lane]);
             auto fin = eng.take_finished();
             if (!fin.empty()) {
                 const auto now = Clock::now();
@@ -1189,7 +1194,7 @@ ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, cc
                     queue.pop_front();
                 }
                 if (wait_memory) std::this_thread::sleep_for(std::chrono::microseconds(200));
-                eng.round(16);
+                eng.round(kRoundSteps[0][lane]);
                 for (auto& f : eng.take_finished()) record((int)f.tag, f.status, &f.info);
             }
         };
