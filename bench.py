@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x2"])
     ap.add_argument("--cpu-sample-steps", type=int, default=12,
                     help="block steps of the oracle timed on the host (0: skip)")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="time every A.D launch (all block steps launched directly)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
@@ -143,7 +145,7 @@ def main():
     import torch
 
     import ccg_inputs as ci
-    from paper_1204_0069_amd import CCG_PROFILE, Context
+    from paper_1204_0069_amd import CCG_PROFILE, CCG_PROFILE_SAMPLED, Context
 
     dev = "cuda:0"
     n, p = args.n, args.p
@@ -156,14 +158,15 @@ def main():
     torch.cuda.synchronize()
 
     ctx = Context(0)
-    flags = 0 if args.no_profile else CCG_PROFILE
+    flags = 0 if args.no_profile else (CCG_PROFILE if args.profile_all else CCG_PROFILE_SAMPLED)
     infos = []
     for _ in range(args.warmup):
         ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
     ctx.kernel_time(reset=True)
 
-    # Timed region: every A.D launch bracketed by HIP events on the library's stream
-    # (block steps launched directly; see CCG_PROFILE in include/ccg.h).
+    # Timed region: the A.D launches of every 4th round of 16 block steps bracketed by
+    # HIP events on the library's stream (launched directly); the other rounds replay
+    # the captured graph (CCG_PROFILE_SAMPLED; --profile-all times every launch).
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -205,6 +208,8 @@ def main():
                     "traffic": recorded_traffic(n, p, args.prec), "traffic_unit": "B/launch",
                     "kernel": "k_ad",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
+                    "timed": ("every A.D launch" if args.profile_all else
+                              "the A.D launches of every 4th round of 16 block steps"),
                     "bytes_per_launch": bytes_per_launch}
 
     cpu = None

@@ -68,6 +68,8 @@ typedef enum {
                                  positive or not finite), continue from the current agents
                                  in the next wider precision (BF16X2 -> FP32 -> FP64);
                                  info then totals every stage */
+#define CCG_PROFILE_SAMPLED 0x10u  /* as CCG_PROFILE for every 4th round of graph_k block
+                                      steps; the other rounds run from the captured graph */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
@@ -79,7 +81,8 @@ typedef struct {
     double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
                             low-precision modes, whose vectors carry FP32 rounding) */
     int graph_k;         /* block steps per captured graph / per host poll (default 16) */
-    unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_ESCALATE */
+    unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_PROFILE_SAMPLED |
+                            CCG_ESCALATE */
 } ccg_opts;
 
 /* Per-solve report. */
@@ -224,7 +227,8 @@ ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int reps, d
 ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int reps, double *us);
 
 /* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
- * block steps run with CCG_PROFILE since the last reset; reset != 0 clears them. */
+ * block steps run with CCG_PROFILE (every launch) or CCG_PROFILE_SAMPLED (the launches
+ * of the timed rounds) since the last reset; reset != 0 clears them. */
 ccg_status ccg_kernel_time(ccg_ctx *ctx, double *ms, long long *launches, int reset);
 
 #ifdef __cplusplus

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libccg.so")
 CCG_HOST_PTRS = 0x1
 CCG_NO_GRAPH = 0x2
 CCG_PROFILE = 0x4
+CCG_PROFILE_SAMPLED = 0x10
 CCG_ESCALATE = 0x8
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}

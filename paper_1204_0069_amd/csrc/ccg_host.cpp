@@ -73,8 +73,17 @@ struct Solve {
     int64_t lda;           // its leading dimension in elements
     const double* A64;     // FP64 matrix of the explicit residual
     int64_t lda64;
-    bool profile;
+    int profile_every;     // time the A.D launches of every n-th round of steps (0: none)
+    int rounds = 0;        // rounds of block steps run so far
 };
+
+// Timing of the A.D launches requested by the flags: every round (CCG_PROFILE),
+// every 4th (CCG_PROFILE_SAMPLED), or none.
+int profile_every(const ccg_opts& o) {
+    if (o.flags & CCG_PROFILE) return 1;
+    if (o.flags & CCG_PROFILE_SAMPLED) return 4;
+    return 0;
+}
 
 // Vector blocks of the block steps: FP64 for plain cCG, FP32 for the inner solve of
 // the refinement modes.
@@ -144,9 +153,9 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
 
 // One block step: A.D (+ products, stop test, rank step, alpha, beta), then the
 // X, R, D update.
-void enqueue_step(const Solve& s, size_t ev_slot) {
+void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     Workspace& w = s.c->ws;
-    if (s.profile) {
+    if (timed) {
         HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, pooled_event(s.c, 2 * ev_slot),
                          pooled_event(s.c, 2 * ev_slot + 1)));
     } else {
@@ -188,7 +197,7 @@ void capture_steps(Solve& s, int steps) {
     HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
     try {
-        for (int i = 0; i < steps; ++i) enqueue_step(s, 0);
+        for (int i = 0; i < steps; ++i) enqueue_step(s, 0, false);
     } catch (const CcgError&) {
         ok = false;
     }
@@ -202,14 +211,17 @@ void capture_steps(Solve& s, int steps) {
     HIP_OK(hipGraphDestroy(gr));
 }
 
-// Run `steps` block steps, through a captured graph when allowed.  While profiling,
-// steps are launched directly: the runtime does not time events recorded inside a
-// graph, so each A.D launch is bracketed by its own event pair on the stream.
-void run_steps(Solve& s, int steps, bool use_graph) {
+// Run `steps` block steps, through a captured graph when allowed.  A round whose
+// A.D launches are timed runs them directly, each bracketed by its own event pair
+// on the stream (the runtime does not time events recorded inside a graph).
+// Returns whether this round was timed.
+bool run_steps(Solve& s, int steps, bool use_graph) {
     ccg_ctx* c = s.c;
-    if (!use_graph || s.profile) {
-        for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i);
-        return;
+    const bool timed = s.profile_every > 0 && s.rounds % s.profile_every == 0;
+    ++s.rounds;
+    if (!use_graph || timed) {
+        for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i, timed);
+        return timed;
     }
     const int64_t key[6] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
                             s.lda};
@@ -221,6 +233,7 @@ void run_steps(Solve& s, int steps, bool use_graph) {
         std::copy(key, key + 6, c->graph_key);
     }
     HIP_OK(hipGraphLaunch(c->graph, c->stream));
+    return false;
 }
 
 // The A.D kernel reads columns with 16-byte loads.  A caller matrix whose columns
@@ -277,7 +290,7 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
     const double* Ause = aligned_matrix(c, n, A, lda);
-    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, (o.flags & CCG_PROFILE) != 0};
+    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, profile_every(o)};
     ensure_workspace(c, n, P);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
@@ -304,12 +317,12 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
             const int left = maxit - h.iter;
             const int k = left > 0 ? gk : 1;   // steps past maxit are no-ops: keep one graph
             const int it0 = h.iter;
-            run_steps(s, k, use_graph);
+            const bool timed = run_steps(s, k, use_graph);
             read_state(c);
             // A.D launches that streamed A: one per completed step, plus the one
             // whose stop test ended the batch
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
-            if (s.profile) collect_profile(c, streamed);
+            if (timed) collect_profile(c, streamed);
             bytes += bytes_iter * streamed;
         }
         if (h.done == RECUR_CONV) {
@@ -396,7 +409,7 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
     const double* A64 = aligned_matrix(c, n, A, lda);
     ensure_workspace(c, n, P);
     const LowCopy lc = low_copy(c, n, A64, lda, prec);
-    Solve s{c, n, p, P, prec, lc.hi, lc.lo, lc.ld, A64, lda, (o.flags & CCG_PROFILE) != 0};
+    Solve s{c, n, p, P, prec, lc.hi, lc.lo, lc.ld, A64, lda, profile_every(o)};
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -454,10 +467,10 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
         while (h.done == RUNNING) {
             const int k = gk;   // steps past maxit are no-ops: keep one graph
             const int it0 = h.iter;
-            run_steps(s, k, use_graph);
+            const bool timed = run_steps(s, k, use_graph);
             read_state(c);
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
-            if (s.profile) collect_profile(c, streamed);
+            if (timed) collect_profile(c, streamed);
             bytes += s_low * n * n * streamed;
         }
         iters += h.iter;
@@ -638,7 +651,7 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         const ccg_opts o = fill_defaults(opts);
         const int P = pad_agents(p);
         const double* Ause = aligned_matrix(c, n, A, lda);
-        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, false};
+        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, 0};
         ensure_workspace(c, n, P);
         Workspace& w = c->ws;
         HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
@@ -657,7 +670,7 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         enqueue_residual(s, RES_INIT, 1);
         read_state(c);
         for (int k = 0; k < ksteps && h.done == RUNNING; ++k) {
-            enqueue_step(s, 0);
+            enqueue_step(s, 0, false);
             read_state(c);
             for (int cc = 0; cc < p; ++cc)
                 for (int r = 0; r < p; ++r) {
@@ -707,7 +720,7 @@ ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int reps, dou
         HIP_OK(launch_tune_vectors(blk, w.D, w.Dl, 1u, c->stream));
         HIP_OK(launch_tune_vectors(blk, w.R, w.Rl, 2u, c->stream));
         const LowCopy lc = pr == PREC_F64 ? LowCopy{A, nullptr, lda, 0.0} : low_copy(c, n, A, lda, pr);
-        Solve s{c, n, p, P, pr, lc.hi, lc.lo, lc.ld, A, lda, false};
+        Solve s{c, n, p, P, pr, lc.hi, lc.lo, lc.ld, A, lda, 0};
         DevState& h = *c->st_host;
         std::memset(&h, 0, sizeof(DevState));
         h.done = RUNNING;

@@ -141,6 +141,25 @@ def test_graph_and_direct_launch_agree(gpu_ctx):
     assert torch.equal(X1, X2)
 
 
+def test_profiled_solves_agree_and_count_launches(gpu_ctx):
+    """Timing the A.D launches (every round, or every 4th round with the rest from the
+    graph) changes how steps are launched, not what they compute."""
+    from paper_1204_0069_amd import CCG_PROFILE, CCG_PROFILE_SAMPLED
+    A, b, X0 = ci.system(700, 3, 1e3, seed=9)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000)
+    gpu_ctx.kernel_time(reset=True)
+    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_PROFILE)
+    ms_all, n_all = gpu_ctx.kernel_time(reset=True)
+    X3, i3 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_PROFILE_SAMPLED)
+    ms_s, n_s = gpu_ctx.kernel_time(reset=True)
+    assert i1["iters"] == i2["iters"] == i3["iters"]
+    assert torch.equal(X1, X2) and torch.equal(X1, X3)
+    assert i1["iters"] > 64                            # several rounds of 16 steps
+    assert n_all == i1["iters"] + 1 + i1["restarts"]   # every launch that streamed A
+    assert 0 < n_s < n_all                             # the launches of every 4th round
+    assert ms_all > 0.0 and ms_s > 0.0
+
+
 # ----------------------------------------------------------------- edge cases
 
 def test_duplicate_columns_deflate(gpu_ctx):
