@@ -15,7 +15,7 @@ namespace ccg {
 constexpr int kMaxP = 16;       // largest padded agent count
 constexpr int kWG = 256;        // threads per workgroup for every kernel
 constexpr int kRowAlign = 512;  // n_pad granularity
-constexpr int kGroup = 16;      // workgroups per first-level reduction group
+constexpr int kGroup = 32;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 

@@ -142,16 +142,18 @@ __device__ __forceinline__ void reset_ticket(unsigned* c) {
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Sum, for entry e, the rows m0 .. m0+cnt-1 of src (row stride ne) in row order.
-// Loads are issued in unrolled batches of 16 so that their latencies overlap.
+// Loads are issued in unrolled batches of B so that their latencies overlap; the
+// batch only groups the loads, the additions stay in row order.
+template <int B>
 __device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int m0, int cnt) {
     double s = 0.0;
-    for (int base = 0; base < cnt; base += 16) {
-        double v[16];
+    for (int base = 0; base < cnt; base += B) {
+        double v[B];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
+        for (int q = 0; q < B; ++q)
             v[q] = (base + q < cnt) ? ld_agent(&src[(int64_t)(m0 + base + q) * ne + e]) : 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
+        for (int q = 0; q < B; ++q)
             if (base + q < cnt) s += v[q];
     }
     return s;
@@ -160,6 +162,7 @@ __device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int
 // out[e] = sum over rows 0..cnt-1 of src (row stride ne), for every e < ne, with the
 // rows of each entry split into contiguous slices over spare threads and the slice
 // sums added in slice order (a fixed tree).  scratch: kWG doubles of LDS.
+template <int B>
 __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
     const int tid = threadIdx.x;
     const int tpe = ne >= kWG ? 1 : kWG / ne;          // threads per entry
@@ -169,7 +172,7 @@ __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, do
         double s = 0.0;
         if (e < ne && tid / tpe < kWG / tpe) {
             const int m0 = sub * slice;
-            s = sum_rows(src, ne, e, m0, max(0, min(slice, cnt - m0)));
+            s = sum_rows<B>(src, ne, e, m0, max(0, min(slice, cnt - m0)));
         }
         scratch[tid] = s;
         __syncthreads();
@@ -185,7 +188,12 @@ __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, do
 // Sum `ne` values per tile (mine[], LDS) over the nwg tiles of one system, in tile
 // order within groups of kGroup and in group order across groups.  Returns true in
 // the one workgroup that ends up holding the totals in out[] (LDS).  Tickets are
-// reset by their last taker, so the scratch is ready for the next launch.
+// reset by their last taker, so the scratch is ready for the next launch.  B: loads
+// in flight per thread while summing rows; with B = kGroup a group's rows, and the
+// group sums of up to kGroup^2 tiles, take one round trip to memory each where
+// every entry has a thread of its own (large ne), at the price of registers that
+// the kernels with few agents would pay in occupancy.
+template <int B>
 __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const RedBuf rb, double* out,
                                             int* s_flag, double* scratch, int bid, int nwg) {
     const int tid = threadIdx.x;
@@ -200,11 +208,11 @@ __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const Re
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[grp]);
     if (ngroups == 1) {
-        sum_table(rb.l1, ne, gsize, out, scratch);
+        sum_table<B>(rb.l1, ne, gsize, out, scratch);
         return true;
     }
     // group sum -> level-2 row of this group
-    sum_table(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    sum_table<B>(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
     for (int e = tid; e < ne; e += kWG) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
     stores_done();
     __syncthreads();
@@ -212,7 +220,7 @@ __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const Re
     __syncthreads();
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
-    sum_table(rb.l2, ne, ngroups, out, scratch);
+    sum_table<B>(rb.l2, ne, ngroups, out, scratch);
     return true;
 }
 
@@ -633,7 +641,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
         gmine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
+    if (!grid_reduce<(P >= 8 ? kGroup : 16)>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
 
     // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
     DevState* st = a.st;
@@ -932,7 +940,7 @@ __device__ __forceinline__ void res_tile(const ResArgs& a, const int tile, const
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
+    if (!grid_reduce<(P >= 8 ? kGroup : 16)>(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
     if (tid == 0) {
         if (a.set_nb) st->nb = sqrt(tot[P * P]);
         double mn = INFINITY;
