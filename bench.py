@@ -60,8 +60,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=48, help="served mode: timed requests")
     ap.add_argument("--pool", type=int, default=12, help="served mode: distinct matrices")
     ap.add_argument("--n-hi", type=int, default=16384, help="served mode: largest n")
+    ap.add_argument("--rate-frac", type=float, default=0.5,
+                    help="served mode: arrival rate as a fraction of the closed-loop rate")
     ap.add_argument("--rate", type=float, default=0.0,
-                    help="served mode: arrivals per second (0: half the measured closed-loop rate)")
+                    help="served mode: arrivals per second (0: --rate-frac x the measured closed-loop rate)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served mode: HBM budget")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
                     help="served mode: skip the plain FP64 comparison")
@@ -443,7 +445,7 @@ def run_served(args):
     for t in ts:
         ctx.wait(t)
     closed = 8 / (time.perf_counter() - c0)
-    rate = args.rate if args.rate > 0 else 0.5 * closed
+    rate = args.rate if args.rate > 0 else args.rate_frac * closed
     gaps = rng.exponential(1.0 / rate, args.requests)
     arrivals = np.cumsum(gaps) - gaps[0]
     tickets = []
@@ -469,8 +471,9 @@ def run_served(args):
         "steps": args.requests, "warmup": 8, "ms_per_step": round(total / args.requests * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
         "data": "synthetic",
-        "config": {"workload": f"served stream: Poisson arrivals at {rate:.3f}/s (half the closed-loop "
-                               f"rate {closed:.3f}/s), n log-uniform in [128, {args.n_hi}], p=4, kappa "
+        "config": {"workload": f"served stream: Poisson arrivals at {rate:.3f}/s ({rate / closed:.2f} x the "
+                               f"closed-loop rate {closed:.3f}/s of the first 8 requests), n log-uniform in "
+                               f"[128, {args.n_hi}], p=4, kappa "
                                f"log-uniform in [1e2, 1e6], precision uniform over fp64/fp32/bf16x2, "
                                f"{args.pool} pooled matrices in pinned host memory (upload in latency), "
                                f"precision escalation on breakdown, "
