@@ -459,6 +459,18 @@ def run_served(args):
     total = time.perf_counter() - t0
     infos = [r[1] for r in results]
     lat = np.array([i["seconds"] for i in infos]) * 1e3
+    # upload share of each latency: A, b and X0 at the pinned-memory copy rate measured
+    # here (largest pool matrix, host to device, after the stream)
+    big = max(range(len(pool)), key=lambda k: pool[k][0])
+    torch.cuda.synchronize()
+    u0 = time.perf_counter()
+    tmp = pool[big][2].to(dev, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = pool[big][2].numel() * 8 / (time.perf_counter() - u0)
+    del tmp
+    up_ms = np.array([(pool[reqs[8 + j][0]][0] ** 2 + 5 * pool[reqs[8 + j][0]][0]) * 8 / h2d * 1e3
+                      for j in range(args.requests)])
+    lat_x = lat - up_ms
     st = {}
     for i, j in zip(infos, range(args.requests)):
         key = f"{reqs[8 + j][3]}:{i['status_name']}"
@@ -480,6 +492,9 @@ def run_served(args):
                                f"HBM budget {args.budget_gib:g} GiB", "requests": args.requests},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},
+        "latency_ms_excluding_upload": {"p50": round(float(np.percentile(lat_x, 50)), 3),
+                                        "p99": round(float(np.percentile(lat_x, 99)), 3),
+                                        "h2d_GB_s": round(h2d / 1e9, 1)},
         "statuses": st,
         "rel_res_max_converged": float(max((i["rel_res"] for i in ok), default=float("nan"))),
         "roofline": {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

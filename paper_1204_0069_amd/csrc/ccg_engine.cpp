@@ -1035,7 +1035,9 @@ void serve(ccg_ctx* c, Server* sv, int lane) {
                         msg = "system exceeds the HBM budget";
                     } else {
                         ok = eng.admit(rq.prob, rq.ticket);
-                        // nothing resident in any lane and still no room: never fits
+                        // nothing resident in any lane and still no room: never fits (one
+                        // more try, in case the other lane released its memory meanwhile)
+                        if (!ok && eng.idle() && sv->arena.empty()) ok = eng.admit(rq.prob, rq.ticket);
                         if (!ok && eng.idle() && sv->arena.empty()) {
                             err = CCG_ERR_NOMEM;
                             msg = "no device memory for the system";
@@ -1174,6 +1176,8 @@ ccg_status ccg_solve_batched(ccg_ctx* c, int count, const ccg_problem* probs, cc
                     bool ok = false;
                     try {
                         ok = eng.admit(probs[i], (uint64_t)i);
+                        // the other lane may have released its memory meanwhile
+                        if (!ok && eng.idle() && arena.empty()) ok = eng.admit(probs[i], (uint64_t)i);
                     } catch (const CcgError& e) {
                         if (e.st == CCG_ERR_DEVICE) throw;
                         record(i, e.st, nullptr);

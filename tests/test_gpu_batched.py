@@ -189,3 +189,29 @@ def test_batched_escalation_equals_single(gpu_ctx):
         assert s[1]["prec_final"] == b[1]["prec_final"]
     assert all(b[1]["status"] == 0 for b in batched), [b[1] for b in batched]
     assert batched[0][1]["prec_final"] != 2      # the first system escalated
+
+# Systems with n >= 4096 run in the large-system lane (its own stream and thread),
+# the rest in the small-system lane; the lanes share the context's HBM budget.
+LANES = [(4096, 2, 1e2, "fp64"), (4200, 4, 1e2, "fp32"), (4200, 3, 1e2, "fp32"),
+         (300, 3, 1e3, "fp64"), (900, 4, 1e3, "fp32"), (1500, 2, 1e2, "bf16x2")]
+
+
+def test_both_lanes_equal_single_solves_under_a_shared_budget(gpu_ctx):
+    """The two FP32 copies of the n = 4200 matrices (70 MB each) do not fit the 100 MB
+    budget together, so the large lane runs them one after the other while the small
+    lane goes on; every result equals its single solve, batched and served."""
+    print("case lanes: batched and served, 6 systems, budget 100 MB", flush=True)
+    systems = _systems(LANES, seed=1600)
+    singles = [_single(gpu_ctx, sy) for sy in systems]
+    ctx = Context(0, hbm_budget=100 << 20)
+    try:
+        batched = ctx.solve_batched(systems)
+        tickets = [ctx.submit(sy["A"], sy["b"], sy["X0"], sy["tol"], sy["maxit"], prec=sy["prec"])
+                   for sy in systems]
+        served = [ctx.wait(t) for t in tickets]
+    finally:
+        ctx.close()
+    for s_, b_, v_ in zip(singles, batched, served):
+        _same(s_, b_)
+        _same(s_, v_)
+    assert all(b_[1]["status"] == 0 for b_ in batched)
