@@ -589,14 +589,6 @@ class Engine {
                                 hipMemcpyDeviceToHost, s_));
         HIP_OK(hipStreamSynchronize(s_));
         // --- advance every system
-#ifdef CCG_ENGINE_TRACE
-        for (auto& sy : live_) {
-            const DevState& h = h_states_[sy.slot];
-            fprintf(stderr, "round slot %d n %d P %d ph %d res %d/%d | done %d iter %d minres %.3e nb %.3e mask %x\n",
-                    sy.slot, sy.n, sy.P, (int)sy.ph, (int)sy.res_due, sy.res_mode, h.done, h.iter, h.minres, h.nb,
-                    h.mask);
-        }
-#endif
         for (auto& sy : live_) advance(sy);
         finish_retired();
     }
