@@ -4,8 +4,10 @@
 // whole columns (one contiguous chunk of cols * n doubles) per workgroup, with
 // 16-byte non-temporal loads, and adds it up.  With an n x dcols block D it also
 // reads the whole of D in every workgroup, spread over its chunk, as the A.D tile
-// kernel does with the direction block.  It does no other work, so its time is the
-// floor that the memory system sets for that pattern of traffic.
+// kernel does with the direction block.  With `stagger`, workgroup b starts its
+// chunk at step (7 b) mod steps and wraps around, as the A.D kernel staggers its
+// tiles.  It does no other work, so its time is the floor that the memory system
+// sets for that pattern of traffic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,13 +21,16 @@ namespace {
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(kWG) void k_stream(const dvec2* __restrict__ a, int64_t chunk,
-                                                const dvec2* __restrict__ d, int64_t dlen, double* out) {
+                                                const dvec2* __restrict__ d, int64_t dlen, int stagger,
+                                                double* out) {
     constexpr int U = 4;
     const dvec2* p = a + (int64_t)blockIdx.x * chunk;
     const int64_t steps = (chunk + kWG * U - 1) / (kWG * U);
     const int64_t dstep = d ? (dlen + steps - 1) / steps : 0;
     double s = 0.0;
-    for (int64_t k = 0; k < steps; ++k) {
+    const int64_t k0 = stagger ? (7 * (int64_t)blockIdx.x) % steps : 0;
+    for (int64_t kk = 0; kk < steps; ++kk) {
+        const int64_t k = (k0 + kk) % steps;
         const int64_t i = threadIdx.x + k * kWG * U;
         dvec2 v[U];
 #pragma unroll
@@ -54,7 +59,8 @@ __global__ __launch_bounds__(kWG) void k_stream(const dvec2* __restrict__ a, int
 using namespace ccg;
 using namespace ccg::host;
 
-extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, int reps, double* us) {
+extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, int stagger, int reps,
+                                       double* us) {
     return guarded(c, [&]() -> ccg_status {
         if (n < 2 || n % 2 || cols < 1 || n % cols || dcols < 0 || dcols > kMaxP || reps < 1 || !us)
             throw CcgError{CCG_ERR_ARG, "bad probe argument (n even, cols dividing n, 0 <= dcols <= 16)"};
@@ -83,7 +89,8 @@ extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, i
         ccg_status st = CCG_OK;
         for (int r = 0; r < reps + 2 && st == CCG_OK; ++r) {
             if (hipEventRecord(e0, c->stream) != hipSuccess) { st = CCG_ERR_DEVICE; break; }
-            hipLaunchKernelGGL(k_stream, dim3(nwg), dim3(kWG), 0, c->stream, a, chunk, d, dlen, out);
+            hipLaunchKernelGGL(k_stream, dim3(nwg), dim3(kWG), 0, c->stream, a, chunk, d, dlen, stagger ? 1 : 0,
+                               out);
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, c->stream) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess) {
                 st = CCG_ERR_DEVICE;
