@@ -115,6 +115,22 @@ def test_refined_graph_and_direct_launch_agree(gpu_ctx):
     assert torch.equal(X1, X2)
 
 
+def test_refined_timed_launches_agree(gpu_ctx):
+    """Timing the inner A.D launches (every round, or every 4th) leaves the refined
+    solve bit for bit the same."""
+    from paper_1204_0069_amd import CCG_PROFILE, CCG_PROFILE_SAMPLED
+    A, b, X0 = ci.system(900, 4, 1e3, seed=11)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32")
+    gpu_ctx.kernel_time(reset=True)
+    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32", flags=CCG_PROFILE_SAMPLED)
+    _, n_s = gpu_ctx.kernel_time(reset=True)
+    X3, i3 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32", flags=CCG_PROFILE)
+    _, n_all = gpu_ctx.kernel_time(reset=True)
+    assert i1["iters"] == i2["iters"] == i3["iters"]
+    assert torch.equal(X1, X2) and torch.equal(X1, X3)
+    assert 0 < n_s < n_all
+
+
 def test_refinement_limits(gpu_ctx):
     A, b, X0 = ci.system(500, 4, 1e3, seed=12)
     # one outer step cannot reach 1e-10 with an inner tolerance of 1e-4
