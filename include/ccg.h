@@ -209,13 +209,14 @@ ccg_status ccg_convert_matrix(ccg_ctx *ctx, int n, const double *A, int64_t lda,
                               void *hi, void *lo);
 
 /* Average duration in microseconds of one A.D launch (the block step's stream of A,
- * products, stop test and p x p solves; not in the paper) with tile width `cw` (A
- * columns per wave: 1, 2 or 4; a width beyond the register budget runs at the
- * nearest one that fits) on a synthetic symmetric diagonally dominant system of
- * size n with p agents in precision `prec`, over `reps` launches after 2 warm-up
- * launches.  Uses and overwrites the context's workspace.  For the autotuner that
- * writes the library's table of tile widths (paper_1204_0069_amd/tune.py). */
-ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int reps, double *us);
+ * products, stop test and p x p solves; not in the paper) with tile shape `cw` A
+ * columns per wave (1, 2 or 4) and `nw` waves per workgroup (4, 8 or 16; a shape
+ * beyond the register budget runs at the nearest one that fits) on a synthetic
+ * symmetric diagonally dominant system of size n with p agents in precision `prec`,
+ * over `reps` launches after 2 warm-up launches.  Uses and overwrites the context's
+ * workspace.  For the autotuner that writes the library's table of tile shapes
+ * (paper_1204_0069_amd/tune.py). */
+ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int reps, double *us);
 
 /* Median duration in microseconds, over `reps` launches after 2 warm-up launches, of
  * a kernel that only reads: an n x n FP64 matrix (column-major, lda = n; n even),

@@ -102,7 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_cancel.restype = ctypes.c_int
     lib.ccg_convert_matrix.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp]
     lib.ccg_convert_matrix.restype = ctypes.c_int
-    lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, dp]
     lib.ccg_tune_ad.restype = ctypes.c_int
     lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
     lib.ccg_stream_probe.restype = ctypes.c_int
@@ -311,10 +312,10 @@ class Context:
         del keep
         return hi if lo is None else (hi, lo)
 
-    def tune_ad(self, prec: str, p: int, n: int, cw: int, reps: int = 10) -> float:
-        """Microseconds per A.D launch with tile width cw (see ccg_tune_ad)."""
+    def tune_ad(self, prec: str, p: int, n: int, cw: int, reps: int = 10, nw: int = 4) -> float:
+        """Microseconds per A.D launch with tile shape (cw, nw) (see ccg_tune_ad)."""
         us = ctypes.c_double()
-        st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, reps, ctypes.byref(us))
+        st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, nw, reps, ctypes.byref(us))
         if st != 0:
             raise self._err(st)
         return us.value

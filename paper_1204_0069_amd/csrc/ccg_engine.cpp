@@ -11,7 +11,7 @@
 //      over every system that needs one, per padded agent count,
 //   3. the starts of refinement inner solves (per system),
 //   4. k block steps over every resident system (k by lane and mode, kRoundSteps):
-//      per (precision, padded agent count, tile width) class, k pairs of batched
+//      per (precision, padded agent count, tile shape) class, k pairs of batched
 //      A.D and update launches on a stream of the class, replayed from a graph
 //      captured on that stream; the class streams fork from and join back into the
 //      engine stream (a step is a no-op for a system that is not running),
@@ -175,7 +175,9 @@ struct Sys {
     int slot = -1;
     // problem
     int n = 0, p = 0, P = 0, prec = PREC_F64;
-    int cw_step = 2, cw_res = 2;   // A.D tile widths of the block step and the residual
+    // A.D tile shapes (columns per wave, waves per workgroup) of the block step and
+    // of the explicit residual
+    int cw_step = 2, nw_step = 4, cw_res = 2, nw_res = 4;
     double tol = 0.0;
     int maxit = 0;
     ccg_opts o{};
@@ -224,7 +226,7 @@ struct Finished {
 class Engine {
     // a step class's items: A.D tiles at ad_off, update tiles at up_off in the list
     struct StepRange {
-        int prec, P, cw;
+        int prec, P, cw, nw;
         size_t ad_off, ad_n, up_off, up_n;
     };
 
@@ -304,7 +306,9 @@ class Engine {
         sy.P = pad_agents(pr.p);
         sy.prec = o.prec == CCG_FP64 ? PREC_F64 : (o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
         sy.cw_step = ad_cw(sy.prec, sy.P, pr.n);
+        sy.nw_step = ad_nw(sy.prec, sy.P, pr.n);
         sy.cw_res = ad_cw(PREC_F64, sy.P, pr.n);
+        sy.nw_res = ad_nw(PREC_F64, sy.P, pr.n);
         sy.tol = pr.tol;
         sy.maxit = pr.maxit;
         sy.o = o;
@@ -497,6 +501,7 @@ class Engine {
             sy.prec = PREC_F64;
         }
         sy.cw_step = ad_cw(sy.prec, sy.P, sy.n);
+        sy.nw_step = ad_nw(sy.prec, sy.P, sy.n);
         write_records(sy);
         start_stage(sy);
         items_dirty_ = true;
@@ -523,25 +528,27 @@ class Engine {
         if (items_dirty_ || dead_items_ * 8 > step_items_total_ || graph_k_ != k) rebuild_steps(k);
         // --- explicit-residual work list
         items_.clear();
-        struct Range { int P, cw; size_t ad_off, ad_n, up_off, up_n; };
+        struct Range { int P, cw, nw; size_t ad_off, ad_n, up_off, up_n; };
         std::vector<Range> res_ranges;
         for (int P : {1, 2, 4, 8, 16}) {
             for (int cw : {1, 2, 4}) {
-                Range rr{P, cw, items_.size(), 0, 0, 0};
-                for (auto& sy : live_) {
-                    if (!sy.res_due || sy.P != P || sy.cw_res != cw) continue;
-                    const int t = (sy.n + 4 * cw - 1) / (4 * cw);
-                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+                for (int nw : {4, 8, 16}) {
+                    Range rr{P, cw, nw, items_.size(), 0, 0, 0};
+                    for (auto& sy : live_) {
+                        if (!sy.res_due || sy.P != P || sy.cw_res != cw || sy.nw_res != nw) continue;
+                        const int t = (sy.n + cw * nw - 1) / (cw * nw);
+                        for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, 0, 0});
+                    }
+                    rr.ad_n = items_.size() - rr.ad_off;
+                    rr.up_off = items_.size();
+                    for (auto& sy : live_) {
+                        if (!sy.res_due || sy.P != P || sy.cw_res != cw || sy.nw_res != nw) continue;
+                        const int t = sy.w.n_pad / (kWG / P);
+                        for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, sy.res_mode, sy.res_set_nb});
+                    }
+                    rr.up_n = items_.size() - rr.up_off;
+                    if (rr.ad_n) res_ranges.push_back(rr);
                 }
-                rr.ad_n = items_.size() - rr.ad_off;
-                rr.up_off = items_.size();
-                for (auto& sy : live_) {
-                    if (!sy.res_due || sy.P != P || sy.cw_res != cw) continue;
-                    const int t = sy.w.n_pad / (kWG / P);
-                    for (int i = 0; i < t; ++i) items_.push_back(int4{sy.slot, i, sy.res_mode, sy.res_set_nb});
-                }
-                rr.up_n = items_.size() - rr.up_off;
-                if (rr.ad_n) res_ranges.push_back(rr);
             }
         }
         upload_items();
@@ -554,7 +561,7 @@ class Engine {
             if (sy.refine_due) HIP_OK(launch_refine_add(sy.ra, s_));
         // 2. explicit residuals
         for (const Range& r : res_ranges) {
-            HIP_OK(launch_ad_batch(PREC_F64, r.P, r.cw, d_res_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
+            HIP_OK(launch_ad_batch(PREC_F64, r.P, r.cw, r.nw, d_res_ad_, d_items_ + r.ad_off, (int)r.ad_n, s_));
             HIP_OK(launch_res_batch(r.P, d_res_, d_items_ + r.up_off, (int)r.up_n, s_));
         }
         // 3. inner-solve starts
@@ -763,7 +770,7 @@ class Engine {
         // no-ops, and the slot is reused only after the list is rebuilt
         h.done = FINISHED;
         pending_slots_.push_back(sy.slot);
-        dead_items_ += (size_t)((sy.n + 4 * sy.cw_step - 1) / (4 * sy.cw_step));
+        dead_items_ += (size_t)((sy.n + sy.cw_step * sy.nw_step - 1) / (sy.cw_step * sy.nw_step));
         sy.slot = -1;
     }
 
@@ -787,7 +794,7 @@ class Engine {
         for (int sl : pending_slots_) hi_slot_ = std::max(hi_slot_, sl + 1);
     }
 
-    // Step work list of every resident system, by (precision, P, tile width) class;
+    // Step work list of every resident system, by (precision, P, tile shape) class;
     // uploaded once, and each class's k steps captured into a graph of its own.
     void rebuild_steps(int k) {
         for (int sl : pending_slots_) free_slots_.push_back(sl);
@@ -802,23 +809,25 @@ class Engine {
         for (int prec : {PREC_F64, PREC_F32, PREC_BF16X2}) {
             for (int P : {1, 2, 4, 8, 16}) {
                 for (int cw : {1, 2, 4}) {
-                    StepRange r{prec, P, cw, st.size(), 0, 0, 0};
-                    for (auto& sy : live_) {
-                        if (sy.prec != prec || sy.P != P || sy.cw_step != cw) continue;
-                        const int t = (sy.n + 4 * cw - 1) / (4 * cw);
-                        for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
-                    }
-                    r.ad_n = st.size() - r.ad_off;
-                    r.up_off = st.size();
-                    for (auto& sy : live_) {
-                        if (sy.prec != prec || sy.P != P || sy.cw_step != cw) continue;
-                        const int t = sy.w.n_pad / (kWG / P);
-                        for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
-                    }
-                    r.up_n = st.size() - r.up_off;
-                    if (r.ad_n) {
-                        step_ranges_.push_back(r);
-                        step_items_total_ += r.ad_n;
+                    for (int nw : {4, 8, 16}) {
+                        StepRange r{prec, P, cw, nw, st.size(), 0, 0, 0};
+                        for (auto& sy : live_) {
+                            if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
+                            const int t = (sy.n + cw * nw - 1) / (cw * nw);
+                            for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
+                        }
+                        r.ad_n = st.size() - r.ad_off;
+                        r.up_off = st.size();
+                        for (auto& sy : live_) {
+                            if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
+                            const int t = sy.w.n_pad / (kWG / P);
+                            for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
+                        }
+                        r.up_n = st.size() - r.up_off;
+                        if (r.ad_n) {
+                            step_ranges_.push_back(r);
+                            step_items_total_ += r.ad_n;
+                        }
                     }
                 }
             }
@@ -882,7 +891,7 @@ class Engine {
     }
 
     void enqueue_class_step(const StepRange& r, hipStream_t cs) {
-        HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
+        HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, r.nw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
         HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
     }
 

@@ -698,9 +698,10 @@ ccg_status ccg_convert_matrix(ccg_ctx* c, int n, const double* A, int64_t lda, i
     });
 }
 
-ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int reps, double* us) {
+ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int reps, double* us) {
     return guarded(c, [&]() -> ccg_status {
-        if (n < 1 || p < 1 || p > kMaxP || p > n || reps < 1 || !us || (cw != 1 && cw != 2 && cw != 4))
+        if (n < 1 || p < 1 || p > kMaxP || p > n || reps < 1 || !us || (cw != 1 && cw != 2 && cw != 4) ||
+            (nw != 4 && nw != 8 && nw != 16))
             throw CcgError{CCG_ERR_ARG, "bad tuning argument"};
         if (prec != CCG_FP64 && prec != CCG_FP32 && prec != CCG_BF16X2) throw CcgError{CCG_ERR_ARG, "bad precision"};
         const int pr = prec == CCG_FP64 ? PREC_F64 : (prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
@@ -734,7 +735,7 @@ ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int reps, dou
         const AdArgs a = ad_args(s, false);
         double tot = 0.0;
         for (int i = 0; i < reps + 2; ++i) {
-            HIP_OK(launch_ad_cw(pr, P, cw, a, c->stream, e0, e1));
+            HIP_OK(launch_ad_cw(pr, P, cw, nw, a, c->stream, e0, e1));
             HIP_OK(hipStreamSynchronize(c->stream));
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));

@@ -29,10 +29,12 @@ hipError_t launch_convert(int prec, int n, const double* A, int64_t lda, void* h
                           hipStream_t s);
 hipError_t launch_inner_init(const RefArgs& a, hipStream_t s);
 hipError_t launch_refine_add(const RefArgs& a, hipStream_t s);
-hipError_t launch_ad_batch(int prec, int P, int cw, const AdArgs* sys, const int4* items, int nitems, hipStream_t s);
-hipError_t launch_ad_cw(int prec, int P, int cw, const AdArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+hipError_t launch_ad_batch(int prec, int P, int cw, int nw, const AdArgs* sys, const int4* items, int nitems,
+                           hipStream_t s);
+hipError_t launch_ad_cw(int prec, int P, int cw, int nw, const AdArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 int ad_cw(int prec, int P, int n);
+int ad_nw(int prec, int P, int n);
 hipError_t launch_tune_matrix(int n, double* A, int64_t lda, hipStream_t s);
 hipError_t launch_tune_vectors(int64_t cnt, double* d64, float* d32, unsigned seed, hipStream_t s);
 hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);

@@ -56,20 +56,23 @@ template <> struct PT<PREC_BF16X2> {
     static constexpr int E = 8;
 };
 
-// Tile configuration of the A.D kernel: CW A columns per wave (4 waves per
-// workgroup, so 4*CW AD rows per workgroup), SPC wave steps of 64*E contraction
-// elements per staged D chunk, an occupancy hint MINW (waves per SIMD) and
-// non-temporal A loads (A is read exactly once per launch).
-// STG rotates each workgroup's starting chunk so that concurrent workgroups read
-// different offsets of their columns (the column stride is a large power of two).
-template <int CW_, int SPC_, int MINW_, bool NT_, bool STG_ = false>
+// Tile configuration of the A.D kernel: CW A columns per wave and NW waves per
+// workgroup (so NW*CW AD rows per workgroup, all sharing one staged D chunk), SPC
+// wave steps of 64*E contraction elements per staged D chunk, an occupancy hint
+// MINW (waves per SIMD) and non-temporal A loads (A is read exactly once per
+// launch).  STG rotates each workgroup's starting chunk so that concurrent
+// workgroups read different offsets of their columns (the column stride is a large
+// power of two).
+template <int CW_, int SPC_, int MINW_, bool NT_, bool STG_ = false, int NW_ = 4>
 struct AdCfg {
     static constexpr int CW = CW_;
     static constexpr int SPC = SPC_;
     static constexpr int MINW = MINW_;
     static constexpr bool NT = NT_;
     static constexpr bool STG = STG_;
-    static constexpr int ROWS = 4 * CW_;
+    static constexpr int NW = NW_;
+    static constexpr int WG = 64 * NW_;       // threads per workgroup
+    static constexpr int ROWS = NW_ * CW_;
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
@@ -161,22 +164,22 @@ __device__ __forceinline__ double sum_rows(const double* src, int ne, int e, int
 
 // out[e] = sum over rows 0..cnt-1 of src (row stride ne), for every e < ne, with the
 // rows of each entry split into contiguous slices over spare threads and the slice
-// sums added in slice order (a fixed tree).  scratch: kWG doubles of LDS.
-template <int B>
+// sums added in slice order (a fixed tree).  NTH threads; scratch: NTH doubles of LDS.
+template <int B, int NTH>
 __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, double* out, double* scratch) {
     const int tid = threadIdx.x;
-    const int tpe = ne >= kWG ? 1 : kWG / ne;          // threads per entry
+    const int tpe = ne >= NTH ? 1 : NTH / ne;          // threads per entry
     const int slice = (cnt + tpe - 1) / tpe;
-    for (int e0 = 0; e0 < ne; e0 += kWG / tpe) {
+    for (int e0 = 0; e0 < ne; e0 += NTH / tpe) {
         const int e = e0 + tid / tpe, sub = tid % tpe;
         double s = 0.0;
-        if (e < ne && tid / tpe < kWG / tpe) {
+        if (e < ne && tid / tpe < NTH / tpe) {
             const int m0 = sub * slice;
             s = sum_rows<B>(src, ne, e, m0, max(0, min(slice, cnt - m0)));
         }
         scratch[tid] = s;
         __syncthreads();
-        if (sub == 0 && e < ne && tid / tpe < kWG / tpe) {
+        if (sub == 0 && e < ne && tid / tpe < NTH / tpe) {
             double t = scratch[tid];
             for (int q = 1; q < tpe; ++q) t += scratch[tid + q];
             out[e] = t;
@@ -193,14 +196,14 @@ __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, do
 // group sums of up to kGroup^2 tiles, take one round trip to memory each where
 // every entry has a thread of its own (large ne), at the price of registers that
 // the kernels with few agents would pay in occupancy.
-template <int B>
+template <int B, int NTH>
 __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const RedBuf rb, double* out,
                                             int* s_flag, double* scratch, int bid, int nwg) {
     const int tid = threadIdx.x;
     const int ngroups = (nwg + kGroup - 1) / kGroup;
     const int grp = bid / kGroup;
     const int gsize = min(kGroup, nwg - grp * kGroup);
-    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
+    for (int e = tid; e < ne; e += NTH) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
     stores_done();
     __syncthreads();
     if (tid == 0) *s_flag = (ticket(&rb.cnt[grp]) == (unsigned)gsize - 1) ? 1 : 0;
@@ -208,19 +211,19 @@ __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const Re
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[grp]);
     if (ngroups == 1) {
-        sum_table<B>(rb.l1, ne, gsize, out, scratch);
+        sum_table<B, NTH>(rb.l1, ne, gsize, out, scratch);
         return true;
     }
     // group sum -> level-2 row of this group
-    sum_table<B>(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
-    for (int e = tid; e < ne; e += kWG) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
+    sum_table<B, NTH>(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    for (int e = tid; e < ne; e += NTH) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
     stores_done();
     __syncthreads();
     if (tid == 0) *s_flag = (ticket(&rb.cnt[ngroups]) == (unsigned)ngroups - 1) ? 1 : 0;
     __syncthreads();
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
-    sum_table<B>(rb.l2, ne, ngroups, out, scratch);
+    sum_table<B, NTH>(rb.l2, ne, ngroups, out, scratch);
     return true;
 }
 
@@ -447,7 +450,7 @@ __device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
 
 // ============================================================== k_ad: AD = A D
 
-// One tile (4 * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
+// One tile (NW * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
 template <int PREC, int P, class CFG>
 __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const int ntiles) {
     using TA = typename PT<PREC>::TA;
@@ -461,8 +464,9 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     constexpr int kAdCols = CFG::ROWS;
     constexpr bool NT = CFG::NT;
     constexpr int NV = kCW * P;               // lane sums per wave
-    constexpr int PER = P * KC / kWG;         // staged D values per thread per chunk
-    static_assert(P * KC % kWG == 0, "chunk staging must split evenly");
+    constexpr int WG = CFG::WG;               // threads of the workgroup
+    constexpr int PER = (P * KC + WG - 1) / WG;   // staged D values per thread per chunk
+    constexpr bool PART = PER * WG != P * KC;     // the last round of staging is partial
     static_assert(NV <= 64, "lane sums per wave");
     static_assert(512 % KC == 0, "chunks must tile the padded length");
 
@@ -473,7 +477,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
     __shared__ double gtot[P * (P + 1) + 2 * P * P + P];    // grid totals (last workgroup)
     __shared__ double sm[4 * kMaxP * kMaxP];
-    __shared__ double gscr[kWG];
+    __shared__ double gscr[WG];
     __shared__ int ish[128];
 
     if (!a.product_only && a.st->done != RUNNING) return;
@@ -511,12 +515,13 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     TV pre[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int idx = tid + q * kWG;
+        const int idx = tid + q * WG;
         const int j = idx / KC, kk = idx - (idx / KC) * KC;
-        pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
+        if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
     }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) dch[0][tid + q * kWG] = pre[q];
+    for (int q = 0; q < PER; ++q)
+        if (!PART || tid + q * WG < P * KC) dch[0][tid + q * WG] = pre[q];
     __syncthreads();
 
     for (int it = 0; it < nch; ++it) {
@@ -529,9 +534,9 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
             const int nx = (ch + 1 < nch) ? ch + 1 : 0;
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
-                const int idx = tid + q * kWG;
+                const int idx = tid + q * WG;
                 const int j = idx / KC, kk = idx - (idx / KC) * KC;
-                pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
+                if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
             }
         }
         const TV* dc = dch[buf];
@@ -578,7 +583,8 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
         }
         if (more) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) dch[buf ^ 1][tid + q * kWG] = pre[q];
+            for (int q = 0; q < PER; ++q)
+                if (!PART || tid + q * WG < P * KC) dch[buf ^ 1][tid + q * WG] = pre[q];
         }
         __syncthreads();
     }
@@ -604,7 +610,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     //   G = D^T AD (lower triangle), Z = AD^T R, Y = AD^T AD (lower triangle),
     //   S = D^T R, and the diagonal of R^T R
     const TV* __restrict__ Rv = static_cast<const TV*>(a.R);
-    for (int t = tid; t < kAdCols * P; t += kWG) {
+    for (int t = tid; t < kAdCols * P; t += WG) {
         const int r = t / P, j = t - (t / P) * P;
         const int i = i0 + r;
         drw[r * kMaxP + j] = (i < n) ? double(V[(int64_t)j * a.n_pad + i]) : 0.0;
@@ -614,7 +620,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     constexpr int TRI = P * (P + 1) / 2;
     constexpr int OZ = TRI, OY = TRI + P * P, OS = 2 * TRI + P * P, OQ = 2 * TRI + 2 * P * P;
     constexpr int NE = OQ + P;
-    for (int e = tid; e < NE; e += kWG) {
+    for (int e = tid; e < NE; e += WG) {
         const double* U;
         const double* Wv;
         int x, y;
@@ -641,7 +647,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
         gmine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce<(P >= 8 ? kGroup : 16)>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
+    if (!grid_reduce<(P >= 8 ? kGroup : 16), WG>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
 
     // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
     DevState* st = a.st;
@@ -655,7 +661,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     double* rinv = sm + 2 * kMaxP * kMaxP;    // 1 / L[i][i]
     double* lred = gscr;                      // per-lane values reduced by lane 0
     // G and Y are symmetric in exact arithmetic: expand their lower triangles
-    for (int t = tid; t < P * P; t += kWG) {
+    for (int t = tid; t < P * P; t += WG) {
         const int x = t / P, y = t - (t / P) * P;
         const int hi = max(x, y), lo = min(x, y);
         Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
@@ -830,13 +836,13 @@ template <class CFG>
 __host__ __device__ constexpr int ad_tiles(int n) { return (n + CFG::ROWS - 1) / CFG::ROWS; }
 
 template <int PREC, int P, class CFG>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
+__global__ __launch_bounds__(CFG::WG) __attribute__((amdgpu_waves_per_eu(CFG::MINW))) void k_ad(AdArgs a) {
     ad_tile<PREC, P, CFG>(a, blockIdx.x, gridDim.x);
 }
 
 // Many systems in one launch: workgroup w runs tile items[w].y of system items[w].x.
 template <int PREC, int P, class CFG>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CFG::MINW)))
+__global__ __launch_bounds__(CFG::WG) __attribute__((amdgpu_waves_per_eu(CFG::MINW)))
 void k_ad_batch(const AdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const AdArgs a = sys[it.x];
@@ -940,7 +946,7 @@ __device__ __forceinline__ void res_tile(const ResArgs& a, const int tile, const
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce<(P >= 8 ? kGroup : 16)>(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
+    if (!grid_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
     if (tid == 0) {
         if (a.set_nb) st->nb = sqrt(tot[P * P]);
         double mn = INFINITY;
@@ -984,30 +990,36 @@ __global__ __launch_bounds__(kWG) void k_res_batch(const ResArgs* __restrict__ s
 
 // ================================================================ A.D launchers
 //
-// Tile configuration: CW A columns per wave (from the tuning table, or given), one
-// wave step per staged chunk unless P * E elements are fewer than a workgroup,
-// 4 waves per SIMD, non-temporal A loads and staggered chunk starts.
-template <int PREC, int P, int CW>
-using AdCfgOf = AdCfg<CW, (P * 64 * PT<PREC>::E >= kWG ? 1 : kWG / (P * 64 * PT<PREC>::E)), 4, true, true>;
+// Tile configuration: CW A columns per wave and NW waves per workgroup (from the
+// tuning table, or given); wave steps per staged chunk so that a chunk stages at
+// least one value per thread, at most 512 rows; 4 waves per SIMD, non-temporal A
+// loads and staggered chunk starts.
+template <int PREC, int P, int CW, int NW>
+using AdCfgOf = AdCfg<CW,
+                      (P * 64 * PT<PREC>::E >= 64 * NW ? 1
+                       : (64 * NW / (P * 64 * PT<PREC>::E) > 512 / (64 * PT<PREC>::E)
+                              ? 512 / (64 * PT<PREC>::E)
+                              : 64 * NW / (P * 64 * PT<PREC>::E))),
+                      4, true, true, NW>;
 
-template <int PREC, int P, int CW>
+template <int PREC, int P, int CW, int NW>
 inline hipError_t launch_ad_t(const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    using C = AdCfgOf<PREC, P, CW>;
+    using C = AdCfgOf<PREC, P, CW, NW>;
     const dim3 grid((a.n + C::ROWS - 1) / C::ROWS);
     // With an event pair the launch records them itself (the kernel's own begin
     // and end), with no separate marker packets around it.
     if (e0) {
-        hipExtLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(C::WG), 0, s, e0, e1, 0, a);
     } else {
-        hipLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(kWG), 0, s, a);
+        hipLaunchKernelGGL((k_ad<PREC, P, C>), grid, dim3(C::WG), 0, s, a);
     }
     return hipGetLastError();
 }
 
-template <int PREC, int P, int CW>
+template <int PREC, int P, int CW, int NW>
 inline hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int nitems, hipStream_t s) {
-    using C = AdCfgOf<PREC, P, CW>;
-    hipLaunchKernelGGL((k_ad_batch<PREC, P, C>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    using C = AdCfgOf<PREC, P, CW, NW>;
+    hipLaunchKernelGGL((k_ad_batch<PREC, P, C>), dim3(nitems), dim3(C::WG), 0, s, sys, items);
     return hipGetLastError();
 }
 
@@ -1020,40 +1032,56 @@ __host__ __device__ constexpr bool ad_cw4_fits(int prec, int P) {
 __host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw) {
     return cw >= 4 ? (ad_cw4_fits(prec, P) ? 4 : 2) : (cw >= 2 ? 2 : 1);
 }
+// Waves per workgroup: 4, 8 or 16 (one staged D chunk shared by more columns, so
+// fewer re-reads of D), 16 only up to P = 8, where a thread's registers still fit
+// a quarter of a SIMD's file; P = 16 runs 4.
+__host__ __device__ constexpr int ad_nw_fit(int P, int nw) {
+    return P >= 16 ? 4 : (nw >= 16 ? 16 : (nw >= 8 ? 8 : 4));
+}
+
+template <int PREC, int P, int CW>
+inline hipError_t launch_ad_w(int nw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                              hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (P < 16) {
+        if (nw >= 16)
+            return one ? launch_ad_t<PREC, P, CW, 16>(*one, s, e0, e1)
+                       : launch_ad_batch_t<PREC, P, CW, 16>(sys, items, nitems, s);
+        if (nw >= 8)
+            return one ? launch_ad_t<PREC, P, CW, 8>(*one, s, e0, e1)
+                       : launch_ad_batch_t<PREC, P, CW, 8>(sys, items, nitems, s);
+    }
+    return one ? launch_ad_t<PREC, P, CW, 4>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, CW, 4>(sys, items, nitems, s);
+}
 
 template <int PREC, int P>
-inline hipError_t launch_ad_pc(int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
-                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+inline hipError_t launch_ad_pc(int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                               int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int W4 = ad_cw4_fits(PREC, P) ? 4 : 2;
-    if (cw >= 4) {
-        return one ? launch_ad_t<PREC, P, W4>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, W4>(sys, items, nitems, s);
-    }
-    if (cw >= 2) {
-        return one ? launch_ad_t<PREC, P, 2>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, 2>(sys, items, nitems, s);
-    }
-    return one ? launch_ad_t<PREC, P, 1>(*one, s, e0, e1) : launch_ad_batch_t<PREC, P, 1>(sys, items, nitems, s);
+    if (cw >= 4) return launch_ad_w<PREC, P, W4>(nw, one, sys, items, nitems, s, e0, e1);
+    if (cw >= 2) return launch_ad_w<PREC, P, 2>(nw, one, sys, items, nitems, s, e0, e1);
+    return launch_ad_w<PREC, P, 1>(nw, one, sys, items, nitems, s, e0, e1);
 }
 
 // One system (one != nullptr) or a batch of (system, tile) items.
 template <int PREC>
-inline hipError_t launch_ad_prec(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items,
+inline hipError_t launch_ad_prec(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                                  int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (P) {
-        case 1: return launch_ad_pc<PREC, 1>(cw, one, sys, items, nitems, s, e0, e1);
-        case 2: return launch_ad_pc<PREC, 2>(cw, one, sys, items, nitems, s, e0, e1);
-        case 4: return launch_ad_pc<PREC, 4>(cw, one, sys, items, nitems, s, e0, e1);
-        case 8: return launch_ad_pc<PREC, 8>(cw, one, sys, items, nitems, s, e0, e1);
-        case 16: return launch_ad_pc<PREC, 16>(cw, one, sys, items, nitems, s, e0, e1);
+        case 1: return launch_ad_pc<PREC, 1>(cw, nw, one, sys, items, nitems, s, e0, e1);
+        case 2: return launch_ad_pc<PREC, 2>(cw, nw, one, sys, items, nitems, s, e0, e1);
+        case 4: return launch_ad_pc<PREC, 4>(cw, nw, one, sys, items, nitems, s, e0, e1);
+        case 8: return launch_ad_pc<PREC, 8>(cw, nw, one, sys, items, nitems, s, e0, e1);
+        case 16: return launch_ad_pc<PREC, 16>(cw, nw, one, sys, items, nitems, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
 
 // Entry points of the per-precision translation units.
-hipError_t launch_ad_f64(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
-                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_ad_f32(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
-                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_ad_bf16(int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
-                          hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_ad_f64(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                         int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_ad_f32(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                         int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_ad_bf16(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                          int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace ccg

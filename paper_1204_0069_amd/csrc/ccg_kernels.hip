@@ -159,16 +159,24 @@ __global__ void k_refine_add(RefArgs a) {
 
 // ================================================================== launchers
 
-// A columns per wave of the A.D tile for a system: the tuning table's choice for
-// (precision, padded agent count, n), else 2.
-int ad_cw(int prec, int P, int n) {
+// A columns per wave and waves per workgroup of the A.D tile for a system: the
+// tuning table's choice for (precision, padded agent count, n), else 2 and 4.
+static const TuneRow* tune_row(int prec, int P, int n) {
     for (const TuneRow& r : kTuneTable)
-        if (r.prec == prec && r.P == P && n <= r.n_max) return ad_cw_fit(prec, P, r.cw);
-    return 2;
+        if (r.prec == prec && r.P == P && n <= r.n_max) return &r;
+    return nullptr;
+}
+int ad_cw(int prec, int P, int n) {
+    const TuneRow* r = tune_row(prec, P, n);
+    return r ? ad_cw_fit(prec, P, r->cw) : 2;
+}
+int ad_nw(int prec, int P, int n) {
+    const TuneRow* r = tune_row(prec, P, n);
+    return r ? ad_nw_fit(P, r->nw) : 4;
 }
 
-// AD rows per A.D tile (4 waves per workgroup).
-int ad_tile_rows(int prec, int P, int n) { return 4 * ad_cw(prec, P, n); }
+// AD rows per A.D tile.
+int ad_tile_rows(int prec, int P, int n) { return ad_nw(prec, P, n) * ad_cw(prec, P, n); }
 
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
@@ -191,22 +199,23 @@ static hipError_t launch_res_t(const ResArgs& a, hipStream_t s) {
         default: return hipErrorInvalidValue;                          \
     }
 
-static hipError_t launch_ad_any(int prec, int P, int cw, const AdArgs* one, const AdArgs* sys, const int4* items,
-                                int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t launch_ad_any(int prec, int P, int cw, int nw, const AdArgs* one, const AdArgs* sys,
+                                const int4* items, int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (prec) {
-        case PREC_F64: return launch_ad_f64(P, cw, one, sys, items, nitems, s, e0, e1);
-        case PREC_F32: return launch_ad_f32(P, cw, one, sys, items, nitems, s, e0, e1);
-        case PREC_BF16X2: return launch_ad_bf16(P, cw, one, sys, items, nitems, s, e0, e1);
+        case PREC_F64: return launch_ad_f64(P, cw, nw, one, sys, items, nitems, s, e0, e1);
+        case PREC_F32: return launch_ad_f32(P, cw, nw, one, sys, items, nitems, s, e0, e1);
+        case PREC_BF16X2: return launch_ad_bf16(P, cw, nw, one, sys, items, nitems, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    return launch_ad_any(prec, P, ad_cw(prec, P, a.n), &a, nullptr, nullptr, 0, s, e0, e1);
+    return launch_ad_any(prec, P, ad_cw(prec, P, a.n), ad_nw(prec, P, a.n), &a, nullptr, nullptr, 0, s, e0, e1);
 }
 
-hipError_t launch_ad_cw(int prec, int P, int cw, const AdArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    return launch_ad_any(prec, P, cw, &a, nullptr, nullptr, 0, s, e0, e1);
+hipError_t launch_ad_cw(int prec, int P, int cw, int nw, const AdArgs& a, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
+    return launch_ad_any(prec, P, cw, nw, &a, nullptr, nullptr, 0, s, e0, e1);
 }
 
 hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
@@ -233,11 +242,12 @@ static hipError_t launch_res_batch_t(const ResArgs* sys, const int4* items, int 
     return hipGetLastError();
 }
 
-// Batched A.D over (system, tile) items whose systems all use `cw` columns per wave.
-hipError_t launch_ad_batch(int prec, int P, int cw, const AdArgs* sys, const int4* items, int nitems,
+// Batched A.D over (system, tile) items whose systems all use `cw` columns per wave
+// and `nw` waves per workgroup.
+hipError_t launch_ad_batch(int prec, int P, int cw, int nw, const AdArgs* sys, const int4* items, int nitems,
                            hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    return launch_ad_any(prec, P, cw, nullptr, sys, items, nitems, s, nullptr, nullptr);
+    return launch_ad_any(prec, P, cw, nw, nullptr, sys, items, nitems, s, nullptr, nullptr);
 }
 
 hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {

@@ -1,15 +1,15 @@
-"""Autotuner of the A.D tile width (A columns per wave) on the GPU.
+"""Autotuner of the A.D tile shape (A columns per wave, waves per workgroup) on the GPU.
 
     python -m paper_1204_0069_amd.tune [--reps 10] [--out csrc/ccg_tune_table.h]
 
 For every precision, padded agent count P and a ladder of system sizes n it times
 the full A.D launch of the block step (stream of A, Gram products, stop test and
-p x p solves) for each candidate width with ccg_tune_ad, keeps the fastest, merges
+p x p solves) for each candidate shape with ccg_tune_ad, keeps the fastest, merges
 neighbouring sizes with the same choice into n ranges and writes the table that
 the library compiles in (csrc/ccg_tune_table.h).  Rebuild the library afterwards
 (python -m paper_1204_0069_amd.build).
 
-The width changes the tile decomposition, hence the order in which the Gram
+The shape changes the tile decomposition, hence the order in which the Gram
 partial sums are added; the table is fixed at build time, so results stay
 reproducible from run to run.
 """
@@ -26,6 +26,8 @@ PRECS = (("fp64", "PREC_F64"), ("fp32", "PREC_F32"), ("bf16x2", "PREC_BF16X2"))
 AGENTS = (1, 2, 4, 8, 16)
 SIZES = (128, 256, 512, 1024, 2048, 4096, 8192, 16384)
 WIDTHS = (1, 2, 4)
+WAVES = (4, 8, 16)
+DEFAULT = (2, 4)
 
 
 def fits4(prec: str, P: int) -> bool:
@@ -33,21 +35,31 @@ def fits4(prec: str, P: int) -> bool:
     return P < 16 and (prec != "fp64" or P <= 4)
 
 
-MARGIN = 0.03   # another width must beat the default (2) by 3 % to be chosen
+def shapes(prec: str, P: int):
+    """Candidate (columns per wave, waves per workgroup), as the library runs them
+    (ad_cw_fit, ad_nw_fit): 4 columns where they fit, more than 4 waves below P = 16."""
+    ws = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
+    if P >= 16:
+        ws = [w for w in ws if w <= 2]
+    nws = (4,) if P >= 16 else WAVES
+    return [(w, nw) for nw in nws for w in ws]
 
 
-def choose(t: dict) -> int:
-    """Fastest width, keeping the default 2 unless another is clearly faster (short
+MARGIN = 0.03   # another shape must beat the default (2, 4) by 3 % to be chosen
+
+
+def choose(t: dict):
+    """Fastest shape, keeping the default unless another is clearly faster (short
     launches differ by timing noise)."""
     w = min(t, key=t.get)
-    if 2 in t and t[2] <= (1.0 + MARGIN) * t[w]:
-        return 2
+    if DEFAULT in t and t[DEFAULT] <= (1.0 + MARGIN) * t[w]:
+        return DEFAULT
     return w
 
 
 def rows_from(best_by_class):
-    """Table rows from {(cname, P): [(n, width), ...]}: neighbouring sizes with the
-    same width merge, and a row covers sizes up to 1.5 x its largest timed n."""
+    """Table rows from {(cname, P): [(n, shape), ...]}: neighbouring sizes with the
+    same shape merge, and a row covers sizes up to 1.5 x its largest timed n."""
     rows = []
     for (cname, P), best in best_by_class.items():
         merged = []
@@ -58,7 +70,7 @@ def rows_from(best_by_class):
                 merged.append((n, w))
         for i, (n, w) in enumerate(merged):
             last = i == len(merged) - 1
-            rows.append((cname, P, (1 << 30) if last else n + (n // 2), w))
+            rows.append((cname, P, (1 << 30) if last else n + (n // 2), w[0], w[1]))
     return rows
 
 
@@ -66,18 +78,15 @@ def tune(ctx, reps: int, log=print):
     best_by_class = {}
     for prec, cname in PRECS:
         for P in AGENTS:
-            widths = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
-            if P >= 16:
-                widths = [w for w in widths if w <= 2]
             best = []
             for n in SIZES:
                 if P > n:
                     continue
-                t = {w: ctx.tune_ad(prec, P, n, w, reps) for w in widths}
-                w = choose(t)
-                best.append((n, w))
-                log(f"{prec:7s} P={P:2d} n={n:6d} " + "  ".join(f"cw{k}:{v:9.2f}us" for k, v in t.items())
-                    + f"  -> {w}")
+                t = {sh: ctx.tune_ad(prec, P, n, sh[0], reps, nw=sh[1]) for sh in shapes(prec, P)}
+                sh = choose(t)
+                best.append((n, sh))
+                log(f"{prec:7s} P={P:2d} n={n:6d} " + "  ".join(f"c{k[0]}w{k[1]}:{v:9.2f}us" for k, v in t.items())
+                    + f"  -> {sh[0]},{sh[1]}")
             best_by_class[(cname, P)] = best
     return rows_from(best_by_class)
 
@@ -92,17 +101,19 @@ def rows_from_log(path: str):
         if not m:
             continue
         prec, P, n = m.group(1), int(m.group(2)), int(m.group(3))
-        t = {int(k): float(v) for k, v in re.findall(r"cw(\d):\s*([\d.]+)us", m.group(4))}
+        # "c2w8: 91.3us" entries, or "cw2: 91.3us" from logs of 4-wave workgroups only
+        t = {(int(c), int(w)): float(v) for c, w, v in re.findall(r"c(\d)w(\d+):\s*([\d.]+)us", m.group(4))}
+        t.update({(int(c), 4): float(v) for c, v in re.findall(r"cw(\d):\s*([\d.]+)us", m.group(4))})
         best_by_class.setdefault((names[prec], P), []).append((n, choose(t)))
     return rows_from(best_by_class)
 
 
 def write_table(rows, device: str, path: str = OUT):
     lines = [
-        "// A.D tile widths (A columns per wave) by precision, padded agent count and",
-        "// system size.  Written by `python -m paper_1204_0069_amd.tune` from timings of",
-        "// every candidate width on the GPU; the first row whose (prec, P) match and whose",
-        "// n_max >= n applies, and a size no row covers uses 2.",
+        "// A.D tile shapes (A columns per wave, waves per workgroup) by precision, padded",
+        "// agent count and system size.  Written by `python -m paper_1204_0069_amd.tune`",
+        "// from timings of every candidate shape on the GPU; the first row whose (prec, P)",
+        "// match and whose n_max >= n applies, and a size no row covers uses 2 and 4.",
         f"// Tuned on: {device}, {datetime.date.today().isoformat()}.",
         "#pragma once",
         "",
@@ -113,11 +124,12 @@ def write_table(rows, device: str, path: str = OUT):
         "    int P;        // padded agent count",
         "    int n_max;    // largest n of the row",
         "    int cw;       // A columns per wave: 1, 2 or 4",
+        "    int nw;       // waves per workgroup: 4, 8 or 16",
         "};",
         "",
         "static const TuneRow kTuneTable[] = {",
     ]
-    lines += [f"    {{{c}, {P}, {n_max}, {w}}}," for c, P, n_max, w in rows]
+    lines += [f"    {{{c}, {P}, {n_max}, {w}, {nw}}}," for c, P, n_max, w, nw in rows]
     lines += ["};", "", "}  // namespace ccg", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))

@@ -161,12 +161,14 @@ def test_full_size_fp32_solve(gpu_ctx):
 
 
 def test_escalation_after_breakdown(gpu_ctx):
-    """At cond(A) = 1e10 the BF16x2 copy of A (about 2^-17 relative error per element)
-    is far from positive definite, so its refinement cannot progress; with
-    CCG_ESCALATE the solve goes on from its agents in a wider precision, meets the
-    target, reports the precision it ended in and totals over every stage."""
+    """At cond(A) = 1e8 the BF16x2 copy of A (about 2^-17 relative error per element)
+    is too coarse for its refinement to progress; with CCG_ESCALATE the solve goes on
+    from its agents in a wider precision, meets the target, reports the precision it
+    ended in and totals over every stage.  (At cond 1e10 the FP64 stage alone takes
+    anywhere from 2e4 to over 1e5 block steps, depending on rounding, in the oracle as
+    on the GPU, which makes a step limit a coin toss.)"""
     from paper_1204_0069_amd import CCG_ESCALATE
-    n, p, kappa, tol = 128, 4, 1e10, 1e-5
+    n, p, kappa, tol = 128, 4, 1e8, 1e-5
     A, b, X0 = ci.system(n, p, kappa, seed=505)
     X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 100000, prec="bf16x2", raise_on_error=False)
     assert i1["status"] != 0 and i1["prec_final"] == 2, i1

@@ -1,10 +1,11 @@
 """Every A.D tile width the tuned table selects gives oracle-matching steps.
 
-The table (csrc/ccg_tune_table.h) picks 1, 2 or 4 A columns per wave by precision,
-agent count and n; each width is a separate kernel instantiation.  For every
+The table (csrc/ccg_tune_table.h) picks 1, 2 or 4 A columns per wave and 4, 8 or 16
+waves per workgroup by precision, agent count and n; each shape is a separate kernel
+instantiation.  For every
 (precision, P) class below and every width the table uses for it, a system whose n
 falls in that row runs through the library: FP64 block steps against the oracle
-(per step, 1e-10), FP32 refined solves against the explicit FP64 residual.
+(per step, 1e-10), FP32 and BF16 hi+lo refined solves against the explicit FP64 residual.
 """
 import os
 import re
@@ -27,32 +28,44 @@ def _t(x):
 
 
 def _cases(prec_name, Ps, n_cap):
-    rows = [(c, int(P), int(n), int(w)) for c, P, n, w in
-            re.findall(r"\{(PREC_\w+), (\d+), (\d+), (\d)\}", open(TABLE).read())]
+    """One (P, n, width, waves) case per tile shape the table uses for each P, at the
+    smallest n of the first row that selects it (sizes above n_cap are skipped)."""
+    rows = [(c, int(P), int(n), int(w), int(nw)) for c, P, n, w, nw in
+            re.findall(r"\{(PREC_\w+), (\d+), (\d+), (\d), (\d+)\}", open(TABLE).read())]
     out = []
     for P in Ps:
         lo = 0
         seen = set()
-        for c, PP, n_max, w in rows:
+        for c, PP, n_max, w, nw in rows:
             if c != prec_name or PP != P:
                 continue
             n = max(lo + 1, 64, P)
-            if w not in seen and n <= min(n_max, n_cap):
-                out.append((P, n, w))
-                seen.add(w)
+            if (w, nw) not in seen and n <= min(n_max, n_cap):
+                out.append((P, n, w, nw))
+                seen.add((w, nw))
             lo = n_max
     return out
 
 
-FP64_CASES = _cases("PREC_F64", (1, 4, 8), 4096)
-FP32_CASES = _cases("PREC_F32", (2, 8), 4096)
+def _system(n, p, kappa, seed):
+    """Spectrum systems up to n = 4096; larger ones use the Gram construction built on
+    the device (a QR of that size on the host takes too long for a test)."""
+    if n <= 4096:
+        return ci.system(n, p, kappa, seed=seed)
+    A, b, X0 = ci.system(n, p, kappa, seed=seed, device=DEV, kind="gram")
+    return A.cpu().numpy(), b, X0
 
 
-@pytest.mark.parametrize("P,n,w", FP64_CASES)
-def test_fp64_steps_at_each_width(gpu_ctx, P, n, w):
+FP64_CASES = _cases("PREC_F64", (1, 4, 8), 8192)
+FP32_CASES = _cases("PREC_F32", (2, 8), 8192)
+LOW_CASES = [("fp32",) + c for c in FP32_CASES] + [("bf16x2",) + c for c in _cases("PREC_BF16X2", (4, 8), 8192)]
+
+
+@pytest.mark.parametrize("P,n,w,nw", FP64_CASES)
+def test_fp64_steps_at_each_width(gpu_ctx, P, n, w, nw):
     p = max(1, P - 1) if P > 1 else 1
-    print(f"case width {w} fp64 n={n} p={p}", flush=True)
-    A, b, X0 = ci.system(n, p, 1e3, seed=1300 + n)
+    print(f"case width {w} waves {nw} fp64 n={n} p={p}", flush=True)
+    A, b, X0 = _system(n, p, 1e3, 1300 + n)
     k = 4
     orc = oracle.ccg(A, b, X0, tol=0.0, maxit=k, trace_k=k, want_rd=True)
     g = gpu_ctx.debug_step(_t(A), _t(b), _t(X0), k)
@@ -63,12 +76,12 @@ def test_fp64_steps_at_each_width(gpu_ctx, P, n, w):
     assert np.linalg.norm(Xg - orc["X"]) <= 1e-10 * np.linalg.norm(orc["X"])
 
 
-@pytest.mark.parametrize("P,n,w", FP32_CASES)
-def test_fp32_solve_at_each_width(gpu_ctx, P, n, w):
+@pytest.mark.parametrize("prec,P,n,w,nw", LOW_CASES)
+def test_refined_solve_at_each_width(gpu_ctx, prec, P, n, w, nw):
     p = P
-    print(f"case width {w} fp32 n={n} p={p}", flush=True)
-    A, b, X0 = ci.system(n, p, 1e2, seed=1400 + n)
-    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec="fp32")
+    print(f"case width {w} waves {nw} {prec} n={n} p={p}", flush=True)
+    A, b, X0 = _system(n, p, 1e2, 1400 + n)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec=prec)
     assert info["status"] == 0, info
     T = oracle.residual(A, b, X.cpu().numpy())
     assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() <= 1.01e-10
@@ -77,8 +90,11 @@ def test_fp32_solve_at_each_width(gpu_ctx, P, n, w):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
 def test_tuner_entry_times_every_width(gpu_ctx, prec):
     for w in (1, 2, 4):
-        us = gpu_ctx.tune_ad(prec, 4, 512, w, reps=2)
-        assert 0.0 < us < 1e5
+        for nw in (4, 8, 16):
+            us = gpu_ctx.tune_ad(prec, 4, 512, w, reps=2, nw=nw)
+            assert 0.0 < us < 1e5
+    with pytest.raises(Exception):
+        gpu_ctx.tune_ad(prec, 4, 512, 2, reps=2, nw=6)
 
 
 def test_stream_probe_times_the_traffic_shape(gpu_ctx):

@@ -1,5 +1,5 @@
-"""Host logic of the tile-width autotuner (CPU only): the merge of per-size choices
-into table rows, and the validity of the committed table."""
+"""Host logic of the tile-shape autotuner (CPU only): the candidate shapes, the merge
+of per-size choices into table rows, and the validity of the committed table."""
 import os
 import re
 
@@ -7,56 +7,70 @@ from paper_1204_0069_amd import tune
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "..", "paper_1204_0069_amd", "csrc", "ccg_tune_table.h")
+ROW = r"\{(PREC_\w+), (\d+), (\d+), (\d), (\d+)\}"
 
 
 class FakeCtx:
-    """Timings: width 1 wins below n = 1024, width 4 above 4096 where it fits, else 2."""
+    """Timings: width 1 wins below n = 1024, width 4 above 4096 where it fits, else 2;
+    16 waves per workgroup win from n = 8192 on, 4 below."""
 
     def __init__(self):
         self.calls = []
 
-    def tune_ad(self, prec, P, n, cw, reps):
-        self.calls.append((prec, P, n, cw))
+    def tune_ad(self, prec, P, n, cw, reps, nw=4):
+        self.calls.append((prec, P, n, cw, nw))
         if n < 1024:
-            return {1: 1.0, 2: 2.0, 4: 3.0}[cw]
-        if n > 4096:
-            return {1: 3.0, 2: 2.0, 4: 1.0}[cw]
-        return {1: 2.0, 2: 1.0, 4: 3.0}[cw]
+            t = {1: 1.0, 2: 2.0, 4: 3.0}[cw]
+        elif n > 4096:
+            t = {1: 3.0, 2: 2.0, 4: 1.0}[cw]
+        else:
+            t = {1: 2.0, 2: 1.0, 4: 3.0}[cw]
+        return t * ({4: 1.0, 8: 1.1, 16: 1.2}[nw] if n < 8192 else {4: 1.0, 8: 0.9, 16: 0.8}[nw])
 
 
 def _rows_for(rows, c, P):
-    return [(n_max, w) for cc, PP, n_max, w in rows if cc == c and PP == P]
+    return [(n_max, w, nw) for cc, PP, n_max, w, nw in rows if cc == c and PP == P]
+
+
+def test_candidate_shapes_follow_the_register_rules():
+    assert (4, 16) in tune.shapes("fp32", 8) and (4, 4) not in tune.shapes("fp64", 8)
+    assert all(nw == 4 and w <= 2 for w, nw in tune.shapes("fp64", 16))
+    assert tune.DEFAULT in tune.shapes("bf16x2", 1)
 
 
 def test_merge_and_limits():
     ctx = FakeCtx()
     rows = tune.tune(ctx, reps=1, log=lambda s: None)
-    # FP32, P = 8: 1 up to 512, 2 for 1024..4096, 4 beyond
-    assert _rows_for(rows, "PREC_F32", 8) == [(768, 1), (6144, 2), (1 << 30, 4)]
+    # FP32, P = 8: width 1 up to 512, 2 for 1024..4096, then 4 with 16 waves from 8192 on
+    assert _rows_for(rows, "PREC_F32", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 16)]
     # FP64, P = 8 may not use 4 columns per wave: 2 from 1024 on
-    assert _rows_for(rows, "PREC_F64", 8) == [(768, 1), (1 << 30, 2)]
-    # P = 16 never times width 4; no size below P is timed
-    assert not any(P == 16 and w == 4 for _, P, _, w in ctx.calls)
-    assert all(P <= n for _, P, n, _ in ctx.calls)
+    assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 2, 16)]
+    # P = 16 never times width 4 or more than 4 waves; no size below P is timed
+    assert not any(P == 16 and (w == 4 or nw != 4) for _, P, _, w, nw in ctx.calls)
+    assert all(P <= n for _, P, n, _, _ in ctx.calls)
 
 
 def test_written_table_round_trips(tmp_path):
-    rows = [("PREC_F64", 8, 1536, 1), ("PREC_F64", 8, 1 << 30, 2)]
+    rows = [("PREC_F64", 8, 1536, 1, 4), ("PREC_F64", 8, 1 << 30, 2, 16)]
     out = tmp_path / "t.h"
     tune.write_table(rows, "test device", str(out))
-    text = out.read_text()
-    got = re.findall(r"\{(PREC_\w+), (\d+), (\d+), (\d)\}", text)
-    assert [(c, int(P), int(n), int(w)) for c, P, n, w in got] == rows
+    got = re.findall(ROW, out.read_text())
+    assert [(c, int(P), int(n), int(w), int(nw)) for c, P, n, w, nw in got] == rows
+
+
+def test_old_logs_read_as_four_waves(tmp_path):
+    log = tmp_path / "old.txt"
+    log.write_text("fp64    P= 8 n=  8192 cw1:   142.41us  cw2:    96.12us  -> 2\n")
+    assert tune.rows_from_log(str(log)) == [("PREC_F64", 8, 1 << 30, 2, 4)]
 
 
 def test_committed_table_is_valid():
     text = open(TABLE).read()
-    rows = [(c, int(P), int(n), int(w)) for c, P, n, w in
-            re.findall(r"\{(PREC_\w+), (\d+), (\d+), (\d)\}", text)]
+    rows = [(c, int(P), int(n), int(w), int(nw)) for c, P, n, w, nw in re.findall(ROW, text)]
     assert rows, "empty tuning table"
     last = {}
-    for c, P, n_max, w in rows:
+    for c, P, n_max, w, nw in rows:
         assert c in ("PREC_F64", "PREC_F32", "PREC_BF16X2")
-        assert P in (1, 2, 4, 8, 16) and w in (1, 2, 4)
+        assert P in (1, 2, 4, 8, 16) and w in (1, 2, 4) and nw in (4, 8, 16)
         assert n_max > last.get((c, P), 0), "rows of one class must grow in n"
         last[(c, P)] = n_max
