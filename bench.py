@@ -288,10 +288,14 @@ def stream_ceiling(args):
     rows = []
     for stagger in (False, True):
         for dcols in (0, args.p):
-            for cols in (4, 8, 16):
-                us = ctx.stream_probe(n, cols, dcols, stagger=stagger, reps=20)
-                rows.append({"cols_per_workgroup": cols, "direction_cols": dcols, "stagger": stagger,
-                             "median_us": round(us, 2), "GB_s": round(8.0 * n * n / (us * 1e-6) / 1e9, 1)})
+            for waves in (4, 8, 16):
+                for cols in (4, 8, 16, 32):
+                    if cols < waves // 2 or cols > 4 * waves:
+                        continue
+                    us = ctx.stream_probe(n, cols, dcols, stagger=stagger, reps=20, waves=waves)
+                    rows.append({"cols_per_workgroup": cols, "waves": waves, "direction_cols": dcols,
+                                 "stagger": stagger, "median_us": round(us, 2),
+                                 "GB_s": round(8.0 * n * n / (us * 1e-6) / 1e9, 1)})
     ctx.close()
     print(json.dumps({"probe": "ccg_stream_probe", "n": n, "matrix_bytes": 8 * n * n, "rows": rows}))
 

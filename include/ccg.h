@@ -220,13 +220,14 @@ ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int
 
 /* Median duration in microseconds, over `reps` launches after 2 warm-up launches, of
  * a kernel that only reads: an n x n FP64 matrix (column-major, lda = n; n even),
- * `cols` whole columns per workgroup (cols divides n), with 16-byte non-temporal
- * loads, and, when dcols > 0 (at most 16), also the whole of an n x dcols FP64 block
- * in every workgroup, as the A.D tile kernel reads the direction block.  stagger != 0
- * rotates each workgroup's starting offset in its columns as the A.D kernel does.
- * The floor that the memory system sets for that traffic, to set A.D timings
- * against (not in the paper).  Allocates and frees its own n^2 + n dcols doubles. */
-ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int stagger, int reps,
+ * `cols` whole columns per workgroup of `waves` x 64 threads (cols divides n; waves
+ * 4, 8 or 16), with 16-byte non-temporal loads, and, when dcols > 0 (at most 16), also
+ * the whole of an n x dcols FP64 block in every workgroup, as the A.D tile kernel
+ * reads the direction block.  stagger != 0 rotates each workgroup's starting offset in
+ * its columns as the A.D kernel does.  The floor that the memory system sets for that
+ * traffic, to set A.D timings against (not in the paper).  Allocates and frees its
+ * own n^2 + n dcols doubles.  CCG_ERR_ARG for arguments outside these ranges. */
+ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int stagger, int waves, int reps,
                             double *us);
 
 /* Accumulated duration (milliseconds) and launch count of the A.D kernel in the

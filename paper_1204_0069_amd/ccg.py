@@ -105,7 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, dp]
     lib.ccg_tune_ad.restype = ctypes.c_int
-    lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, dp]
     lib.ccg_stream_probe.restype = ctypes.c_int
     lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     lib.ccg_kernel_time.restype = ctypes.c_int
@@ -320,11 +321,13 @@ class Context:
             raise self._err(st)
         return us.value
 
-    def stream_probe(self, n: int, cols: int, dcols: int = 0, stagger: bool = True, reps: int = 20) -> float:
+    def stream_probe(self, n: int, cols: int, dcols: int = 0, stagger: bool = True, reps: int = 20,
+                     waves: int = 4) -> float:
         """Median microseconds of the read-only stream of an n x n FP64 matrix, cols
-        columns per workgroup, plus an n x dcols block per workgroup (ccg_stream_probe)."""
+        columns per workgroup of waves x 64 threads, plus an n x dcols block per
+        workgroup (ccg_stream_probe)."""
         us = ctypes.c_double()
-        st = self.lib.ccg_stream_probe(self.h, n, cols, dcols, int(stagger), reps, ctypes.byref(us))
+        st = self.lib.ccg_stream_probe(self.h, n, cols, dcols, int(stagger), waves, reps, ctypes.byref(us))
         if st != 0:
             raise self._err(st)
         return us.value

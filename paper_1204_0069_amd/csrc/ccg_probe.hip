@@ -1,8 +1,8 @@
 // Read-stream ceiling of the A.D traffic shape (a measurement aid, not in the paper).
 //
 // k_stream reads an n x n FP64 matrix stored column-major with lda = n, `cols`
-// whole columns (one contiguous chunk of cols * n doubles) per workgroup, with
-// 16-byte non-temporal loads, and adds it up.  With an n x dcols block D it also
+// whole columns (one contiguous chunk of cols * n doubles) per workgroup of WG
+// threads, with 16-byte non-temporal loads, and adds it up.  With an n x dcols block D it also
 // reads the whole of D in every workgroup, spread over its chunk, as the A.D tile
 // kernel does with the direction block.  With `stagger`, workgroup b starts its
 // chunk at step (7 b) mod steps and wraps around, as the A.D kernel staggers its
@@ -20,33 +20,34 @@ namespace {
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(kWG) void k_stream(const dvec2* __restrict__ a, int64_t chunk,
-                                                const dvec2* __restrict__ d, int64_t dlen, int stagger,
-                                                double* out) {
+template <int WG>
+__global__ __launch_bounds__(WG) void k_stream(const dvec2* __restrict__ a, int64_t chunk,
+                                               const dvec2* __restrict__ d, int64_t dlen, int stagger,
+                                               double* out) {
     constexpr int U = 4;
     const dvec2* p = a + (int64_t)blockIdx.x * chunk;
-    const int64_t steps = (chunk + kWG * U - 1) / (kWG * U);
+    const int64_t steps = (chunk + WG * U - 1) / (WG * U);
     const int64_t dstep = d ? (dlen + steps - 1) / steps : 0;
     double s = 0.0;
     const int64_t k0 = stagger ? (7 * (int64_t)blockIdx.x) % steps : 0;
     for (int64_t kk = 0; kk < steps; ++kk) {
         const int64_t k = (k0 + kk) % steps;
-        const int64_t i = threadIdx.x + k * kWG * U;
+        const int64_t i = threadIdx.x + k * WG * U;
         dvec2 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            v[u] = (i + u * kWG < chunk) ? __builtin_nontemporal_load(&p[i + u * kWG]) : dvec2{0.0, 0.0};
-        for (int64_t j = k * dstep + threadIdx.x; j < (k + 1) * dstep && j < dlen; j += kWG) {
+            v[u] = (i + u * WG < chunk) ? __builtin_nontemporal_load(&p[i + u * WG]) : dvec2{0.0, 0.0};
+        for (int64_t j = k * dstep + threadIdx.x; j < (k + 1) * dstep && j < dlen; j += WG) {
             const dvec2 w = d[j];
             s += w.x * w.y;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) s += v[u].x + v[u].y;
     }
-    __shared__ double red[kWG];
+    __shared__ double red[WG];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int o = kWG / 2; o > 0; o >>= 1) {
+    for (int o = WG / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -59,11 +60,13 @@ __global__ __launch_bounds__(kWG) void k_stream(const dvec2* __restrict__ a, int
 using namespace ccg;
 using namespace ccg::host;
 
-extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, int stagger, int reps,
-                                       double* us) {
+extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, int stagger, int waves,
+                                       int reps, double* us) {
     return guarded(c, [&]() -> ccg_status {
-        if (n < 2 || n % 2 || cols < 1 || n % cols || dcols < 0 || dcols > kMaxP || reps < 1 || !us)
-            throw CcgError{CCG_ERR_ARG, "bad probe argument (n even, cols dividing n, 0 <= dcols <= 16)"};
+        if (n < 2 || n % 2 || cols < 1 || n % cols || dcols < 0 || dcols > kMaxP || reps < 1 || !us ||
+            (waves != 4 && waves != 8 && waves != 16))
+            throw CcgError{CCG_ERR_ARG,
+                           "bad probe argument (n even, cols dividing n, 0 <= dcols <= 16, waves 4, 8 or 16)"};
         const size_t elems = (size_t)n * n;
         const int nwg = n / cols;
         void* buf = nullptr;
@@ -89,8 +92,13 @@ extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, i
         ccg_status st = CCG_OK;
         for (int r = 0; r < reps + 2 && st == CCG_OK; ++r) {
             if (hipEventRecord(e0, c->stream) != hipSuccess) { st = CCG_ERR_DEVICE; break; }
-            hipLaunchKernelGGL(k_stream, dim3(nwg), dim3(kWG), 0, c->stream, a, chunk, d, dlen, stagger ? 1 : 0,
-                               out);
+            const int sg = stagger ? 1 : 0;
+            if (waves == 4)
+                hipLaunchKernelGGL(k_stream<256>, dim3(nwg), dim3(256), 0, c->stream, a, chunk, d, dlen, sg, out);
+            else if (waves == 8)
+                hipLaunchKernelGGL(k_stream<512>, dim3(nwg), dim3(512), 0, c->stream, a, chunk, d, dlen, sg, out);
+            else
+                hipLaunchKernelGGL(k_stream<1024>, dim3(nwg), dim3(1024), 0, c->stream, a, chunk, d, dlen, sg, out);
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, c->stream) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess) {
                 st = CCG_ERR_DEVICE;

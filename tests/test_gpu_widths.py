@@ -100,9 +100,12 @@ def test_tuner_entry_times_every_width(gpu_ctx, prec):
 def test_stream_probe_times_the_traffic_shape(gpu_ctx):
     """The read-only floor probe runs in every shape bench.py asks of it and reports a
     positive time; re-reading the direction block does not make it faster."""
-    t0 = gpu_ctx.stream_probe(1024, 8, 0, stagger=False, reps=3)
-    t1 = gpu_ctx.stream_probe(1024, 8, 8, stagger=True, reps=3)
-    assert 0.0 < t0 < 1e5 and 0.0 < t1 < 1e5
-    assert t1 >= 0.5 * t0
+    for waves in (4, 8, 16):
+        t0 = gpu_ctx.stream_probe(1024, 8, 0, stagger=False, reps=3, waves=waves)
+        t1 = gpu_ctx.stream_probe(1024, 8, 8, stagger=True, reps=3, waves=waves)
+        assert 0.0 < t0 < 1e5 and 0.0 < t1 < 1e5
+        assert t1 >= 0.5 * t0
     with pytest.raises(Exception):
         gpu_ctx.stream_probe(1000, 3, 0)          # cols must divide n
+    with pytest.raises(Exception):
+        gpu_ctx.stream_probe(1024, 8, 0, waves=6)
