@@ -70,6 +70,8 @@ typedef enum {
                                  info then totals every stage */
 #define CCG_PROFILE_SAMPLED 0x10u  /* as CCG_PROFILE for every 4th round of graph_k block
                                       steps; the other rounds run from the captured graph */
+#define CCG_SYM_AD    0x20u  /* FP64 block steps with p <= 8 and n >= 1024 form A D from
+                                 the upper block triangle of A only (see ccg_solve) */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
@@ -118,7 +120,13 @@ const char *ccg_last_error(const ccg_ctx *ctx);
 
 /* Solve A x = b with p cooperating agents (Alg. 2 + Alg. 3, stop test of Alg. 4).
  * X: in, the p starting points X0; out, the final p agents.  tol > 0 is relative
- * to ||b||; maxit bounds the block steps.  opts and info may be NULL.
+ * to ||b||; maxit bounds the block steps.  opts and info may be NULL.  A must be
+ * symmetric (the A.D kernel streams column i of A as row i).  With CCG_SYM_AD the
+ * FP64 block steps of a system with n >= 1024 and p <= 8 form A D from the blocks
+ * A(I, J), I <= J, of 128 x 128 (A(I, J) D(J) for rows I and A(I, J)^T D(I) for
+ * rows J), so they read only the upper block triangle; the explicit residuals and
+ * the other modes read all of A.  (On MI355X this pass is slower than streaming
+ * all of A at the sizes measured; it is kept for comparison.)
  *
  * opts->prec selects how A is streamed:
  *  - CCG_FP64: plain cCG on the FP64 matrix and FP64 agents.
@@ -230,10 +238,14 @@ ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int
 ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int stagger, int waves, int reps,
                             double *us);
 
-/* Accumulated duration (milliseconds) and launch count of the A.D kernel in the
- * block steps run with CCG_PROFILE (every launch) or CCG_PROFILE_SAMPLED (the launches
- * of the timed rounds) since the last reset; reset != 0 clears them. */
-ccg_status ccg_kernel_time(ccg_ctx *ctx, double *ms, long long *launches, int reset);
+/* Accumulated duration (milliseconds), launch count and algorithmic bytes of the A.D
+ * pass (the A.D kernel, or the symmetric pass's two kernels from the start of the
+ * first to the end of the second) in the block steps run with CCG_PROFILE (every
+ * launch) or CCG_PROFILE_SAMPLED (the launches of the timed rounds) of ccg_solve
+ * since the last reset; reset != 0 clears them.  The bytes per launch are those of
+ * A as streamed (n^2 elements, or n (n + 1) / 2 for the symmetric pass) plus the D
+ * and R rows (2 n p vector elements).  Any output pointer may be NULL. */
+ccg_status ccg_kernel_time(ccg_ctx *ctx, double *ms, long long *launches, double *bytes, int reset);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@ CCG_NO_GRAPH = 0x2
 CCG_PROFILE = 0x4
 CCG_PROFILE_SAMPLED = 0x10
 CCG_ESCALATE = 0x8
+CCG_SYM_AD = 0x20
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 
@@ -108,7 +109,7 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, dp]
     lib.ccg_stream_probe.restype = ctypes.c_int
-    lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
+    lib.ccg_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), dp, ctypes.c_int]
     lib.ccg_kernel_time.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -265,7 +266,7 @@ class Context:
         return Xt.t(), info.as_dict()
 
     def debug_step(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, ksteps: int,
-                   rank_tau: float = 0.0):
+                   rank_tau: float = 0.0, flags: int = 0):
         """Exactly ksteps FP64 block steps; returns dict of X, R, D (n x p, CPU float64)
         and alphas, betas (ksteps x p x p, [step, row, col])."""
         aptr, lda, keep = _colmajor_matrix(A)
@@ -277,7 +278,7 @@ class Context:
         D = torch.zeros(p, n, dtype=torch.float64, device=A.device)
         al = (ctypes.c_double * max(1, ksteps * p * p))()
         be = (ctypes.c_double * max(1, ksteps * p * p))()
-        o = make_opts(rank_tau=rank_tau)
+        o = make_opts(rank_tau=rank_tau, flags=flags)
         torch.cuda.synchronize(A.device)
         dptr = ctypes.POINTER(ctypes.c_double)
         st = self.lib.ccg_debug_step(self.h, n, p, aptr, lda, b.data_ptr(), Xt.data_ptr(), n,
@@ -332,8 +333,13 @@ class Context:
             raise self._err(st)
         return us.value
 
-    def kernel_time(self, reset: bool = False):
+    def kernel_time(self, reset: bool = False, with_bytes: bool = False):
+        """(ms, launches) of the timed A.D passes, and their algorithmic bytes with
+        with_bytes (ccg_kernel_time)."""
         ms = ctypes.c_double()
         cnt = ctypes.c_longlong()
-        self.lib.ccg_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(cnt), int(reset))
+        nbytes = ctypes.c_double()
+        self.lib.ccg_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(nbytes), int(reset))
+        if with_bytes:
+            return ms.value, cnt.value, nbytes.value
         return ms.value, cnt.value

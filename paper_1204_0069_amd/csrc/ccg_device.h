@@ -67,6 +67,30 @@ struct AdArgs {
     DevState* st;
 };
 
+// Arguments of the symmetric A.D pass (FP64, P <= 8).  AD = A D is formed from the
+// blocks A(I, J), I <= J, of a partition of A into kSymB x kSymB blocks: block (I, J)
+// adds A(I, J) D(J) to rows I and A(I, J)^T D(I) to rows J, so only the upper block
+// triangle of A is read.  Workgroup u runs the strip units[u] = (I, J0) of up to
+// kSymW blocks (I, J0 .. J0 + kSymW - 1) and writes its partial sums into part:
+// slot I of block J for A(I, J)^T D(I) (I < J), slot I + s of block I for strip s of
+// block row I.  Block K has K + ceil((nb - K) / kSymW) <= nb slots.
+constexpr int kSymB = 128;      // block size (2 rows per lane of a wave)
+constexpr int kSymW = 4;        // blocks per strip
+constexpr int kSymMaxP = 8;     // largest padded agent count of the symmetric pass
+
+struct SymArgs {
+    const double* A;     // column-major, lda (lda * 8 % 16 == 0); blocks I <= J read
+    int64_t lda;
+    int n;
+    int n_pad;
+    int nb;              // ceil(n / kSymB)
+    int tmax;            // slot stride of part (>= nb)
+    const double* V;     // D block (agent-major, n_pad rows)
+    double* part;        // [block][slot][kSymB rows][P] partial sums
+    const int2* units;   // (I, J0) per strip, I <= J0
+    const DevState* st;
+};
+
 struct UpdArgs {
     int n_pad;
     void* X;             // agent-major blocks (vector type)

@@ -33,36 +33,51 @@ void free_workspace(ccg_ctx* c) {
     c->ws = Workspace();
 }
 
-// The workspace depends only on (n_pad, P); the reduction scratch is sized for n_pad
-// rows, which covers every n with the same padded size.
-void ensure_workspace(ccg_ctx* c, int n, int P) {
+// Strip list of the symmetric A.D pass for the workspace's current n (built on the
+// device, in stream order, when n changes).
+void ensure_sym_units(ccg_ctx* c) {
+    Workspace& w = c->ws;
+    if (!w.part || w.n < kSymMinN) return;
+    const int nb = sym_blocks(w.n);
+    if (w.sym_nb == nb) return;
+    HIP_OK(launch_sym_units(nb, w.units, c->stream));
+    w.sym_nb = nb;
+}
+
+// The workspace depends only on (n_pad, P) and on whether it holds the scratch of
+// the symmetric A.D pass (sym); the reduction scratch is sized for n_pad rows, which
+// covers every n with the same padded size.
+void ensure_workspace(ccg_ctx* c, int n, int P, bool sym = false) {
     const int n_pad = (int)round_up(n, kRowAlign);
     Workspace& w = c->ws;
-    if (w.base && w.n_pad == n_pad && w.P == P) {
+    sym = sym && sym_eligible(PREC_F64, P, n);
+    if (w.base && w.n_pad == n_pad && w.P == P && (!sym || w.part)) {
         // rows n..n_pad of AD must read as zero (the A.D kernel stores rows < n only)
         if (w.n != n) {
             HIP_OK(hipMemsetAsync(w.AD, 0, sizeof(double) * (size_t)n_pad * P, c->stream));
             HIP_OK(hipMemsetAsync(w.ADl, 0, sizeof(float) * (size_t)n_pad * P, c->stream));
         }
         w.n = n;
+        ensure_sym_units(c);
         return;
     }
     free_workspace(c);
     Workspace nw;
-    const size_t bytes = carve(nw, nullptr, n, n_pad, P);
+    const size_t bytes = carve(nw, nullptr, n, n_pad, P, sym);
     if (c->budget && bytes + c->acopy_bytes + c->lowA_bytes > c->budget)
         throw CcgError{CCG_ERR_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget"};
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess)
         throw CcgError{CCG_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     HIP_OK(hipMemsetAsync(base, 0, bytes, c->stream));
-    carve(nw, static_cast<char*>(base), n, n_pad, P);
+    carve(nw, static_cast<char*>(base), n, n_pad, P, sym);
     nw.base = base;
     nw.bytes = bytes;
     nw.n = n;
     nw.n_pad = n_pad;
     nw.P = P;
     w = nw;
+    ensure_sym_units(c);
 }
 
 struct Solve {
@@ -74,8 +89,45 @@ struct Solve {
     const double* A64;     // FP64 matrix of the explicit residual
     int64_t lda64;
     int profile_every;     // time the A.D launches of every n-th round of steps (0: none)
+    bool sym_ad = false;   // CCG_SYM_AD: symmetric A.D pass where eligible
     int rounds = 0;        // rounds of block steps run so far
 };
+
+// Block steps of this solve run the symmetric A.D pass.
+bool use_sym(const Solve& s) {
+    return s.sym_ad && sym_eligible(s.prec, s.P, s.n) && s.c->ws.part && s.c->ws.sym_nb == sym_blocks(s.n);
+}
+
+// Bytes of A one block step streams, and the algorithmic bytes of its A.D pass
+// (A, or its upper triangle, plus the D and R rows) for the kernel timing.
+double step_bytes_A(const Solve& s) {
+    if (use_sym(s)) return sym_bytes_A(s.n);
+    const double sa = s.prec == PREC_F64 ? 8.0 : 4.0;
+    return sa * s.n * s.n;
+}
+double step_alg_bytes(const Solve& s) {
+    const double sv = s.prec == PREC_F64 ? 8.0 : 4.0;
+    const double vec = 2.0 * sv * s.n * s.p;
+    if (use_sym(s)) return 8.0 * 0.5 * (double)s.n * (s.n + 1) + vec;
+    const double sa = s.prec == PREC_F64 ? 8.0 : 4.0;
+    return sa * s.n * s.n + vec;
+}
+
+SymArgs sym_args(const Solve& s) {
+    const Workspace& w = s.c->ws;
+    SymArgs a;
+    a.A = static_cast<const double*>(s.A);
+    a.lda = s.lda;
+    a.n = s.n;
+    a.n_pad = w.n_pad;
+    a.nb = sym_blocks(s.n);
+    a.tmax = w.sym_tmax;
+    a.V = w.D;
+    a.part = w.part;
+    a.units = w.units;
+    a.st = w.st;
+    return a;
+}
 
 // Timing of the A.D launches requested by the flags: every round (CCG_PROFILE),
 // every 4th (CCG_PROFILE_SAMPLED), or none.
@@ -155,11 +207,12 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
 // X, R, D update.
 void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     Workspace& w = s.c->ws;
-    if (timed) {
-        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, pooled_event(s.c, 2 * ev_slot),
-                         pooled_event(s.c, 2 * ev_slot + 1)));
+    hipEvent_t e0 = timed ? pooled_event(s.c, 2 * ev_slot) : nullptr;
+    hipEvent_t e1 = timed ? pooled_event(s.c, 2 * ev_slot + 1) : nullptr;
+    if (use_sym(s)) {
+        HIP_OK(launch_sym(s.P, sym_args(s), ad_args(s, false), sym_units(sym_blocks(s.n)), s.c->stream, e0, e1));
     } else {
-        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream));
+        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, e0, e1));
     }
     const Blocks b = blocks(s);
     UpdArgs u;
@@ -181,12 +234,14 @@ void write_state(ccg_ctx* c) {
     HIP_OK(hipMemcpyAsync(c->ws.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
 }
 
-void collect_profile(ccg_ctx* c, int steps) {
+void collect_profile(const Solve& s, int steps) {
+    ccg_ctx* c = s.c;
     for (int i = 0; i < steps; ++i) {
         float ms = 0.f;
         HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
         c->prof_ms += ms;
         c->prof_launches += 1;
+        c->prof_bytes += step_alg_bytes(s);
     }
 }
 
@@ -290,8 +345,8 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
     const double* Ause = aligned_matrix(c, n, A, lda);
-    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, profile_every(o)};
-    ensure_workspace(c, n, P);
+    Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, profile_every(o), (o.flags & CCG_SYM_AD) != 0};
+    ensure_workspace(c, n, P, s.sym_ad);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -308,7 +363,8 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
     write_state(c);
     enqueue_residual(s, RES_INIT, 1);
     read_state(c);
-    const double bytes_iter = (double)n * n * sizeof(double);
+    const double bytes_iter = (double)n * n * sizeof(double);   // an explicit residual
+    const double bytes_step = step_bytes_A(s);
     double bytes = bytes_iter;   // the initial residual
     const bool use_graph = !(o.flags & CCG_NO_GRAPH);
     const int gk = o.graph_k > 0 ? o.graph_k : 16;
@@ -322,8 +378,8 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
             // A.D launches that streamed A: one per completed step, plus the one
             // whose stop test ended the batch
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
-            if (timed) collect_profile(c, streamed);
-            bytes += bytes_iter * streamed;
+            if (timed) collect_profile(s, streamed);
+            bytes += bytes_step * streamed;
         }
         if (h.done == RECUR_CONV) {
             enqueue_residual(s, RES_CONFIRM, 0);
@@ -470,7 +526,7 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
             const bool timed = run_steps(s, k, use_graph);
             read_state(c);
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
-            if (timed) collect_profile(c, streamed);
+            if (timed) collect_profile(s, streamed);
             bytes += s_low * n * n * streamed;
         }
         iters += h.iter;
@@ -651,8 +707,8 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         const ccg_opts o = fill_defaults(opts);
         const int P = pad_agents(p);
         const double* Ause = aligned_matrix(c, n, A, lda);
-        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, 0};
-        ensure_workspace(c, n, P);
+        Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, 0, (o.flags & CCG_SYM_AD) != 0};
+        ensure_workspace(c, n, P, s.sym_ad);
         Workspace& w = c->ws;
         HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
         HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -746,13 +802,15 @@ ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int r
     });
 }
 
-ccg_status ccg_kernel_time(ccg_ctx* c, double* ms, long long* launches, int reset) {
+ccg_status ccg_kernel_time(ccg_ctx* c, double* ms, long long* launches, double* bytes, int reset) {
     if (!c) return CCG_ERR_ARG;
     if (ms) *ms = c->prof_ms;
     if (launches) *launches = c->prof_launches;
+    if (bytes) *bytes = c->prof_bytes;
     if (reset) {
         c->prof_ms = 0.0;
         c->prof_launches = 0;
+        c->prof_bytes = 0.0;
     }
     return CCG_OK;
 }

@@ -42,6 +42,32 @@ hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int ni
 int ad_tile_rows(int prec, int P, int n);
 int ad_workgroups(int n);
 int row_workgroups(int n_pad, int P);
+hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
+hipError_t launch_sym_units(int nb, int2* units, hipStream_t s);
+
+// The symmetric A.D pass (upper block triangle of A, CCG_SYM_AD) serves FP64 block
+// steps of single systems with P <= kSymMaxP and n >= kSymMinN; smaller systems
+// stream A whole (their time is set by the step's fixed latency, not by the bytes
+// of A).
+constexpr int kSymMinN = 1024;
+inline bool sym_eligible(int prec, int P, int n) { return prec == PREC_F64 && P <= kSymMaxP && n >= kSymMinN; }
+inline int sym_blocks(int n) { return (n + kSymB - 1) / kSymB; }
+// strips of kSymW blocks in the upper block triangle of nb blocks
+inline int sym_units(int nb) {
+    int u = 0;
+    for (int I = 0; I < nb; ++I) u += (nb - I + kSymW - 1) / kSymW;
+    return u;
+}
+// bytes of A the symmetric pass reads: every block (I, J), I <= J, whole
+inline double sym_bytes_A(int n) {
+    double diag = 0.0;
+    for (int K = 0; K * kSymB < n; ++K) {
+        const double bk = std::min(kSymB, n - K * kSymB);
+        diag += bk * bk;
+    }
+    return 8.0 * 0.5 * ((double)n * n + diag);
+}
 
 namespace host {
 
@@ -81,6 +107,11 @@ struct Workspace {
     float* ADl = nullptr;
     RedBuf red_ad{}, red_res{};
     DevState* st = nullptr;
+    // symmetric A.D pass (carved on request, for P <= kSymMaxP and n_pad >= kSymMinN)
+    double* part = nullptr;          // n_pad/kSymB blocks x as many slots x kSymB x P
+    int2* units = nullptr;           // strip list of sym_nb blocks
+    int sym_tmax = 0;                // slot stride of part
+    int sym_nb = 0;                  // blocks of the strip list in units (0: none built)
 };
 
 struct Carver {
@@ -123,6 +154,7 @@ struct ccg_ctx {
     // A.D timing (CCG_PROFILE)
     double prof_ms = 0.0;
     long long prof_launches = 0;
+    double prof_bytes = 0.0;              // algorithmic bytes of the timed launches
     std::vector<hipEvent_t> ev_pool;
     // captured block-step graph
     hipGraphExec_t graph = nullptr;
@@ -146,7 +178,8 @@ namespace host {
 void stop_server(ccg_ctx* c);
 
 // Lay out (or only size, when base == nullptr) the workspace.
-inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
+// With sym, also the partial sums and strip list of the symmetric A.D pass.
+inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P, bool sym = false) {
     Carver cv{base};
     const size_t blk = (size_t)n_pad * P;
     w.Xr = cv.take<double>(blk);
@@ -161,6 +194,12 @@ inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P) {
     w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) + 2 * P * P + P);
     w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
+    if (sym && P <= kSymMaxP && n_pad >= kSymMinN) {
+        const int nbp = n_pad / kSymB;
+        w.sym_tmax = nbp;
+        w.part = cv.take<double>((size_t)nbp * nbp * kSymB * P);
+        w.units = cv.take<int2>((size_t)sym_units(nbp));
+    }
     return cv.off;
 }
 

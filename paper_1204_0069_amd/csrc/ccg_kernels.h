@@ -450,28 +450,57 @@ __device__ __forceinline__ int wave_fold(T (&v)[M], int lane) {
 
 // ============================================================== k_ad: AD = A D
 
-// One tile (NW * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
-template <int PREC, int P, class CFG>
-__device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const int ntiles) {
-    using TA = typename PT<PREC>::TA;
-    using TV = typename PT<PREC>::TV;
-    using TACC = typename PT<PREC>::TACC;
-    constexpr int E = PT<PREC>::E;
-    constexpr int KSTEP = 64 * E;
-    constexpr int SPC = CFG::SPC;             // wave steps per chunk
-    constexpr int KC = SPC * KSTEP;
-    constexpr int kCW = CFG::CW;
-    constexpr int kAdCols = CFG::ROWS;
-    constexpr bool NT = CFG::NT;
-    constexpr int NV = kCW * P;               // lane sums per wave
-    constexpr int WG = CFG::WG;               // threads of the workgroup
-    constexpr int PER = (P * KC + WG - 1) / WG;   // staged D values per thread per chunk
-    constexpr bool PART = PER * WG != P * KC;     // the last round of staging is partial
-    static_assert(NV <= 64, "lane sums per wave");
-    static_assert(512 % KC == 0, "chunks must tile the padded length");
+// State of the block step that the last workgroup needs, read at kernel entry so
+// that its latency hides under the stream (the previous launches have finished
+// writing it).
+struct StepState0 {
+    unsigned mask;
+    double nb, tol, tau;
+    int iter, maxit, m;
+};
+__device__ __forceinline__ StepState0 read_state0(const DevState* st) {
+    StepState0 s;
+    s.mask = st->mask;
+    s.nb = st->nb;
+    s.tol = st->tol;
+    s.tau = st->tau;
+    s.iter = st->iter;
+    s.maxit = st->maxit;
+    s.m = st->m;
+    return s;
+}
 
-    __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
-    __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
+// Thread t < ROWS * P of a workgroup holds element (row i0 + t / P, agent t % P) of
+// D and of R (zero for rows >= n), loaded at kernel entry so that the latency of the
+// loads hides under the rest of the work.
+struct DRval {
+    double d, r;
+};
+template <int PREC, int P, int ROWS>
+__device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
+    using TV = typename PT<PREC>::TV;
+    DRval v{0.0, 0.0};
+    const int t = threadIdx.x;
+    if (t < ROWS * P) {
+        const int r = t / P, j = t - (t / P) * P;
+        const int i = i0 + r;
+        if (i < a.n) {
+            v.d = double(static_cast<const TV*>(a.V)[(int64_t)j * a.n_pad + i]);
+            v.r = double(static_cast<const TV*>(a.R)[(int64_t)j * a.n_pad + i]);
+        }
+    }
+    return v;
+}
+
+// The products of the ROWS AD rows of workgroup `tile` (in adt, LDS, row stride
+// kMaxP, zero for rows >= n) with the D and R rows (dr, see load_dr), their
+// fixed-order reduction over the `ntiles` workgroups, and in the last workgroup the
+// stop test, the rank step (Alg. 3), alpha and beta.  WG threads.
+template <int PREC, int P, int ROWS, int WG>
+__device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
+                                        const StepState0& s0, const DRval dr) {
+    using TV = typename PT<PREC>::TV;
+    constexpr int kAdCols = ROWS;
     __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
     __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
     __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
@@ -479,142 +508,24 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     __shared__ double sm[4 * kMaxP * kMaxP];
     __shared__ double gscr[WG];
     __shared__ int ish[128];
-
-    if (!a.product_only && a.st->done != RUNNING) return;
-    // state the last workgroup needs, read now so that its latency hides under the
-    // stream (the previous launches have finished writing it)
-    const unsigned mask0 = a.st->mask;
-    const double nb0 = a.st->nb, tol0 = a.st->tol, tau0 = a.st->tau;
-    const int iter0 = a.st->iter, maxit0 = a.st->maxit, m0 = a.st->m;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n;
-    const int i0 = tile * kAdCols;                        // first AD row of the workgroup
-    const int iw = i0 + wave * kCW;                       // first row of this wave
+    const int i0 = tile * kAdCols;
     const TV* __restrict__ V = static_cast<const TV*>(a.V);
-    const int64_t lda = a.lda;
-    const TA* colhi[kCW];
-    const TA* collo[kCW];
-#pragma unroll
-    for (int c = 0; c < kCW; ++c) {
-        const int i = min(iw + c, n - 1);                 // rows >= n compute a copy, never stored
-        colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
-        collo[c] = (PREC == PREC_BF16X2) ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
-    }
-
-    TACC acc[kCW][P];
-#pragma unroll
-    for (int c = 0; c < kCW; ++c)
-#pragma unroll
-        for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
-
-    const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
-    // first chunk of this workgroup (rotated when staggering); chunks then wrap
-    const int c0 = CFG::STG ? (int)(((unsigned)tile * 7u) % (unsigned)nch) : 0;
-    TV pre[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int idx = tid + q * WG;
-        const int j = idx / KC, kk = idx - (idx / KC) * KC;
-        if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q)
-        if (!PART || tid + q * WG < P * KC) dch[0][tid + q * WG] = pre[q];
-    __syncthreads();
-
-    for (int it = 0; it < nch; ++it) {
-        const int buf = it & 1;
-        int ch = c0 + it;
-        if (ch >= nch) ch -= nch;
-        const int k0 = ch * KC;
-        const bool more = it + 1 < nch;
-        if (more) {
-            const int nx = (ch + 1 < nch) ? ch + 1 : 0;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int idx = tid + q * WG;
-                const int j = idx / KC, kk = idx - (idx / KC) * KC;
-                if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
-            }
-        }
-        const TV* dc = dch[buf];
-        if (k0 + KC <= n) {
-#pragma unroll
-            for (int s = 0; s < SPC; ++s) {
-                const int kk = s * KSTEP + lane * E;
-                TACC av[kCW][E];
-#pragma unroll
-                for (int c = 0; c < kCW; ++c) Loader<PREC, NT>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    TACC d[E];
-#pragma unroll
-                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
-#pragma unroll
-                    for (int c = 0; c < kCW; ++c)
-#pragma unroll
-                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
-                }
-            }
-        } else {
-            // last, partial chunk: element loads guarded by k < n
-            for (int s = 0; s < SPC; ++s) {
-                const int kk = s * KSTEP + lane * E;
-                TACC av[kCW][E];
-#pragma unroll
-                for (int c = 0; c < kCW; ++c)
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC, NT>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
-                                                     : TACC(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    TACC d[E];
-#pragma unroll
-                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
-#pragma unroll
-                    for (int c = 0; c < kCW; ++c)
-#pragma unroll
-                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
-                }
-            }
-        }
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (!PART || tid + q * WG < P * KC) dch[buf ^ 1][tid + q * WG] = pre[q];
-        }
-        __syncthreads();
-    }
-
-    // ---- lane sums -> complete AD rows (fixed butterfly order)
-    TACC v[NV];
-#pragma unroll
-    for (int c = 0; c < kCW; ++c)
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
-    const int idx = wave_fold<NV>(v, lane);
-    constexpr int REP = 64 / NV;             // lanes holding the same total
-    if (lane % REP == 0) {
-        const int c = idx / P, j = idx - (idx / P) * P;
-        const int i = iw + c;
-        const TV y = TV(v[0]);
-        if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
-        adt[(wave * kCW + c) * kMaxP + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
-    }
-    if (a.product_only) return;
+    const unsigned mask0 = s0.mask;
+    const double nb0 = s0.nb, tol0 = s0.tol, tau0 = s0.tau;
+    const int iter0 = s0.iter, maxit0 = s0.maxit, m0 = s0.m;
 
     // ---- the workgroup's share of the products over its rows, packed as
     //   G = D^T AD (lower triangle), Z = AD^T R, Y = AD^T AD (lower triangle),
     //   S = D^T R, and the diagonal of R^T R
-    const TV* __restrict__ Rv = static_cast<const TV*>(a.R);
-    for (int t = tid; t < kAdCols * P; t += WG) {
-        const int r = t / P, j = t - (t / P) * P;
-        const int i = i0 + r;
-        drw[r * kMaxP + j] = (i < n) ? double(V[(int64_t)j * a.n_pad + i]) : 0.0;
-        rrw[r * kMaxP + j] = (i < n) ? double(Rv[(int64_t)j * a.n_pad + i]) : 0.0;
+    static_assert(kAdCols * P <= WG, "one D and R value per thread");
+    if (tid < kAdCols * P) {
+        const int r = tid / P, j = tid - (tid / P) * P;
+        drw[r * kMaxP + j] = dr.d;
+        rrw[r * kMaxP + j] = dr.r;
     }
     __syncthreads();
     constexpr int TRI = P * (P + 1) / 2;
@@ -832,6 +743,157 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     }
 }
 
+// One tile (NW * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
+template <int PREC, int P, class CFG>
+__device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const int ntiles) {
+    using TA = typename PT<PREC>::TA;
+    using TV = typename PT<PREC>::TV;
+    using TACC = typename PT<PREC>::TACC;
+    constexpr int E = PT<PREC>::E;
+    constexpr int KSTEP = 64 * E;
+    constexpr int SPC = CFG::SPC;             // wave steps per chunk
+    constexpr int KC = SPC * KSTEP;
+    constexpr int kCW = CFG::CW;
+    constexpr int kAdCols = CFG::ROWS;
+    constexpr bool NT = CFG::NT;
+    constexpr int NV = kCW * P;               // lane sums per wave
+    constexpr int WG = CFG::WG;               // threads of the workgroup
+    constexpr int PER = (P * KC + WG - 1) / WG;   // staged D values per thread per chunk
+    constexpr bool PART = PER * WG != P * KC;     // the last round of staging is partial
+    static_assert(NV <= 64, "lane sums per wave");
+    static_assert(512 % KC == 0, "chunks must tile the padded length");
+
+    __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
+    __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
+
+    if (!a.product_only && a.st->done != RUNNING) return;
+    // state the last workgroup needs, read now so that its latency hides under the
+    // stream (the previous launches have finished writing it), and the D and R rows
+    // of the products
+    const StepState0 s0 = read_state0(a.st);
+    const DRval dr = a.product_only ? DRval{0.0, 0.0} : load_dr<PREC, P, CFG::ROWS>(a, tile * CFG::ROWS);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n;
+    const int i0 = tile * kAdCols;                        // first AD row of the workgroup
+    const int iw = i0 + wave * kCW;                       // first row of this wave
+    const TV* __restrict__ V = static_cast<const TV*>(a.V);
+    const int64_t lda = a.lda;
+    const TA* colhi[kCW];
+    const TA* collo[kCW];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c) {
+        const int i = min(iw + c, n - 1);                 // rows >= n compute a copy, never stored
+        colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
+        collo[c] = (PREC == PREC_BF16X2) ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
+    }
+
+    TACC acc[kCW][P];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
+
+    const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
+    // first chunk of this workgroup (rotated when staggering); chunks then wrap
+    const int c0 = CFG::STG ? (int)(((unsigned)tile * 7u) % (unsigned)nch) : 0;
+    TV pre[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * WG;
+        const int j = idx / KC, kk = idx - (idx / KC) * KC;
+        if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + c0 * KC + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (!PART || tid + q * WG < P * KC) dch[0][tid + q * WG] = pre[q];
+    __syncthreads();
+
+    for (int it = 0; it < nch; ++it) {
+        const int buf = it & 1;
+        int ch = c0 + it;
+        if (ch >= nch) ch -= nch;
+        const int k0 = ch * KC;
+        const bool more = it + 1 < nch;
+        if (more) {
+            const int nx = (ch + 1 < nch) ? ch + 1 : 0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = tid + q * WG;
+                const int j = idx / KC, kk = idx - (idx / KC) * KC;
+                if (!PART || idx < P * KC) pre[q] = V[(int64_t)j * a.n_pad + nx * KC + kk];
+            }
+        }
+        const TV* dc = dch[buf];
+        if (k0 + KC <= n) {
+#pragma unroll
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
+#pragma unroll
+                for (int c = 0; c < kCW; ++c) Loader<PREC, NT>::load(colhi[c] + k0 + kk, collo[c] + k0 + kk, av[c]);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        } else {
+            // last, partial chunk: element loads guarded by k < n
+            for (int s = 0; s < SPC; ++s) {
+                const int kk = s * KSTEP + lane * E;
+                TACC av[kCW][E];
+#pragma unroll
+                for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        av[c][e] = (k0 + kk + e < n) ? Loader<PREC, NT>::load1(colhi[c] + k0 + kk + e, collo[c] + k0 + kk + e)
+                                                     : TACC(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dc[j * KC + kk + e]);
+#pragma unroll
+                    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[c][e], d[e], acc[c][j]);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (!PART || tid + q * WG < P * KC) dch[buf ^ 1][tid + q * WG] = pre[q];
+        }
+        __syncthreads();
+    }
+
+    // ---- lane sums -> complete AD rows (fixed butterfly order)
+    TACC v[NV];
+#pragma unroll
+    for (int c = 0; c < kCW; ++c)
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
+    const int idx = wave_fold<NV>(v, lane);
+    constexpr int REP = 64 / NV;             // lanes holding the same total
+    if (lane % REP == 0) {
+        const int c = idx / P, j = idx - (idx / P) * P;
+        const int i = iw + c;
+        const TV y = TV(v[0]);
+        if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
+        adt[(wave * kCW + c) * kMaxP + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
+    }
+    if (a.product_only) return;
+    ad_tail<PREC, P, kAdCols, WG>(a, tile, ntiles, adt, s0, dr);
+}
+
 template <class CFG>
 __host__ __device__ constexpr int ad_tiles(int n) { return (n + CFG::ROWS - 1) / CFG::ROWS; }
 
@@ -847,6 +909,303 @@ void k_ad_batch(const AdArgs* __restrict__ sys, const int4* __restrict__ items) 
     const int4 it = items[blockIdx.x];
     const AdArgs a = sys[it.x];
     ad_tile<PREC, P, CFG>(a, it.y, ad_tiles<CFG>(a.n));
+}
+
+// -------------------------------------------- cross-lane sums of FP64 values (gfx950)
+//
+// The same reduce-scatter as wave_fold, for doubles, with VALU lane exchanges only:
+// offsets 32 and 16 with v_permlane32_swap / v_permlane16_swap (which swap the
+// upper half of one register with the lower half of another, so a swap followed by
+// one addition leaves each half with its own index summed over the pair), offsets 8,
+// 4, 2 and 1 with DPP moves (row rotate by 8, half-row mirror, quad permutes).  Each
+// round pairs every lane with one lane of the other half of its group, so after the
+// rounds every lane holds the sum over all 64 lanes of the value it ends up with.
+
+__device__ __forceinline__ void dsplit(double v, unsigned& lo, unsigned& hi) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    lo = (unsigned)u;
+    hi = (unsigned)(u >> 32);
+}
+__device__ __forceinline__ double djoin(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// x's upper 32 (O = 32) or odd 16-lane rows (O = 16) <-> y's lower / even ones
+template <int O>
+__device__ __forceinline__ void lane_swap(double& x, double& y) {
+    unsigned xl, xh, yl, yh;
+    dsplit(x, xl, xh);
+    dsplit(y, yl, yh);
+    if constexpr (O == 32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        x = djoin(l[0], h[0]);
+        y = djoin(l[1], h[1]);
+    } else {
+        static_assert(O == 16, "swap offsets 32 and 16");
+        const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        x = djoin(l[0], h[0]);
+        y = djoin(l[1], h[1]);
+    }
+}
+// the value of the partner lane at offset O < 16 (8: l ^ 8; 4: the mirror lane in
+// the same 8-lane half row, 7 - l % 8; 2 and 1: l ^ 2, l ^ 1)
+template <int O>
+__device__ __forceinline__ double lane_pair(double v) {
+    constexpr int CTRL = O == 8 ? 0x128 : O == 4 ? 0x141 : O == 2 ? 0x4E : 0xB1;
+    unsigned lo, hi;
+    dsplit(v, lo, hi);
+    lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xf, 0xf, false);
+    hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xf, 0xf, false);
+    return djoin(lo, hi);
+}
+
+template <int M, int O>
+struct Fold64 {
+    __device__ static __forceinline__ void run(double* v, int lane, int& idx) {
+        if constexpr (O >= 1) {
+            if constexpr (M > 1) {
+                constexpr int h = M / 2;
+                if constexpr (O >= 16) {
+#pragma unroll
+                    for (int q = 0; q < h; ++q) {
+                        lane_swap<O>(v[q], v[q + h]);
+                        v[q] = v[q] + v[q + h];
+                    }
+                } else {
+                    const bool up = (lane & O) != 0;
+#pragma unroll
+                    for (int q = 0; q < h; ++q) {
+                        const double send = up ? v[q] : v[q + h];
+                        const double keep = up ? v[q + h] : v[q];
+                        v[q] = keep + lane_pair<O>(send);
+                    }
+                }
+                if (lane & O) idx += h;
+                Fold64<h, O / 2>::run(v, lane, idx);
+            } else {
+                if constexpr (O >= 16) {
+                    double x = v[0], y = v[0];
+                    lane_swap<O>(x, y);
+                    v[0] = x + y;
+                } else {
+                    v[0] += lane_pair<O>(v[0]);
+                }
+                Fold64<1, O / 2>::run(v, lane, idx);
+            }
+        }
+    }
+};
+
+// Reduce-scatter of M = 2^q doubles per lane over the 64 lanes: returns the index
+// (0..M-1) of the total this lane holds in v[0]; 64 / M lanes hold each total.
+template <int M>
+__device__ __forceinline__ int wave_fold64(double (&v)[M], int lane) {
+    int idx = 0;
+    Fold64<M, 32>::run(v, lane, idx);
+    return idx;
+}
+
+// ================================ symmetric A.D: upper block triangle of A only
+//
+// k_sym streams the blocks A(I, J), I <= J, of 128 x 128, strip by strip (see
+// SymArgs).  A workgroup of 4 waves runs one strip of block row I: lane l holds rows
+// I*128 + 2l and 2l + 1 (one 16-byte load per column) and the matching D(I) rows in
+// registers; wave w takes columns w*32 .. w*32 + 31 of each block, two at a time.
+// For column j of block J it adds
+//   A(I, J)[:, j] * D[j, :]     to the lane's rows of block I (registers, the whole strip),
+//   A(I, J)[:, j]^T D(I)        as a sum over the 128 rows: a fixed xor butterfly over
+//                               the lanes, stored as slot I of block J (I < J only).
+// The D rows of the wave's 32 columns are staged in a wave-private LDS area, so the
+// column stream has no workgroup barrier.  At the end of the strip the four waves'
+// block-row sums are added in wave order and stored as slot I + s of block I.
+// k_fin adds up each block's slots in slot order and then runs the products, the
+// grid reduction and the step algebra of the A.D kernel (ad_tail).
+
+// A(r0 .. r0 + 1, j) of an n x n column-major matrix, zero outside it.  `full`: the
+// rows are inside the matrix (uniform over the workgroup).
+__device__ __forceinline__ void sym_load(const double* __restrict__ A, int64_t lda, int n, int j, int r0,
+                                         bool full, double (&v)[2]) {
+    v[0] = 0.0;
+    v[1] = 0.0;
+    if (j >= n) return;
+    const double* col = A + (int64_t)j * lda;
+    if (full) {
+        const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(col + r0));
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        if (r0 < n) v[0] = col[r0];
+        if (r0 + 1 < n) v[1] = col[r0 + 1];
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k_sym(SymArgs a) {
+    constexpr int COLS = kSymB / 4;                 // columns of a block per wave
+    constexpr int G = 4;                            // columns per load group
+    constexpr int GPB = COLS / G;                   // groups per block and wave
+    constexpr int NV = 2 * P;                       // butterfly values per column pair
+    constexpr int DPL = (COLS * P + 63) / 64;       // staged D values per lane
+    static_assert(P <= kSymMaxP && NV <= 64, "symmetric pass: P <= 8");
+    __shared__ double dj[4][COLS * P];              // D rows of each wave's columns
+    __shared__ double yred[4][kSymB * P];           // the waves' block-row sums
+    if (a.st->done != RUNNING) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int2 u = a.units[blockIdx.x];
+    const int I = u.x, Js = u.y;
+    const int Je = min(Js + kSymW, a.nb);
+    const int n = a.n;
+    const int64_t lda = a.lda;
+    const int64_t np = a.n_pad;
+    const int I0 = I * kSymB;
+    const int r0 = I0 + 2 * lane;
+    const bool full = I0 + kSymB <= n;
+    const double* __restrict__ A = a.A;
+    const double* __restrict__ V = a.V;
+
+    double di[2][P], yi[2][P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const d2v x = *reinterpret_cast<const d2v*>(V + p * np + r0);
+        di[0][p] = x.x;
+        di[1][p] = x.y;
+        yi[0][p] = 0.0;
+        yi[1][p] = 0.0;
+    }
+    // D rows of this wave's columns of block J, staged value q at dj[wave][c*P + p]
+    double dnx[DPL];
+    auto dload = [&](int J) {
+        const int c0 = J * kSymB + wave * COLS;
+#pragma unroll
+        for (int m = 0; m < DPL; ++m) {
+            const int q = lane + 64 * m;
+            const int p = q / COLS, c = q - (q / COLS) * COLS;
+            dnx[m] = (q < COLS * P) ? V[p * np + c0 + c] : 0.0;
+        }
+    };
+    // first column of load group g of the strip (4 groups per block and wave)
+    auto gcol = [&](int g) { return (Js + g / GPB) * kSymB + wave * COLS + G * (g - (g / GPB) * GPB); };
+    auto gload = [&](int g, double (&v)[G][2]) {
+        const int j0 = gcol(g);
+#pragma unroll
+        for (int c = 0; c < G; ++c) sym_load(A, lda, n, j0 + c, r0, full, v[c]);
+    };
+    auto gwork = [&](int g, double (&v)[G][2]) {
+        const int J = Js + g / GPB;
+        const int cb = G * (g - (g / GPB) * GPB);           // first column of the group in the wave's 32
+        if (cb == 0) {
+            // every lane has finished reading the previous block's rows (program
+            // order within the wave); stage this block's and fetch the next one's
+#pragma unroll
+            for (int m = 0; m < DPL; ++m) {
+                const int q = lane + 64 * m;
+                if (q < COLS * P) {
+                    const int p = q / COLS, cc = q - (q / COLS) * COLS;
+                    dj[wave][cc * P + p] = dnx[m];
+                }
+            }
+            if (J + 1 < Je) dload(J + 1);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        // rows of block I += A(I, J)[:, group] * D[group, :]
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            double dd[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) dd[p] = dj[wave][(cb + c) * P + p];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                yi[0][p] = fma(v[c][0], dd[p], yi[0][p]);
+                yi[1][p] = fma(v[c][1], dd[p], yi[1][p]);
+            }
+        }
+        // rows of block J += A(I, J)[:, group]^T D(I), a column pair per butterfly
+        if (J != I) {
+            double* out = a.part + (((int64_t)J * a.tmax + I) * kSymB + wave * COLS + cb) * P;
+#pragma unroll
+            for (int c = 0; c < G; c += 2) {
+                double t[NV];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) t[b * P + p] = fma(v[c + b][1], di[1][p], v[c + b][0] * di[0][p]);
+                const int idx = wave_fold64<NV>(t, lane);
+                if (lane % (64 / NV) == 0) out[c * P + idx] = t[0];
+            }
+        }
+    };
+    const int ng = (Je - Js) * GPB;
+    double va[G][2], vb[G][2];
+    dload(Js);
+    gload(0, va);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng) gload(g + 1, vb);
+        gwork(g, va);
+        if (g + 1 < ng) {
+            if (g + 2 < ng) gload(g + 2, va);
+            gwork(g + 1, vb);
+        }
+    }
+    // the strip's sums for block row I: the four waves added in wave order
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        yred[wave][(2 * lane) * P + p] = yi[0][p];
+        yred[wave][(2 * lane + 1) * P + p] = yi[1][p];
+    }
+    __syncthreads();
+    double* outI = a.part + ((int64_t)I * a.tmax + I + (Js - I) / kSymW) * kSymB * P;
+    for (int q = tid; q < kSymB * P; q += kWG) outI[q] = ((yred[0][q] + yred[1][q]) + yred[2][q]) + yred[3][q];
+}
+
+// AD rows of the symmetric pass from the partial slots, kFinRows rows per workgroup
+// (kSymB % kFinRows == 0, so all rows of a workgroup lie in one block K), then the
+// products, the reduction and the step algebra.  Slot t of an output is summed by
+// thread phase t mod TPO in slot order; the phases are then added in phase order.
+constexpr int kFinRows = 8;
+
+template <int P>
+__global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
+    constexpr int NO = kFinRows * P;          // outputs of the workgroup
+    constexpr int TPO = kWG / NO;             // threads per output
+    constexpr int U = 16;                     // loads in flight per thread
+    __shared__ double adt[kFinRows * kMaxP];
+    __shared__ double sub[kWG];
+    if (a.st->done != RUNNING) return;
+    const StepState0 s0 = read_state0(a.st);
+    const int tid = threadIdx.x;
+    const int o = tid % NO, ph = tid / NO;
+    const int i0 = blockIdx.x * kFinRows;
+    const DRval dr = load_dr<PREC_F64, P, kFinRows>(a, i0);
+    const int K = i0 / kSymB;
+    const int T = K + (sa.nb - K + kSymW - 1) / kSymW;
+    const int64_t stride = (int64_t)kSymB * P;
+    const double* src = sa.part + ((int64_t)K * sa.tmax * kSymB + (i0 - K * kSymB)) * P + o;
+    double acc = 0.0;
+    for (int t0 = ph; t0 < T; t0 += U * TPO) {
+        double v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) v[q] = (t0 + q * TPO < T) ? src[(t0 + q * TPO) * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            if (t0 + q * TPO < T) acc += v[q];
+    }
+    sub[tid] = acc;
+    __syncthreads();
+    if (tid < NO) {
+        double y = sub[tid];
+        for (int q = 1; q < TPO; ++q) y += sub[tid + q * NO];
+        const int r = tid / P, j = tid - (tid / P) * P;
+        const int i = i0 + r;
+        if (i < a.n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
+        adt[r * kMaxP + j] = (i < a.n) ? y : 0.0;
+    }
+    // ad_tail's first barrier orders these adt writes before their use
+    ad_tail<PREC_F64, P, kFinRows, kWG>(a, blockIdx.x, gridDim.x, adt, s0, dr);
 }
 
 // ===================== k_upd: X += D alpha, R -= AD alpha, D = R + D beta
@@ -1079,6 +1438,28 @@ inline hipError_t launch_ad_prec(int P, int cw, int nw, const AdArgs* one, const
 // Entry points of the per-precision translation units.
 hipError_t launch_ad_f64(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                          int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Symmetric A.D pass of one FP64 system: k_sym over `nunits` strips, then k_fin.
+// With an event pair, e0 is recorded at the start of k_sym and e1 at the end of k_fin.
+template <int P>
+inline hipError_t launch_sym_t(const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+    const dim3 gs(nunits), gf((a.n + kFinRows - 1) / kFinRows);
+    if (e0) {
+        hipExtLaunchKernelGGL((k_sym<P>), gs, dim3(kWG), 0, s, e0, nullptr, 0, sa);
+    } else {
+        hipLaunchKernelGGL((k_sym<P>), gs, dim3(kWG), 0, s, sa);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (e1) {
+        hipExtLaunchKernelGGL((k_fin<P>), gf, dim3(kWG), 0, s, nullptr, e1, 0, sa, a);
+    } else {
+        hipLaunchKernelGGL((k_fin<P>), gf, dim3(kWG), 0, s, sa, a);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_sym_f64(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1);
 hipError_t launch_ad_f32(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                          int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_ad_bf16(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,

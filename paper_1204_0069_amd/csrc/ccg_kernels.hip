@@ -218,6 +218,27 @@ hipError_t launch_ad_cw(int prec, int P, int cw, int nw, const AdArgs& a, hipStr
     return launch_ad_any(prec, P, cw, nw, &a, nullptr, nullptr, 0, s, e0, e1);
 }
 
+hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1) {
+    return launch_sym_f64(P, sa, a, nunits, s, e0, e1);
+}
+
+// The strip list of the symmetric pass for nb blocks: strips of kSymW blocks first,
+// then the shorter ones at the ends of the block rows.  One thread.
+__global__ void k_sym_units(int nb, int2* units) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int u = 0;
+    for (int len = kSymW; len >= 1; --len)
+        for (int I = 0; I < nb; ++I)
+            for (int J0 = I; J0 < nb; J0 += kSymW)
+                if (min(kSymW, nb - J0) == len) units[u++] = int2{I, J0};
+}
+
+hipError_t launch_sym_units(int nb, int2* units, hipStream_t s) {
+    hipLaunchKernelGGL(k_sym_units, dim3(1), dim3(64), 0, s, nb, units);
+    return hipGetLastError();
+}
+
 hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
     switch (prec) {
 #define C64(PP) launch_upd_t<PREC_F64, PP>(a, s)
