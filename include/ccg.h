@@ -221,10 +221,13 @@ ccg_status ccg_convert_matrix(ccg_ctx *ctx, int n, const double *A, int64_t lda,
  * columns per wave (1, 2 or 4) and `nw` waves per workgroup (4, 8 or 16; a shape
  * beyond the register budget runs at the nearest one that fits) on a synthetic
  * symmetric diagonally dominant system of size n with p agents in precision `prec`,
- * over `reps` launches after 2 warm-up launches.  Uses and overwrites the context's
- * workspace.  For the autotuner that writes the library's table of tile shapes
- * (paper_1204_0069_amd/tune.py). */
-ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int reps, double *us);
+ * over `reps` launches after 2 warm-up launches.  batched = 1 times the kernel of
+ * ccg_solve_batched instead (the system's tiles as work items; timed with events
+ * recorded around the launch).  Uses and overwrites the context's workspace.  For
+ * the autotuner that writes the library's table of tile shapes
+ * (paper_1204_0069_amd/tune.py).  CCG_ERR_ARG for arguments outside these ranges. */
+ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int batched, int reps,
+                       double *us);
 
 /* Median duration in microseconds, over `reps` launches after 2 warm-up launches, of
  * a kernel that only reads: an n x n FP64 matrix (column-major, lda = n; n even),

@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.ccg_convert_matrix.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp]
     lib.ccg_convert_matrix.restype = ctypes.c_int
     lib.ccg_tune_ad.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_int, dp]
+                                ctypes.c_int, ctypes.c_int, dp]
     lib.ccg_tune_ad.restype = ctypes.c_int
     lib.ccg_stream_probe.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, dp]
@@ -314,10 +314,12 @@ class Context:
         del keep
         return hi if lo is None else (hi, lo)
 
-    def tune_ad(self, prec: str, p: int, n: int, cw: int, reps: int = 10, nw: int = 4) -> float:
-        """Microseconds per A.D launch with tile shape (cw, nw) (see ccg_tune_ad)."""
+    def tune_ad(self, prec: str, p: int, n: int, cw: int, reps: int = 10, nw: int = 4,
+                batched: bool = False) -> float:
+        """Microseconds per A.D launch with tile shape (cw, nw), of the single-system
+        or (batched) the batched kernel (see ccg_tune_ad)."""
         us = ctypes.c_double()
-        st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, nw, reps, ctypes.byref(us))
+        st = self.lib.ccg_tune_ad(self.h, PREC[prec], p, n, cw, nw, int(batched), reps, ctypes.byref(us))
         if st != 0:
             raise self._err(st)
         return us.value

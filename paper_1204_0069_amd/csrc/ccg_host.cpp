@@ -754,10 +754,10 @@ ccg_status ccg_convert_matrix(ccg_ctx* c, int n, const double* A, int64_t lda, i
     });
 }
 
-ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int reps, double* us) {
+ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int batched, int reps, double* us) {
     return guarded(c, [&]() -> ccg_status {
         if (n < 1 || p < 1 || p > kMaxP || p > n || reps < 1 || !us || (cw != 1 && cw != 2 && cw != 4) ||
-            (nw != 4 && nw != 8 && nw != 16))
+            (nw != 4 && nw != 8 && nw != 16) || (batched != 0 && batched != 1))
             throw CcgError{CCG_ERR_ARG, "bad tuning argument"};
         if (prec != CCG_FP64 && prec != CCG_FP32 && prec != CCG_BF16X2) throw CcgError{CCG_ERR_ARG, "bad precision"};
         const int pr = prec == CCG_FP64 ? PREC_F64 : (prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
@@ -789,9 +789,36 @@ ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int r
         write_state(c);
         hipEvent_t e0 = pooled_event(c, 0), e1 = pooled_event(c, 1);
         const AdArgs a = ad_args(s, false);
+        // the batched kernel runs the system's tiles as (system 0, tile) work items
+        void* bbuf = nullptr;
+        struct FreeB {
+            void*& p;
+            ~FreeB() { if (p) (void)hipFree(p); }
+        } fb{bbuf};
+        const int rows = ad_fit_rows(pr, P, cw, nw);
+        const int ntiles = (n + rows - 1) / rows;
+        AdArgs* d_sys = nullptr;
+        int4* d_items = nullptr;
+        if (batched) {
+            const size_t ioff = round_up((int64_t)sizeof(AdArgs), 256);
+            if (hipMalloc(&bbuf, ioff + sizeof(int4) * (size_t)ntiles) != hipSuccess)
+                throw CcgError{CCG_ERR_NOMEM, "tuning item list allocation failed"};
+            d_sys = static_cast<AdArgs*>(bbuf);
+            d_items = reinterpret_cast<int4*>(static_cast<char*>(bbuf) + ioff);
+            std::vector<int4> items((size_t)ntiles);
+            for (int t = 0; t < ntiles; ++t) items[(size_t)t] = int4{0, t, 0, 0};
+            HIP_OK(hipMemcpy(d_sys, &a, sizeof(AdArgs), hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d_items, items.data(), sizeof(int4) * (size_t)ntiles, hipMemcpyHostToDevice));
+        }
         double tot = 0.0;
         for (int i = 0; i < reps + 2; ++i) {
-            HIP_OK(launch_ad_cw(pr, P, cw, nw, a, c->stream, e0, e1));
+            if (batched) {
+                HIP_OK(hipEventRecord(e0, c->stream));
+                HIP_OK(launch_ad_batch(pr, P, cw, nw, d_sys, d_items, ntiles, c->stream));
+                HIP_OK(hipEventRecord(e1, c->stream));
+            } else {
+                HIP_OK(launch_ad_cw(pr, P, cw, nw, a, c->stream, e0, e1));
+            }
             HIP_OK(hipStreamSynchronize(c->stream));
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));

@@ -39,7 +39,7 @@ hipError_t launch_tune_matrix(int n, double* A, int64_t lda, hipStream_t s);
 hipError_t launch_tune_vectors(int64_t cnt, double* d64, float* d32, unsigned seed, hipStream_t s);
 hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);
 hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int nitems, hipStream_t s);
-int ad_tile_rows(int prec, int P, int n);
+int ad_fit_rows(int prec, int P, int cw, int nw);
 int ad_workgroups(int n);
 int row_workgroups(int n_pad, int P);
 hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0 = nullptr,

@@ -472,14 +472,17 @@ __device__ __forceinline__ StepState0 read_state0(const DevState* st) {
 
 // Thread t < ROWS * P of a workgroup holds element (row i0 + t / P, agent t % P) of
 // D and of R (zero for rows >= n), loaded at kernel entry so that the latency of the
-// loads hides under the rest of the work.
+// loads hides under the rest of the work.  `early` false: not loaded yet, ad_tail
+// loads them itself (the low-precision A.D kernels run at their register limit, and
+// two values held through the stream cost them spills).
 struct DRval {
     double d, r;
+    bool early;
 };
 template <int PREC, int P, int ROWS>
 __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
     using TV = typename PT<PREC>::TV;
-    DRval v{0.0, 0.0};
+    DRval v{0.0, 0.0, true};
     const int t = threadIdx.x;
     if (t < ROWS * P) {
         const int r = t / P, j = t - (t / P) * P;
@@ -523,9 +526,10 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
     //   S = D^T R, and the diagonal of R^T R
     static_assert(kAdCols * P <= WG, "one D and R value per thread");
     if (tid < kAdCols * P) {
+        const DRval v = dr.early ? dr : load_dr<PREC, P, ROWS>(a, i0);
         const int r = tid / P, j = tid - (tid / P) * P;
-        drw[r * kMaxP + j] = dr.d;
-        rrw[r * kMaxP + j] = dr.r;
+        drw[r * kMaxP + j] = v.d;
+        rrw[r * kMaxP + j] = v.r;
     }
     __syncthreads();
     constexpr int TRI = P * (P + 1) / 2;
@@ -771,7 +775,8 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     // stream (the previous launches have finished writing it), and the D and R rows
     // of the products
     const StepState0 s0 = read_state0(a.st);
-    const DRval dr = a.product_only ? DRval{0.0, 0.0} : load_dr<PREC, P, CFG::ROWS>(a, tile * CFG::ROWS);
+    const DRval dr = (a.product_only || PREC != PREC_F64) ? DRval{0.0, 0.0, false}
+                                                          : load_dr<PREC, P, CFG::ROWS>(a, tile * CFG::ROWS);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);

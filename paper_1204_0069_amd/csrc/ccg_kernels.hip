@@ -175,8 +175,8 @@ int ad_nw(int prec, int P, int n) {
     return r ? ad_nw_fit(P, r->nw) : 4;
 }
 
-// AD rows per A.D tile.
-int ad_tile_rows(int prec, int P, int n) { return ad_nw(prec, P, n) * ad_cw(prec, P, n); }
+// AD rows per A.D tile of a requested shape, as the launchers run it.
+int ad_fit_rows(int prec, int P, int cw, int nw) { return ad_cw_fit(prec, P, cw) * ad_nw_fit(P, nw); }
 
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {

@@ -4,10 +4,13 @@
 
 For every precision, padded agent count P and a ladder of system sizes n it times
 the full A.D launch of the block step (stream of A, Gram products, stop test and
-p x p solves) for each candidate shape with ccg_tune_ad, keeps the fastest, merges
-neighbouring sizes with the same choice into n ranges and writes the table that
-the library compiles in (csrc/ccg_tune_table.h).  Rebuild the library afterwards
-(python -m paper_1204_0069_amd.build).
+p x p solves) for each candidate shape with ccg_tune_ad, in the single-system kernel
+and in the batched one (a system solved batched uses the shape its single solve
+uses, so that both give the same result; the batched kernel needs more registers
+and spills in some shapes), scores each shape by the slower of the two, keeps the
+best, merges neighbouring sizes with the same choice into n ranges and writes the
+table that the library compiles in (csrc/ccg_tune_table.h).  Rebuild the library
+afterwards (python -m paper_1204_0069_amd.build).
 
 The shape changes the tile decomposition, hence the order in which the Gram
 partial sums are added; the table is fixed at build time, so results stay
@@ -82,10 +85,13 @@ def tune(ctx, reps: int, log=print):
             for n in SIZES:
                 if P > n:
                     continue
-                t = {sh: ctx.tune_ad(prec, P, n, sh[0], reps, nw=sh[1]) for sh in shapes(prec, P)}
+                ts = {sh: ctx.tune_ad(prec, P, n, sh[0], reps, nw=sh[1]) for sh in shapes(prec, P)}
+                tb = {sh: ctx.tune_ad(prec, P, n, sh[0], reps, nw=sh[1], batched=True) for sh in shapes(prec, P)}
+                t = {sh: max(ts[sh], tb[sh]) for sh in ts}
                 sh = choose(t)
                 best.append((n, sh))
-                log(f"{prec:7s} P={P:2d} n={n:6d} " + "  ".join(f"c{k[0]}w{k[1]}:{v:9.2f}us" for k, v in t.items())
+                log(f"{prec:7s} P={P:2d} n={n:6d} "
+                    + "  ".join(f"c{k[0]}w{k[1]}:{v:9.2f}us({ts[k]:.2f}/{tb[k]:.2f})" for k, v in t.items())
                     + f"  -> {sh[0]},{sh[1]}")
             best_by_class[(cname, P)] = best
     return rows_from(best_by_class)
@@ -101,7 +107,8 @@ def rows_from_log(path: str):
         if not m:
             continue
         prec, P, n = m.group(1), int(m.group(2)), int(m.group(3))
-        # "c2w8: 91.3us" entries, or "cw2: 91.3us" from logs of 4-wave workgroups only
+        # "c2w8: 91.3us(90.1/91.3)" entries (the score, then the single-system and the
+        # batched time), or "cw2: 91.3us" from logs of 4-wave workgroups only
         t = {(int(c), int(w)): float(v) for c, w, v in re.findall(r"c(\d)w(\d+):\s*([\d.]+)us", m.group(4))}
         t.update({(int(c), 4): float(v) for c, v in re.findall(r"cw(\d):\s*([\d.]+)us", m.group(4))})
         best_by_class.setdefault((names[prec], P), []).append((n, choose(t)))

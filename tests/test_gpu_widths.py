@@ -91,8 +91,9 @@ def test_refined_solve_at_each_width(gpu_ctx, prec, P, n, w, nw):
 def test_tuner_entry_times_every_width(gpu_ctx, prec):
     for w in (1, 2, 4):
         for nw in (4, 8, 16):
-            us = gpu_ctx.tune_ad(prec, 4, 512, w, reps=2, nw=nw)
-            assert 0.0 < us < 1e5
+            for batched in (False, True):
+                us = gpu_ctx.tune_ad(prec, 4, 515, w, reps=2, nw=nw, batched=batched)
+                assert 0.0 < us < 1e5
     with pytest.raises(Exception):
         gpu_ctx.tune_ad(prec, 4, 512, 2, reps=2, nw=6)
 

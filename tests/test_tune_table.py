@@ -12,13 +12,16 @@ ROW = r"\{(PREC_\w+), (\d+), (\d+), (\d), (\d+)\}"
 
 class FakeCtx:
     """Timings: width 1 wins below n = 1024, width 4 above 4096 where it fits, else 2;
-    16 waves per workgroup win from n = 8192 on, 4 below."""
+    16 waves per workgroup win from n = 8192 on, 4 below.  The batched kernel times
+    the same, except that 16 waves at width 4 are slow there (as a spilling shape)."""
 
     def __init__(self):
         self.calls = []
 
-    def tune_ad(self, prec, P, n, cw, reps, nw=4):
+    def tune_ad(self, prec, P, n, cw, reps, nw=4, batched=False):
         self.calls.append((prec, P, n, cw, nw))
+        if batched and cw == 4 and nw == 16:
+            return 100.0
         if n < 1024:
             t = {1: 1.0, 2: 2.0, 4: 3.0}[cw]
         elif n > 4096:
@@ -41,8 +44,9 @@ def test_candidate_shapes_follow_the_register_rules():
 def test_merge_and_limits():
     ctx = FakeCtx()
     rows = tune.tune(ctx, reps=1, log=lambda s: None)
-    # FP32, P = 8: width 1 up to 512, 2 for 1024..4096, then 4 with 16 waves from 8192 on
-    assert _rows_for(rows, "PREC_F32", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 16)]
+    # FP32, P = 8: width 1 up to 512, 2 for 1024..4096, then from 8192 on width 4 with
+    # 8 waves: 16 waves are faster in the single-system kernel but slow batched
+    assert _rows_for(rows, "PREC_F32", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 8)]
     # FP64, P = 8 may not use 4 columns per wave: 2 from 1024 on
     assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 2, 16)]
     # P = 16 never times width 4 or more than 4 waves; no size below P is timed
@@ -56,6 +60,13 @@ def test_written_table_round_trips(tmp_path):
     tune.write_table(rows, "test device", str(out))
     got = re.findall(ROW, out.read_text())
     assert [(c, int(P), int(n), int(w), int(nw)) for c, P, n, w, nw in got] == rows
+
+
+def test_logs_read_the_score(tmp_path):
+    log = tmp_path / "new.txt"
+    log.write_text("fp64    P= 8 n=  8192 c2w4:    98.54us(98.50/98.54)  c2w8:    93.86us(93.70/93.86)"
+                   "  -> 2,8\n")
+    assert tune.rows_from_log(str(log)) == [("PREC_F64", 8, 1 << 30, 2, 8)]
 
 
 def test_old_logs_read_as_four_waves(tmp_path):
