@@ -305,17 +305,20 @@ def run_batched(args):
     import torch
 
     import ccg_inputs as ci
-    from paper_1204_0069_amd import Context
+    from paper_1204_0069_amd import CCG_ESCALATE, PREC, Context
 
     dev = "cuda:0"
     specs = ci.batch_specs(count=args.count, n_lo=64, n_hi=4096, p_choices=(2, 4, 8),
                            k_lo=1e2, k_hi=1e5)
+    # low-precision systems move to a wider precision when their refinement breaks
+    # down (at kappa near 1e5 the BF16x2 copy's rounding times kappa is close to 1)
+    flags = CCG_ESCALATE if args.prec != "fp64" else 0
     systems = []
     for sp in specs:
         A = ci.spd_spectrum(sp["n"], sp["kappa"], sp["seed"], device=dev)
         b = torch.as_tensor(ci.normal_block(sp["n"], 0, ci.item_seed("bb", sp["seed"])), device=dev)
         X0 = torch.as_tensor(ci.normal_block(sp["n"], sp["p"], ci.item_seed("bx", sp["seed"])), device=dev)
-        systems.append(dict(A=A, b=b, X0=X0, tol=args.tol, maxit=10 ** 6, prec=args.prec))
+        systems.append(dict(A=A, b=b, X0=X0, tol=args.tol, maxit=10 ** 6, prec=args.prec, flags=flags))
     torch.cuda.synchronize()
     ctx = Context(0)
     if args.single_fp64:
@@ -356,8 +359,11 @@ def run_batched(args):
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x2": "bf16x2"}[args.prec], "data": "synthetic",
         "config": {"workload": f"batch of {len(specs)} dense SPD systems, n log-uniform in [64, 4096], "
                                f"p in {{2, 4, 8}}, kappa log-uniform in [1e2, 1e5], {args.prec.upper()} A, "
-                               f"tol {args.tol:g}", "count": len(specs), "prec": args.prec},
-        "converged": ok, "iters_mean": float(np.mean([i["iters"] for i in infos])),
+                               f"tol {args.tol:g}"
+                               + (", precision escalation on breakdown" if flags else ""),
+                   "count": len(specs), "prec": args.prec},
+        "converged": ok, "escalated": sum(1 for i in infos if i["prec_final"] != PREC[args.prec]),
+        "iters_mean": float(np.mean([i["iters"] for i in infos])),
         "iters_max": int(max(i["iters"] for i in infos)),
         "rel_res_max": float(max(i["rel_res"] for i in infos)),
         "roofline": {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
