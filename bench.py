@@ -211,7 +211,7 @@ def main():
                     "kernel": "k_ad",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
                     "timed": ("every A.D launch" if args.profile_all else
-                              "the A.D launches of every 4th round of 16 block steps"),
+                              "the A.D launches of every 4th round of block steps"),
                     "bytes_per_launch": bytes_per_launch}
 
     cpu = None

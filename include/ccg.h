@@ -68,8 +68,8 @@ typedef enum {
                                  positive or not finite), continue from the current agents
                                  in the next wider precision (BF16X2 -> FP32 -> FP64);
                                  info then totals every stage */
-#define CCG_PROFILE_SAMPLED 0x10u  /* as CCG_PROFILE for every 4th round of graph_k block
-                                      steps; the other rounds run from the captured graph */
+#define CCG_PROFILE_SAMPLED 0x10u  /* as CCG_PROFILE for every 4th round of block steps;
+                                      the other rounds run from the captured graphs */
 #define CCG_SYM_AD    0x20u  /* FP64 block steps with p <= 8 and n >= 1024 form A D from
                                  the upper block triangle of A only (see ccg_solve) */
 
@@ -82,7 +82,9 @@ typedef struct {
     int max_refine;      /* low-precision modes: outer refinement steps (default 60) */
     double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
                             low-precision modes, whose vectors carry FP32 rounding) */
-    int graph_k;         /* block steps per captured graph / per host poll (default 16) */
+    int graph_k;         /* block steps per captured graph / per host poll (default 16);
+                            CCG_FP64 solves lengthen a round up to 8 graph_k while the
+                            residual's decay predicts many more steps */
     unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_PROFILE_SAMPLED |
                             CCG_ESCALATE */
 } ccg_opts;

@@ -28,7 +28,8 @@ using namespace ccg::host;
 namespace {
 
 void free_workspace(ccg_ctx* c) {
-    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
     if (c->ws.base) (void)hipFree(c->ws.base);
     c->ws = Workspace();
 }
@@ -245,8 +246,8 @@ void collect_profile(const Solve& s, int steps) {
     }
 }
 
-// Capture `steps` block steps into c->graph.
-void capture_steps(Solve& s, int steps) {
+// Capture `steps` block steps into a graph.
+hipGraphExec_t capture_steps(Solve& s, int steps) {
     ccg_ctx* c = s.c;
     hipGraph_t gr = nullptr;
     HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -262,8 +263,11 @@ void capture_steps(Solve& s, int steps) {
         if (gr) (void)hipGraphDestroy(gr);
         throw CcgError{CCG_ERR_DEVICE, "stream capture of the block step failed"};
     }
-    HIP_OK(hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0));
-    HIP_OK(hipGraphDestroy(gr));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIP_OK(ei);
+    return ex;
 }
 
 // Run `steps` block steps, through a captured graph when allowed.  A round whose
@@ -280,15 +284,37 @@ bool run_steps(Solve& s, int steps, bool use_graph) {
     }
     const int64_t key[6] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
                             s.lda};
-    const bool same = c->graph && c->graph_k == steps && std::equal(key, key + 6, c->graph_key);
-    if (!same) {
-        if (c->graph) { HIP_OK(hipGraphExecDestroy(c->graph)); c->graph = nullptr; }
-        capture_steps(s, steps);
-        c->graph_k = steps;
+    if (!std::equal(key, key + 6, c->graph_key)) {
+        for (auto& g : c->graphs) HIP_OK(hipGraphExecDestroy(g.second));
+        c->graphs.clear();
         std::copy(key, key + 6, c->graph_key);
     }
-    HIP_OK(hipGraphLaunch(c->graph, c->stream));
+    hipGraphExec_t ex = nullptr;
+    for (auto& g : c->graphs)
+        if (g.first == steps) ex = g.second;
+    if (!ex) {
+        ex = capture_steps(s, steps);
+        c->graphs.emplace_back(steps, ex);
+    }
+    HIP_OK(hipGraphLaunch(ex, c->stream));
     return false;
+}
+
+// Block steps of the next round of an FP64 solve.  Each round ends with the host
+// reading the device state (about 45 us in which the GPU idles at n = 8192), so
+// while the residual is far from the tolerance the rounds grow: from the decay of
+// min_j ||R_j|| over the last round (prev -> cur in `done` steps) the steps still
+// needed are predicted, and the round takes up to half of them, in powers of two
+// from graph_k up to 8 graph_k.  Steps after the stop return at once, so a round
+// that overshoots costs a few microseconds per step.  The steps themselves, and so
+// the results, do not depend on where the rounds end.
+int next_round(int gk, double prev, double cur, int done, double tol) {
+    if (!(prev > 0.0) || !(cur > 0.0) || !(tol > 0.0) || done <= 0 || cur >= prev || cur <= tol) return gk;
+    const double rate = std::log(cur / prev) / done;      // < 0
+    const double left = std::log(tol / cur) / rate;       // predicted steps to go
+    int k = gk;
+    while (k < 8 * gk && 2.0 * k <= 0.5 * left) k *= 2;
+    return k;
 }
 
 // The A.D kernel reads columns with 16-byte loads.  A caller matrix whose columns
@@ -368,13 +394,16 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
     double bytes = bytes_iter;   // the initial residual
     const bool use_graph = !(o.flags & CCG_NO_GRAPH);
     const int gk = o.graph_k > 0 ? o.graph_k : 16;
+    int round_k = gk;
     while (h.done == RUNNING || h.done == RECUR_CONV) {
         if (h.done == RUNNING) {
             const int left = maxit - h.iter;
-            const int k = left > 0 ? gk : 1;   // steps past maxit are no-ops: keep one graph
+            const int k = left > 0 ? round_k : 1;   // steps past maxit are no-ops
             const int it0 = h.iter;
+            const double res0 = h.minres;
             const bool timed = run_steps(s, k, use_graph);
             read_state(c);
+            round_k = next_round(gk, res0, h.minres, h.iter - it0, tol);
             // A.D launches that streamed A: one per completed step, plus the one
             // whose stop test ended the batch
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);

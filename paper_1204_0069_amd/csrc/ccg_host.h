@@ -156,9 +156,8 @@ struct ccg_ctx {
     long long prof_launches = 0;
     double prof_bytes = 0.0;              // algorithmic bytes of the timed launches
     std::vector<hipEvent_t> ev_pool;
-    // captured block-step graph
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
+    // captured block-step graphs, one per round length, all for graph_key
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
     int64_t graph_key[6] = {0, 0, 0, 0, 0, 0};
     // aligned copy of a caller matrix with unaligned columns
     void* acopy = nullptr;

@@ -141,6 +141,19 @@ def test_graph_and_direct_launch_agree(gpu_ctx):
     assert torch.equal(X1, X2)
 
 
+def test_round_lengths_do_not_change_results(gpu_ctx):
+    """FP64 rounds grow from graph_k up to 8 graph_k while the residual is far from tol;
+    where they end must not change the steps: graph_k 1, 4 and 16 (rounds of 1..128
+    steps, several graphs in one context) give the same result, and so does a solve
+    after the other sizes' graphs were captured."""
+    A, b, X0 = ci.system(2100, 6, 1e4, seed=9)
+    runs = [gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, graph_k=k) for k in (16, 1, 4, 16)]
+    for X, info in runs[1:]:
+        assert info["status"] == 0 and info["iters"] == runs[0][1]["iters"]
+        assert torch.equal(X, runs[0][0])
+    assert runs[0][1]["iters"] > 128
+
+
 def test_profiled_solves_agree_and_count_launches(gpu_ctx):
     """Timing the A.D launches (every round, or every 4th round with the rest from the
     graph) changes how steps are launched, not what they compute."""
