@@ -83,8 +83,9 @@ typedef struct {
     double rank_tau;     /* rank threshold on scaled pivots (default 1e-14; 1e-12 in the
                             low-precision modes, whose vectors carry FP32 rounding) */
     int graph_k;         /* block steps per captured graph / per host poll (default 16);
-                            CCG_FP64 solves lengthen a round up to 8 graph_k while the
-                            residual's decay predicts many more steps */
+                            ccg_solve lengthens a round up to 8 graph_k while the
+                            residual's decay predicts many more steps (FP64 solves and
+                            the inner solves of the refinement modes) */
     unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_PROFILE_SAMPLED |
                             CCG_ESCALATE */
 } ccg_opts;

@@ -300,7 +300,8 @@ bool run_steps(Solve& s, int steps, bool use_graph) {
     return false;
 }
 
-// Block steps of the next round of an FP64 solve.  Each round ends with the host
+// Block steps of the next round of a solve (FP64, or the inner solve of a
+// refinement step, whose target is its inner tolerance).  Each round ends with the host
 // reading the device state (about 45 us in which the GPU idles at n = 8192), so
 // while the residual is far from the tolerance the rounds grow: from the decay of
 // min_j ||R_j|| over the last round (prev -> cur in `done` steps) the steps still
@@ -549,11 +550,14 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
         h.nb = 1.0;
         h.maxit = std::min(o.inner_maxit, maxit - iters);
         write_state(c);
+        int round_k = gk;
         while (h.done == RUNNING) {
-            const int k = gk;   // steps past maxit are no-ops: keep one graph
+            const int k = round_k;   // steps past maxit are no-ops
             const int it0 = h.iter;
+            const double res0 = h.minres;
             const bool timed = run_steps(s, k, use_graph);
             read_state(c);
+            round_k = next_round(gk, res0, h.minres, h.iter - it0, h.tol);
             const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
             if (timed) collect_profile(s, streamed);
             bytes += s_low * n * n * streamed;
