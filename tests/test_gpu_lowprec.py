@@ -177,3 +177,57 @@ def test_escalation_after_breakdown(gpu_ctx):
     T = oracle.residual(A, b, X2.cpu().numpy())
     assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() <= 1.01 * tol
     assert i2["iters"] > i1["iters"] and i2["bytes_A"] > i1["bytes_A"]
+
+
+@pytest.fixture(scope="module")
+def c3_system():
+    """The n = 32768, p = 8 workload of the mixed-precision modes (A = M^T M / n + sigma I,
+    cond 1e3, built on the device)."""
+    n, p = 32768, 8
+    A = ci.spd_gram(n, 1e3, ci.item_seed("C3", 1204, base=n), device=DEV)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", 1204, base=n)), device=DEV)
+    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", 1204, base=n)), device=DEV)
+    yield A, b, X0
+    del A
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
+def test_full_size_n32768_refined_solve(gpu_ctx, c3_system, prec):
+    """At n = 32768 (4 GiB as BF16 hi + lo planes, 8 GiB in FP64) the oracle cannot run a
+    solve; what holds at any size is checked instead: the low-precision copy is the
+    oracle's conversion, bit for bit, on sampled columns; the explicit FP64 residual of
+    the best agent (torch's own product) meets tol and matches the reported one; and
+    sampled rows of that residual, summed in FP64 on the host, agree with it."""
+    A, b, X0 = c3_system
+    n = A.shape[0]
+    print(f"case full-size {prec} n={n} p=8", flush=True)
+    rng = np.random.default_rng(32768)
+    cols = np.sort(rng.choice(n, 4, replace=False))
+    Ac = A[:, cols].cpu().numpy()          # columns of the symmetric A, also its rows
+    # (the copy keeps A's element order; A is symmetric, so columns are rows too)
+    if prec == "fp32":
+        lowA = gpu_ctx.convert_matrix(A, "fp32")
+        got = lowA[:, cols].cpu().numpy()
+        del lowA
+        assert np.array_equal(got.view(np.uint32), lp.to_f32(Ac).view(np.uint32))
+    else:
+        hi, lo = gpu_ctx.convert_matrix(A, "bf16x2")
+        ghi, glo = hi[:, cols].cpu().numpy(), lo[:, cols].cpu().numpy()
+        del hi, lo
+        whi, wlo = lp.to_bf16x2(Ac)
+        assert np.array_equal(ghi.view(np.uint16), lp.bf16_bits(whi))
+        assert np.array_equal(glo.view(np.uint16), lp.bf16_bits(wlo))
+    torch.cuda.empty_cache()
+    X, info = gpu_ctx.solve(A, b, X0, 1e-10, 100000, prec=prec)
+    assert info["status"] == 0, info
+    T = b[:, None] - A @ X
+    rel = (torch.linalg.norm(T, dim=0) / torch.linalg.norm(b)).cpu().numpy()
+    j = info["best_agent"]
+    assert rel[j] <= 1e-10 and abs(info["rel_res"] - rel[j]) <= 1e-3 * rel[j] + 1e-14
+    xj = X[:, j].cpu().numpy()
+    rows = np.sort(rng.choice(n, 8, replace=False))
+    Ar = A[rows, :].cpu().numpy()
+    t_host = b.cpu().numpy()[rows] - Ar @ xj
+    scale = np.abs(b.cpu().numpy()[rows]) + np.abs(Ar) @ np.abs(xj)
+    assert np.all(np.abs(t_host - T[rows, j].cpu().numpy()) <= 2.0 * n * 1.11e-16 * scale)

@@ -310,3 +310,26 @@ def test_inputs_are_not_modified(gpu_ctx):
         assert torch.equal(At, A0) and torch.equal(bt, b0) and torch.equal(Xt, X00)
         g = gpu_ctx.debug_step(At, bt, Xt, 2)
         assert torch.equal(Xt, X00)
+
+
+@pytest.mark.parametrize("pad", [2, 3, 64])
+@pytest.mark.parametrize("n,p,prec,flags", [(1100, 5, "fp64", 0), (1100, 5, "fp64", "sym"), (700, 4, "fp32", 0),
+                                          (700, 4, "bf16x2", 0)])
+def test_leading_dimension_larger_than_n(gpu_ctx, n, p, prec, flags, pad):
+    """A passed as the n x n corner of a larger array (lda = n + pad): an even pad keeps
+    its columns 16-byte aligned and is streamed in place, an odd pad makes the library
+    copy it to an aligned buffer first.  Either way the result equals that of the
+    contiguous matrix, bit for bit."""
+    from paper_1204_0069_amd import CCG_SYM_AD
+    fl = CCG_SYM_AD if flags == "sym" else 0
+    print(f"case lda n={n} pad={pad} p={p} {prec} flags={flags}", flush=True)
+    A, b, X0 = ci.system(n, p, 1e3, seed=3100 + n + pad)
+    big = torch.zeros(n + pad, n + pad, dtype=torch.float64, device=DEV)
+    big[:n, :n] = _t(A)
+    view = big[:n, :n]
+    assert view.stride(0) == n + pad
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, prec=prec, flags=fl)
+    X2, i2 = gpu_ctx.solve(view, _t(b), _t(X0), 1e-10, 20000, prec=prec, flags=fl)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert i1["iters"] == i2["iters"] and torch.equal(X1, X2)
+    assert torch.equal(big[:n, :n], _t(A)) and not big[n:, :].any() and not big[:, n:].any()
