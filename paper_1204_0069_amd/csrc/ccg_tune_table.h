@@ -22,17 +22,17 @@ static const TuneRow kTuneTable[] = {
     {PREC_F64, 1, 12288, 4, 4},
     {PREC_F64, 1, 1073741824, 2, 4},
     {PREC_F64, 2, 384, 2, 4},
-    {PREC_F64, 2, 768, 2, 8},
-    {PREC_F64, 2, 1536, 4, 8},
-    {PREC_F64, 2, 6144, 1, 8},
+    {PREC_F64, 2, 768, 4, 4},
+    {PREC_F64, 2, 3072, 2, 4},
+    {PREC_F64, 2, 6144, 4, 4},
     {PREC_F64, 2, 12288, 2, 4},
     {PREC_F64, 2, 1073741824, 1, 4},
     {PREC_F64, 4, 384, 2, 4},
-    {PREC_F64, 4, 768, 2, 8},
+    {PREC_F64, 4, 768, 4, 4},
     {PREC_F64, 4, 3072, 2, 4},
     {PREC_F64, 4, 6144, 4, 4},
     {PREC_F64, 4, 12288, 2, 4},
-    {PREC_F64, 4, 1073741824, 4, 16},
+    {PREC_F64, 4, 1073741824, 4, 4},
     {PREC_F64, 8, 384, 2, 4},
     {PREC_F64, 8, 768, 2, 8},
     {PREC_F64, 8, 3072, 2, 4},
@@ -40,25 +40,20 @@ static const TuneRow kTuneTable[] = {
     {PREC_F64, 16, 1073741824, 2, 4},
     {PREC_F32, 1, 192, 1, 4},
     {PREC_F32, 1, 384, 2, 4},
-    {PREC_F32, 1, 768, 4, 4},
-    {PREC_F32, 1, 1536, 4, 8},
+    {PREC_F32, 1, 1536, 4, 4},
     {PREC_F32, 1, 3072, 2, 4},
-    {PREC_F32, 1, 6144, 2, 8},
     {PREC_F32, 1, 12288, 4, 4},
     {PREC_F32, 1, 1073741824, 2, 4},
     {PREC_F32, 2, 192, 1, 4},
     {PREC_F32, 2, 384, 2, 4},
     {PREC_F32, 2, 768, 4, 4},
-    {PREC_F32, 2, 1536, 4, 8},
     {PREC_F32, 2, 3072, 2, 4},
     {PREC_F32, 2, 1073741824, 4, 4},
     {PREC_F32, 4, 192, 1, 4},
     {PREC_F32, 4, 384, 2, 4},
-    {PREC_F32, 4, 768, 2, 8},
-    {PREC_F32, 4, 1536, 4, 8},
-    {PREC_F32, 4, 3072, 2, 4},
-    {PREC_F32, 4, 12288, 2, 8},
-    {PREC_F32, 4, 1073741824, 4, 16},
+    {PREC_F32, 4, 768, 4, 4},
+    {PREC_F32, 4, 6144, 2, 4},
+    {PREC_F32, 4, 1073741824, 4, 4},
     {PREC_F32, 8, 192, 1, 4},
     {PREC_F32, 8, 384, 1, 8},
     {PREC_F32, 8, 768, 2, 8},
@@ -70,18 +65,15 @@ static const TuneRow kTuneTable[] = {
     {PREC_BF16X2, 1, 384, 2, 4},
     {PREC_BF16X2, 1, 768, 4, 4},
     {PREC_BF16X2, 1, 12288, 2, 4},
-    {PREC_BF16X2, 1, 1073741824, 4, 16},
+    {PREC_BF16X2, 1, 1073741824, 4, 4},
     {PREC_BF16X2, 2, 192, 1, 4},
     {PREC_BF16X2, 2, 384, 2, 4},
     {PREC_BF16X2, 2, 768, 4, 4},
     {PREC_BF16X2, 2, 12288, 2, 4},
-    {PREC_BF16X2, 2, 1073741824, 4, 8},
-    {PREC_BF16X2, 4, 384, 1, 8},
-    {PREC_BF16X2, 4, 768, 2, 8},
-    {PREC_BF16X2, 4, 3072, 2, 4},
-    {PREC_BF16X2, 4, 6144, 2, 8},
-    {PREC_BF16X2, 4, 12288, 2, 16},
-    {PREC_BF16X2, 4, 1073741824, 4, 8},
+    {PREC_BF16X2, 2, 1073741824, 4, 4},
+    {PREC_BF16X2, 4, 192, 1, 4},
+    {PREC_BF16X2, 4, 12288, 2, 4},
+    {PREC_BF16X2, 4, 1073741824, 4, 4},
     {PREC_BF16X2, 8, 384, 1, 8},
     {PREC_BF16X2, 8, 768, 1, 4},
     {PREC_BF16X2, 8, 6144, 2, 4},

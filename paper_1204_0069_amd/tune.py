@@ -38,13 +38,20 @@ def fits4(prec: str, P: int) -> bool:
     return P < 16 and (prec != "fp64" or P <= 4)
 
 
+# Padded agent counts whose shapes may use more than 4 waves per workgroup.  At P <= 4
+# the wider shapes won in the one-system timings but lost in the engine, which runs
+# several systems of a class in one launch: the served stream (p = 4) fell from 18.0
+# to 16.6 requests/s with them, on one box.
+WIDE_P = (8,)
+
+
 def shapes(prec: str, P: int):
     """Candidate (columns per wave, waves per workgroup), as the library runs them
-    (ad_cw_fit, ad_nw_fit): 4 columns where they fit, more than 4 waves below P = 16."""
+    (ad_cw_fit, ad_nw_fit): 4 columns where they fit, more than 4 waves at WIDE_P."""
     ws = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
     if P >= 16:
         ws = [w for w in ws if w <= 2]
-    nws = (4,) if P >= 16 else WAVES
+    nws = WAVES if P in WIDE_P else (4,)
     return [(w, nw) for nw in nws for w in ws]
 
 
@@ -111,6 +118,8 @@ def rows_from_log(path: str):
         # batched time), or "cw2: 91.3us" from logs of 4-wave workgroups only
         t = {(int(c), int(w)): float(v) for c, w, v in re.findall(r"c(\d)w(\d+):\s*([\d.]+)us", m.group(4))}
         t.update({(int(c), 4): float(v) for c, v in re.findall(r"cw(\d):\s*([\d.]+)us", m.group(4))})
+        allowed = set(shapes(prec, P))
+        t = {k: v for k, v in t.items() if k in allowed}
         best_by_class.setdefault((names[prec], P), []).append((n, choose(t)))
     return rows_from(best_by_class)
 
