@@ -282,12 +282,14 @@ bool run_steps(Solve& s, int steps, bool use_graph) {
         for (int i = 0; i < steps; ++i) enqueue_step(s, (size_t)i, timed);
         return timed;
     }
-    const int64_t key[6] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
-                            s.lda};
-    if (!std::equal(key, key + 6, c->graph_key)) {
+    // everything a captured step depends on: sizes, precision, workspace, matrix and
+    // which A.D pass the steps launch
+    const int64_t key[7] = {s.n, s.P, s.prec, (int64_t)(intptr_t)c->ws.base, (int64_t)(intptr_t)s.A,
+                            s.lda, use_sym(s) ? 1 : 0};
+    if (!std::equal(key, key + 7, c->graph_key)) {
         for (auto& g : c->graphs) HIP_OK(hipGraphExecDestroy(g.second));
         c->graphs.clear();
-        std::copy(key, key + 6, c->graph_key);
+        std::copy(key, key + 7, c->graph_key);
     }
     hipGraphExec_t ex = nullptr;
     for (auto& g : c->graphs)

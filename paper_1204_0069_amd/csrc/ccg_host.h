@@ -158,7 +158,7 @@ struct ccg_ctx {
     std::vector<hipEvent_t> ev_pool;
     // captured block-step graphs, one per round length, all for graph_key
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
-    int64_t graph_key[6] = {0, 0, 0, 0, 0, 0};
+    int64_t graph_key[7] = {0, 0, 0, 0, 0, 0, 0};
     // aligned copy of a caller matrix with unaligned columns
     void* acopy = nullptr;
     size_t acopy_bytes = 0;

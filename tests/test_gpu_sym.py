@@ -60,6 +60,22 @@ def test_symmetric_and_whole_matrix_solves_agree(gpu_ctx):
     assert abs(i_s["bytes_A"] - (steps * sym_step + (1 + 1 + i_s["restarts"]) * 8 * n * n)) <= 1.0
 
 
+def test_pass_choice_is_part_of_the_captured_graph(gpu_ctx):
+    """Solves of the same system with and without CCG_SYM_AD in one context each replay
+    their own graphs: each gives the result of a fresh context with the same flags."""
+    A, b, X0 = ci.system(1300, 4, 1e3, seed=2701)
+    runs = [gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, flags=f) for f in (CCG_SYM_AD, 0, CCG_SYM_AD, 0)]
+    for f, (X, info) in zip((CCG_SYM_AD, 0), runs[:2]):
+        fresh = Context(0)
+        try:
+            Xf, i_f = fresh.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, flags=f)
+        finally:
+            fresh.close()
+        assert info["iters"] == i_f["iters"] and torch.equal(X, Xf)
+    assert torch.equal(runs[0][0], runs[2][0]) and torch.equal(runs[1][0], runs[3][0])
+    assert not torch.equal(runs[0][0], runs[1][0])
+
+
 def test_symmetric_profile_reports_triangle_bytes(gpu_ctx):
     n, p = 1500, 8
     A, b, X0 = ci.system(n, p, 1e3, seed=2401)
