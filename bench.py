@@ -128,7 +128,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no "
-                                   "multi-GPU path (see DESIGN.md for how it would shard)",
+                                   "multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -166,7 +166,7 @@ def main():
         ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
     ctx.kernel_time(reset=True)
 
-    # Timed region: the A.D launches of every 4th round of 16 block steps bracketed by
+    # Timed region: the A.D launches of every 4th round of block steps bracketed by
     # HIP events on the library's stream (launched directly); the other rounds replay
     # the captured graph (CCG_PROFILE_SAMPLED; --profile-all times every launch).
     lat = []
