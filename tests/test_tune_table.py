@@ -39,6 +39,10 @@ def test_candidate_shapes_follow_the_register_rules():
     assert (4, 16) in tune.shapes("fp32", 8) and (4, 4) not in tune.shapes("fp64", 8)
     assert all(nw == 4 and w <= 2 for w, nw in tune.shapes("fp64", 16))
     assert tune.DEFAULT in tune.shapes("bf16x2", 1)
+    # wider workgroups only where the engine was measured not to lose with them
+    for prec in ("fp64", "fp32", "bf16x2"):
+        for P in (1, 2, 4, 8, 16):
+            assert any(nw > 4 for _, nw in tune.shapes(prec, P)) == (P in tune.WIDE_P)
 
 
 def test_merge_and_limits():
@@ -47,6 +51,8 @@ def test_merge_and_limits():
     # FP32, P = 8: width 1 up to 512, 2 for 1024..4096, then from 8192 on width 4 with
     # 8 waves: 16 waves are faster in the single-system kernel but slow batched
     assert _rows_for(rows, "PREC_F32", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 8)]
+    # P = 4 keeps 4 waves per workgroup
+    assert all(nw == 4 for _, _, nw in _rows_for(rows, "PREC_F32", 4))
     # FP64, P = 8 may not use 4 columns per wave: 2 from 1024 on
     assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 2, 16)]
     # P = 16 never times width 4 or more than 4 waves; no size below P is timed
