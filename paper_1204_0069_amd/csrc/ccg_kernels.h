@@ -802,7 +802,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
 
     const int nch = (n + KC - 1) / KC;     // chunks end at <= n_pad: KC divides 512
     // first chunk of this workgroup (rotated when staggering); chunks then wrap
-    const int c0 = CFG::STG ? (int)(((unsigned)tile * 7u) % (unsigned)nch) : 0;
+    const int c0 = CFG::STG ? (int)(((unsigned)tile * 13u) % (unsigned)nch) : 0;
     TV pre[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {

@@ -5,7 +5,7 @@
 // threads, with 16-byte non-temporal loads, and adds it up.  With an n x dcols block D it also
 // reads the whole of D in every workgroup, spread over its chunk, as the A.D tile
 // kernel does with the direction block.  With `stagger`, workgroup b starts its
-// chunk at step (7 b) mod steps and wraps around, as the A.D kernel staggers its
+// chunk at step (13 b) mod steps and wraps around, as the A.D kernel staggers its
 // tiles.  It does no other work, so its time is the floor that the memory system
 // sets for that pattern of traffic.
 #include <hip/hip_runtime.h>
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(WG) void k_stream(const dvec2* __restrict__ a, int6
     const int64_t steps = (chunk + WG * U - 1) / (WG * U);
     const int64_t dstep = d ? (dlen + steps - 1) / steps : 0;
     double s = 0.0;
-    const int64_t k0 = stagger ? (7 * (int64_t)blockIdx.x) % steps : 0;
+    const int64_t k0 = stagger ? (13 * (int64_t)blockIdx.x) % steps : 0;
     for (int64_t kk = 0; kk < steps; ++kk) {
         const int64_t k = (k0 + kk) % steps;
         const int64_t i = threadIdx.x + k * WG * U;
