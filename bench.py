@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--seed", type=int, default=None,
+                    help="base seed of the single-system inputs (default: the fixed base seed)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x2"])
     ap.add_argument("--cpu-sample-steps", type=int, default=12,
@@ -151,12 +153,13 @@ def main():
 
     dev = "cuda:0"
     n, p = args.n, args.p
+    seed = ci.BASE_SEED if args.seed is None else args.seed
     if args.kind == "gram":
-        A = ci.spd_gram(n, args.kappa, ci.item_seed("G", ci.BASE_SEED, base=n), device=dev)
+        A = ci.spd_gram(n, args.kappa, ci.item_seed("G", seed, base=n), device=dev)
     else:
-        A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", ci.BASE_SEED, base=n), device=dev)
-    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", ci.BASE_SEED, base=n)), device=dev)
-    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", ci.BASE_SEED, base=n)), device=dev)
+        A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", seed, base=n), device=dev)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", seed, base=n)), device=dev)
+    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", seed, base=n)), device=dev)
     torch.cuda.synchronize()
 
     ctx = Context(0)
@@ -248,7 +251,7 @@ def main():
         "config": {"workload": f"dense SPD n={n}, kappa={args.kappa:g} "
                                f"({'log-uniform spectrum' if args.kind == 'spectrum' else 'M^T M/n + sigma I'}), "
                                f"p={p} agents, {args.prec.upper()} A, tol {args.tol:g}",
-                   "n": n, "p": p, "kappa": args.kappa, "tol": args.tol, "prec": args.prec,
+                   "n": n, "p": p, "kappa": args.kappa, "tol": args.tol, "prec": args.prec, "seed": seed,
                    "kind": args.kind},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3)},
