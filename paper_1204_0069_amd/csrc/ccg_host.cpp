@@ -1,6 +1,6 @@
-// Host driver and C interface (include/ccg.h) of the cooperative CG library.
+// Host side and C interface (include/ccg.h) of the cooperative CG library.
 //
-// The driver owns one workspace per context, sized for the largest solve so far.
+// The host side owns one workspace per context, sized for the largest solve so far.
 // A solve is: pack X0 into the row-major agent block, form R0 = B - A X0 (an A
 // stream plus the residual epilogue), then repeat groups of block steps
 // (k_ad, k_upd, k_dir) -- captured once into a HIP graph and replayed -- polling
