@@ -15,6 +15,7 @@ from scipy.sparse.linalg import cg as scipy_cg
 
 import ccg_inputs as ci
 import oracle
+from restart_util import first_restart_step
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "ccg_oracle.c")
 
@@ -32,6 +33,11 @@ MUTANTS = {
     "matmat_wrong_column": ("double mkj = M[k + (size_t)j * ldm];", "double mkj = M[k];"),
     "chol_solve_skips_back_substitution": ("for (int i = m - 1; i >= 0; --i) {     /* L^T z = y */",
                                            "for (int i = m - 1; i >= m; --i) {     /* L^T z = y */"),
+    # the restart branch of the stop rule (explicit residual fails the confirmation)
+    "restart_keeps_D": ("memcpy(D, T, (size_t)n * m * sizeof(double));\n                inf.restarts++;",
+                        "inf.restarts++;"),
+    "restart_keeps_R": ("memcpy(R, T, (size_t)n * m * sizeof(double));", ";"),
+    "restart_not_counted": ("inf.restarts++;", ";"),
 }
 
 
@@ -76,6 +82,18 @@ def _battery(lib):
     xs = np.linalg.solve(A, b)
     if not np.all(np.isfinite(r["X"])) or np.abs(r["X"] - xs[:, None]).max() > 1e-10 * np.abs(xs).max():
         failed.append("finite_termination")
+    # restart = fresh start from the agents at the restart step (Alg. 2 init, Alg. 4)
+    A, b, X0 = ci.system(60, 3, 1e5, seed=0)
+    full = oracle.ccg(A, b, X0, tol=1e-10, maxit=5000, lib=lib)
+    kr = first_restart_step(A, b, X0, 1e-10, max(full["iters"], 1), lib=lib)
+    ok = full["status"] == 0 and kr is not None
+    if ok:
+        at = oracle.ccg(A, b, X0, tol=0.0, maxit=kr, lib=lib)
+        fresh = oracle.ccg(A, b, at["X"], tol=1e-10, maxit=5000, lib=lib)
+        ok = (fresh["restarts"] == full["restarts"] - 1 and fresh["iters"] == full["iters"] - kr
+              and np.array_equal(fresh["X"], full["X"]))
+    if not ok:
+        failed.append("restart")
     return failed
 
 

@@ -24,6 +24,7 @@ from scipy.sparse.linalg import cg as scipy_cg
 import ccg_inputs as ci
 import oracle
 from oracle import exact
+from restart_util import first_restart_step
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -171,6 +172,38 @@ def test_duplicate_start_columns_deflate_at_step_zero():
     assert r["deflations"] >= 1 and r["p_final"] == 2
     T = b[:, None] - A @ r["X"]
     assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() <= 1e-10
+
+
+# ------------------------------- stop rule of Alg. 4: confirmation and restart
+
+RESTART_CASES = [(60, 3, 1e5, 0), (60, 2, 1e6, 3), (300, 3, 1e6, 7)]
+
+
+@pytest.mark.parametrize("n,p,kappa,seed", RESTART_CASES)
+def test_restart_continues_as_a_fresh_start(n, p, kappa, seed):
+    """When the recurrence residual passes the stop test but the explicit residual
+    B - A X does not, the run restarts.  Alg. 2's first lines define what a start
+    from X is (R = B - A X, D = R), so the rest of the run must equal, bit for bit,
+    a fresh run started from the agents at the restart step, and the count of
+    restarts must be that fresh run's count plus one."""
+    A, b, X0 = ci.system(n, p, kappa, seed=seed)
+    tol = 1e-10
+    full = oracle.ccg(A, b, X0, tol=tol, maxit=50000)
+    assert full["status"] == 0 and full["restarts"] >= 1 and full["deflations"] == 0
+    kr = first_restart_step(A, b, X0, tol, full["iters"])
+    assert kr is not None and 0 < kr < full["iters"]
+    at = oracle.ccg(A, b, X0, tol=0.0, maxit=kr, want_rd=True)
+    nb = np.linalg.norm(b)
+    # at step kr the recurrence residual passes the test (numpy norms) ...
+    assert (np.linalg.norm(at["R"], axis=0) / nb).min() <= tol
+    # ... while the explicit residual, formed by numpy, fails it
+    T = b[:, None] - A @ at["X"]
+    assert (np.linalg.norm(T, axis=0) / nb).min() > tol
+    fresh = oracle.ccg(A, b, at["X"], tol=tol, maxit=50000)
+    assert fresh["status"] == 0
+    assert fresh["restarts"] == full["restarts"] - 1
+    assert fresh["iters"] == full["iters"] - kr
+    assert np.array_equal(fresh["X"], full["X"])
 
 
 # ------------------------------------------------------------- error handling
