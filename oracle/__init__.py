@@ -4,8 +4,13 @@ TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package; the library under
 ``paper_1204_0069_amd`` never does, and the two share no code.
 
-The arithmetic lives in ``ccg_oracle.c`` (plain loops, FP64, column-major).  This
-module only builds it with gcc, loads it with ctypes and marshals numpy arrays.
+The arithmetic lives in ``ccg_oracle.c`` (plain loops, column-major).  This module
+only builds it with gcc, loads it with ctypes and marshals numpy arrays.  The source
+is built twice: ``libccg_oracle.so`` computes in FP64 (double), the oracle proper;
+``libccg_oracle_ld.so`` runs the same code with every internal value in x86 80-bit
+extended precision (``long double``, 11 more significand bits), as a reference for
+how far an FP64 trajectory of the method has drifted from the method's own
+trajectory (``extended()``).  Both take and return FP64 arrays.
 
 Entry points
 ------------
@@ -29,6 +34,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ccg_oracle.c")
 _LIB = os.path.join(_HERE, "libccg_oracle.so")
+_LIB_LD = os.path.join(_HERE, "libccg_oracle_ld.so")
 
 # gcc flags: baseline x86-64 (the library built here also runs on other hosts),
 # no FMA contraction so every product and sum rounds as written.
@@ -45,16 +51,23 @@ class _Info(ctypes.Structure):
                 ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double)]
 
 
+def _build_one(path: str, extra, force: bool) -> None:
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.run(["gcc", *GCC_FLAGS, *extra, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile ccg_oracle.c into libccg_oracle.so next to it (gcc)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
+    """Compile ccg_oracle.c into libccg_oracle.so (FP64) and libccg_oracle_ld.so
+    (80-bit extended) next to it (gcc)."""
+    _build_one(_LIB, [], force)
+    _build_one(_LIB_LD, ["-DORC_REAL=long double"], force)
     return _LIB
 
 
 _lib = None
+_lib_ld = None
 
 
 def bind(path: str):
@@ -79,6 +92,16 @@ def _load():
             build(force=True)
         _lib = bind(_LIB)
     return _lib
+
+
+def extended():
+    """The oracle built with 80-bit extended internal arithmetic (pass as ``lib``)."""
+    global _lib_ld
+    if _lib_ld is None:
+        if not os.path.exists(_LIB_LD) or os.path.getmtime(_LIB_LD) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib_ld = bind(_LIB_LD)
+    return _lib_ld
 
 
 def _ptr(a):

@@ -1,5 +1,5 @@
 /*
- * Reference (oracle) implementation of cooperative conjugate gradient, plain FP64 C.
+ * Reference (oracle) implementation of cooperative conjugate gradient, plain C.
  *
  * THIS IS TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg may load it.  It shares no code with the HIP path
@@ -41,12 +41,23 @@
  *   - Dropped agents keep their last iterate in X.
  *
  * Storage: every matrix is column-major.  A is n x n with leading dimension lda;
- * X is n x p with leading dimension ldx.  Internal R, D, AD are n x p with leading
- * dimension n, column j = agent j.
+ * X is n x p with leading dimension ldx.  Internal X, R, D, AD are n x p with
+ * leading dimension n, column j = agent j.
+ *
+ * Precision: every internal value has the type `real`, FP64 (double) by default.
+ * Built with -DORC_REAL='long double' (x86 80-bit extended, 64-bit significand)
+ * the same code runs the same algorithm with 11 more bits in every operation; the
+ * interface stays FP64 (inputs are exact in either type, outputs are rounded to
+ * double once at the end).
  */
-#include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
+
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -72,14 +83,14 @@ typedef struct {
 
 /* Y = A * M for A n x n (lda) and M n x m (ldm), one agent column at a time:
  * Y[:,j] = sum_k A[:,k] M[k,j]   (Table 1: each agent forms A d_j). */
-static void matmat(int n, int m, const double *A, int lda, const double *M, int ldm,
-                   double *Y, int ldy)
+static void matmat(int n, int m, const double *A, int lda, const real *M, int ldm,
+                   real *Y, int ldy)
 {
     for (int j = 0; j < m; ++j) {
-        double *y = Y + (size_t)j * ldy;
+        real *y = Y + (size_t)j * ldy;
         for (int i = 0; i < n; ++i) y[i] = 0.0;
         for (int k = 0; k < n; ++k) {
-            double mkj = M[k + (size_t)j * ldm];
+            real mkj = M[k + (size_t)j * ldm];
             const double *a = A + (size_t)k * lda;
             for (int i = 0; i < n; ++i) y[i] += a[i] * mkj;
         }
@@ -88,11 +99,11 @@ static void matmat(int n, int m, const double *A, int lda, const double *M, int 
 
 /* C = U^T V for U, V n x m (leading dimension n): C[i,j] = sum_r U[r,i] V[r,j].
  * C is m x m, column-major with leading dimension m. */
-static void gram(int n, int m, const double *U, const double *V, double *C)
+static void gram(int n, int m, const real *U, const real *V, real *C)
 {
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
-            double s = 0.0;
+            real s = 0.0;
             for (int r = 0; r < n; ++r) s += U[r + (size_t)i * n] * V[r + (size_t)j * n];
             C[i + j * m] = s;
         }
@@ -100,18 +111,18 @@ static void gram(int n, int m, const double *U, const double *V, double *C)
 
 /* Cholesky G = L L^T (m x m, column-major, lower triangle of L written, upper zero).
  * Returns 0 on success, -1 if a pivot is not positive. */
-static int cholesky(int m, const double *G, double *L)
+static int cholesky(int m, const real *G, real *L)
 {
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) L[i + j * m] = 0.0;
     for (int j = 0; j < m; ++j) {
-        double d = G[j + j * m];
+        real d = G[j + j * m];
         for (int k = 0; k < j; ++k) d -= L[j + k * m] * L[j + k * m];
         if (!(d > 0.0)) return -1;
-        double ljj = sqrt(d);
+        real ljj = sqrt(d);
         L[j + j * m] = ljj;
         for (int i = j + 1; i < m; ++i) {
-            double s = G[i + j * m];
+            real s = G[i + j * m];
             for (int k = 0; k < j; ++k) s -= L[i + k * m] * L[j + k * m];
             L[i + j * m] = s / ljj;
         }
@@ -120,18 +131,18 @@ static int cholesky(int m, const double *G, double *L)
 }
 
 /* Solve (L L^T) Z = B for Z (m x q, column-major, leading dimension m). */
-static void chol_solve(int m, const double *L, int q, const double *B, double *Z)
+static void chol_solve(int m, const real *L, int q, const real *B, real *Z)
 {
     for (int c = 0; c < q; ++c) {
-        const double *bc = B + (size_t)c * m;
-        double *z = Z + (size_t)c * m;
+        const real *bc = B + (size_t)c * m;
+        real *z = Z + (size_t)c * m;
         for (int i = 0; i < m; ++i) {          /* L y = b */
-            double s = bc[i];
+            real s = bc[i];
             for (int k = 0; k < i; ++k) s -= L[i + k * m] * z[k];
             z[i] = s / L[i + i * m];
         }
         for (int i = m - 1; i >= 0; --i) {     /* L^T z = y */
-            double s = z[i];
+            real s = z[i];
             for (int k = i + 1; k < m; ++k) s -= L[k + i * m] * z[k];
             z[i] = s / L[i + i * m];
         }
@@ -143,21 +154,21 @@ static void chol_solve(int m, const double *L, int q, const double *B, double *Z
  * returns their count.  Returns -1 if a diagonal entry is negative (A not SPD),
  * -2 if a non-finite value is met.  Columns with G_ii == 0 (a zero direction) are
  * never chosen. */
-static int rank_select(int m, const double *G, double tau, int *keep)
+static int rank_select(int m, const real *G, double tau, int *keep)
 {
-    double H[ORC_MAXP * ORC_MAXP];
-    double s[ORC_MAXP];
+    real H[ORC_MAXP * ORC_MAXP];
+    real s[ORC_MAXP];
     int cand[ORC_MAXP], taken[ORC_MAXP];
     int ncand = 0, ntaken = 0;
     for (int i = 0; i < m; ++i) {
-        double g = G[i + i * m];
+        real g = G[i + i * m];
         if (!isfinite(g)) return -2;
         if (g < 0.0) return -1;
         s[i] = sqrt(g);
     }
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
-            double g = G[i + j * m];
+            real g = G[i + j * m];
             if (!isfinite(g)) return -2;
             H[i + j * m] = (s[i] > 0.0 && s[j] > 0.0) ? g / (s[i] * s[j]) : 0.0;
         }
@@ -168,14 +179,14 @@ static int rank_select(int m, const double *G, double tau, int *keep)
         for (int c = 1; c < ncand; ++c)
             if (H[cand[c] + cand[c] * m] > H[cand[best] + cand[best] * m]) best = c;
         int piv = cand[best];
-        double d = H[piv + piv * m];
+        real d = H[piv + piv * m];
         if (!(d > tau)) break;
         taken[ntaken++] = piv;
         for (int c = best; c + 1 < ncand; ++c) cand[c] = cand[c + 1];
         --ncand;
         /* Schur complement update of the remaining candidates. */
-        double r = sqrt(d);
-        double l[ORC_MAXP];
+        real r = sqrt(d);
+        real l[ORC_MAXP];
         for (int c = 0; c < ncand; ++c) l[c] = H[cand[c] + piv * m] / r;
         for (int a = 0; a < ncand; ++a)
             for (int c = 0; c < ncand; ++c)
@@ -189,24 +200,24 @@ static int rank_select(int m, const double *G, double tau, int *keep)
     return ntaken;
 }
 
-static double norm2(int n, const double *v)
+static real norm2(int n, const real *v)
 {
-    double s = 0.0;
+    real s = 0.0;
     for (int i = 0; i < n; ++i) s += v[i] * v[i];
     return sqrt(s);
 }
 
 /* T = B - A X for the columns listed in cols[0..m) of X (ldx); T is n x m. */
 static void explicit_residual(int n, const double *A, int lda, const double *b,
-                              const double *X, int ldx, int m, const int *cols, double *T)
+                              const real *X, int ldx, int m, const int *cols, real *T)
 {
     for (int c = 0; c < m; ++c) {
-        double *t = T + (size_t)c * n;
-        const double *x = X + (size_t)cols[c] * ldx;
+        real *t = T + (size_t)c * n;
+        const real *x = X + (size_t)cols[c] * ldx;
         for (int i = 0; i < n; ++i) t[i] = 0.0;
         for (int k = 0; k < n; ++k) {
             const double *a = A + (size_t)k * lda;
-            double xk = x[k];
+            real xk = x[k];
             for (int i = 0; i < n; ++i) t[i] += a[i] * xk;
         }
         for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
@@ -221,7 +232,15 @@ int oracle_residual(int n, int p, const double *A, int lda, const double *b,
     int cols[ORC_MAXP];
     if (p > ORC_MAXP) return ORC_ERR_ARG;
     for (int j = 0; j < p; ++j) cols[j] = j;
-    explicit_residual(n, A, lda, b, X, ldx, p, cols, T);
+    size_t np = (size_t)n * p;
+    real *Xr = calloc(np, sizeof(real));
+    real *Tr = calloc(np, sizeof(real));
+    if (!Xr || !Tr) { free(Xr); free(Tr); return ORC_ERR_NOMEM; }
+    for (int j = 0; j < p; ++j)
+        for (int i = 0; i < n; ++i) Xr[i + (size_t)j * n] = X[i + (size_t)j * ldx];
+    explicit_residual(n, A, lda, b, Xr, n, p, cols, Tr);
+    for (size_t i = 0; i < np; ++i) T[i] = (double)Tr[i];
+    free(Xr); free(Tr);
     return ORC_OK;
 }
 
@@ -253,13 +272,14 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
         return ORC_ERR_ARG;
     }
     size_t np = (size_t)n * p;
-    double *R = calloc(np, sizeof(double));
-    double *D = calloc(np, sizeof(double));
-    double *AD = calloc(np, sizeof(double));
-    double *T = calloc(np, sizeof(double));
-    double *Xa = calloc(np, sizeof(double));
-    if (!R || !D || !AD || !T || !Xa) {
-        free(R); free(D); free(AD); free(T); free(Xa);
+    real *R = calloc(np, sizeof(real));
+    real *D = calloc(np, sizeof(real));
+    real *AD = calloc(np, sizeof(real));
+    real *T = calloc(np, sizeof(real));
+    real *Xa = calloc(np, sizeof(real));
+    real *Xr = calloc(np, sizeof(real));   /* the agents, leading dimension n */
+    if (!R || !D || !AD || !T || !Xa || !Xr) {
+        free(R); free(D); free(AD); free(T); free(Xa); free(Xr);
         inf.status = ORC_ERR_NOMEM;
         if (info) *info = inf;
         return ORC_ERR_NOMEM;
@@ -267,19 +287,23 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
     int act[ORC_MAXP];   /* active agents (original indices), ascending */
     int m = p;
     for (int j = 0; j < p; ++j) act[j] = j;
-    double G[ORC_MAXP * ORC_MAXP], S[ORC_MAXP * ORC_MAXP], L[ORC_MAXP * ORC_MAXP];
-    double alpha[ORC_MAXP * ORC_MAXP], beta[ORC_MAXP * ORC_MAXP], W[ORC_MAXP * ORC_MAXP];
+    real G[ORC_MAXP * ORC_MAXP], S[ORC_MAXP * ORC_MAXP], L[ORC_MAXP * ORC_MAXP];
+    real alpha[ORC_MAXP * ORC_MAXP], beta[ORC_MAXP * ORC_MAXP], W[ORC_MAXP * ORC_MAXP];
     int status = ORC_NOT_CONVERGED;
     int k = 0;
+    for (int j = 0; j < p; ++j)
+        for (int i = 0; i < n; ++i) Xr[i + (size_t)j * n] = X[i + (size_t)j * ldx];
 
-    const double nb = norm2(n, b);
+    real nb = 0.0;
+    for (int i = 0; i < n; ++i) nb += (real)b[i] * b[i];
+    nb = sqrt(nb);
     if (!isfinite(nb)) { status = ORC_ERR_NONFINITE; goto done; }
     if (nb == 0.0) { status = ORC_ERR_ARG; goto done; }
 
     /* Alg. 2, first lines: R0 = B - A X0, D0 = R0.  Columns of R, D, AD, Xa are
      * stored compactly for the active agents: column c <-> agent act[c]. */
-    explicit_residual(n, A, lda, b, X, ldx, m, act, R);
-    memcpy(D, R, np * sizeof(double));
+    explicit_residual(n, A, lda, b, Xr, n, m, act, R);
+    memcpy(D, R, np * sizeof(real));
     if (trace_k > 0) {
         memset(trace_alpha, 0, (size_t)trace_k * p * p * sizeof(double));
         memset(trace_beta, 0, (size_t)trace_k * p * p * sizeof(double));
@@ -289,24 +313,24 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
         if (m == 0) { status = ORC_OK; break; }
         /* Stop test on the recurrence residual (Alg. 4: minimum over agents). */
         if (tol > 0.0) {
-            double mn = INFINITY;
+            real mn = INFINITY;
             for (int c = 0; c < m; ++c) {
-                double r = norm2(n, R + (size_t)c * n) / nb;
+                real r = norm2(n, R + (size_t)c * n) / nb;
                 if (!isfinite(r)) { status = ORC_ERR_NONFINITE; goto done; }
                 if (r < mn) mn = r;
             }
             if (mn <= tol) {
                 /* confirm with the explicit residual */
-                explicit_residual(n, A, lda, b, X, ldx, m, act, T);
-                double tm = INFINITY;
+                explicit_residual(n, A, lda, b, Xr, n, m, act, T);
+                real tm = INFINITY;
                 for (int c = 0; c < m; ++c) {
-                    double r = norm2(n, T + (size_t)c * n) / nb;
+                    real r = norm2(n, T + (size_t)c * n) / nb;
                     if (r < tm) tm = r;
                 }
                 if (tm <= tol) { status = ORC_OK; break; }
                 /* restart: R = B - A X, D = R */
-                memcpy(R, T, (size_t)n * m * sizeof(double));
-                memcpy(D, T, (size_t)n * m * sizeof(double));
+                memcpy(R, T, (size_t)n * m * sizeof(real));
+                memcpy(D, T, (size_t)n * m * sizeof(real));
                 inf.restarts++;
             }
         }
@@ -325,20 +349,20 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
         if (r < m) {
             inf.deflations++;
             /* restrict columns and the p x p blocks to keep[] */
-            double G2[ORC_MAXP * ORC_MAXP], S2[ORC_MAXP * ORC_MAXP];
+            real G2[ORC_MAXP * ORC_MAXP], S2[ORC_MAXP * ORC_MAXP];
             for (int b2 = 0; b2 < r; ++b2)
                 for (int a2 = 0; a2 < r; ++a2) {
                     G2[a2 + b2 * r] = G[keep[a2] + keep[b2] * m];
                     S2[a2 + b2 * r] = S[keep[a2] + keep[b2] * m];
                 }
-            memcpy(G, G2, sizeof(double) * r * r);
-            memcpy(S, S2, sizeof(double) * r * r);
+            memcpy(G, G2, sizeof(real) * r * r);
+            memcpy(S, S2, sizeof(real) * r * r);
             for (int c = 0; c < r; ++c) {
                 int src = keep[c];
                 if (src != c) {
-                    memmove(R + (size_t)c * n, R + (size_t)src * n, (size_t)n * sizeof(double));
-                    memmove(D + (size_t)c * n, D + (size_t)src * n, (size_t)n * sizeof(double));
-                    memmove(AD + (size_t)c * n, AD + (size_t)src * n, (size_t)n * sizeof(double));
+                    memmove(R + (size_t)c * n, R + (size_t)src * n, (size_t)n * sizeof(real));
+                    memmove(D + (size_t)c * n, D + (size_t)src * n, (size_t)n * sizeof(real));
+                    memmove(AD + (size_t)c * n, AD + (size_t)src * n, (size_t)n * sizeof(real));
                 }
                 act[c] = act[src];
             }
@@ -352,12 +376,12 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
 
         /* X += D alpha ; R -= (A D) alpha   (Alg. 2 update of X; Table 1 for R) */
         for (int c = 0; c < m; ++c) {
-            double *x = X + (size_t)act[c] * ldx;
-            double *rr = R + (size_t)c * n;
+            real *x = Xr + (size_t)act[c] * n;
+            real *rr = R + (size_t)c * n;
             for (int l = 0; l < m; ++l) {
-                double a = alpha[l + c * m];
-                const double *d = D + (size_t)l * n;
-                const double *ad = AD + (size_t)l * n;
+                real a = alpha[l + c * m];
+                const real *d = D + (size_t)l * n;
+                const real *ad = AD + (size_t)l * n;
                 for (int i = 0; i < n; ++i) {
                     x[i] += d[i] * a;
                     rr[i] -= ad[i] * a;
@@ -375,23 +399,23 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
             double *tb = trace_beta + (size_t)k * p * p;
             for (int b2 = 0; b2 < m; ++b2)
                 for (int a2 = 0; a2 < m; ++a2) {
-                    ta[act[a2] + act[b2] * p] = alpha[a2 + b2 * m];
-                    tb[act[a2] + act[b2] * p] = beta[a2 + b2 * m];
+                    ta[act[a2] + act[b2] * p] = (double)alpha[a2 + b2 * m];
+                    tb[act[a2] + act[b2] * p] = (double)beta[a2 + b2 * m];
                 }
         }
 
         /* D = R + D beta   (Alg. 2 direction update); build into T, then copy. */
         for (int c = 0; c < m; ++c) {
-            double *t = T + (size_t)c * n;
-            const double *rr = R + (size_t)c * n;
+            real *t = T + (size_t)c * n;
+            const real *rr = R + (size_t)c * n;
             for (int i = 0; i < n; ++i) t[i] = rr[i];
             for (int l = 0; l < m; ++l) {
-                double bb = beta[l + c * m];
-                const double *d = D + (size_t)l * n;
+                real bb = beta[l + c * m];
+                const real *d = D + (size_t)l * n;
                 for (int i = 0; i < n; ++i) t[i] += d[i] * bb;
             }
         }
-        memcpy(D, T, (size_t)n * m * sizeof(double));
+        memcpy(D, T, (size_t)n * m * sizeof(real));
         ++k;
     }
 
@@ -402,27 +426,30 @@ done:
         /* explicit residual of every agent; best agent */
         int all[ORC_MAXP];
         for (int j = 0; j < p; ++j) all[j] = j;
-        explicit_residual(n, A, lda, b, X, ldx, p, all, Xa);
-        double mn = INFINITY, mx = 0.0;
+        explicit_residual(n, A, lda, b, Xr, n, p, all, Xa);
+        real mn = INFINITY, mx = 0.0;
         for (int j = 0; j < p; ++j) {
-            double r = norm2(n, Xa + (size_t)j * n) / nb;
+            real r = norm2(n, Xa + (size_t)j * n) / nb;
             if (r < mn) { mn = r; inf.best_agent = j; }
             if (r > mx) mx = r;
         }
-        inf.rel_res = mn;
-        inf.rel_res_max = mx;
+        inf.rel_res = (double)mn;
+        inf.rel_res_max = (double)mx;
     }
+    for (int j = 0; j < p; ++j)
+        for (int i = 0; i < n; ++i) X[i + (size_t)j * ldx] = (double)Xr[i + (size_t)j * n];
     if (R_out || D_out) {
         if (R_out) memset(R_out, 0, np * sizeof(double));
         if (D_out) memset(D_out, 0, np * sizeof(double));
-        for (int c = 0; c < m; ++c) {
-            if (R_out) memcpy(R_out + (size_t)act[c] * n, R + (size_t)c * n, (size_t)n * sizeof(double));
-            if (D_out) memcpy(D_out + (size_t)act[c] * n, D + (size_t)c * n, (size_t)n * sizeof(double));
-        }
+        for (int c = 0; c < m; ++c)
+            for (int i = 0; i < n; ++i) {
+                if (R_out) R_out[(size_t)act[c] * n + i] = (double)R[(size_t)c * n + i];
+                if (D_out) D_out[(size_t)act[c] * n + i] = (double)D[(size_t)c * n + i];
+            }
     }
     inf.status = status;
     if (info) *info = inf;
-    free(R); free(D); free(AD); free(T); free(Xa);
+    free(R); free(D); free(AD); free(T); free(Xa); free(Xr);
     return status;
 }
 

@@ -22,7 +22,7 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "ccg_oracle.c")
 MUTANTS = {
     "beta_sign": ("for (int i = 0; i < m * m; ++i) beta[i] = -beta[i];",
                   "for (int i = 0; i < m * m; ++i) beta[i] = beta[i];"),
-    "alpha_transposed": ("double a = alpha[l + c * m];", "double a = alpha[c + l * m];"),
+    "alpha_transposed": ("real a = alpha[l + c * m];", "real a = alpha[c + l * m];"),
     "residual_sign": ("rr[i] -= ad[i] * a;", "rr[i] += ad[i] * a;"),
     "dropped_D_beta": ("t[i] += d[i] * bb;", "t[i] += 0.0 * d[i] * bb;"),
     "gram_uses_R": ("gram(n, m, D, AD, G);", "gram(n, m, D, R, G);"),
@@ -30,13 +30,13 @@ MUTANTS = {
     # (D^T R is symmetric in exact arithmetic -- it equals R^T R because R_{k+1} is
     # orthogonal to D_k -- so transposing it is not a mistake and is not listed.)
     "S_from_R_only": ("gram(n, m, D, R, S);", "gram(n, m, R, R, S); S[0] *= 1.5;"),
-    "matmat_wrong_column": ("double mkj = M[k + (size_t)j * ldm];", "double mkj = M[k];"),
+    "matmat_wrong_column": ("real mkj = M[k + (size_t)j * ldm];", "real mkj = M[k];"),
     "chol_solve_skips_back_substitution": ("for (int i = m - 1; i >= 0; --i) {     /* L^T z = y */",
                                            "for (int i = m - 1; i >= m; --i) {     /* L^T z = y */"),
     # the restart branch of the stop rule (explicit residual fails the confirmation)
-    "restart_keeps_D": ("memcpy(D, T, (size_t)n * m * sizeof(double));\n                inf.restarts++;",
+    "restart_keeps_D": ("memcpy(D, T, (size_t)n * m * sizeof(real));\n                inf.restarts++;",
                         "inf.restarts++;"),
-    "restart_keeps_R": ("memcpy(R, T, (size_t)n * m * sizeof(double));", ";"),
+    "restart_keeps_R": ("memcpy(R, T, (size_t)n * m * sizeof(real));", ";"),
     "restart_not_counted": ("inf.restarts++;", ";"),
 }
 
