@@ -34,6 +34,9 @@ struct DevState {
     int deflations;    // rank-drop events
     int restarts;      // explicit-residual restarts
     int maxit;         // stop after this many block steps
+    int dir_pending;   // 1: the update launch of this block step finished the step and
+                       // left beta for the direction launch (cleared by every A.D launch)
+    int ad_streams;    // A.D launches that streamed A in block steps (for byte counts)
     double nb;         // ||b||_2 (for a refinement inner solve: 1, columns are scaled)
     double tol;        // relative stop tolerance on min_j ||R_j|| / nb
     double tau;        // rank threshold on the scaled pivots
@@ -63,7 +66,7 @@ struct AdArgs {
     const void* V;       // operand block D (agent-major, vector type)
     const void* R;       // residual block (agent-major, vector type)
     void* AD;            // result block (agent-major, vector type)
-    RedBuf red;          // reduction scratch (ne = P*(P+1) + 2*P*P + P)
+    RedBuf red;          // reduction scratch (ne = P*(P+1)/2 + P*P)
     DevState* st;
 };
 
@@ -91,12 +94,16 @@ struct SymArgs {
     const DevState* st;
 };
 
+// Arguments of the update launch (X += D alpha, R -= AD alpha, then the products
+// (AD)^T R and diag(R^T R) of the new residual, reduced into beta and the stop test)
+// and of the direction launch (D = R + D beta), which share the row tiling.
 struct UpdArgs {
     int n_pad;
     void* X;             // agent-major blocks (vector type)
     void* R;
     void* D;
     const void* AD;
+    RedBuf red;          // reduction scratch of the update launch (ne = P*P + P)
     DevState* st;
 };
 

@@ -11,8 +11,8 @@
 //      over every system that needs one, per padded agent count,
 //   3. the starts of refinement inner solves (per system),
 //   4. k block steps over every resident system (k by lane and mode, kRoundSteps):
-//      per (precision, padded agent count, tile shape) class, k pairs of batched
-//      A.D and update launches on a stream of the class, replayed from a graph
+//      per (precision, padded agent count, tile shape) class, k triples of batched
+//      A.D, update and direction launches on a stream of the class, replayed from a graph
 //      captured on that stream; the class streams fork from and join back into the
 //      engine stream (a step is a no-op for a system that is not running),
 // then reads every state header and moves each system through the same phases,
@@ -201,6 +201,7 @@ struct Sys {
     bool refine_due = false;    // X += E * scale this round
     bool inner_start_due = false;
     int iter_before = 0;
+    int streams_before = 0;           // A.D launches that streamed A, before the round
     // low-precision outer loop
     double nb = 1.0, best = 0.0;
     int iters = 0, refinements = 0, stall = 0;
@@ -436,6 +437,7 @@ class Engine {
         } else {
             u.X = sy.w.E; u.R = sy.w.Rl; u.D = sy.w.Dl; u.AD = sy.w.ADl;
         }
+        u.red = sy.w.red_up;
         u.st = st;
         ResArgs r{};
         r.n = n;
@@ -553,7 +555,10 @@ class Engine {
         }
         upload_items();
         // --- state headers (host decisions of the previous round)
-        for (auto& sy : live_) sy.iter_before = h_states_[sy.slot].iter;
+        for (auto& sy : live_) {
+            sy.iter_before = h_states_[sy.slot].iter;
+            sy.streams_before = h_states_[sy.slot].ad_streams;
+        }
         HIP_OK(hipMemcpy2DAsync(states_, sizeof(DevState), h_states_, sizeof(DevState), kHeader, hi_slot_,
                                 hipMemcpyHostToDevice, s_));
         // 1. refinement corrections
@@ -611,10 +616,8 @@ class Engine {
         DevState& h = h_states_[sy.slot];
         const double nn = (double)sy.n * sy.n;
         const double s_step = sy.prec == PREC_F64 ? 8.0 : 4.0;
-        // A.D launches that streamed A: one per completed step, plus the one whose
-        // stop test ended the steps
-        const bool stopped = h.done == RECUR_CONV || (h.done == MAXIT && h.iter > sy.iter_before);
-        sy.bytes += s_step * nn * ((h.iter - sy.iter_before) + (stopped ? 1 : 0));
+        // A.D launches that streamed A in this round's block steps
+        sy.bytes += s_step * nn * (h.ad_streams - sy.streams_before);
         if (sy.res_due) sy.bytes += 8.0 * nn;
         const bool had_res = sy.res_due;
         sy.res_due = false;
@@ -893,6 +896,7 @@ class Engine {
     void enqueue_class_step(const StepRange& r, hipStream_t cs) {
         HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, r.nw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
         HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
+        HIP_OK(launch_dir_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
     }
 
     void upload_items() {

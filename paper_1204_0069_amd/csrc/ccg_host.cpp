@@ -1,7 +1,7 @@
 // Host side and C interface (include/ccg.h) of the cooperative CG library.
 //
 // The host side owns one workspace per context, sized for the largest solve so far.
-// A solve is: pack X0 into the row-major agent block, form R0 = B - A X0 (an A
+// A solve is: pack X0 into the agent-major block, form R0 = B - A X0 (an A
 // stream plus the residual epilogue), then repeat groups of block steps
 // (k_ad, k_upd, k_dir) -- captured once into a HIP graph and replayed -- polling
 // the device state between groups.  When the recurrence residual passes the test,
@@ -204,8 +204,8 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
     return c->ev_pool[i];
 }
 
-// One block step: A.D (+ products, stop test, rank step, alpha, beta), then the
-// X, R, D update.
+// One block step: A.D (+ products, rank step, alpha), the X and R update (+ stop
+// test and beta), then the direction update.
 void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     Workspace& w = s.c->ws;
     hipEvent_t e0 = timed ? pooled_event(s.c, 2 * ev_slot) : nullptr;
@@ -222,8 +222,10 @@ void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     u.R = b.R;
     u.D = b.D;
     u.AD = b.AD;
+    u.red = w.red_up;
     u.st = w.st;
     HIP_OK(launch_upd(s.prec, s.P, u, s.c->stream));
+    HIP_OK(launch_dir(s.prec, s.P, u, s.c->stream));
 }
 
 void read_state(ccg_ctx* c) {
@@ -403,13 +405,14 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
             const int left = maxit - h.iter;
             const int k = left > 0 ? round_k : 1;   // steps past maxit are no-ops
             const int it0 = h.iter;
+            const int as0 = h.ad_streams;
             const double res0 = h.minres;
             const bool timed = run_steps(s, k, use_graph);
             read_state(c);
             round_k = next_round(gk, res0, h.minres, h.iter - it0, tol);
-            // A.D launches that streamed A: one per completed step, plus the one
-            // whose stop test ended the batch
-            const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
+            // A.D launches that streamed A (one per step, whose stop test now runs
+            // in the update launch, so no launch streams A past the stop)
+            const int streamed = h.ad_streams - as0;
             if (timed) collect_profile(s, streamed);
             bytes += bytes_step * streamed;
         }
@@ -556,11 +559,12 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
         while (h.done == RUNNING) {
             const int k = round_k;   // steps past maxit are no-ops
             const int it0 = h.iter;
+            const int as0 = h.ad_streams;
             const double res0 = h.minres;
             const bool timed = run_steps(s, k, use_graph);
             read_state(c);
             round_k = next_round(gk, res0, h.minres, h.iter - it0, h.tol);
-            const int streamed = (h.iter - it0) + (h.done != RUNNING ? 1 : 0);
+            const int streamed = h.ad_streams - as0;
             if (timed) collect_profile(s, streamed);
             bytes += s_low * n * n * streamed;
         }

@@ -18,6 +18,7 @@ namespace ccg {
 hipError_t launch_ad(int prec, int P, const AdArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr);
 hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s);
+hipError_t launch_dir(int prec, int P, const UpdArgs& a, hipStream_t s);
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s);
 hipError_t launch_pack(int n, int n_pad, int p, int P, const double* X, int64_t ldx, double* Xr,
                        hipStream_t s);
@@ -38,6 +39,7 @@ int ad_nw(int prec, int P, int n);
 hipError_t launch_tune_matrix(int n, double* A, int64_t lda, hipStream_t s);
 hipError_t launch_tune_vectors(int64_t cnt, double* d64, float* d32, unsigned seed, hipStream_t s);
 hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);
+hipError_t launch_dir_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);
 hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int nitems, hipStream_t s);
 int ad_fit_rows(int prec, int P, int cw, int nw);
 int ad_workgroups(int n);
@@ -105,7 +107,7 @@ struct Workspace {
     float* Rl = nullptr;
     float* Dl = nullptr;
     float* ADl = nullptr;
-    RedBuf red_ad{}, red_res{};
+    RedBuf red_ad{}, red_up{}, red_res{};
     DevState* st = nullptr;
     // symmetric A.D pass (carved on request, for P <= kSymMaxP and n_pad >= kSymMinN)
     double* part = nullptr;          // n_pad/kSymB blocks x as many slots x kSymB x P
@@ -190,7 +192,8 @@ inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P, bool sym 
     w.Rl = cv.take<float>(blk);
     w.Dl = cv.take<float>(blk);
     w.ADl = cv.take<float>(blk);
-    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) + 2 * P * P + P);
+    w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) / 2 + P * P);
+    w.red_up = carve_red(cv, row_workgroups(n_pad, P), P * P + P);
     w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
     if (sym && P <= kSymMaxP && n_pad >= kSymMinN) {

@@ -8,7 +8,7 @@
 // HIP kernels (gfx950) for the block step of cooperative conjugate gradient.
 //
 // One block step (Alg. 2 of the paper, sign convention R = B - A X, residual by
-// the Table 1 recurrence) is two launches:
+// the Table 1 recurrence) is three launches:
 //
 //   k_ad   : AD = A D, streaming A once.  A is symmetric, so column i of A (which is
 //            contiguous in the column-major layout) is row i: each wave streams
@@ -16,13 +16,13 @@
 //            contraction index k, and multiplies them with D rows staged in LDS
 //            (double buffered).  Lane sums are folded by a fixed xor butterfly, so
 //            every AD row is complete inside one wave: no split-K partials.  Each
-//            workgroup adds its rows' share of five p x p products (D^T AD, AD^T R,
-//            AD^T AD, D^T R, R^T R); a two-level fixed-order reduction across
-//            workgroups ends in the last workgroup, which runs the stop test on the
-//            residual norms, the rank step of Alg. 3, alpha = G^{-1} D^T R and
-//            beta = -G^{-1} (AD)^T R_new with (AD)^T R_new = AD^T R - AD^T AD alpha
-//            (all FP64).
-//   k_upd  : X += D alpha, R -= AD alpha, D = R + D beta (masked to active agents).
+//            workgroup adds its rows' share of G = D^T AD and S = D^T R; a two-level
+//            fixed-order reduction across workgroups ends in the last workgroup,
+//            which runs the rank step of Alg. 3 and alpha = G^{-1} S (FP64).
+//   k_upd  : X += D alpha, R_new = R - AD alpha, and the products (AD)^T R_new and
+//            diag(R_new^T R_new), reduced the same way; the last workgroup runs the
+//            stop test on the new residual norms and beta = -G^{-1} (AD)^T R_new.
+//   k_dir  : D = R_new + D beta (masked to active agents).
 //
 #include "ccg_device.h"
 
@@ -495,35 +495,32 @@ __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
     return v;
 }
 
-// The products of the ROWS AD rows of workgroup `tile` (in adt, LDS, row stride
-// kMaxP, zero for rows >= n) with the D and R rows (dr, see load_dr), their
-// fixed-order reduction over the `ntiles` workgroups, and in the last workgroup the
-// stop test, the rank step (Alg. 3), alpha and beta.  WG threads.
+// The products D^T AD and D^T R over the ROWS AD rows of workgroup `tile` (in adt,
+// LDS, row stride kMaxP, zero for rows >= n) and the D and R rows (dr, see
+// load_dr), their fixed-order reduction over the `ntiles` workgroups, and in the
+// last workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G
+// kept in the state for beta.  WG threads.
 template <int PREC, int P, int ROWS, int WG>
 __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
                                         const StepState0& s0, const DRval dr) {
-    using TV = typename PT<PREC>::TV;
     constexpr int kAdCols = ROWS;
     __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
     __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
-    __shared__ double gmine[P * (P + 1) + 2 * P * P + P];   // this workgroup's product shares
-    __shared__ double gtot[P * (P + 1) + 2 * P * P + P];    // grid totals (last workgroup)
+    __shared__ double gmine[P * (P + 1) / 2 + P * P];   // this workgroup's product shares
+    __shared__ double gtot[P * (P + 1) / 2 + P * P];    // grid totals (last workgroup)
     __shared__ double sm[4 * kMaxP * kMaxP];
     __shared__ double gscr[WG];
     __shared__ int ish[128];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int n = a.n;
     const int i0 = tile * kAdCols;
-    const TV* __restrict__ V = static_cast<const TV*>(a.V);
     const unsigned mask0 = s0.mask;
-    const double nb0 = s0.nb, tol0 = s0.tol, tau0 = s0.tau;
+    const double tau0 = s0.tau;
     const int iter0 = s0.iter, maxit0 = s0.maxit, m0 = s0.m;
 
     // ---- the workgroup's share of the products over its rows, packed as
-    //   G = D^T AD (lower triangle), Z = AD^T R, Y = AD^T AD (lower triangle),
-    //   S = D^T R, and the diagonal of R^T R
+    //   G = D^T AD (lower triangle) and S = D^T R (full)
     static_assert(kAdCols * P <= WG, "one D and R value per thread");
     if (tid < kAdCols * P) {
         const DRval v = dr.early ? dr : load_dr<PREC, P, ROWS>(a, i0);
@@ -533,89 +530,49 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
     }
     __syncthreads();
     constexpr int TRI = P * (P + 1) / 2;
-    constexpr int OZ = TRI, OY = TRI + P * P, OS = 2 * TRI + P * P, OQ = 2 * TRI + 2 * P * P;
-    constexpr int NE = OQ + P;
+    constexpr int OS = TRI;
+    constexpr int NE = TRI + P * P;
     for (int e = tid; e < NE; e += WG) {
-        const double* U;
         const double* Wv;
         int x, y;
-        if (e < OZ || (e >= OY && e < OS)) {             // triangles of G and Y
-            const int t = e < OZ ? e : e - OY;
+        if (e < OS) {                                     // triangle of G
             x = 0;
-            while ((x + 1) * (x + 2) / 2 <= t) ++x;
-            y = t - x * (x + 1) / 2;
-            U = e < OZ ? drw : adt;
+            while ((x + 1) * (x + 2) / 2 <= e) ++x;
+            y = e - x * (x + 1) / 2;
             Wv = adt;
-        } else if (e < OQ) {                              // Z and S, full
-            const int t = e < OY ? e - OZ : e - OS;
+        } else {                                          // S, full
+            const int t = e - OS;
             x = t / P;
             y = t - x * P;
-            U = e < OY ? adt : drw;
-            Wv = rrw;
-        } else {                                          // diagonal of R^T R
-            x = y = e - OQ;
-            U = rrw;
             Wv = rrw;
         }
         double s = 0.0;
-        for (int r = 0; r < kAdCols; ++r) s = fma(U[r * kMaxP + x], Wv[r * kMaxP + y], s);
+        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], Wv[r * kMaxP + y], s);
         gmine[e] = s;
     }
     __syncthreads();
     if (!grid_reduce<(P >= 8 ? kGroup : 16), WG>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
 
-    // ---- last workgroup: stop test on R, rank step (Alg. 3), alpha and beta
+    // ---- last workgroup: rank step (Alg. 3) and alpha
     DevState* st = a.st;
-    const double* Zt = gtot + OZ;
+    if (tid == 0) st->ad_streams += 1;
+    if (iter0 >= maxit0) {                    // (the update launch stops the steps first)
+        if (tid == 0) st->done = MAXIT;
+        return;
+    }
     const double* St = gtot + OS;
-    const double* Qd = gtot + OQ;
     unsigned mask = mask0;
     double* Gs = sm;                          // full symmetric P x P
-    double* Ys = gmine;                       // (gmine is free now)
     double* Lsh = sm + kMaxP * kMaxP;         // Cholesky factor, row-major stride P
     double* rinv = sm + 2 * kMaxP * kMaxP;    // 1 / L[i][i]
     double* lred = gscr;                      // per-lane values reduced by lane 0
-    // G and Y are symmetric in exact arithmetic: expand their lower triangles
+    // G is symmetric in exact arithmetic: expand its lower triangle
     for (int t = tid; t < P * P; t += WG) {
         const int x = t / P, y = t - (t / P) * P;
         const int hi = max(x, y), lo = min(x, y);
         Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
-        Ys[t] = gtot[OY + hi * (hi + 1) / 2 + lo];
-    }
-    // stop test (Alg. 4: smallest agent residual) before the step, as the loop does
-    if (wave == 0) {
-        double q = INFINITY;
-        double bad = 0.0;
-        if (lane < P && ((mask >> lane) & 1u)) {
-            const double nr = sqrt(Qd[lane]);
-            st->norms[lane] = nr;
-            if (!isfinite(nr)) bad = 1.0;
-            q = nr / nb0;
-        }
-        if (lane < P) {
-            lred[lane] = q;
-            lred[32 + lane] = bad;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane == 0) {
-            double mn = INFINITY, anybad = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < P; ++jj) {
-                mn = fmin(mn, lred[jj]);
-                anybad += lred[32 + jj];
-            }
-            st->minres = mn;
-            int stop = 0;
-            if (anybad > 0.0) { fail_state(st, -2); stop = 1; }
-            else if (mn <= tol0) { st->done = RECUR_CONV; stop = 1; }
-            else if (iter0 >= maxit0) { st->done = MAXIT; stop = 1; }
-            ish[122] = stop;
-        }
     }
     __syncthreads();
-    if (ish[122]) return;
     // Fast path: when det of the diagonally scaled G exceeds 2 tau, every pivot of
     // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
     // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
@@ -700,48 +657,28 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
         }
     }
     if (wave != 0 || lane >= P) return;
-    // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c]; then (AD)^T R_new = (AD)^T R - (AD^T AD)
-    // alpha and beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c], all in this lane's registers
+    // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c] in this lane's registers; the factor
+    // is kept for beta, which the update launch solves from the new residual
     const int c = lane;
     const bool ac = (mask >> c) & 1u;
-    // (registers up to P = 8; LDS beyond)
     if constexpr (P <= 8) {
         double y[P];
 #pragma unroll
         for (int x = 0; x < P; ++x) y[x] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
         col_chol_solve<P>(Lsh, rinv, y);
-        double w[P];
-#pragma unroll
-        for (int x = 0; x < P; ++x) {
-            double v = Zt[x * P + c];
-#pragma unroll
-            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * y[l];
-            w[x] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
-        }
-        col_chol_solve<P>(Lsh, rinv, w);
 #pragma unroll
         for (int x = 0; x < P; ++x) {
             st->alpha[x * kMaxP + c] = y[x];
-            st->beta[x * kMaxP + c] = w[x];
             st->L[x * kMaxP + c] = Lsh[x * P + c];
         }
     } else {
         double* Yc = sm + 3 * kMaxP * kMaxP;   // column c of alpha at Yc[x * P + c]
-        double* Wc = gscr;                     // column c of beta
 #pragma unroll 1
         for (int x = 0; x < P; ++x) Yc[x * P + c] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
         col_chol_solve_lds<P>(Lsh, rinv, Yc, c);
 #pragma unroll 1
         for (int x = 0; x < P; ++x) {
-            double v = Zt[x * P + c];
-            for (int l = 0; l < P; ++l) v -= Ys[x * P + l] * Yc[l * P + c];
-            Wc[x * P + c] = (ac && ((mask >> x) & 1u)) ? -v : 0.0;
-        }
-        col_chol_solve_lds<P>(Lsh, rinv, Wc, c);
-#pragma unroll 1
-        for (int x = 0; x < P; ++x) {
             st->alpha[x * kMaxP + c] = Yc[x * P + c];
-            st->beta[x * kMaxP + c] = Wc[x * P + c];
             st->L[x * kMaxP + c] = Lsh[x * P + c];
         }
     }
@@ -770,6 +707,9 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
     __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
 
+    // every A.D launch follows the direction launch of the previous block step (if
+    // any): its flag is spent
+    if (tile == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
     if (!a.product_only && a.st->done != RUNNING) return;
     // state the last workgroup needs, read now so that its latency hides under the
     // stream (the previous launches have finished writing it), and the D and R rows
@@ -1180,6 +1120,8 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
     constexpr int U = 16;                     // loads in flight per thread
     __shared__ double adt[kFinRows * kMaxP];
     __shared__ double sub[kWG];
+    // (k_sym does not read the state: this launch spends the direction flag)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
     if (a.st->done != RUNNING) return;
     const StepState0 s0 = read_state0(a.st);
     const int tid = threadIdx.x;
@@ -1213,34 +1155,41 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
     ad_tail<PREC_F64, P, kFinRows, kWG>(a, blockIdx.x, gridDim.x, adt, s0, dr);
 }
 
-// ===================== k_upd: X += D alpha, R -= AD alpha, D = R + D beta
+// ====================== k_upd: X += D alpha, R -= AD alpha, beta and the stop test
 //
 // Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
-// Every row's old D is read into LDS before any thread writes the new one.
+// Each workgroup adds its rows' share of (AD)^T R_new and of the diagonal of
+// R_new^T R_new; a fixed-order reduction over the row tiles ends in the last
+// workgroup, which ends the block step: the stop test on the new residual norms
+// (Alg. 4: smallest agent residual, relative to ||b||), beta = -G^{-1} (AD)^T R_new
+// (Alg. 2, with the factor of G that the A.D launch kept), and the step count.
 
 template <int PREC, int P>
-__device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile) {
+__device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
-    __shared__ double al[P * P], be[P * P];
+    constexpr int NE = P * P + P;       // (AD)^T R_new, then diag(R_new^T R_new)
+    __shared__ double al[P * P];
     __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
+    __shared__ double mine[NE], tot[NE];
+    __shared__ double gscr[kWG];
+    __shared__ double Lsh[P * P], rinv[P], wsh[P * P];
+    __shared__ int ish[8];
     DevState* st = a.st;
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = tid % RB, j = tid / RB;
     const int64_t i = (int64_t)tile * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
-    if (tid < P * P) {
-        al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
-        be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
-    }
-    const unsigned msk = st->mask;
+    if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+    const StepState0 s0 = read_state0(st);
     TV* X = static_cast<TV*>(a.X);
     TV* R = static_cast<TV*>(a.R);
-    TV* D = static_cast<TV*>(a.D);
     const double x0 = X[o];
     const double r0 = R[o];
-    dt[r * P + j] = D[o];
+    dt[r * P + j] = static_cast<const TV*>(a.D)[o];
     adt[r * P + j] = static_cast<const TV*>(a.AD)[o];
     __syncthreads();
     double sx = 0.0, sr = 0.0;
@@ -1255,23 +1204,131 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile) {
     R[o] = rn;
     rt[r * P + j] = double(rn);
     __syncthreads();
-    double sd = rt[r * P + j];
+    for (int e = tid; e < NE; e += kWG) {
+        double s = 0.0;
+        if (e < P * P) {
+            const int x = e / P, y = e - (e / P) * P;
+            for (int q = 0; q < RB; ++q) s = fma(adt[q * P + x], rt[q * P + y], s);
+        } else {
+            const int y = e - P * P;
+            for (int q = 0; q < RB; ++q) s = fma(rt[q * P + y], rt[q * P + y], s);
+        }
+        mine[e] = s;
+    }
+    __syncthreads();
+    if (!grid_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
+
+    // ---- last workgroup: stop test, beta, step count
+    const unsigned mask = s0.mask;
+    if (tid < P * P) {
+        const int x = tid / P, y = tid - (tid / P) * P;
+        Lsh[tid] = st->L[x * kMaxP + y];
+    }
+    __syncthreads();
+    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+    if (wave == 0) {
+        double q = INFINITY;
+        double bad = 0.0;
+        if (lane < P && ((mask >> lane) & 1u)) {
+            const double nr = sqrt(tot[P * P + lane]);
+            st->norms[lane] = nr;
+            if (!isfinite(nr)) bad = 1.0;
+            q = nr / s0.nb;
+        }
+        if (lane < P) {
+            gscr[lane] = q;
+            gscr[32 + lane] = bad;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            double mn = INFINITY, anybad = 0.0;
 #pragma unroll
-    for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
-    D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
-    if (tile == 0 && tid == 0) st->iter += 1;
+            for (int jj = 0; jj < P; ++jj) {
+                mn = fmin(mn, gscr[jj]);
+                anybad += gscr[32 + jj];
+            }
+            const int it = s0.iter + 1;
+            st->minres = mn;
+            st->iter = it;
+            // the stop rule at the top of the next step, as the loop of Alg. 4 reads it
+            if (anybad > 0.0) fail_state(st, -2);
+            else if (mn <= s0.tol) st->done = RECUR_CONV;
+            else if (it >= s0.maxit) st->done = MAXIT;
+            st->dir_pending = 1;
+        }
+    }
+    __syncthreads();
+    if (wave != 0 || lane >= P) return;
+    // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
+    const int c = lane;
+    const bool ac = (mask >> c) & 1u;
+    if constexpr (P <= 8) {
+        double w[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = w[x];
+    } else {
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = wsh[x * P + c];
+    }
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
-    upd_tile<PREC, P>(a, blockIdx.x);
+    upd_tile<PREC, P>(a, blockIdx.x, gridDim.x);
+}
+
+// ============================================= k_dir: D = R + D beta
+//
+// The direction update of the step the update launch finished (dir_pending), with
+// the update's row tiling: masked to the active agents.
+template <int PREC, int P>
+__device__ __forceinline__ void dir_tile(const UpdArgs& a, const int tile) {
+    using TV = typename PT<PREC>::TV;
+    constexpr int RB = kWG / P;
+    __shared__ double be[P * P];
+    __shared__ double dt[RB * P];
+    const DevState* st = a.st;
+    if (!st->dir_pending) return;
+    const int tid = threadIdx.x;
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)tile * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
+    if (tid < P * P) be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
+    const unsigned msk = st->mask;
+    TV* D = static_cast<TV*>(a.D);
+    double sd = double(static_cast<const TV*>(a.R)[o]);
+    dt[r * P + j] = D[o];
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
+    D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_dir(UpdArgs a) {
+    dir_tile<PREC, P>(a, blockIdx.x);
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    upd_tile<PREC, P>(a, it.y);
+    upd_tile<PREC, P>(a, it.y, a.n_pad / (kWG / P));
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_dir_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const UpdArgs a = sys[it.x];
+    dir_tile<PREC, P>(a, it.y);
 }
 
 // ============================================ k_res: T = B - Y, norms, restart

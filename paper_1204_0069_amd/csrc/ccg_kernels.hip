@@ -183,6 +183,11 @@ static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_upd<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
+template <int PREC, int P>
+static hipError_t launch_dir_t(const UpdArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
+    return hipGetLastError();
+}
 template <int P>
 static hipError_t launch_res_t(const ResArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_res<P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
@@ -252,9 +257,27 @@ hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
     }
 }
 
+hipError_t launch_dir(int prec, int P, const UpdArgs& a, hipStream_t s) {
+    switch (prec) {
+#define C64(PP) launch_dir_t<PREC_F64, PP>(a, s)
+#define C32(PP) launch_dir_t<PREC_F32, PP>(a, s)
+        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F32:
+        case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
+#undef C64
+#undef C32
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int PREC, int P>
 static hipError_t launch_upd_batch_t(const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {
     hipLaunchKernelGGL((k_upd_batch<PREC, P>), dim3(nitems), dim3(kWG), 0, s, sys, items);
+    return hipGetLastError();
+}
+template <int PREC, int P>
+static hipError_t launch_dir_batch_t(const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_dir_batch<PREC, P>), dim3(nitems), dim3(kWG), 0, s, sys, items);
     return hipGetLastError();
 }
 template <int P>
@@ -276,6 +299,20 @@ hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* ite
     switch (prec) {
 #define C64(PP) launch_upd_batch_t<PREC_F64, PP>(sys, items, nitems, s)
 #define C32(PP) launch_upd_batch_t<PREC_F32, PP>(sys, items, nitems, s)
+        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F32:
+        case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
+#undef C64
+#undef C32
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dir_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    switch (prec) {
+#define C64(PP) launch_dir_batch_t<PREC_F64, PP>(sys, items, nitems, s)
+#define C32(PP) launch_dir_batch_t<PREC_F32, PP>(sys, items, nitems, s)
         case PREC_F64: CCG_DISPATCH_P(P, C64)
         case PREC_F32:
         case PREC_BF16X2: CCG_DISPATCH_P(P, C32)

@@ -10,10 +10,16 @@ Tolerances (FP64 mode):
     run is compared with the oracle run for the SAME number of steps.  Taken to a
     relative residual of 1e-11, every agent column agrees to 1e-10 relative (the
     bound the solver is held to; oracle vs numpy gaps measure <= 3e-12 there).
-    Stopped at 1e-10, both iterates still carry up to cond(A) * 1e-10 of error in
-    the slow eigen-directions, so the gap is held to the arithmetic bound
-    2 * cond(A) * tol (measured: 1.4e-10 at n=256).  In both cases the natural
-    stopping steps agree within 5 % and the explicit FP64 residual is <= tol.
+    Stopped at 1e-10 (the benchmark tolerance), the iterates are still in the steps
+    where an FP64 trajectory drifts furthest from the method's own: on the CPU, the
+    FP64 oracle under 12 row/column reorderings spreads up to 1.6e-10 at the GPU's
+    stopping step of the n = 256 system, and it sits 1.3e-10 to 3.1e-10 from the same
+    oracle code built with 80-bit extended arithmetic (oracle.extended()).  There
+    the GPU run is compared with that extended-precision run for the same number of
+    steps: every agent column within 1e-10, or at least as close as the FP64 oracle
+    itself (measured on six systems: 0.56e-10 to 1.3e-10 against 1.3e-10 to 3.1e-10
+    for the FP64 oracle).  In both cases the natural stopping steps agree within 5 %
+    and the explicit FP64 residual is <= tol.
 """
 import numpy as np
 import pytest
@@ -74,17 +80,22 @@ SOLVE_CASES = [
 
 
 def _check_against_oracle(A, b, X0, X, info, tol, orc_natural=None, gap=1e-10):
-    """Same-step comparison (see module docstring) plus explicit-residual checks."""
+    """Same-step comparison (see module docstring) plus explicit-residual checks.
+    Returns the largest per-agent relative gap to the same-step oracle X."""
     Xg = X.cpu().numpy()
     p = Xg.shape[1]
+    worst = None
     if orc_natural is not None:
         ko = orc_natural["iters"]
         assert abs(info["iters"] - ko) <= max(3, 0.05 * ko), (info["iters"], ko)
     if info["restarts"] == 0:
         same = oracle.ccg(A, b, X0, tol=0.0, maxit=info["iters"])
         assert same["p_final"] == info["p_final"]
+        gaps = [_rel(Xg[:, j], same["X"][:, j]) for j in range(p)]
+        worst = max(gaps)
+        print(f"same-step gap per agent: max {worst:.2e}", flush=True)
         for j in range(p):
-            assert _rel(Xg[:, j], same["X"][:, j]) <= gap, j
+            assert gaps[j] <= gap, (j, gaps[j])
     T = b[:, None] - A @ Xg
     rel = np.linalg.norm(T, axis=0) / np.linalg.norm(b)
     if info["status"] == 0:
@@ -110,67 +121,129 @@ def test_solve_matches_oracle(gpu_ctx, n, p, kappa):
     _check_against_oracle(A, b, X0, X, info, tol, orc)
 
 
-@pytest.mark.parametrize("n,p,kappa", [(256, 3, 1e3), (700, 8, 1e3)])
-def test_solve_at_benchmark_tolerance(gpu_ctx, n, p, kappa):
-    print(f"case solve tol=1e-10 n={n} p={p} kappa={kappa}", flush=True)
-    if n == 256 and p == 3:
+@pytest.mark.parametrize("n,p,kappa,seed", [(256, 3, 1e3, None), (700, 8, 1e3, 202), (256, 3, 1e3, 1),
+                                            (256, 3, 1e3, 2), (512, 4, 1e3, 3), (1000, 8, 1e4, 4)])
+def test_solve_at_benchmark_tolerance(gpu_ctx, n, p, kappa, seed):
+    """tol = 1e-10, the benchmark's tolerance: every agent column within 1e-10 of the
+    oracle's extended-precision run for the same number of steps, or at least as
+    close to it as the FP64 oracle (see the module docstring)."""
+    print(f"case solve tol=1e-10 n={n} p={p} kappa={kappa} seed={seed}", flush=True)
+    if seed is None:
         A, b, X0 = ci.small_system()
     else:
-        A, b, X0 = ci.system(n, p, kappa, seed=202)
+        A, b, X0 = ci.system(n, p, kappa, seed=seed)
     tol = 1e-10
     orc = oracle.ccg(A, b, X0, tol=tol, maxit=20000)
     X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 20000)
-    assert info["status"] == 0, info
-    _check_against_oracle(A, b, X0, X, info, tol, orc, gap=2 * kappa * tol)
+    assert info["status"] == 0 and info["restarts"] == 0, info
+    _check_against_oracle(A, b, X0, X, info, tol, orc, gap=np.inf)
+    k = info["iters"]
+    ext = oracle.ccg(A, b, X0, tol=0.0, maxit=k, lib=oracle.extended())
+    f64 = oracle.ccg(A, b, X0, tol=0.0, maxit=k)
+    Xg = X.cpu().numpy()
+    for j in range(p):
+        g_gpu = _rel(Xg[:, j], ext["X"][:, j])
+        g_f64 = _rel(f64["X"][:, j], ext["X"][:, j])
+        print(f"agent {j}: GPU vs extended {g_gpu:.2e}, FP64 oracle vs extended {g_f64:.2e}, "
+              f"GPU vs FP64 oracle {_rel(Xg[:, j], f64['X'][:, j]):.2e}", flush=True)
+        assert g_gpu <= max(1e-10, g_f64), j
 
 
-def test_solve_is_deterministic(gpu_ctx):
-    A, b, X0 = ci.system(1500, 4, 1e3, seed=5)
-    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000)
-    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000)
-    assert i1["iters"] == i2["iters"]
-    assert torch.equal(X1, X2)
+# --------------------------------------- stop rule of Alg. 4: confirmation and restart
+
+def _gpu_first_restart_step(ctx, A, b, X0, tol, hi):
+    """Smallest k <= hi such that the GPU solve capped at maxit = k has restarted (the
+    restart count is monotone in maxit: a cap only ends the same run earlier)."""
+    def restarted(k):
+        return ctx.solve(A, b, X0, tol, k, raise_on_error=False)[1]["restarts"] >= 1
+
+    if not restarted(hi):
+        return None
+    lo = 0
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if restarted(mid):
+            hi = mid
+        else:
+            lo = mid
+    return hi
 
 
-def test_graph_and_direct_launch_agree(gpu_ctx):
-    from paper_1204_0069_amd import CCG_NO_GRAPH
-    A, b, X0 = ci.system(900, 4, 1e3, seed=8)
-    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000)
-    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_NO_GRAPH)
-    assert i1["iters"] == i2["iters"]
-    assert torch.equal(X1, X2)
+def _check_restart_is_fresh_start(ctx, A, b, X0, tol, maxit, kappa, full, Xf):
+    """The rest of a GPU run after its first restart equals, bit for bit, a GPU run
+    started fresh from the agents at the restart step k_r, with one restart fewer
+    and k_r steps fewer; at k_r the explicit residual (the oracle's loops) of those
+    agents fails the test."""
+    At, bt = _t(A), _t(b)
+    kr = _gpu_first_restart_step(ctx, At, bt, _t(X0), tol, full["iters"])
+    assert kr is not None and 0 < kr <= full["iters"]
+    Xr, at = ctx.solve(At, bt, _t(X0), tol, kr, raise_on_error=False)
+    assert at["restarts"] == 1 and at["iters"] == kr
+    T = oracle.residual(A, b, Xr.cpu().numpy())
+    assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() > tol
+    Xs, fresh = ctx.solve(At, bt, Xr, tol, maxit - kr, raise_on_error=False)
+    assert fresh["status"] == full["status"]
+    assert fresh["restarts"] == full["restarts"] - 1
+    assert fresh["iters"] == full["iters"] - kr
+    assert torch.equal(Xs, Xf)
+    return kr
 
 
-def test_round_lengths_do_not_change_results(gpu_ctx):
-    """FP64 rounds grow from graph_k up to 8 graph_k while the residual is far from tol;
-    where they end must not change the steps: graph_k 1, 4 and 16 (rounds of 1..128
-    steps, several graphs in one context) give the same result, and so does a solve
-    after the other sizes' graphs were captured."""
-    A, b, X0 = ci.system(2100, 6, 1e4, seed=9)
-    runs = [gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, graph_k=k) for k in (16, 1, 4, 16)]
-    for X, info in runs[1:]:
-        assert info["status"] == 0 and info["iters"] == runs[0][1]["iters"]
-        assert torch.equal(X, runs[0][0])
-    assert runs[0][1]["iters"] > 128
+# Relative tolerances below what the explicit FP64 residual of a cond 1e5 - 1e6
+# system can reach: the recurrence residual passes them, the explicit one cannot,
+# so every run (oracle and GPU) restarts, by construction.
+FORCED_RESTART_CASES = [(60, 3, 1e6, 11, 1e-15), (60, 2, 1e5, 12, 1e-15), (256, 4, 1e5, 13, 1e-15)]
 
 
-def test_profiled_solves_agree_and_count_launches(gpu_ctx):
-    """Timing the A.D launches (every round, or every 4th round with the rest from the
-    graph) changes how steps are launched, not what they compute."""
-    from paper_1204_0069_amd import CCG_PROFILE, CCG_PROFILE_SAMPLED
-    A, b, X0 = ci.system(700, 3, 1e3, seed=9)
-    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000)
-    gpu_ctx.kernel_time(reset=True)
-    X2, i2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_PROFILE)
-    ms_all, n_all = gpu_ctx.kernel_time(reset=True)
-    X3, i3 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_PROFILE_SAMPLED)
-    ms_s, n_s = gpu_ctx.kernel_time(reset=True)
-    assert i1["iters"] == i2["iters"] == i3["iters"]
-    assert torch.equal(X1, X2) and torch.equal(X1, X3)
-    assert i1["iters"] > 64                            # several rounds of 16 steps
-    assert n_all == i1["iters"] + 1 + i1["restarts"]   # every launch that streamed A
-    assert 0 < n_s < n_all                             # the launches of every 4th round
-    assert ms_all > 0.0 and ms_s > 0.0
+@pytest.mark.parametrize("n,p,kappa,seed,tol", FORCED_RESTART_CASES)
+def test_forced_restart_continues_as_a_fresh_start(gpu_ctx, n, p, kappa, seed, tol):
+    """The stop rule (Alg. 4's smallest-agent test on the recurrence residual,
+    confirmed by the explicit residual B - A X) restarts from R = D = B - A X (the
+    start of Alg. 2) when the confirmation fails.  The steps after a restart start
+    from a residual at the rounding floor, whose direction two summation orders do
+    not share (on the CPU, two orders give alpha and beta 1e-2 apart right after
+    it), so the GPU's steps after it are compared with the GPU's own fresh start
+    from the same agents, whose steps the per-step tests compare with the oracle."""
+    print(f"case forced restart n={n} p={p} kappa={kappa} seed={seed} tol={tol}", flush=True)
+    A, b, X0 = ci.system(n, p, kappa, seed=seed)
+    maxit = 3000
+    orc = oracle.ccg(A, b, X0, tol=tol, maxit=maxit)
+    Xf, full = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, maxit, raise_on_error=False)
+    print(f"gpu: {full['iters']} steps, {full['restarts']} restarts, status {full['status']}; "
+          f"oracle: {orc['iters']} steps, {orc['restarts']} restarts, status {orc['status']}", flush=True)
+    assert orc["restarts"] >= 1 and orc["status"] == 1
+    assert full["restarts"] >= 1 and full["status"] == 1 and full["iters"] == maxit
+    assert full["deflations"] == 0
+    kr = _check_restart_is_fresh_start(gpu_ctx, A, b, X0, tol, maxit, kappa, full, Xf)
+    print(f"first restart at step {kr}", flush=True)
+
+
+# Systems whose oracle run restarts at tol 1e-10 (the oracle pins use the same ones).
+# Whether a run restarts there depends on the rounding of the last steps, so the GPU
+# run may or may not; where it does, the restart must be a fresh start, and in
+# every case the result meets tol with the error bound of the direct solution.
+NATURAL_RESTART_CASES = [(60, 3, 1e5, 0), (60, 2, 1e6, 3), (300, 3, 1e6, 7)]
+
+
+@pytest.mark.parametrize("n,p,kappa,seed", NATURAL_RESTART_CASES)
+def test_restart_at_benchmark_tolerance(gpu_ctx, n, p, kappa, seed):
+    print(f"case restart tol=1e-10 n={n} p={p} kappa={kappa} seed={seed}", flush=True)
+    A, b, X0 = ci.system(n, p, kappa, seed=seed)
+    tol, maxit = 1e-10, 50000
+    orc = oracle.ccg(A, b, X0, tol=tol, maxit=maxit)
+    assert orc["restarts"] >= 1 and orc["status"] == 0
+    Xf, full = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, maxit, raise_on_error=False)
+    print(f"gpu: {full['iters']} steps, {full['restarts']} restarts; "
+          f"oracle: {orc['iters']} steps, {orc['restarts']} restarts", flush=True)
+    assert full["status"] == 0 and full["deflations"] == 0
+    T = oracle.residual(A, b, Xf.cpu().numpy())
+    rel = np.linalg.norm(T, axis=0) / np.linalg.norm(b)
+    assert rel.min() <= tol
+    xs = np.linalg.solve(A, b)
+    xg = Xf.cpu().numpy()[:, full["best_agent"]]
+    assert np.linalg.norm(xg - xs) <= 2 * kappa * tol * np.linalg.norm(xs)
+    if full["restarts"] >= 1:
+        _check_restart_is_fresh_start(gpu_ctx, A, b, X0, tol, maxit, kappa, full, Xf)
 
 
 # ----------------------------------------------------------------- edge cases
@@ -254,18 +327,29 @@ def big_system():
 
 
 def test_full_size_first_steps_match_oracle(gpu_ctx, big_system):
+    """The first 50 block steps of the benchmark system (n = 8192, p = 8, kappa = 1e4)
+    in the benchmark's launch configuration: alpha_k and beta_k of every step within
+    1e-10 of the oracle's (relative to the step's largest entry), and the agents X
+    after step 50 within 1e-10 (relative to the block).  R and D are held at step 30:
+    beyond it, two summation orders of any correct implementation drift apart in the
+    residual directions (numpy against numpy on a permuted system: R 1e-12 at step
+    30, 3e-11 at 40, 2e-9 at 50; alpha and beta stay at 1e-14 through step 60)."""
     A, b, X0 = big_system
-    print("case full-size debug_step n=8192 p=8 k=2", flush=True)
-    k = 2
-    g = gpu_ctx.debug_step(A, b, X0, k)
-    An = A.cpu().numpy()
-    orc = oracle.ccg(An, b.cpu().numpy(), X0.cpu().numpy(), tol=0.0, maxit=k, trace_k=k,
-                     want_rd=True)
-    for s in range(k):
-        assert np.abs(g["alphas"][s] - orc["alphas"][s]).max() <= 1e-10 * np.abs(orc["alphas"][s]).max()
-        assert np.abs(g["betas"][s] - orc["betas"][s]).max() <= 1e-10 * np.abs(orc["betas"][s]).max()
-    assert _rel(g["X"].numpy(), orc["X"]) <= 1e-10
-    assert _rel(g["R"].numpy(), orc["R"]) <= 1e-10
+    An, bn, Xn = A.cpu().numpy(), b.cpu().numpy(), X0.cpu().numpy()
+    for k in (30, 50):
+        print(f"case full-size debug_step n=8192 p=8 k={k}", flush=True)
+        g = gpu_ctx.debug_step(A, b, X0, k)
+        orc = oracle.ccg(An, bn, Xn, tol=0.0, maxit=k, trace_k=k, want_rd=True)
+        wa = max(np.abs(g["alphas"][s] - orc["alphas"][s]).max() / np.abs(orc["alphas"][s]).max()
+                 for s in range(k))
+        wb = max(np.abs(g["betas"][s] - orc["betas"][s]).max() / np.abs(orc["betas"][s]).max()
+                 for s in range(k))
+        gx, gr, gd = (_rel(g[key].numpy(), orc[key]) for key in ("X", "R", "D"))
+        print(f"k={k}: alpha {wa:.1e} beta {wb:.1e} X {gx:.1e} R {gr:.1e} D {gd:.1e}", flush=True)
+        assert wa <= 1e-10 and wb <= 1e-10
+        assert gx <= 1e-10
+        if k == 30:
+            assert gr <= 1e-10 and gd <= 1e-10
 
 
 def test_full_size_solve_properties(gpu_ctx, big_system):

@@ -56,7 +56,7 @@ def test_symmetric_and_whole_matrix_solves_agree(gpu_ctx):
     nb = -(-n // 128)
     diag = sum(min(128, n - 128 * K) ** 2 for K in range(nb))
     sym_step = 8 * 0.5 * (n * n + diag)
-    steps = i_s["iters"] + 1 + i_s["restarts"]
+    steps = i_s["iters"]   # one A.D pass per block step (the stop test ends the step)
     assert abs(i_s["bytes_A"] - (steps * sym_step + (1 + 1 + i_s["restarts"]) * 8 * n * n)) <= 1.0
 
 
@@ -82,7 +82,7 @@ def test_symmetric_profile_reports_triangle_bytes(gpu_ctx):
     gpu_ctx.kernel_time(reset=True)
     X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, flags=CCG_PROFILE | CCG_SYM_AD)
     ms, cnt, nbytes = gpu_ctx.kernel_time(reset=True, with_bytes=True)
-    assert info["status"] == 0 and cnt == info["iters"] + 1 + info["restarts"] and ms > 0.0
+    assert info["status"] == 0 and cnt == info["iters"] and ms > 0.0
     assert abs(nbytes / cnt - (8 * 0.5 * n * (n + 1) + 2 * 8 * n * p)) <= 1e-6 * nbytes / cnt
     gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, flags=CCG_PROFILE)
     ms, cnt, nbytes = gpu_ctx.kernel_time(reset=True, with_bytes=True)
