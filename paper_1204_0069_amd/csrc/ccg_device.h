@@ -19,6 +19,10 @@ constexpr int kGroup = 32;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 
+// Row tiling of the update and direction launches: one workgroup per block of
+// kWG / P rows (one element per thread).
+__host__ __device__ inline int upd_blocks(int n_pad, int P) { return n_pad / (256 / P); }
+
 // Device iteration state, one per solve.  Written only by "last workgroup"
 // epilogues and by the residual kernel; read by every kernel at entry.
 // OUTER: a refinement residual found the solve unfinished; the host starts the
@@ -34,8 +38,8 @@ struct DevState {
     int deflations;    // rank-drop events
     int restarts;      // explicit-residual restarts
     int maxit;         // stop after this many block steps
-    int dir_pending;   // 1: the update launch of this block step finished the step and
-                       // left beta for the direction launch (cleared by every A.D launch)
+    int dir_pending;   // 1: the update launch of this block step ran, and the direction
+                       // launch completes the step (cleared by every A.D launch)
     int ad_streams;    // A.D launches that streamed A in block steps (for byte counts)
     double nb;         // ||b||_2 (for a refinement inner solve: 1, columns are scaled)
     double tol;        // relative stop tolerance on min_j ||R_j|| / nb
@@ -94,16 +98,16 @@ struct SymArgs {
     const DevState* st;
 };
 
-// Arguments of the update launch (X += D alpha, R -= AD alpha, then the products
-// (AD)^T R and diag(R^T R) of the new residual, reduced into beta and the stop test)
-// and of the direction launch (D = R + D beta), which share the row tiling.
+// Arguments of the update launch (X += D alpha, R -= AD alpha, and each tile's share
+// of (AD)^T R and diag(R^T R) of the new residual) and of the direction launch (the
+// totals of those shares, the stop test, beta, and D = R + D beta).
 struct UpdArgs {
     int n_pad;
     void* X;             // agent-major blocks (vector type)
     void* R;
     void* D;
     const void* AD;
-    RedBuf red;          // reduction scratch of the update launch (ne = P*P + P)
+    RedBuf red;          // products of the update (ne = P*P + P): per block, per group
     DevState* st;
 };
 

@@ -228,7 +228,7 @@ class Engine {
     // a step class's items: A.D tiles at ad_off, update tiles at up_off in the list
     struct StepRange {
         int prec, P, cw, nw;
-        size_t ad_off, ad_n, up_off, up_n;
+        size_t ad_off, ad_n, up_off, up_n, dir_off, dir_n;
     };
 
   public:
@@ -813,7 +813,7 @@ class Engine {
             for (int P : {1, 2, 4, 8, 16}) {
                 for (int cw : {1, 2, 4}) {
                     for (int nw : {4, 8, 16}) {
-                        StepRange r{prec, P, cw, nw, st.size(), 0, 0, 0};
+                        StepRange r{prec, P, cw, nw, st.size(), 0, 0, 0, 0, 0};
                         for (auto& sy : live_) {
                             if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
                             const int t = (sy.n + cw * nw - 1) / (cw * nw);
@@ -823,10 +823,17 @@ class Engine {
                         r.up_off = st.size();
                         for (auto& sy : live_) {
                             if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
-                            const int t = sy.w.n_pad / (kWG / P);
+                            const int t = upd_blocks(sy.w.n_pad, P);
                             for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
                         }
                         r.up_n = st.size() - r.up_off;
+                        r.dir_off = st.size();
+                        for (auto& sy : live_) {
+                            if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
+                            const int t = upd_blocks(sy.w.n_pad, P);
+                            for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
+                        }
+                        r.dir_n = st.size() - r.dir_off;
                         if (r.ad_n) {
                             step_ranges_.push_back(r);
                             step_items_total_ += r.ad_n;
@@ -896,7 +903,7 @@ class Engine {
     void enqueue_class_step(const StepRange& r, hipStream_t cs) {
         HIP_OK(launch_ad_batch(r.prec, r.P, r.cw, r.nw, d_ad_, d_step_ + r.ad_off, (int)r.ad_n, cs));
         HIP_OK(launch_upd_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
-        HIP_OK(launch_dir_batch(r.prec, r.P, d_upd_, d_step_ + r.up_off, (int)r.up_n, cs));
+        HIP_OK(launch_dir_batch(r.prec, r.P, d_upd_, d_step_ + r.dir_off, (int)r.dir_n, cs));
     }
 
     void upload_items() {

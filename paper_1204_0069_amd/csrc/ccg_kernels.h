@@ -20,9 +20,10 @@
 //            fixed-order reduction across workgroups ends in the last workgroup,
 //            which runs the rank step of Alg. 3 and alpha = G^{-1} S (FP64).
 //   k_upd  : X += D alpha, R_new = R - AD alpha, and the products (AD)^T R_new and
-//            diag(R_new^T R_new), reduced the same way; the last workgroup runs the
-//            stop test on the new residual norms and beta = -G^{-1} (AD)^T R_new.
-//   k_dir  : D = R_new + D beta (masked to active agents).
+//            diag(R_new^T R_new), summed per group of workgroups.
+//   k_dir  : every workgroup adds those shares up in a fixed order and solves
+//            beta = -G^{-1} (AD)^T R_new itself, then D = R_new + D beta (masked to
+//            active agents); workgroup 0 runs the stop test on the new norms.
 //
 #include "ccg_device.h"
 
@@ -224,6 +225,28 @@ __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const Re
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[ngroups]);
     sum_table<B, NTH>(rb.l2, ne, ngroups, out, scratch);
+    return true;
+}
+
+// The first level of grid_reduce alone: the last workgroup of each group of kGroup
+// tiles sums its group's rows (tile order) into rb.l2[grp].  Returns true in that
+// workgroup.  The group sums are read by a later launch, which adds them up in
+// group order.
+template <int B, int NTH>
+__device__ __forceinline__ bool group_reduce(const double* mine, int ne, const RedBuf rb, double* out,
+                                             int* s_flag, double* scratch, int bid, int nwg) {
+    const int tid = threadIdx.x;
+    const int grp = bid / kGroup;
+    const int gsize = min(kGroup, nwg - grp * kGroup);
+    for (int e = tid; e < ne; e += NTH) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
+    stores_done();
+    __syncthreads();
+    if (tid == 0) *s_flag = (ticket(&rb.cnt[grp]) == (unsigned)gsize - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    if (tid == 0) reset_ticket(&rb.cnt[grp]);
+    sum_table<B, NTH>(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    for (int e = tid; e < ne; e += NTH) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
     return true;
 }
 
@@ -1155,14 +1178,13 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
     ad_tail<PREC_F64, P, kFinRows, kWG>(a, blockIdx.x, gridDim.x, adt, s0, dr);
 }
 
-// ====================== k_upd: X += D alpha, R -= AD alpha, beta and the stop test
+// ============ k_upd: X += D alpha, R -= AD alpha, and the products of the new residual
 //
-// Thread (r, j) of a workgroup owns element (row0 + r, agent j); RB = 256 / P rows.
-// Each workgroup adds its rows' share of (AD)^T R_new and of the diagonal of
-// R_new^T R_new; a fixed-order reduction over the row tiles ends in the last
-// workgroup, which ends the block step: the stop test on the new residual norms
-// (Alg. 4: smallest agent residual, relative to ||b||), beta = -G^{-1} (AD)^T R_new
-// (Alg. 2, with the factor of G that the A.D launch kept), and the step count.
+// Thread (r, j) of a workgroup owns element (row0 + r, agent j) of a block of
+// RB = 256 / P rows.  Each workgroup forms its rows' share of (AD)^T R_new (P x P)
+// and of diag(R_new^T R_new) (P values), summed in row order; the last workgroup of
+// each group of kGroup blocks adds up its group's shares in block order.  The
+// direction launch adds up the group sums.
 
 template <int PREC, int P>
 __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
@@ -1171,20 +1193,17 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
     constexpr int NE = P * P + P;       // (AD)^T R_new, then diag(R_new^T R_new)
     __shared__ double al[P * P];
     __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
-    __shared__ double mine[NE], tot[NE];
+    __shared__ double mine[NE], gsum[NE];
     __shared__ double gscr[kWG];
-    __shared__ double Lsh[P * P], rinv[P], wsh[P * P];
-    __shared__ int ish[8];
+    __shared__ int ish[4];
     DevState* st = a.st;
     if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = tid % RB, j = tid / RB;
     const int64_t i = (int64_t)tile * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
+    if (tile == 0 && tid == 0) st->dir_pending = 1;
     if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
-    const StepState0 s0 = read_state0(st);
     TV* X = static_cast<TV*>(a.X);
     TV* R = static_cast<TV*>(a.R);
     const double x0 = X[o];
@@ -1216,68 +1235,7 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
         mine[e] = s;
     }
     __syncthreads();
-    if (!grid_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, tot, &ish[0], gscr, tile, ntiles)) return;
-
-    // ---- last workgroup: stop test, beta, step count
-    const unsigned mask = s0.mask;
-    if (tid < P * P) {
-        const int x = tid / P, y = tid - (tid / P) * P;
-        Lsh[tid] = st->L[x * kMaxP + y];
-    }
-    __syncthreads();
-    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
-    if (wave == 0) {
-        double q = INFINITY;
-        double bad = 0.0;
-        if (lane < P && ((mask >> lane) & 1u)) {
-            const double nr = sqrt(tot[P * P + lane]);
-            st->norms[lane] = nr;
-            if (!isfinite(nr)) bad = 1.0;
-            q = nr / s0.nb;
-        }
-        if (lane < P) {
-            gscr[lane] = q;
-            gscr[32 + lane] = bad;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane == 0) {
-            double mn = INFINITY, anybad = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < P; ++jj) {
-                mn = fmin(mn, gscr[jj]);
-                anybad += gscr[32 + jj];
-            }
-            const int it = s0.iter + 1;
-            st->minres = mn;
-            st->iter = it;
-            // the stop rule at the top of the next step, as the loop of Alg. 4 reads it
-            if (anybad > 0.0) fail_state(st, -2);
-            else if (mn <= s0.tol) st->done = RECUR_CONV;
-            else if (it >= s0.maxit) st->done = MAXIT;
-            st->dir_pending = 1;
-        }
-    }
-    __syncthreads();
-    if (wave != 0 || lane >= P) return;
-    // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
-    const int c = lane;
-    const bool ac = (mask >> c) & 1u;
-    if constexpr (P <= 8) {
-        double w[P];
-#pragma unroll
-        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-        col_chol_solve<P>(Lsh, rinv, w);
-#pragma unroll
-        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = w[x];
-    } else {
-#pragma unroll 1
-        for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-        col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
-#pragma unroll 1
-        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = wsh[x * P + c];
-    }
+    (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
 }
 
 template <int PREC, int P>
@@ -1285,50 +1243,142 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
     upd_tile<PREC, P>(a, blockIdx.x, gridDim.x);
 }
 
-// ============================================= k_dir: D = R + D beta
+// ====================== k_dir: stop test, beta = -G^{-1} (AD)^T R_new, D = R_new + D beta
 //
-// The direction update of the step the update launch finished (dir_pending), with
-// the update's row tiling: masked to the active agents.
+// Runs when the update launch of this block step ran (dir_pending).  Every
+// workgroup adds up the update's group sums in group order, and so holds the
+// same totals, bit for bit; from them it solves beta (Alg. 2, with the factor of G
+// that the A.D launch kept) and updates the D rows of its block (masked to the
+// active agents).  Workgroup 0 also ends the step in the state: the stop test on the
+// new residual norms (Alg. 4: smallest agent residual relative to ||b||), beta,
+// and the step count.
 template <int PREC, int P>
-__device__ __forceinline__ void dir_tile(const UpdArgs& a, const int tile) {
+__device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const int ngrp) {
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
+    constexpr int NE = P * P + P;
+    __shared__ double tot[NE];
     __shared__ double be[P * P];
+    __shared__ double Lsh[P * P], rinv[P], wsh[P * P];
+    __shared__ double lred[64];
     __shared__ double dt[RB * P];
-    const DevState* st = a.st;
-    if (!st->dir_pending) return;
+    DevState* st = a.st;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = tid % RB, j = tid / RB;
-    const int64_t i = (int64_t)tile * RB + r;
+    const int64_t i = (int64_t)blk * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
-    if (tid < P * P) be[tid] = st->beta[(tid / P) * kMaxP + (tid % P)];
-    const unsigned msk = st->mask;
+    // (loads only before the flag is tested: nothing is written unless it is set)
+    const int pending = st->dir_pending;
+    const unsigned mask = st->mask;
     TV* D = static_cast<TV*>(a.D);
-    double sd = double(static_cast<const TV*>(a.R)[o]);
-    dt[r * P + j] = D[o];
+    const double rv = double(static_cast<const TV*>(a.R)[o]);
+    const double dv = double(D[o]);
+    const double lv = tid < P * P ? st->L[(tid / P) * kMaxP + (tid % P)] : 0.0;
+    // totals of the update's products: its group sums added in group order (the
+    // loads of up to 32 groups in flight together)
+    double tv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = tid + h * kWG;
+        if (e < NE) {
+            double s = 0.0;
+            for (int g0 = 0; g0 < ngrp; g0 += kGroup) {
+                double v[kGroup];
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t) v[t] = (g0 + t < ngrp) ? a.red.l2[(int64_t)(g0 + t) * NE + e] : 0.0;
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t)
+                    if (g0 + t < ngrp) s += v[t];
+            }
+            tv[h] = s;
+        }
+    }
+    if (!pending) return;
+    dt[r * P + j] = dv;
+    if (tid < P * P) Lsh[tid] = lv;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (tid + h * kWG < NE) tot[tid + h * kWG] = tv[h];
     __syncthreads();
+    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+    __syncthreads();
+    if (wave == 0 && lane < P) {
+        // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
+        const int c = lane;
+        const bool ac = (mask >> c) & 1u;
+        if constexpr (P <= 8) {
+            double w[P];
+#pragma unroll
+            for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+            col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+            for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
+        } else {
+#pragma unroll 1
+            for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+            col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
+#pragma unroll 1
+            for (int x = 0; x < P; ++x) be[x * P + c] = wsh[x * P + c];
+        }
+    }
+    __syncthreads();
+    double sd = rv;
 #pragma unroll
     for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
-    D[o] = ((msk >> j) & 1u) ? TV(sd) : TV(0);
+    D[o] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+    if (blk != 0 || wave != 0) return;
+    // ---- workgroup 0: the step's report and the stop rule at the top of the next step
+    double q = INFINITY, bad = 0.0;
+    if (lane < P && ((mask >> lane) & 1u)) {
+        const double nr = sqrt(tot[P * P + lane]);
+        st->norms[lane] = nr;
+        if (!isfinite(nr)) bad = 1.0;
+        q = nr / st->nb;
+    }
+    if (lane < P) {
+        lred[lane] = q;
+        lred[32 + lane] = bad;
+#pragma unroll
+        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + lane] = be[x * P + lane];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane == 0) {
+        double mn = INFINITY, anybad = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < P; ++jj) {
+            mn = fmin(mn, lred[jj]);
+            anybad += lred[32 + jj];
+        }
+        const int it = st->iter + 1;
+        st->minres = mn;
+        st->iter = it;
+        if (anybad > 0.0) fail_state(st, -2);
+        else if (mn <= st->tol) st->done = RECUR_CONV;
+        else if (it >= st->maxit) st->done = MAXIT;
+    }
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir(UpdArgs a) {
-    dir_tile<PREC, P>(a, blockIdx.x);
+    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P) + kGroup - 1) / kGroup);
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    upd_tile<PREC, P>(a, it.y, a.n_pad / (kWG / P));
+    upd_tile<PREC, P>(a, it.y, upd_blocks(a.n_pad, P));
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    dir_tile<PREC, P>(a, it.y);
+    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P) + kGroup - 1) / kGroup);
 }
 
 // ============================================ k_res: T = B - Y, norms, restart

@@ -180,12 +180,12 @@ int ad_fit_rows(int prec, int P, int cw, int nw) { return ad_cw_fit(prec, P, cw)
 
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(upd_blocks(a.n_pad, P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int PREC, int P>
 static hipError_t launch_dir_t(const UpdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(a.n_pad / (kWG / P)), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(upd_blocks(a.n_pad, P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int P>
