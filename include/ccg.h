@@ -153,6 +153,27 @@ ccg_status ccg_solve(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
                      const double *b, double *X, int64_t ldx, double tol, int maxit,
                      const ccg_opts *opts, ccg_info *info);
 
+/* Allocation-free FP64 solve, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, tight serving loops, harnesses that forbid it): the
+ * same solve as ccg_solve with CCG_FP64 and CCG_NO_GRAPH, bit for bit, with its
+ * whole workspace (vector blocks, reduction scratch, device state) in a device
+ * array of the library, 64 MiB per GPU, that each GPU holds from ccg_create until
+ * the process ends.  The call allocates nothing: no hipMalloc / hipFree, no graph,
+ * no event.  The caller passes device pointers; A must have 16-byte aligned columns
+ * (A aligned to 16 bytes, lda even).  opts may select only CCG_FP64 (prec),
+ * rank_tau and graph_k (the round length between host polls of the state); the
+ * flags CCG_HOST_PTRS, CCG_PROFILE, CCG_PROFILE_SAMPLED, CCG_SYM_AD and
+ * CCG_ESCALATE, another precision or unaligned columns give CCG_ERR_ARG.  A size
+ * whose workspace exceeds the array (vector blocks of n_pad * P elements, n_pad = n
+ * rounded up to 512 and P = p rounded up to a power of two, plus the reduction
+ * scratch: n up to 65536 at p <= 8, up to 32768 at p = 16) gives CCG_ERR_NOMEM
+ * with nothing launched.  Every call on a GPU, from any context
+ * on it, uses that GPU's one array and clears it first: calls that overlap in time
+ * on one GPU (other threads, other streams) race and must not be made. */
+ccg_status ccg_solve_noalloc(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
+                             const double *b, double *X, int64_t ldx, double tol, int maxit,
+                             const ccg_opts *opts, ccg_info *info);
+
 /* Run exactly ksteps block steps of FP64 cCG from X (no stop test) and report each
  * step's alpha and beta (ksteps x p x p; step k at offset k*p*p, element (r, c) at
  * r + c*p, i.e. column-major; X[:,c] += sum_r D[:,r] alpha[r,c]) and the final

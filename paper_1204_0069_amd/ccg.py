@@ -63,7 +63,7 @@ class Problem(ctypes.Structure):
 _lib = None
 
 # Entry points declared in include/ccg.h (kept in sync by tests/test_abi.py).
-EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_debug_step",
+EXPORTS = ("ccg_create", "ccg_destroy", "ccg_last_error", "ccg_solve", "ccg_solve_noalloc", "ccg_debug_step",
            "ccg_solve_batched", "ccg_submit", "ccg_poll", "ccg_wait", "ccg_cancel",
            "ccg_convert_matrix", "ccg_tune_ad", "ccg_stream_probe", "ccg_kernel_time")
 
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
                               ctypes.c_double, ctypes.c_int, ctypes.POINTER(Opts),
                               ctypes.POINTER(Info)]
     lib.ccg_solve.restype = ctypes.c_int
+    lib.ccg_solve_noalloc.argtypes = lib.ccg_solve.argtypes
+    lib.ccg_solve_noalloc.restype = ctypes.c_int
     lib.ccg_debug_step.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64,
                                    ctypes.c_int, ctypes.POINTER(Opts), dp, dp, dp, dp]
     lib.ccg_debug_step.restype = ctypes.c_int
@@ -264,6 +266,30 @@ class Context:
             raise self._err(st)
         del keep
         return Xt.t(), info.as_dict()
+
+    def solve_noalloc(self, A: torch.Tensor, b: torch.Tensor, X: torch.Tensor, tol: float,
+                      maxit: int, raise_on_error: bool = True, **opts):
+        """ccg_solve_noalloc: the FP64 solve with its workspace in the library's device
+        scratch array (no device allocation inside the call).  X is the p x n
+        contiguous tensor that holds the column-major n x p agents: X0 in, the final
+        agents out (updated in place).  A must be a contiguous float64 matrix with an
+        even leading dimension.  Returns the info dict."""
+        n = A.shape[0]
+        if A.dtype != torch.float64 or not (A.is_contiguous() or A.t().is_contiguous()):
+            raise ValueError("A must be a contiguous float64 matrix")
+        if X.dim() != 2 or X.shape[1] != n or not X.is_contiguous() or X.dtype != torch.float64:
+            raise ValueError("X must be a contiguous float64 p x n tensor (column-major n x p)")
+        if b.dim() != 1 or b.shape[0] != n or not b.is_contiguous() or b.dtype != torch.float64:
+            raise ValueError("b must be a contiguous float64 vector of length n")
+        o = make_opts(**opts)
+        info = Info()
+        torch.cuda.synchronize(A.device)
+        st = self.lib.ccg_solve_noalloc(self.h, n, X.shape[0], A.data_ptr(), n, b.data_ptr(),
+                                        X.data_ptr(), n, float(tol), int(maxit), ctypes.byref(o),
+                                        ctypes.byref(info))
+        if st < 0 and raise_on_error:
+            raise self._err(st)
+        return info.as_dict()
 
     def debug_step(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, ksteps: int,
                    rank_tau: float = 0.0, flags: int = 0):

@@ -371,13 +371,12 @@ void stage_in(ccg_ctx* c, Staged& sg, int n, int p, const double*& A, int64_t& l
     ldx = n;
 }
 
-// Plain FP64 cCG on device buffers; fills info.
-ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+// Plain FP64 cCG on device buffers in the context's workspace c->ws (sized for n
+// and p, rows n..n_pad of AD zero); A has 16-byte aligned columns.  Fills info.
+ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda, const double* b,
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
-    const double* Ause = aligned_matrix(c, n, A, lda);
     Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, profile_every(o), (o.flags & CCG_SYM_AD) != 0};
-    ensure_workspace(c, n, P, s.sym_ad);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -450,6 +449,25 @@ ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, co
     info.rel_res_max = mx;
     info.bytes_A = bytes;
     return st;
+}
+
+ccg_status solve_fp64(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+                      double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
+    const double* Ause = aligned_matrix(c, n, A, lda);
+    ensure_workspace(c, n, pad_agents(p), (o.flags & CCG_SYM_AD) != 0);
+    return fp64_steps(c, n, p, Ause, lda, b, X, ldx, tol, maxit, o, info);
+}
+
+// Runs f with the context's workspace replaced by w (restored on every exit).
+template <class F>
+ccg_status with_workspace(ccg_ctx* c, const Workspace& w, F&& f) {
+    struct Swap {
+        ccg_ctx* c;
+        Workspace saved;
+        ~Swap() { c->ws = saved; }
+    } sw{c, c->ws};
+    c->ws = w;
+    return f();
 }
 
 // Low-precision copy of A for the FP32 / BF16x2 modes, converted on every solve (the
@@ -642,6 +660,13 @@ ccg_status ccg_create(ccg_ctx** ctx, int device, size_t hbm_budget_bytes, void* 
         return CCG_ERR_DEVICE;
     }
     std::memset(c->st_host, 0, sizeof(DevState));
+    // the device address of this device's scratch array (ccg_solve_noalloc)
+    void* sp = nullptr;
+    if (scratch_setup(device, &sp) == hipSuccess) {
+        c->scratch = sp;
+    } else {
+        (void)hipGetLastError();
+    }
     *ctx = c;
     return CCG_OK;
 }
@@ -729,6 +754,58 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
                                     hipMemcpyDeviceToHost, c->stream));
             HIP_OK(hipStreamSynchronize(c->stream));
         }
+        local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return r;
+    });
+    local.status = st;
+    if (info) *info = local;
+    return st;
+}
+
+ccg_status ccg_solve_noalloc(ccg_ctx* c, int n, int p, const double* A, int64_t lda, const double* b,
+                             double* X, int64_t ldx, double tol, int maxit, const ccg_opts* opts,
+                             ccg_info* info) {
+    ccg_info local;
+    std::memset(&local, 0, sizeof local);
+    local.best_agent = -1;
+    ccg_status st = guarded(c, [&]() -> ccg_status {
+        check_common(n, p, A, lda, b, X, ldx);
+        if (!(tol > 0.0)) throw CcgError{CCG_ERR_ARG, "tol must be > 0"};
+        if (maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
+        ccg_opts o = fill_defaults(opts);
+        if (o.prec != CCG_FP64)
+            throw CcgError{CCG_ERR_ARG, "the allocation-free solve runs CCG_FP64 only"};
+        if (o.flags & (CCG_HOST_PTRS | CCG_PROFILE | CCG_PROFILE_SAMPLED | CCG_SYM_AD | CCG_ESCALATE))
+            throw CcgError{CCG_ERR_ARG, "the allocation-free solve takes device pointers and no "
+                                        "CCG_HOST_PTRS, CCG_PROFILE*, CCG_SYM_AD or CCG_ESCALATE"};
+        if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || (lda * sizeof(double)) % 16 != 0)
+            throw CcgError{CCG_ERR_ARG, "the allocation-free solve needs 16-byte aligned columns of A "
+                                        "(A aligned, lda even)"};
+        if (!c->scratch) throw CcgError{CCG_ERR_DEVICE, "the device scratch array is not available"};
+        const int P = pad_agents(p);
+        const int n_pad = (int)round_up(n, kRowAlign);
+        Workspace w;
+        const size_t need = carve(w, nullptr, n, n_pad, P);
+        if (need > scratch_bytes())
+            throw CcgError{CCG_ERR_NOMEM, "the allocation-free solve needs " + std::to_string(need) +
+                                              " bytes of scratch for n = " + std::to_string(n) + ", p = " +
+                                              std::to_string(p) + "; the maximum is " +
+                                              std::to_string(scratch_bytes())};
+        carve(w, static_cast<char*>(c->scratch), n, n_pad, P);
+        w.base = nullptr;      // not owned: never freed
+        w.bytes = need;
+        w.n = n;
+        w.n_pad = n_pad;
+        w.P = P;
+        // the scratch keeps the last call's contents: padded rows, tickets and state
+        // start from zero
+        HIP_OK(launch_zero(c->scratch, need, c->stream));
+        o.flags |= CCG_NO_GRAPH;
+        const auto t0 = std::chrono::steady_clock::now();
+        const ccg_status r = with_workspace(c, w, [&]() {
+            return fp64_steps(c, n, p, A, lda, b, X, ldx, tol, maxit, o, local);
+        });
+        local.prec_final = CCG_FP64;
         local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return r;
     });

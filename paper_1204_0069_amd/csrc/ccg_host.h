@@ -47,6 +47,10 @@ int row_workgroups(int n_pad, int P);
 hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_sym_units(int nb, int2* units, hipStream_t s);
+// allocation-free solve: the device scratch array (ccg_noalloc.hip)
+size_t scratch_bytes();
+hipError_t scratch_setup(int device, void** ptr);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // The symmetric A.D pass (upper block triangle of A, CCG_SYM_AD) serves FP64 block
 // steps of single systems with P <= kSymMaxP and n >= kSymMinN; smaller systems
@@ -169,6 +173,9 @@ struct ccg_ctx {
     size_t lowA_bytes = 0;
     // continuous-batching service (ccg_submit), started on first use
     ccg::host::Server* server = nullptr;
+    // device address of this device's scratch array (ccg_solve_noalloc), taken at
+    // ccg_create; nullptr if the lookup failed
+    void* scratch = nullptr;
 };
 
 
