@@ -129,6 +129,20 @@ template <bool NT> struct Loader<PREC_BF16X2, NT> {
 };
 
 // ------------------------------------------------------ cross-workgroup reduction
+//
+// Partial sums pass between workgroups (on MI355X across XCDs, whose L2 caches are
+// not coherent with each other) through agent-scope atomic stores and loads, which
+// gfx950 issues with the sc1 bit: the stores write through to the device-coherent
+// level and the loads read from it, so no L2 writeback or invalidate is needed.  The
+// order is: every thread's partial stores, then s_waitcnt vmcnt(0) (each store
+// acknowledged by the coherent level), then the ticket fetch-add; the workgroup that
+// draws the last ticket waits for the add's return (the ticket value, which decides
+// whether it sums at all) before it issues the loads.  The asm statement is a
+// compiler barrier for every memory access, and the loads depend on the ticket
+// through the workgroup barrier that broadcasts it, so neither the compiler nor the
+// memory pipeline can move a load before the add or a store after it.  (An
+// acquire-release ticket would add buffer_wbl2 and buffer_inv of the XCD's whole L2
+// to every workgroup of every launch, which is what this scheme avoids.)
 
 __device__ __forceinline__ void st_agent(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
