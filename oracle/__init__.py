@@ -10,7 +10,9 @@ is built twice: ``libccg_oracle.so`` computes in FP64 (double), the oracle prope
 ``libccg_oracle_ld.so`` runs the same code with every internal value in x86 80-bit
 extended precision (``long double``, 11 more significand bits), as a reference for
 how far an FP64 trajectory of the method has drifted from the method's own
-trajectory (``extended()``).  Both take and return FP64 arrays.
+trajectory (``extended()``); ``libccg_oracle_omp.so`` is the FP64 oracle with its
+products with A split by rows over OpenMP threads, bit-identical to the first, for
+timing it on all host cores (``all_cores()``).  All take and return FP64 arrays.
 
 Entry points
 ------------
@@ -35,6 +37,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ccg_oracle.c")
 _LIB = os.path.join(_HERE, "libccg_oracle.so")
 _LIB_LD = os.path.join(_HERE, "libccg_oracle_ld.so")
+_LIB_OMP = os.path.join(_HERE, "libccg_oracle_omp.so")
 
 # gcc flags: baseline x86-64 (the library built here also runs on other hosts),
 # no FMA contraction so every product and sum rounds as written.
@@ -48,7 +51,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("p_final", ctypes.c_int),
                 ("best_agent", ctypes.c_int), ("deflations", ctypes.c_int),
-                ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double)]
+                ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double),
+                ("reinflations", ctypes.c_int)]
 
 
 def _build_one(path: str, extra, force: bool) -> None:
@@ -63,11 +67,13 @@ def build(force: bool = True) -> str:
     (80-bit extended) next to it (gcc)."""
     _build_one(_LIB, [], force)
     _build_one(_LIB_LD, ["-DORC_REAL=long double"], force)
+    _build_one(_LIB_OMP, ["-fopenmp", "-DORC_ROWS=1024"], force)
     return _LIB
 
 
 _lib = None
 _lib_ld = None
+_lib_omp = None
 
 
 def bind(path: str):
@@ -77,8 +83,10 @@ def bind(path: str):
     lib.oracle_ccg.restype = ctypes.c_int
     lib.oracle_ccg.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp, dp,
                                ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                               ctypes.c_double, ctypes.c_int, dp, dp, dp, dp,
+                               ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int,
                                ctypes.POINTER(_Info)]
+    lib.oracle_splitmix64.restype = None
+    lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_residual.restype = ctypes.c_int
     lib.oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp,
                                     dp, ctypes.c_int, dp]
@@ -92,6 +100,18 @@ def _load():
             build(force=True)
         _lib = bind(_LIB)
     return _lib
+
+
+def all_cores():
+    """The FP64 oracle built with OpenMP: the products with A split by rows over the
+    threads (OMP_NUM_THREADS), with the same bits as the one-thread build (pass as
+    ``lib``).  For timing the oracle on every host core."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib_omp = bind(_LIB_OMP)
+    return _lib_omp
 
 
 def extended():
@@ -115,10 +135,12 @@ def _colmajor(A):
 
 
 def ccg(A, b, X0, tol: float, maxit: int, tau: float = 1e-14, trace_k: int = 0,
-        want_rd: bool = False, lib=None) -> dict:
+        want_rd: bool = False, lib=None, reinflate_max: int = 0) -> dict:
     """Run the oracle cCG.  A (n x n), b (n,), X0 (n x p) are numpy arrays.
 
-    tol == 0 runs exactly ``maxit`` steps with no stop test.  Returns a dict with
+    tol == 0 runs exactly ``maxit`` steps with no stop test.  reinflate_max > 0 lets
+    up to that many rank drops re-inflate the dropped agents (see oracle_ccg in the C
+    source) instead of going on with fewer.  Returns a dict with
     X, info fields, and (if asked) alphas/betas of shape (trace_k, p, p) indexed
     [step, row, col] and the final R, D (n x p).  ``lib`` selects another build of
     the same source (see ``bind``).
@@ -140,10 +162,11 @@ def ccg(A, b, X0, tol: float, maxit: int, tau: float = 1e-14, trace_k: int = 0,
     info = _Info()
     lib.oracle_ccg(n, p, _ptr(A), n, _ptr(b), _ptr(X), n, float(tol), int(maxit),
                    float(tau), int(trace_k), _ptr(ta), _ptr(tb), _ptr(Rout), _ptr(Dout),
-                   ctypes.byref(info))
+                   int(reinflate_max), ctypes.byref(info))
     out = {"X": X, "status": info.status, "status_name": ORC_STATUS.get(info.status, "?"),
            "iters": info.iters, "restarts": info.restarts, "p_final": info.p_final,
            "best_agent": info.best_agent, "deflations": info.deflations,
+           "reinflations": info.reinflations,
            "rel_res": info.rel_res, "rel_res_max": info.rel_res_max}
     if trace_k > 0:
         # stored column-major per step: element (r, c) at r + c*p
@@ -153,6 +176,14 @@ def ccg(A, b, X0, tol: float, maxit: int, tau: float = 1e-14, trace_k: int = 0,
         out["R"] = Rout.reshape(p, n).T.copy()
         out["D"] = Dout.reshape(p, n).T.copy()
     return out
+
+
+def splitmix64(state: int, count: int) -> list:
+    """The first ``count`` outputs of the oracle's SplitMix64 generator from ``state``."""
+    lib = _load()
+    out = (ctypes.c_uint64 * count)()
+    lib.oracle_splitmix64(ctypes.c_uint64(state), int(count), out)
+    return [int(v) for v in out]
 
 
 def residual(A, b, X) -> np.ndarray:

@@ -50,6 +50,7 @@
  * interface stays FP64 (inputs are exact in either type, outputs are rounded to
  * double once at the end).
  */
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <tgmath.h>
@@ -58,6 +59,14 @@
 #define ORC_REAL double
 #endif
 typedef ORC_REAL real;
+
+/* Rows per share of the products with A.  The default build takes every row in one
+ * share.  The all-cores build (-fopenmp -DORC_ROWS=1024) hands shares of rows to
+ * threads; each element is still the same sum over k in the same order, so every
+ * build gives the same bits. */
+#ifndef ORC_ROWS
+#define ORC_ROWS 2147483647
+#endif
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -77,7 +86,38 @@ typedef struct {
     int deflations;   /* rank-drop events */
     double rel_res;   /* min_j ||b - A x_j|| / ||b|| over all agents */
     double rel_res_max;
+    int reinflations; /* re-inflation events (see oracle_ccg) */
 } orc_info;
+
+/* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the state advances by the golden-ratio increment and
+ * each output is the state passed through the published 64-bit finaliser. */
+static uint64_t splitmix64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* The first `count` outputs from `state` (exported so that the tests can hold the
+ * generator to its published values). */
+void oracle_splitmix64(uint64_t state, int count, uint64_t *out)
+{
+    for (int i = 0; i < count; ++i) out[i] = splitmix64_next(&state);
+}
+
+/* Entry i of the draw of re-inflation event e for agent j: the (i+1)-th SplitMix64
+ * output from the state 0x1204 << 48 ^ e << 32 ^ j, mapped to [-1, 1) by its top 53
+ * bits (exactly: 2 * (z >> 11) * 2^-53 - 1). */
+static uint64_t reinflate_state(int e, int j)
+{
+    return (0x1204ull << 48) ^ ((uint64_t)e << 32) ^ (uint64_t)j;
+}
+static double unit_draw(uint64_t z)
+{
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
 
 /* ---------- plain dense helpers ---------- */
 
@@ -88,11 +128,15 @@ static void matmat(int n, int m, const double *A, int lda, const real *M, int ld
 {
     for (int j = 0; j < m; ++j) {
         real *y = Y + (size_t)j * ldy;
-        for (int i = 0; i < n; ++i) y[i] = 0.0;
-        for (int k = 0; k < n; ++k) {
-            real mkj = M[k + (size_t)j * ldm];
-            const double *a = A + (size_t)k * lda;
-            for (int i = 0; i < n; ++i) y[i] += a[i] * mkj;
+#pragma omp parallel for schedule(static)
+        for (int i0 = 0; i0 < n; i0 += (ORC_ROWS < n ? ORC_ROWS : n)) {
+            int i1 = n - i0 > ORC_ROWS ? i0 + ORC_ROWS : n;
+            for (int i = i0; i < i1; ++i) y[i] = 0.0;
+            for (int k = 0; k < n; ++k) {
+                real mkj = M[k + (size_t)j * ldm];
+                const double *a = A + (size_t)k * lda;
+                for (int i = i0; i < i1; ++i) y[i] += a[i] * mkj;
+            }
         }
     }
 }
@@ -214,13 +258,17 @@ static void explicit_residual(int n, const double *A, int lda, const double *b,
     for (int c = 0; c < m; ++c) {
         real *t = T + (size_t)c * n;
         const real *x = X + (size_t)cols[c] * ldx;
-        for (int i = 0; i < n; ++i) t[i] = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double *a = A + (size_t)k * lda;
-            real xk = x[k];
-            for (int i = 0; i < n; ++i) t[i] += a[i] * xk;
+#pragma omp parallel for schedule(static)
+        for (int i0 = 0; i0 < n; i0 += (ORC_ROWS < n ? ORC_ROWS : n)) {
+            int i1 = n - i0 > ORC_ROWS ? i0 + ORC_ROWS : n;
+            for (int i = i0; i < i1; ++i) t[i] = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double *a = A + (size_t)k * lda;
+                real xk = x[k];
+                for (int i = i0; i < i1; ++i) t[i] += a[i] * xk;
+            }
+            for (int i = i0; i < i1; ++i) t[i] = b[i] - t[i];
         }
-        for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
     }
 }
 
@@ -256,11 +304,17 @@ int oracle_residual(int n, int p, const double *A, int lda, const double *b,
  *   steps into trace_alpha / trace_beta (each trace_k * p * p doubles).
  *   R_out, D_out (nullable): final R and D (n x p, leading dimension n; zero
  *   columns for dropped agents).
+ *   reinflate_max: re-inflation events allowed (0: plain Alg. 3).  A policy beyond
+ *   the paper: when the rank step would drop some (not all) agents, each agent outside the kept set
+ *   J instead restarts from the iterate of the active agent with the smallest
+ *   residual norm (ties: lowest index) plus a uniform draw in [-1, 1) per entry
+ *   (SplitMix64, see reinflate_state), and the whole block restarts as Alg. 2 starts
+ *   (R = B - A X, D = R, all p agents active), in place of that step.
  */
 int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
                double *X, int ldx, double tol, int maxit, double tau,
                int trace_k, double *trace_alpha, double *trace_beta,
-               double *R_out, double *D_out, orc_info *info)
+               double *R_out, double *D_out, int reinflate_max, orc_info *info)
 {
     orc_info inf;
     memset(&inf, 0, sizeof inf);
@@ -346,6 +400,31 @@ int oracle_ccg(int n, int p, const double *A, int lda, const double *b,
         int r = rank_select(m, G, tau, keep);
         if (r == -2) { status = ORC_ERR_NONFINITE; goto done; }
         if (r == -1) { status = ORC_ERR_NOT_SPD; goto done; }
+        if (r > 0 && r < m && inf.reinflations < reinflate_max) {
+            /* re-inflation (see above) in place of this step */
+            int best = act[0];
+            real bestn = norm2(n, R);
+            for (int c = 1; c < m; ++c) {
+                real v = norm2(n, R + (size_t)c * n);
+                if (v < bestn) { bestn = v; best = act[c]; }
+            }
+            int kept[ORC_MAXP];
+            for (int j = 0; j < p; ++j) kept[j] = 0;
+            for (int q = 0; q < r; ++q) kept[act[keep[q]]] = 1;
+            real *xb = T;                        /* the best iterate, copied first */
+            for (int i = 0; i < n; ++i) xb[i] = Xr[i + (size_t)best * n];
+            for (int j = 0; j < p; ++j) {
+                if (kept[j]) continue;
+                uint64_t st = reinflate_state(inf.reinflations, j);
+                for (int i = 0; i < n; ++i) Xr[i + (size_t)j * n] = xb[i] + unit_draw(splitmix64_next(&st));
+            }
+            m = p;
+            for (int j = 0; j < p; ++j) act[j] = j;
+            explicit_residual(n, A, lda, b, Xr, n, m, act, R);
+            memcpy(D, R, (size_t)n * m * sizeof(real));
+            inf.reinflations++;
+            continue;
+        }
         if (r < m) {
             inf.deflations++;
             /* restrict columns and the p x p blocks to keep[] */

@@ -38,6 +38,11 @@ MUTANTS = {
                         "inf.restarts++;"),
     "restart_keeps_R": ("memcpy(R, T, (size_t)n * m * sizeof(real));", ";"),
     "restart_not_counted": ("inf.restarts++;", ";"),
+    # re-inflation (a policy beyond Alg. 3): the restart after it must be a fresh start
+    "reinflate_keeps_D": ("memcpy(D, R, (size_t)n * m * sizeof(real));\n            inf.reinflations++;",
+                          "inf.reinflations++;"),
+    "reinflate_without_draw": ("Xr[i + (size_t)j * n] = xb[i] + unit_draw(splitmix64_next(&st));",
+                               "Xr[i + (size_t)j * n] = xb[i];"),
 }
 
 
@@ -94,6 +99,20 @@ def _battery(lib):
               and np.array_equal(fresh["X"], full["X"]))
     if not ok:
         failed.append("restart")
+    # re-inflation: the dropped duplicate agent restarts from the best start plus the
+    # SplitMix64 draw, and the run is a fresh start from those agents
+    A, b, X0 = ci.small_system()
+    X0 = X0.copy()
+    X0[:, 2] = X0[:, 0]
+    full = oracle.ccg(A, b, X0, tol=1e-11, maxit=5000, reinflate_max=1, lib=lib)
+    best = int(np.argmin(np.linalg.norm(b[:, None] - A @ X0, axis=0)))
+    z = np.array(oracle.splitmix64((0x1204 << 48) ^ 2, A.shape[0]), dtype=np.uint64)
+    X1 = X0.copy()
+    X1[:, 2] = X0[:, best] + ((z >> np.uint64(11)).astype(np.float64) * (2.0 / 2 ** 53) - 1.0)
+    fresh = oracle.ccg(A, b, X1, tol=1e-11, maxit=5000, lib=lib)
+    if not (full["reinflations"] == 1 and full["p_final"] == 3 and fresh["iters"] == full["iters"]
+            and np.array_equal(fresh["X"], full["X"])):
+        failed.append("reinflate")
     return failed
 
 

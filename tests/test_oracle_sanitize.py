@@ -27,6 +27,7 @@ def test_oracle_is_clean_under_asan_ubsan(tmp_path, real):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stderr
     lines = [l for l in r.stdout.splitlines() if l.startswith("n=")]
-    assert len(lines) == 5
+    assert len(lines) == 6
     assert any("restarts=0" not in l for l in lines)        # a restart ran
     assert any("deflations=0" not in l for l in lines)      # the rank step dropped agents
+    assert any("reinflations=0" not in l for l in lines)    # and agents were re-inflated
