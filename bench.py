@@ -21,6 +21,14 @@ Other modes (their own JSON line each):
                   log-uniform in [128, 16384], p = 4, kappa log-uniform in
                   [1e2, 1e6], precision drawn from fp64 / fp32 / bf16x2, A in pinned
                   host memory, upload inside the latency); reports p50/p99 latency.
+  --mode paper    the paper's own experiment (Sec. 5): A = U diag(lam) U^T with U
+                  Haar, lam uniform in [1, 1e6], b and the starting points uniform in
+                  [-10, 10], n from 1000 to 25000, cCG with p = 3 against CG (p = 1)
+                  from the first of the three starting points, stop when the best
+                  agent's residual norm is <= 1e-3, read both as absolute and as
+                  relative to ||b||; reports the mean block steps per n, their ratio
+                  CG / cCG and the log-log slope of cCG's steps against n, beside the
+                  paper's Table 4 ratios and Fig. 5 slope.
 """
 from __future__ import annotations
 
@@ -55,12 +63,21 @@ def parse():
                     help="time every A.D launch (all block steps launched directly)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "paper"])
+    ap.add_argument("--paper-sizes", default="1000,1500,2000,2500,3000,3500,4000,4500,5000,6000,7000,8000,"
+                                             "9000,10000,11000,12000,13000,14000,15000,16000,17000,18000,"
+                                             "19000,20000,21000,22000,23000,24000,25000",
+                    help="paper mode: system sizes")
+    ap.add_argument("--paper-ics", type=int, default=0,
+                    help="paper mode: starting blocks per size (0: 20 below n = 5000, 10 from there, "
+                         "as in Sec. 5)")
+    ap.add_argument("--paper-tol-sweep", action="store_true",
+                    help="paper mode: only the tolerance sweep of Table 2 (n = 8000, tol 1e-3 .. 1e-9)")
     ap.add_argument("--kind", default="spectrum", choices=["spectrum", "gram"],
                     help="single mode: Q diag(lam) Q^T, or M^T M / n + sigma I")
     ap.add_argument("--count", type=int, default=1024, help="batched mode: systems per batch")
-    ap.add_argument("--requests", type=int, default=48, help="served mode: timed requests")
-    ap.add_argument("--pool", type=int, default=12, help="served mode: distinct matrices")
+    ap.add_argument("--requests", type=int, default=1000, help="served mode: timed requests")
+    ap.add_argument("--pool", type=int, default=64, help="served mode: distinct matrices")
     ap.add_argument("--n-hi", type=int, default=16384, help="served mode: largest n")
     ap.add_argument("--rate-frac", type=float, default=0.5,
                     help="served mode: arrival rate as a fraction of the closed-loop rate")
@@ -75,6 +92,8 @@ def parse():
     ap.add_argument("--single-fp64", action="store_true",
                     help="batched mode: time the plain FP64 baseline instead (every 8th system, one "
                          "ccg_solve at a time)")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="single mode: skip the n = 32768 sub-record (FP64 and BF16x2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (3 times) and exit: the "
                          "known-size kernel that scales hardware byte counters")
@@ -144,6 +163,8 @@ def main():
         return run_batched(args)
     if args.mode == "served":
         return run_served(args)
+    if args.mode == "paper":
+        return run_paper(args)
 
     import numpy as np
     import torch
@@ -164,85 +185,27 @@ def main():
 
     ctx = Context(0)
     flags = 0 if args.no_profile else (CCG_PROFILE if args.profile_all else CCG_PROFILE_SAMPLED)
-    infos = []
-    for _ in range(args.warmup):
-        ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
-    ctx.kernel_time(reset=True)
-
-    # Timed region: the A.D launches of every 4th round of block steps bracketed by
-    # HIP events on the library's stream (launched directly); the other rounds replay
-    # the captured graph (CCG_PROFILE_SAMPLED; --profile-all times every launch).
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        X, info = ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=flags)
-        lat.append(time.perf_counter() - s0)
-        infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    total = t1 - t0
-    ad_ms, ad_launches = ctx.kernel_time(reset=True)
-
-    # Second region, same solves through captured graphs and no events (context only).
-    graph_rate = None
-    if not args.no_profile:
-        ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec)
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec)
-        torch.cuda.synchronize()
-        graph_rate = args.steps / (time.perf_counter() - g0)
-
-    iters = [i["iters"] for i in infos]
-    # explicit residual of the last result, independent of the library (rocBLAS)
-    T = b[:, None] - A @ X
-    rel = (torch.linalg.norm(T, dim=0) / torch.linalg.norm(b)).cpu().numpy()
-
-    s_a = {"fp64": 8, "fp32": 4, "bf16x2": 4}[args.prec]
-    s_v = 8 if args.prec == "fp64" else 4
-    bytes_per_launch = n * n * s_a + 2 * n * p * s_v
+    t = time_solves(ctx, A, b, X0, args.tol, args.prec, args.steps, args.warmup, flags,
+                    graph_rate=not args.no_profile)
+    iters = [i["iters"] for i in t["infos"]]
     roofline = None
-    if ad_launches > 0:
-        avg_s = ad_ms / 1e3 / ad_launches
-        achieved = bytes_per_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": recorded_traffic(n, p, args.prec), "traffic_unit": "B/launch",
-                    "kernel": "k_ad",
-                    "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
-                    "timed": ("every A.D launch" if args.profile_all else
-                              "the A.D launches of every 4th round of block steps"),
-                    "bytes_per_launch": bytes_per_launch}
+    if t["ad_launches"] > 0:
+        roofline = roofline_record(n, p, args.prec, t["ad_ms"], t["ad_launches"], args.profile_all)
+    error = result_errors(ctx, A, b, X0, t["X"], t["infos"][-1], args.tol, args.prec)
 
     cpu = None
     if args.cpu_sample_steps > 0:
-        import oracle
-        An = A.cpu().numpy()
-        bn = b.cpu().numpy()
-        Xn = X0.cpu().numpy()
-        c0 = time.perf_counter()
-        oracle.ccg(An, bn, Xn, tol=0.0, maxit=args.cpu_sample_steps)
-        c1 = time.perf_counter()
-        per_step = (c1 - c0) / (args.cpu_sample_steps + 1)   # + the initial residual pass
-        steps_per_solve = float(np.mean(iters)) + 2.0        # + initial and confirming residuals
-        cpu = {"value": round(1.0 / (per_step * steps_per_solve), 6), "unit": "solves/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_sample_steps} block steps of the same n={n}, p={p} system "
-                         f"({c1 - c0:.1f} s, {per_step:.3f} s per A stream); solves/s = 1 / "
-                         f"(s per step x {steps_per_solve:.0f} steps per solve)"}
+        cpu = cpu_baseline(A, b, X0, args.cpu_sample_steps, float(np.mean(iters)))
 
-    lat_ms = np.array(lat) * 1e3
+    lat_ms = np.array(t["lat"]) * 1e3
     out = {
         "metric": METRIC,
-        "value": round(args.steps / total, 4),
+        "value": round(args.steps / t["total"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(total / args.steps * 1e3, 3),
+        "ms_per_step": round(t["total"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -255,16 +218,288 @@ def main():
                    "kind": args.kind},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3)},
-        "solves_per_s_graph": None if graph_rate is None else round(graph_rate, 4),
+        "solves_per_s_graph": None if t["graph_rate"] is None else round(t["graph_rate"], 4),
         "iters_per_solve": float(np.mean(iters)),
-        "restarts": int(sum(i["restarts"] for i in infos)),
-        "rel_res": float(rel.min()),
-        "status": infos[-1]["status_name"],
+        "restarts": int(sum(i["restarts"] for i in t["infos"])),
+        "rel_res": t["rel_res"],
+        "status": t["infos"][-1]["status_name"],
+        "error": error,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    del A, b, X0, t
+    torch.cuda.empty_cache()
+    if args.c3 and args.n == 8192 and args.kind == "spectrum" and args.prec == "fp64":
+        out["c3"] = run_c3(ctx, args)
     print(json.dumps(out))
     ctx.close()
+
+
+def time_solves(ctx, A, b, X0, tol, prec, steps, warmup, flags, graph_rate=True):
+    """Warm-up solves, then `steps` timed solves (A.D launches timed per `flags`), then
+    optionally the same solves from captured graphs with no events.  Inputs resident
+    in HBM; the timed region is bracketed by device synchronisations."""
+    import torch
+    for _ in range(warmup):
+        ctx.solve(A, b, X0, tol, 100000, prec=prec, flags=flags)
+    ctx.kernel_time(reset=True)
+    lat, infos = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        X, info = ctx.solve(A, b, X0, tol, 100000, prec=prec, flags=flags)
+        lat.append(time.perf_counter() - s0)
+        infos.append(info)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ad_ms, ad_launches = ctx.kernel_time(reset=True)
+    g_rate = None
+    if graph_rate and flags:
+        ctx.solve(A, b, X0, tol, 100000, prec=prec)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.solve(A, b, X0, tol, 100000, prec=prec)
+        torch.cuda.synchronize()
+        g_rate = steps / (time.perf_counter() - g0)
+    # explicit residual of the last result, independent of the library (rocBLAS)
+    T = b[:, None] - A @ X
+    rel = (torch.linalg.norm(T, dim=0) / torch.linalg.norm(b)).cpu().numpy()
+    return {"lat": lat, "infos": infos, "total": total, "ad_ms": ad_ms, "ad_launches": ad_launches,
+            "graph_rate": g_rate, "X": X, "rel_res": float(rel.min())}
+
+
+def roofline_record(n, p, prec, ad_ms, ad_launches, every):
+    s_a = {"fp64": 8, "fp32": 4, "bf16x2": 4}[prec]
+    s_v = 8 if prec == "fp64" else 4
+    bytes_per_launch = n * n * s_a + 2 * n * p * s_v
+    avg_s = ad_ms / 1e3 / ad_launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(n, p, prec), "traffic_unit": "B/launch",
+            "kernel": "k_ad",
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": ad_launches,
+            "timed": ("every A.D launch" if every else
+                      "the A.D launches of every 4th round of block steps"),
+            "bytes_per_launch": bytes_per_launch}
+
+
+def result_errors(ctx, A, b, X0, X, info, tol, prec):
+    """Per-result error of the reported (best) agent: against x* = A^{-1} b (FP64 LU,
+    rocSOLVER through torch), and for the low-precision modes against the result of
+    the same solve in FP64 mode (one more, untimed, solve)."""
+    import torch
+    xs = torch.linalg.solve(A, b)
+    j = info["best_agent"]
+    nx = torch.linalg.norm(xs)
+    err = {"vs_xstar": float(torch.linalg.norm(X[:, j] - xs) / nx),
+           "vs_xstar_max_agent": float((torch.linalg.norm(X - xs[:, None], dim=0) / nx).max()),
+           "xstar": "torch.linalg.solve (FP64 LU)"}
+    if prec != "fp64":
+        X64, i64 = ctx.solve(A, b, X0, tol, 100000)
+        err["vs_fp64_mode"] = float(torch.linalg.norm(X[:, j] - X64[:, i64["best_agent"]]) /
+                                    torch.linalg.norm(X64[:, i64["best_agent"]]))
+    del xs
+    return err
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(A, b, X0, sample_steps, steps_per_gpu_solve):
+    """The oracle on the host on `sample_steps` block steps of the same system: one
+    thread (the oracle as built for the tests), and the OpenMP build of the same
+    source (the same bits) on the threads OMP_NUM_THREADS allows."""
+    import numpy as np
+
+    import oracle
+    An = A.cpu().numpy()
+    bn = b.cpu().numpy()
+    Xn = X0.cpu().numpy()
+    n, p = Xn.shape
+    steps_per_solve = steps_per_gpu_solve + 2.0          # + initial and confirming residuals
+    rec = {}
+    for name, lib in (("one", None), ("all", oracle.all_cores())):
+        c0 = time.perf_counter()
+        oracle.ccg(An, bn, Xn, tol=0.0, maxit=sample_steps, lib=lib)
+        c1 = time.perf_counter()
+        per_step = (c1 - c0) / (sample_steps + 1)          # + the initial residual pass
+        rec[name] = (per_step, c1 - c0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    per1, t1 = rec["one"]
+    perA, tA = rec["all"]
+    return {"value": round(1.0 / (per1 * steps_per_solve), 6), "unit": "solves/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{sample_steps} block steps of the same n={n}, p={p} system "
+                      f"({t1:.1f} s, {per1:.3f} s per A stream); solves/s = 1 / "
+                      f"(s per step x {steps_per_solve:.0f} steps per solve)",
+            "all_cores": {"value": round(1.0 / (perA * steps_per_solve), 6), "unit": "solves/s",
+                          "cores": threads,
+                          "sample": f"the same {sample_steps} steps, OpenMP build over rows "
+                                    f"({tA:.1f} s, {perA:.3f} s per A stream)"},
+            "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
+
+
+def run_c3(ctx, args):
+    """n = 32768, p = 8, A = M^T M / n + sigma I (cond 1e3), tol 1e-10: FP64 and
+    BF16 hi+lo with FP64 refinement (the largest single-GPU workload; A is 8 GiB, far
+    beyond the 256 MB MALL)."""
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import CCG_PROFILE_SAMPLED
+    dev = "cuda:0"
+    n, p, kappa = 32768, 8, 1e3
+    A = ci.spd_gram(n, kappa, ci.item_seed("G", ci.BASE_SEED, base=n), device=dev)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", ci.BASE_SEED, base=n)), device=dev)
+    X0 = torch.as_tensor(ci.normal_block(n, p, ci.item_seed("X0", ci.BASE_SEED, base=n)), device=dev)
+    torch.cuda.synchronize()
+    rec = {"workload": f"dense SPD n={n}, M^T M/n + sigma I (cond {kappa:g}), p={p}, tol {args.tol:g}"}
+    xs = torch.linalg.solve(A, b)
+    X64 = None
+    for prec in ("fp64", "bf16x2"):
+        t = time_solves(ctx, A, b, X0, args.tol, prec, 2, 1, CCG_PROFILE_SAMPLED, graph_rate=False)
+        info = t["infos"][-1]
+        j = info["best_agent"]
+        r = {"solves_per_s": round(2 / t["total"], 4), "iters_per_solve": float(np.mean([i["iters"] for i in t["infos"]])),
+             "rel_res": t["rel_res"], "status": info["status_name"],
+             "error_vs_xstar": float(torch.linalg.norm(t["X"][:, j] - xs) / torch.linalg.norm(xs))}
+        if t["ad_launches"] > 0:
+            rr = roofline_record(n, p, prec, t["ad_ms"], t["ad_launches"], False)
+            r["ad_frac"] = rr["frac"]
+            r["ad_avg_launch_us"] = rr["avg_launch_us"]
+        if prec == "fp64":
+            X64 = t["X"][:, j].clone()
+        else:
+            r["error_vs_fp64_mode"] = float(torch.linalg.norm(t["X"][:, j] - X64) / torch.linalg.norm(X64))
+        rec[prec] = r
+        print(json.dumps({"progress": "c3", "prec": prec}), file=sys.stderr, flush=True)
+    del A, b, X0, xs
+    torch.cuda.empty_cache()
+    return rec
+
+
+# The paper's numbers for its own experiment (Sec. 5; Core2Quad, p = 3, tol 1e-3):
+# Table 4's iteration ratios CG / cCG per n, the mean of that column, and the slope
+# of the least-squares line through log(cCG iterations) against log(n) of Fig. 5.
+PAPER_TABLE4_RATIO = {1000: 1.79, 1500: 1.40, 2000: 1.66, 2500: 1.46, 3000: 1.57, 3500: 1.67, 4000: 1.55,
+                      4500: 1.65, 5000: 1.78, 6000: 1.34, 7000: 1.33, 8000: 1.24, 9000: 1.80, 10000: 1.96,
+                      11000: 1.61, 12000: 1.74, 13000: 1.51, 14000: 1.79, 15000: 1.85, 16000: 1.58,
+                      17000: 1.53, 18000: 1.65, 19000: 1.71, 20000: 1.76, 21000: 1.67, 22000: 1.62,
+                      23000: 1.38, 24000: 1.69, 25000: 1.81}
+PAPER_MEAN_RATIO = 1.62
+PAPER_ITER_SLOPE = 0.501
+# Table 2: n = 8000, 10 starting points: (tol, CG iterations, cCG iterations)
+PAPER_TABLE2 = [(1e-3, 372.2, 299.7), (1e-4, 414.0, 319.4), (1e-5, 444.9, 335.0), (1e-6, 476.8, 352.7),
+                (1e-7, 510.7, 336.2), (1e-8, 538.4, 373.5), (1e-9, 559.7, 381.2)]
+
+
+def _paper_system(n, dev):
+    """A, b of the paper's experiment at size n (Sec. 5): U Haar, lam uniform in
+    [1, 1e6], b uniform in [-10, 10]; seeded by n."""
+    import torch
+
+    import ccg_inputs as ci
+    A = ci.spd_spectrum(n, 1e6, ci.item_seed("P", ci.BASE_SEED, base=n), lam_dist="uniform", device=dev)
+    b = torch.as_tensor(ci.uniform_block(n, 0, ci.item_seed("pb", ci.BASE_SEED, base=n)), device=dev)
+    return A, b
+
+
+def _paper_start(n, ic, dev):
+    import torch
+
+    import ccg_inputs as ci
+    return torch.as_tensor(ci.uniform_block(n, 3, ci.item_seed("pX0", ic, base=n)), device=dev)
+
+
+def run_paper(args):
+    """The paper's experiment on the GPU: block steps of cCG (p = 3) and CG (p = 1) to
+    tol 1e-3, both readings of the tolerance.  One JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_1204_0069_amd import Context
+
+    dev = "cuda:0"
+    ctx = Context(0)
+    if args.paper_tol_sweep:
+        n = 8000
+        A, b = _paper_system(n, dev)
+        nb = float(torch.linalg.norm(b))
+        rows = []
+        for tol, cg_paper, ccg_paper in PAPER_TABLE2:
+            row = {"tol": tol, "paper_cg_iters": cg_paper, "paper_ccg_iters": ccg_paper}
+            for reading, t in (("abs", tol / nb), ("rel", tol)):
+                it3, it1 = [], []
+                for ic in range(10):
+                    X0 = _paper_start(n, ic, dev)
+                    it3.append(ctx.solve(A, b, X0, t, 10 ** 6)[1]["iters"])
+                    it1.append(ctx.solve(A, b, X0[:, :1], t, 10 ** 6)[1]["iters"])
+                row[reading] = {"cg_iters": float(np.mean(it1)), "ccg_iters": float(np.mean(it3)),
+                                "ratio": float(np.mean(it1) / np.mean(it3))}
+            rows.append(row)
+            print(json.dumps({"progress": "tol", "tol": tol}), file=sys.stderr, flush=True)
+        ctx.close()
+        print(json.dumps({"mode": "paper_tol_sweep", "n": n, "kappa": 1e6, "starts": 10, "rows": rows,
+                          "paper": "Table 2 (Sec. 5): mean iterations of CG and cCG (p = 3) at n = 8000"}))
+        return
+    sizes = [int(v) for v in args.paper_sizes.split(",") if v]
+    rows = []
+    t_all = time.perf_counter()
+    for n in sizes:
+        A, b = _paper_system(n, dev)
+        nb = float(torch.linalg.norm(b))
+        ics = args.paper_ics or (20 if n < 5000 else 10)
+        row = {"n": n, "starts": ics, "paper_ratio": PAPER_TABLE4_RATIO.get(n)}
+        for reading, t in (("abs", 1e-3 / nb), ("rel", 1e-3)):
+            it3, it1, s3, s1 = [], [], [], []
+            for ic in range(ics):
+                X0 = _paper_start(n, ic, dev)
+                c0 = time.perf_counter()
+                _, i3 = ctx.solve(A, b, X0, t, 10 ** 6)
+                c1 = time.perf_counter()
+                _, i1 = ctx.solve(A, b, X0[:, :1], t, 10 ** 6)
+                c2 = time.perf_counter()
+                assert i3["status"] == 0 and i1["status"] == 0, (i3, i1)
+                it3.append(i3["iters"])
+                it1.append(i1["iters"])
+                s3.append(c1 - c0)
+                s1.append(c2 - c1)
+            row[reading] = {"ccg_iters": float(np.mean(it3)), "cg_iters": float(np.mean(it1)),
+                            "ratio": float(np.mean(it1) / np.mean(it3)),
+                            "ccg_ms": round(1e3 * float(np.mean(s3)), 2),
+                            "cg_ms": round(1e3 * float(np.mean(s1)), 2)}
+        rows.append(row)
+        print(json.dumps({"progress": n, "abs_ratio": round(row["abs"]["ratio"], 3),
+                          "rel_ratio": round(row["rel"]["ratio"], 3)}), file=sys.stderr, flush=True)
+        del A, b
+        torch.cuda.empty_cache()
+    ctx.close()
+    ln = np.log([r["n"] for r in rows])
+    summary = {}
+    for reading in ("abs", "rel"):
+        it = np.log([r[reading]["ccg_iters"] for r in rows])
+        slope = float(np.polyfit(ln, it, 1)[0]) if len(rows) > 1 else None
+        ratios = [r[reading]["ratio"] for r in rows]
+        summary[reading] = {"mean_ratio": round(float(np.mean(ratios)), 3),
+                            "iters_slope": None if slope is None else round(slope, 3)}
+    print(json.dumps({"mode": "paper", "workload": "A = U diag(lam) U^T, U Haar, lam uniform in [1, 1e6], "
+                                                   "b and X0 uniform in [-10, 10], p = 3 against p = 1, tol 1e-3",
+                      "rows": rows, "summary": summary,
+                      "paper": {"mean_ratio": PAPER_MEAN_RATIO, "iters_slope": PAPER_ITER_SLOPE,
+                                "source": "Table 4 (iteration ratio per n) and Fig. 5 (slope), Sec. 5"},
+                      "seconds": round(time.perf_counter() - t_all, 1)}))
 
 
 def _oracle_rate(samples):
@@ -435,6 +670,8 @@ def run_served(args):
         A = ci.spd_spectrum(n, kappa, ci.item_seed("served-A", i), device=dev)
         pool.append((n, kappa, A.cpu().pin_memory()))
         del A
+        if (i + 1) % 8 == 0:
+            print(json.dumps({"progress": "pool", "matrices": i + 1}), file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
     precs = ("fp64", "fp32", "bf16x2")
     total_req = args.requests + 8
@@ -469,7 +706,13 @@ def run_served(args):
         if arrivals[j] > now:
             time.sleep(arrivals[j] - now)
         tickets.append(submit(8 + j))
-    results = [ctx.wait(t) for t in tickets]
+        if (j + 1) % 100 == 0:
+            print(json.dumps({"progress": "submitted", "requests": j + 1}), file=sys.stderr, flush=True)
+    results = []
+    for j, t in enumerate(tickets):
+        results.append(ctx.wait(t))
+        if (j + 1) % 200 == 0:
+            print(json.dumps({"progress": "finished", "requests": j + 1}), file=sys.stderr, flush=True)
     total = time.perf_counter() - t0
     infos = [r[1] for r in results]
     lat = np.array([i["seconds"] for i in infos]) * 1e3
@@ -520,8 +763,10 @@ def run_served(args):
         # the same requests submitted all at once: the service's saturated rate
         c0 = time.perf_counter()
         ts = [submit(8 + j) for j in range(args.requests)]
-        for t in ts:
+        for j, t in enumerate(ts):
             ctx.wait(t)
+            if (j + 1) % 200 == 0:
+                print(json.dumps({"progress": "closed loop", "requests": j + 1}), file=sys.stderr, flush=True)
         out["closed_loop_solves_per_s"] = round(args.requests / (time.perf_counter() - c0), 4)
     ctx.close()
     if args.compare_fp64:
@@ -561,6 +806,8 @@ def _served_fp64_comparison(ctx, pool, reqs, arrivals, args, lat_served):
         service.append(time.perf_counter() - t0)
         ok += info["status"] == 0
         del A
+        if len(service) % 200 == 0:
+            print(json.dumps({"progress": "plain fp64", "requests": len(service)}), file=sys.stderr, flush=True)
     finish = 0.0
     lat = []
     for a, s in zip(arrivals, service):

@@ -215,3 +215,34 @@ def test_both_lanes_equal_single_solves_under_a_shared_budget(gpu_ctx):
         _same(s_, b_)
         _same(s_, v_)
     assert all(b_[1]["status"] == 0 for b_ in batched)
+
+
+def test_served_mix_with_a_poisoned_request(gpu_ctx):
+    """One request in a served mix has a NaN in b.  It ends with CCG_ERR_NONFINITE
+    (its first residual norm is not finite) and leaves the service running; every
+    other request, submitted before and after it, still equals its single solve."""
+    print("case served mix with a NaN right-hand side", flush=True)
+    systems = _systems([(300, 3, 1e3, "fp64"), (500, 4, 1e3, "fp32"), (900, 2, 1e2, "bf16x2"),
+                        (4100, 2, 1e2, "fp64"), (700, 8, 1e3, "fp64")], seed=1700)
+    singles = [_single(gpu_ctx, sy) for sy in systems]
+    bad = dict(systems[0])
+    bb = bad["b"].clone()
+    bb[17] = float("nan")
+    bad["b"] = bb
+    ctx = Context(0)
+    try:
+        t = [ctx.submit(sy["A"], sy["b"], sy["X0"], sy["tol"], sy["maxit"], prec=sy["prec"])
+             for sy in systems[:2]]
+        tb = ctx.submit(bad["A"], bad["b"], bad["X0"], bad["tol"], bad["maxit"], prec=bad["prec"])
+        t += [ctx.submit(sy["A"], sy["b"], sy["X0"], sy["tol"], sy["maxit"], prec=sy["prec"])
+              for sy in systems[2:]]
+        outs = [ctx.wait(x) for x in t]
+        Xb, ib = ctx.wait(tb)
+        for s, o in zip(singles, outs):
+            _same(s, o)
+        assert ib["status"] == -2, ib
+        # the service still takes requests
+        again = ctx.wait(ctx.submit(systems[4]["A"], systems[4]["b"], systems[4]["X0"], 1e-10, 20000))
+        _same(singles[4], again)
+    finally:
+        ctx.close()
