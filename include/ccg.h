@@ -72,6 +72,10 @@ typedef enum {
                                       the other rounds run from the captured graphs */
 #define CCG_SYM_AD    0x20u  /* FP64 block steps with p <= 8 and n >= 1024 form A D from
                                  the upper block triangle of A only (see ccg_solve) */
+#define CCG_REINFLATE 0x40u  /* ccg_solve, CCG_FP64: when the rank step would drop some
+                                 agents (Alg. 3), re-inflate them instead, at most
+                                 opts->max_reinflate times (see ccg_solve); batched and
+                                 served problems with it get CCG_ERR_ARG */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
@@ -87,7 +91,8 @@ typedef struct {
                             residual's decay predicts many more steps (FP64 solves and
                             the inner solves of the refinement modes) */
     unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_PROFILE_SAMPLED |
-                            CCG_ESCALATE */
+                            CCG_ESCALATE | CCG_SYM_AD | CCG_REINFLATE */
+    int max_reinflate;   /* CCG_REINFLATE: re-inflation events allowed (default 3) */
 } ccg_opts;
 
 /* Per-solve report. */
@@ -105,6 +110,7 @@ typedef struct {
     double rel_res_max;  /* max_j of the same */
     double seconds;      /* wall time of the solve inside the library */
     double bytes_A;      /* algorithmic bytes of A streamed (all precisions) */
+    int reinflations;    /* re-inflation events (CCG_REINFLATE) */
 } ccg_info;
 
 typedef struct ccg_ctx ccg_ctx;
@@ -128,7 +134,16 @@ const char *ccg_last_error(const ccg_ctx *ctx);
  * FP64 block steps of a system with n >= 1024 and p <= 8 form A D from the blocks
  * A(I, J), I <= J, of 128 x 128 (A(I, J) D(J) for rows I and A(I, J)^T D(I) for
  * rows J), so they read only the upper block triangle; the explicit residuals and
- * the other modes read all of A.  (On MI355X this pass is slower than streaming
+ * the other modes read all of A.
+ *
+ * With CCG_REINFLATE (CCG_FP64 only; a policy beyond the paper, off by default), a
+ * rank step that would drop some but not all agents instead re-inflates them, up to
+ * opts->max_reinflate times: each agent outside the kept set J restarts from the
+ * iterate of the active agent with the smallest residual norm (ties: lowest index)
+ * plus d, d_i = 2 (z_i >> 11) 2^-53 - 1 with z_i the (i+1)-th output of SplitMix64
+ * (Steele, Lea, Flood 2014) from the state 0x1204 << 48 ^ e << 32 ^ j (e: the event,
+ * from 0; j: the agent), and all p agents restart from R = D = B - A X (the start of
+ * Alg. 2) in place of that step.  info->reinflations counts the events.  (On MI355X this pass is slower than streaming
  * all of A at the sizes measured; it is kept for comparison.)
  *
  * opts->prec selects how A is streamed:
@@ -162,8 +177,8 @@ ccg_status ccg_solve(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
  * no event.  The caller passes device pointers; A must have 16-byte aligned columns
  * (A aligned to 16 bytes, lda even).  opts may select only CCG_FP64 (prec),
  * rank_tau and graph_k (the round length between host polls of the state); the
- * flags CCG_HOST_PTRS, CCG_PROFILE, CCG_PROFILE_SAMPLED, CCG_SYM_AD and
- * CCG_ESCALATE, another precision or unaligned columns give CCG_ERR_ARG.  A size
+ * flags CCG_HOST_PTRS, CCG_PROFILE, CCG_PROFILE_SAMPLED, CCG_SYM_AD, CCG_ESCALATE
+ * and CCG_REINFLATE, another precision or unaligned columns give CCG_ERR_ARG.  A size
  * whose workspace exceeds the array (vector blocks of n_pad * P elements, n_pad = n
  * rounded up to 512 and P = p rounded up to a power of two, plus the reduction
  * scratch: n up to 65536 at p <= 8, up to 32768 at p = 16) gives CCG_ERR_NOMEM

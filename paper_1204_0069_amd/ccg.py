@@ -19,6 +19,7 @@ CCG_PROFILE = 0x4
 CCG_PROFILE_SAMPLED = 0x10
 CCG_ESCALATE = 0x8
 CCG_SYM_AD = 0x20
+CCG_REINFLATE = 0x40
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 
@@ -36,7 +37,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxit", ctypes.c_int), ("max_refine", ctypes.c_int),
                 ("rank_tau", ctypes.c_double), ("graph_k", ctypes.c_int),
-                ("flags", ctypes.c_uint)]
+                ("flags", ctypes.c_uint), ("max_reinflate", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -45,7 +46,8 @@ class Info(ctypes.Structure):
                 ("p_final", ctypes.c_int), ("best_agent", ctypes.c_int),
                 ("deflations", ctypes.c_int), ("prec_final", ctypes.c_int),
                 ("rel_res", ctypes.c_double), ("rel_res_max", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("bytes_A", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("bytes_A", ctypes.c_double),
+                ("reinflations", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -136,9 +138,10 @@ def _colmajor_matrix(A: torch.Tensor):
 
 
 def make_opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_refine=0, rank_tau=0.0,
-              graph_k=0, flags=0) -> Opts:
+              graph_k=0, flags=0, max_reinflate=0) -> Opts:
     return Opts(PREC[prec] if isinstance(prec, str) else int(prec), float(inner_tol),
-                int(inner_maxit), int(max_refine), float(rank_tau), int(graph_k), int(flags))
+                int(inner_maxit), int(max_refine), float(rank_tau), int(graph_k), int(flags),
+                int(max_reinflate))
 
 
 def _problem(A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, tol: float, maxit: int, opts: dict):

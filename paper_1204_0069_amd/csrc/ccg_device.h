@@ -27,7 +27,10 @@ __host__ __device__ inline int upd_blocks(int n_pad, int P) { return n_pad / (25
 // epilogues and by the residual kernel; read by every kernel at entry.
 // OUTER: a refinement residual found the solve unfinished; the host starts the
 // next inner solve (block steps only run while done == RUNNING).
-enum Done : int { RUNNING = 0, RECUR_CONV = 1, FINISHED = 2, MAXIT = 3, FAILED = 4, OUTER = 5 };
+// REINFLATE: the rank step would drop agents and re-inflation is allowed: the step
+// stopped before alpha, mask holds the kept set J and prev_mask the agents active
+// before it; the host re-inflates the others and restarts the block.
+enum Done : int { RUNNING = 0, RECUR_CONV = 1, FINISHED = 2, MAXIT = 3, FAILED = 4, OUTER = 5, REINFLATE = 6 };
 
 struct DevState {
     int done;          // Done code; kernels are no-ops while done != RUNNING
@@ -41,6 +44,8 @@ struct DevState {
     int dir_pending;   // 1: the update launch of this block step ran, and the direction
                        // launch completes the step (cleared by every A.D launch)
     int ad_streams;    // A.D launches that streamed A in block steps (for byte counts)
+    int reinflate_left;  // re-inflation events still allowed (CCG_REINFLATE)
+    unsigned prev_mask;  // REINFLATE: the agents active before the rank step
     double nb;         // ||b||_2 (for a refinement inner solve: 1, columns are scaled)
     double tol;        // relative stop tolerance on min_j ||R_j|| / nb
     double tau;        // rank threshold on the scaled pivots

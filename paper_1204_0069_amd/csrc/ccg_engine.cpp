@@ -294,6 +294,8 @@ class Engine {
         if (pr.maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
         if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)
             throw CcgError{CCG_ERR_ARG, "unknown precision mode"};
+        if (o.flags & CCG_REINFLATE)
+            throw CcgError{CCG_ERR_ARG, "CCG_REINFLATE is a ccg_solve option (not batched or served)"};
         if (free_slots_.empty()) return false;
         const size_t need = footprint(pr, o);
         char* mem = arena_.alloc(need);

@@ -390,16 +390,18 @@ ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda,
     h.tol = tol;
     h.tau = o.rank_tau;
     h.nb = 1.0;
+    h.reinflate_left = (o.flags & CCG_REINFLATE) ? o.max_reinflate : 0;
     write_state(c);
     enqueue_residual(s, RES_INIT, 1);
     read_state(c);
+    int reinflations = 0;
     const double bytes_iter = (double)n * n * sizeof(double);   // an explicit residual
     const double bytes_step = step_bytes_A(s);
     double bytes = bytes_iter;   // the initial residual
     const bool use_graph = !(o.flags & CCG_NO_GRAPH);
     const int gk = o.graph_k > 0 ? o.graph_k : 16;
     int round_k = gk;
-    while (h.done == RUNNING || h.done == RECUR_CONV) {
+    while (h.done == RUNNING || h.done == RECUR_CONV || h.done == REINFLATE) {
         if (h.done == RUNNING) {
             const int left = maxit - h.iter;
             const int k = left > 0 ? round_k : 1;   // steps past maxit are no-ops
@@ -420,6 +422,24 @@ ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda,
             read_state(c);
             bytes += bytes_iter;
         }
+        if (h.done == REINFLATE) {
+            // the agents outside the kept set restart from the best of those active
+            // before the rank step, plus the draw; then the whole block restarts
+            const unsigned all = (1u << p) - 1u;
+            const unsigned dropped = all & ~h.mask;
+            int best = -1;
+            for (int j = 0; j < p; ++j)
+                if (((h.prev_mask >> j) & 1u) && (best < 0 || h.norms[j] < h.norms[best])) best = j;
+            HIP_OK(launch_reinflate(n, w.n_pad, p, dropped, best, reinflations, w.Xr, c->stream));
+            ++reinflations;
+            h.done = RUNNING;
+            set_all_agents(h, p);
+            h.reinflate_left -= 1;
+            write_state(c);
+            enqueue_residual(s, RES_INIT, 0);
+            read_state(c);
+            bytes += bytes_iter;
+        }
     }
     if (h.done == MAXIT) {
         enqueue_residual(s, RES_FINAL, 0);
@@ -437,6 +457,7 @@ ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda,
     info.restarts = h.restarts;
     info.p_final = h.m;
     info.deflations = h.deflations;
+    info.reinflations = reinflations;
     double mn = INFINITY, mx = 0.0;
     int best = -1;
     for (int j = 0; j < p; ++j) {
@@ -709,6 +730,7 @@ void accumulate_stage(ccg_info& acc, const ccg_info& stage) {
     acc.refinements += stage.refinements;
     acc.restarts += stage.restarts;
     acc.deflations += stage.deflations;
+    acc.reinflations += stage.reinflations;
     acc.bytes_A += stage.bytes_A;
 }
 
@@ -724,6 +746,8 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
         const ccg_opts o = fill_defaults(opts);
         if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)
             throw CcgError{CCG_ERR_ARG, "unknown precision mode"};
+        if ((o.flags & CCG_REINFLATE) && (o.prec != CCG_FP64 || (o.flags & CCG_ESCALATE)))
+            throw CcgError{CCG_ERR_ARG, "CCG_REINFLATE runs with CCG_FP64 only"};
         const auto t0 = std::chrono::steady_clock::now();
         Staged sg;
         double* Xd = X;
@@ -748,6 +772,7 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
         local.refinements = acc.refinements;
         local.restarts = acc.restarts;
         local.deflations = acc.deflations;
+        local.reinflations = acc.reinflations;
         local.bytes_A = acc.bytes_A;
         if (o.flags & CCG_HOST_PTRS) {
             HIP_OK(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xd, sizeof(double) * n, sizeof(double) * n, p,
@@ -775,7 +800,8 @@ ccg_status ccg_solve_noalloc(ccg_ctx* c, int n, int p, const double* A, int64_t 
         ccg_opts o = fill_defaults(opts);
         if (o.prec != CCG_FP64)
             throw CcgError{CCG_ERR_ARG, "the allocation-free solve runs CCG_FP64 only"};
-        if (o.flags & (CCG_HOST_PTRS | CCG_PROFILE | CCG_PROFILE_SAMPLED | CCG_SYM_AD | CCG_ESCALATE))
+        if (o.flags & (CCG_HOST_PTRS | CCG_PROFILE | CCG_PROFILE_SAMPLED | CCG_SYM_AD | CCG_ESCALATE |
+                       CCG_REINFLATE))
             throw CcgError{CCG_ERR_ARG, "the allocation-free solve takes device pointers and no "
                                         "CCG_HOST_PTRS, CCG_PROFILE*, CCG_SYM_AD or CCG_ESCALATE"};
         if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || (lda * sizeof(double)) % 16 != 0)

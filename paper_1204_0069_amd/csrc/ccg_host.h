@@ -29,6 +29,8 @@ hipError_t launch_copy_cols(int n, const double* A, int64_t lda, double* B, int6
 hipError_t launch_convert(int prec, int n, const double* A, int64_t lda, void* hi, void* lo, int64_t ldb,
                           hipStream_t s);
 hipError_t launch_inner_init(const RefArgs& a, hipStream_t s);
+hipError_t launch_reinflate(int n, int n_pad, int p, unsigned dropped, int best, int event, double* Xr,
+                            hipStream_t s);
 hipError_t launch_refine_add(const RefArgs& a, hipStream_t s);
 hipError_t launch_ad_batch(int prec, int P, int cw, int nw, const AdArgs* sys, const int4* items, int nitems,
                            hipStream_t s);
@@ -244,6 +246,7 @@ inline ccg_opts fill_defaults(const ccg_opts* in) {
     if (o.max_refine <= 0) o.max_refine = 60;
     if (o.rank_tau <= 0.0) o.rank_tau = o.prec == CCG_FP64 ? 1e-14 : 1e-12;
     if (o.graph_k <= 0) o.graph_k = 16;
+    if (o.max_reinflate <= 0) o.max_reinflate = 3;
     return o;
 }
 

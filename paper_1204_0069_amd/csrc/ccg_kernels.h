@@ -657,6 +657,17 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
             if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
             return;
         }
+        if (r > 0 && r < m && st->reinflate_left > 0) {
+            // re-inflation instead of the drop: the host restarts the block
+            if (tid == 0) {
+                unsigned nm = 0u;
+                for (int q = 0; q < r; ++q) nm |= 1u << act[kp[q]];
+                st->prev_mask = mask;
+                st->mask = nm;
+                st->done = REINFLATE;
+            }
+            return;
+        }
         if (r < m) {
             if (tid == 0) {
                 unsigned nm = 0u;

@@ -157,6 +157,39 @@ __global__ void k_refine_add(RefArgs a) {
     if (s > 0.0) a.X[idx] = fma((double)static_cast<const float*>(a.E)[idx], s, a.X[idx]);
 }
 
+// ================================================== re-inflation of dropped agents
+//
+// X[:, j] = X[:, best] + d for every agent j in `dropped`, d_i = 2 (z_i >> 11) 2^-53 - 1
+// with z_i the (i+1)-th output of SplitMix64 (Steele, Lea, Flood 2014) from the state
+// 0x1204 << 48 ^ e << 32 ^ j: the generator's state after i+1 steps is the start
+// plus (i+1) golden-ratio increments, so each entry is drawn on its own.  Row i of
+// every column is handled by one thread, which reads X[i, best] before any write.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t state0, uint64_t k) {
+    uint64_t z = state0 + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_reinflate(int n, int n_pad, int p, unsigned dropped, int best, int event, double* Xr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xb = Xr[(int64_t)best * n_pad + i];
+    for (int j = 0; j < p; ++j) {
+        if (!((dropped >> j) & 1u)) continue;
+        const uint64_t s0 = (0x1204ull << 48) ^ ((uint64_t)event << 32) ^ (uint64_t)j;
+        const uint64_t z = splitmix64_at(s0, (uint64_t)i + 1);
+        const double d = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        Xr[(int64_t)j * n_pad + i] = xb + d;
+    }
+}
+
+hipError_t launch_reinflate(int n, int n_pad, int p, unsigned dropped, int best, int event, double* Xr,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_reinflate, dim3((n + 255) / 256), dim3(256), 0, s, n, n_pad, p, dropped, best, event, Xr);
+    return hipGetLastError();
+}
+
 // ================================================================== launchers
 
 // A columns per wave and waves per workgroup of the A.D tile for a system: the

@@ -417,3 +417,49 @@ def test_leading_dimension_larger_than_n(gpu_ctx, n, p, prec, flags, pad):
     assert i1["status"] == 0 and i2["status"] == 0
     assert i1["iters"] == i2["iters"] and torch.equal(X1, X2)
     assert torch.equal(big[:n, :n], _t(A)) and not big[n:, :].any() and not big[:, n:].any()
+
+
+# ------------------------------------------- re-inflation (a policy beyond Alg. 3)
+
+def test_reinflation_matches_oracle(gpu_ctx):
+    """Duplicate starting columns: the rank step at step 0 would drop agent 2; with
+    CCG_REINFLATE it restarts from the best start plus the SplitMix64 draw, and the
+    whole block restarts.  The run matches the oracle's re-inflating run: one step
+    (alpha, beta, X, R, D), and the whole solve at tol 1e-11 per agent column."""
+    from paper_1204_0069_amd import CCG_REINFLATE
+    A, b, X0 = ci.small_system()
+    X0 = X0.copy()
+    X0[:, 2] = X0[:, 0]
+    orc1 = oracle.ccg(A, b, X0, tol=0.0, maxit=1, trace_k=1, want_rd=True, reinflate_max=1)
+    X1, i1 = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-30, 1, raise_on_error=False, flags=CCG_REINFLATE,
+                           max_reinflate=1)
+    assert i1["status"] == 1 and i1["iters"] == 1 and i1["reinflations"] == 1
+    assert _rel(X1.cpu().numpy(), orc1["X"]) <= 1e-10
+    tol = 1e-11
+    orc = oracle.ccg(A, b, X0, tol=tol, maxit=5000, reinflate_max=1)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 5000, flags=CCG_REINFLATE, max_reinflate=1)
+    assert info["status"] == 0 and info["reinflations"] == orc["reinflations"] == 1
+    assert info["deflations"] == 0 and info["p_final"] == 3
+    assert abs(info["iters"] - orc["iters"]) <= max(3, 0.05 * orc["iters"])
+    same = oracle.ccg(A, b, X0, tol=0.0, maxit=info["iters"], reinflate_max=1)
+    Xg = X.cpu().numpy()
+    for j in range(3):
+        assert _rel(Xg[:, j], same["X"][:, j]) <= 1e-10, j
+    # without the flag the agent is dropped, as before
+    Xd, idf = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 5000)
+    assert idf["reinflations"] == 0 and idf["deflations"] == 1 and idf["p_final"] == 2
+
+
+def test_reinflation_budget_and_rejections(gpu_ctx):
+    from paper_1204_0069_amd import CCG_REINFLATE
+    A, b, X0 = ci.system(100, 8, 10.0, seed=3)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, flags=CCG_REINFLATE, max_reinflate=3)
+    assert info["status"] == 0 and 1 <= info["reinflations"] <= 3
+    T = oracle.residual(A, b, X.cpu().numpy())
+    assert (np.linalg.norm(T, axis=0) / np.linalg.norm(b)).min() <= 1e-10
+    # FP64 single solves only
+    _, bad = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 5000, raise_on_error=False, prec="fp32",
+                           flags=CCG_REINFLATE)
+    assert bad["status"] == -1
+    res = gpu_ctx.solve_batched([dict(A=_t(A), b=_t(b), X0=_t(X0), tol=1e-10, maxit=5000, flags=CCG_REINFLATE)])
+    assert res[0][1]["status"] == -1
