@@ -106,6 +106,22 @@ struct SymArgs {
 // Arguments of the update launch (X += D alpha, R -= AD alpha, and each tile's share
 // of (AD)^T R and diag(R^T R) of the new residual) and of the direction launch (the
 // totals of those shares, the stop test, beta, and D = R + D beta).
+// Arguments of the small-system tier (systems with n <= kSmallN and P <= kSmallMaxP):
+// one workgroup runs whole block steps of one system, several per launch.
+constexpr int kSmallN = 512;      // the tier's padded size (n_pad == 512)
+constexpr int kSmallMaxP = 8;
+constexpr int kSmallWG = 512;     // threads of the tier's workgroup
+struct SmallArgs {
+    const void* A;       // matrix streamed by the block steps (as AdArgs::A)
+    const void* A_lo;    // BF16 "lo" plane (bf16x2 only)
+    int64_t lda;
+    int n;
+    void* X;             // agent-major blocks of kSmallN rows (vector type)
+    void* R;
+    void* D;
+    DevState* st;
+};
+
 struct UpdArgs {
     int n_pad;
     void* X;             // agent-major blocks (vector type)

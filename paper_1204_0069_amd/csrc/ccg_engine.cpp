@@ -240,6 +240,7 @@ class Engine {
         HIP_OK(hipMalloc(&d_ad_, sizeof(AdArgs) * kSlots));
         HIP_OK(hipMalloc(&d_res_ad_, sizeof(AdArgs) * kSlots));
         HIP_OK(hipMalloc(&d_upd_, sizeof(UpdArgs) * kSlots));
+        HIP_OK(hipMalloc(&d_small_, sizeof(SmallArgs) * kSlots));
         HIP_OK(hipMalloc(&d_res_, sizeof(ResArgs) * kSlots));
         HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&h_states_), sizeof(DevState) * kSlots,
                              hipHostMallocDefault));
@@ -252,6 +253,7 @@ class Engine {
         (void)hipFree(d_ad_);
         (void)hipFree(d_res_ad_);
         (void)hipFree(d_upd_);
+        (void)hipFree(d_small_);
         (void)hipFree(d_res_);
         for (hipGraphExec_t g : class_graphs_) (void)hipGraphExecDestroy(g);
         for (hipStream_t cs : class_streams_) (void)hipStreamDestroy(cs);
@@ -310,6 +312,7 @@ class Engine {
         sy.prec = o.prec == CCG_FP64 ? PREC_F64 : (o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
         sy.cw_step = ad_cw(sy.prec, sy.P, pr.n);
         sy.nw_step = ad_nw(sy.prec, sy.P, pr.n);
+        if (small_tier(sy.P, (int)round_up(pr.n, kRowAlign))) sy.cw_step = sy.nw_step = 0;   // the tier's class
         sy.cw_res = ad_cw(PREC_F64, sy.P, pr.n);
         sy.nw_res = ad_nw(PREC_F64, sy.P, pr.n);
         sy.tol = pr.tol;
@@ -456,6 +459,16 @@ class Engine {
         HIP_OK(hipMemcpyAsync(d_ad_ + sy.slot, &ad, sizeof ad, hipMemcpyHostToDevice, s_));
         HIP_OK(hipMemcpyAsync(d_res_ad_ + sy.slot, &ra, sizeof ra, hipMemcpyHostToDevice, s_));
         HIP_OK(hipMemcpyAsync(d_upd_ + sy.slot, &u, sizeof u, hipMemcpyHostToDevice, s_));
+        SmallArgs sm{};
+        sm.A = ad.A;
+        sm.A_lo = ad.A_lo;
+        sm.lda = ad.lda;
+        sm.n = n;
+        sm.X = u.X;
+        sm.R = u.R;
+        sm.D = u.D;
+        sm.st = st;
+        HIP_OK(hipMemcpyAsync(d_small_ + sy.slot, &sm, sizeof sm, hipMemcpyHostToDevice, s_));
         HIP_OK(hipMemcpyAsync(d_res_ + sy.slot, &r, sizeof r, hipMemcpyHostToDevice, s_));
     }
 
@@ -506,6 +519,7 @@ class Engine {
         }
         sy.cw_step = ad_cw(sy.prec, sy.P, sy.n);
         sy.nw_step = ad_nw(sy.prec, sy.P, sy.n);
+        if (small_tier(sy.P, sy.w.n_pad)) sy.cw_step = sy.nw_step = 0;
         write_records(sy);
         start_stage(sy);
         items_dirty_ = true;
@@ -582,7 +596,7 @@ class Engine {
                 if (use_graph_) {
                     HIP_OK(hipGraphLaunch(class_graphs_[c], s_));
                 } else {
-                    for (int it = 0; it < k; ++it) enqueue_class_step(step_ranges_[c], s_);
+                    enqueue_class_round(step_ranges_[c], k, s_);
                 }
             }
         } else if (!step_ranges_.empty()) {
@@ -593,7 +607,7 @@ class Engine {
                 if (use_graph_) {
                     HIP_OK(hipGraphLaunch(class_graphs_[c], cs));
                 } else {
-                    for (int it = 0; it < k; ++it) enqueue_class_step(step_ranges_[c], cs);
+                    enqueue_class_round(step_ranges_[c], k, cs);
                 }
                 HIP_OK(hipEventRecord(class_events_[c], cs));
                 HIP_OK(hipStreamWaitEvent(s_, class_events_[c], 0));
@@ -775,7 +789,7 @@ class Engine {
         // no-ops, and the slot is reused only after the list is rebuilt
         h.done = FINISHED;
         pending_slots_.push_back(sy.slot);
-        dead_items_ += (size_t)((sy.n + sy.cw_step * sy.nw_step - 1) / (sy.cw_step * sy.nw_step));
+        dead_items_ += sy.cw_step ? (size_t)((sy.n + sy.cw_step * sy.nw_step - 1) / (sy.cw_step * sy.nw_step)) : 1;
         sy.slot = -1;
     }
 
@@ -813,6 +827,16 @@ class Engine {
         step_items_total_ = 0;
         for (int prec : {PREC_F64, PREC_F32, PREC_BF16X2}) {
             for (int P : {1, 2, 4, 8, 16}) {
+                // the small-system tier: one work item (workgroup) per system
+                StepRange rs{prec, P, 0, 0, st.size(), 0, 0, 0, 0, 0};
+                for (auto& sy : live_)
+                    if (sy.prec == prec && sy.P == P && sy.cw_step == 0) st.push_back(int4{sy.slot, 0, 0, 0});
+                rs.ad_n = st.size() - rs.ad_off;
+                rs.up_off = rs.dir_off = st.size();
+                if (rs.ad_n) {
+                    step_ranges_.push_back(rs);
+                    step_items_total_ += rs.ad_n;
+                }
                 for (int cw : {1, 2, 4}) {
                     for (int nw : {4, 8, 16}) {
                         StepRange r{prec, P, cw, nw, st.size(), 0, 0, 0, 0, 0};
@@ -883,7 +907,7 @@ class Engine {
             HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             bool ok = true;
             try {
-                for (int it = 0; it < k; ++it) enqueue_class_step(step_ranges_[c], cs);
+                enqueue_class_round(step_ranges_[c], k, cs);
             } catch (const CcgError&) {
                 ok = false;
             }
@@ -900,6 +924,16 @@ class Engine {
                 throw CcgError{CCG_ERR_DEVICE, "instantiating the batched block-step graph failed"};
             class_graphs_.push_back(ex);
         }
+    }
+
+    // k block steps of one class: one tier launch running k steps per system, or k
+    // triples of batched A.D, update and direction launches
+    void enqueue_class_round(const StepRange& r, int k, hipStream_t cs) {
+        if (r.cw == 0) {
+            HIP_OK(launch_small(r.prec, r.P, nullptr, d_small_, d_step_ + r.ad_off, (int)r.ad_n, k, cs));
+            return;
+        }
+        for (int it = 0; it < k; ++it) enqueue_class_step(r, cs);
     }
 
     void enqueue_class_step(const StepRange& r, hipStream_t cs) {
@@ -934,6 +968,7 @@ class Engine {
     AdArgs* d_ad_ = nullptr;
     AdArgs* d_res_ad_ = nullptr;
     UpdArgs* d_upd_ = nullptr;
+    SmallArgs* d_small_ = nullptr;
     ResArgs* d_res_ = nullptr;
     int4* d_items_ = nullptr;
     int4* h_items_ = nullptr;

@@ -99,6 +99,9 @@ bool use_sym(const Solve& s) {
     return s.sym_ad && sym_eligible(s.prec, s.P, s.n) && s.c->ws.part && s.c->ws.sym_nb == sym_blocks(s.n);
 }
 
+// Block steps of this solve run in the small-system tier (one workgroup per step).
+bool use_small(const Solve& s) { return small_tier(s.P, s.c->ws.n_pad); }
+
 // Bytes of A one block step streams, and the algorithmic bytes of its A.D pass
 // (A, or its upper triangle, plus the D and R rows) for the kernel timing.
 double step_bytes_A(const Solve& s) {
@@ -204,10 +207,30 @@ hipEvent_t pooled_event(ccg_ctx* c, size_t i) {
     return c->ev_pool[i];
 }
 
+SmallArgs small_args(const Solve& s) {
+    const Workspace& w = s.c->ws;
+    const Blocks b = blocks(s);
+    SmallArgs a;
+    a.A = s.A;
+    a.A_lo = s.A_lo;
+    a.lda = s.lda;
+    a.n = s.n;
+    a.X = b.X;
+    a.R = b.R;
+    a.D = b.D;
+    a.st = w.st;
+    return a;
+}
+
 // One block step: A.D (+ products, rank step, alpha), the X and R update (+ stop
-// test and beta), then the direction update.
+// test and beta), then the direction update; in the small-system tier, one launch.
 void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     Workspace& w = s.c->ws;
+    if (use_small(s)) {
+        const SmallArgs sa = small_args(s);
+        HIP_OK(launch_small(s.prec, s.P, &sa, nullptr, nullptr, 0, 1, s.c->stream));
+        return;
+    }
     hipEvent_t e0 = timed ? pooled_event(s.c, 2 * ev_slot) : nullptr;
     hipEvent_t e1 = timed ? pooled_event(s.c, 2 * ev_slot + 1) : nullptr;
     if (use_sym(s)) {
@@ -278,6 +301,13 @@ hipGraphExec_t capture_steps(Solve& s, int steps) {
 // Returns whether this round was timed.
 bool run_steps(Solve& s, int steps, bool use_graph) {
     ccg_ctx* c = s.c;
+    if (use_small(s)) {
+        // the whole round is one launch: one workgroup runs up to `steps` steps
+        ++s.rounds;
+        const SmallArgs sa = small_args(s);
+        HIP_OK(launch_small(s.prec, s.P, &sa, nullptr, nullptr, 0, steps, c->stream));
+        return false;
+    }
     const bool timed = s.profile_every > 0 && s.rounds % s.profile_every == 0;
     ++s.rounds;
     if (!use_graph || timed) {

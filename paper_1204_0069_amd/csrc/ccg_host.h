@@ -49,6 +49,12 @@ int row_workgroups(int n_pad, int P);
 hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_sym_units(int nb, int2* units, hipStream_t s);
+// the small-system tier: one system (one != nullptr) or a batch of (system) items
+hipError_t launch_small(int prec, int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
+                        int steps, hipStream_t s);
+// Systems with n <= kSmallN (n_pad == kSmallN) and P <= kSmallMaxP run their block
+// steps in the small-system tier, in every path.
+inline bool small_tier(int P, int n_pad) { return n_pad == kSmallN && P <= kSmallMaxP; }
 // allocation-free solve: the device scratch array (ccg_noalloc.hip)
 size_t scratch_bytes();
 hipError_t scratch_setup(int device, void** ptr);

@@ -532,72 +532,22 @@ __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
     return v;
 }
 
-// The products D^T AD and D^T R over the ROWS AD rows of workgroup `tile` (in adt,
-// LDS, row stride kMaxP, zero for rows >= n) and the D and R rows (dr, see
-// load_dr), their fixed-order reduction over the `ntiles` workgroups, and in the
-// last workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G
-// kept in the state for beta.  WG threads.
-template <int PREC, int P, int ROWS, int WG>
-__device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
-                                        const StepState0& s0, const DRval dr) {
-    constexpr int kAdCols = ROWS;
-    __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
-    __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
-    __shared__ double gmine[P * (P + 1) / 2 + P * P];   // this workgroup's product shares
-    __shared__ double gtot[P * (P + 1) / 2 + P * P];    // grid totals (last workgroup)
-    __shared__ double sm[4 * kMaxP * kMaxP];
-    __shared__ double gscr[WG];
-    __shared__ int ish[128];
+// The rank step (Alg. 3) and alpha = G^{-1} S of one block step from the totals in
+// gtot (the lower triangle of G = D^T AD, then S = D^T R, FP64), run by all WG
+// threads of the workgroup that holds them.  Writes alpha, the Cholesky factor of G
+// (kept for beta) and, on a rank drop, the active set to the state.  Returns false
+// (uniform) when the step stops: a failure, a re-inflation, or no agent left.
+template <int P, int WG>
+__device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0& s0, DevState* st, double* sm,
+                                           double* gscr, int* ish) {
+    constexpr int OS = P * (P + 1) / 2;
+    const double* St = gtot + OS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int i0 = tile * kAdCols;
     const unsigned mask0 = s0.mask;
     const double tau0 = s0.tau;
-    const int iter0 = s0.iter, maxit0 = s0.maxit, m0 = s0.m;
-
-    // ---- the workgroup's share of the products over its rows, packed as
-    //   G = D^T AD (lower triangle) and S = D^T R (full)
-    static_assert(kAdCols * P <= WG, "one D and R value per thread");
-    if (tid < kAdCols * P) {
-        const DRval v = dr.early ? dr : load_dr<PREC, P, ROWS>(a, i0);
-        const int r = tid / P, j = tid - (tid / P) * P;
-        drw[r * kMaxP + j] = v.d;
-        rrw[r * kMaxP + j] = v.r;
-    }
-    __syncthreads();
-    constexpr int TRI = P * (P + 1) / 2;
-    constexpr int OS = TRI;
-    constexpr int NE = TRI + P * P;
-    for (int e = tid; e < NE; e += WG) {
-        const double* Wv;
-        int x, y;
-        if (e < OS) {                                     // triangle of G
-            x = 0;
-            while ((x + 1) * (x + 2) / 2 <= e) ++x;
-            y = e - x * (x + 1) / 2;
-            Wv = adt;
-        } else {                                          // S, full
-            const int t = e - OS;
-            x = t / P;
-            y = t - x * P;
-            Wv = rrw;
-        }
-        double s = 0.0;
-        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], Wv[r * kMaxP + y], s);
-        gmine[e] = s;
-    }
-    __syncthreads();
-    if (!grid_reduce<(P >= 8 ? kGroup : 16), WG>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
-
-    // ---- last workgroup: rank step (Alg. 3) and alpha
-    DevState* st = a.st;
-    if (tid == 0) st->ad_streams += 1;
-    if (iter0 >= maxit0) {                    // (the update launch stops the steps first)
-        if (tid == 0) st->done = MAXIT;
-        return;
-    }
-    const double* St = gtot + OS;
+    const int m0 = s0.m;
     unsigned mask = mask0;
     double* Gs = sm;                          // full symmetric P x P
     double* Lsh = sm + kMaxP * kMaxP;         // Cholesky factor, row-major stride P
@@ -655,7 +605,7 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
         const int r = wg_rank_select(Gc, m, tau0, kp, H, &ish[0]);
         if (r < 0) {
             if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
-            return;
+            return false;
         }
         if (r > 0 && r < m && st->reinflate_left > 0) {
             // re-inflation instead of the drop: the host restarts the block
@@ -666,7 +616,7 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
                 st->mask = nm;
                 st->done = REINFLATE;
             }
-            return;
+            return false;
         }
         if (r < m) {
             if (tid == 0) {
@@ -681,7 +631,7 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
             }
             __syncthreads();
             mask = (unsigned)ish[121];
-            if (r == 0) return;
+            if (r == 0) return false;
         }
         if (wave == 0) {
             double g[P];
@@ -701,12 +651,12 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
         __syncthreads();
         if (ish[123]) {
             if (tid == 0) fail_state(st, -3);
-            return;
+            return false;
         }
     }
-    if (wave != 0 || lane >= P) return;
+    if (wave != 0 || lane >= P) return true;
     // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c] in this lane's registers; the factor
-    // is kept for beta, which the update launch solves from the new residual
+    // is kept for beta, which is solved from the new residual
     const int c = lane;
     const bool ac = (mask >> c) & 1u;
     if constexpr (P <= 8) {
@@ -730,6 +680,71 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
             st->L[x * kMaxP + c] = Lsh[x * P + c];
         }
     }
+    return true;
+}
+
+// The products D^T AD and D^T R over the ROWS AD rows of workgroup `tile` (in adt,
+// LDS, row stride kMaxP, zero for rows >= n) and the D and R rows (dr, see
+// load_dr), their fixed-order reduction over the `ntiles` workgroups, and in the
+// last workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G
+// kept in the state for beta.  WG threads.
+template <int PREC, int P, int ROWS, int WG>
+__device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
+                                        const StepState0& s0, const DRval dr) {
+    constexpr int kAdCols = ROWS;
+    __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
+    __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
+    __shared__ double gmine[P * (P + 1) / 2 + P * P];   // this workgroup's product shares
+    __shared__ double gtot[P * (P + 1) / 2 + P * P];    // grid totals (last workgroup)
+    __shared__ double sm[4 * kMaxP * kMaxP];
+    __shared__ double gscr[WG];
+    __shared__ int ish[128];
+    const int tid = threadIdx.x;
+    const int i0 = tile * kAdCols;
+    const int iter0 = s0.iter, maxit0 = s0.maxit;
+
+    // ---- the workgroup's share of the products over its rows, packed as
+    //   G = D^T AD (lower triangle) and S = D^T R (full)
+    static_assert(kAdCols * P <= WG, "one D and R value per thread");
+    if (tid < kAdCols * P) {
+        const DRval v = dr.early ? dr : load_dr<PREC, P, ROWS>(a, i0);
+        const int r = tid / P, j = tid - (tid / P) * P;
+        drw[r * kMaxP + j] = v.d;
+        rrw[r * kMaxP + j] = v.r;
+    }
+    __syncthreads();
+    constexpr int TRI = P * (P + 1) / 2;
+    constexpr int OS = TRI;
+    constexpr int NE = TRI + P * P;
+    for (int e = tid; e < NE; e += WG) {
+        const double* Wv;
+        int x, y;
+        if (e < OS) {                                     // triangle of G
+            x = 0;
+            while ((x + 1) * (x + 2) / 2 <= e) ++x;
+            y = e - x * (x + 1) / 2;
+            Wv = adt;
+        } else {                                          // S, full
+            const int t = e - OS;
+            x = t / P;
+            y = t - x * P;
+            Wv = rrw;
+        }
+        double s = 0.0;
+        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], Wv[r * kMaxP + y], s);
+        gmine[e] = s;
+    }
+    __syncthreads();
+    if (!grid_reduce<(P >= 8 ? kGroup : 16), WG>(gmine, NE, a.red, gtot, &ish[0], gscr, tile, ntiles)) return;
+
+    // ---- last workgroup: rank step (Alg. 3) and alpha
+    DevState* st = a.st;
+    if (tid == 0) st->ad_streams += 1;
+    if (iter0 >= maxit0) {                    // (the update launch stops the steps first)
+        if (tid == 0) st->done = MAXIT;
+        return;
+    }
+    (void)step_alpha<P, WG>(gtot, s0, st, sm, gscr, ish);
 }
 
 // One tile (NW * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
@@ -1601,5 +1616,317 @@ hipError_t launch_ad_f32(int P, int cw, int nw, const AdArgs* one, const AdArgs*
                          int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_ad_bf16(int P, int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                           int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+
+}  // namespace ccg
+
+namespace ccg {
+
+// ================= small-system tier: one workgroup runs whole block steps of a system
+//
+// For n <= kSmallN (= the padded size 512) and P <= kSmallMaxP, a block step of a
+// system is latency-bound across workgroups: a grid reduction and three launches
+// cost more than streaming A (at most 2 MB in FP64).  Here one workgroup of 512
+// threads does the whole step, with D, AD and R staged in LDS, and loops over up to
+// `steps` steps per launch; every per-system quantity is summed in a fixed order, so
+// a system's result does not depend on the launch it shares or the round lengths.
+// Every solve of such a size (single, batched, served) runs this tier.
+
+// out[e] = sum over the kSmallN rows of f(e, k, .) for e < NE: each entry's rows in
+// RT slices of consecutive rows (an FMA chain within a slice), then the slices in
+// order.  part: kSmallWG doubles of LDS.
+template <int NE, class F>
+__device__ __forceinline__ void small_rows_sum(F f, double* part, double* out) {
+    constexpr int RT0 = kSmallWG / NE >= 32 ? 32 : (kSmallWG / NE >= 16 ? 16 : (kSmallWG / NE >= 8 ? 8
+                        : (kSmallWG / NE >= 4 ? 4 : (kSmallWG / NE >= 2 ? 2 : 1))));
+    constexpr int SL = kSmallN / RT0;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NE * RT0; t += kSmallWG) {
+        const int e = t / RT0, q = t - (t / RT0) * RT0;
+        double s = 0.0;
+#pragma unroll 4
+        for (int k = q * SL; k < (q + 1) * SL; ++k) s = f(e, k, s);
+        part[t] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < NE; e += kSmallWG) {
+        double s = part[e * RT0];
+        for (int q = 1; q < RT0; ++q) s += part[e * RT0 + q];
+        out[e] = s;
+    }
+    __syncthreads();
+}
+
+template <int PREC, int P>
+__device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps) {
+    using TA = typename PT<PREC>::TA;
+    using TV = typename PT<PREC>::TV;
+    using TACC = typename PT<PREC>::TACC;
+    constexpr int E = PT<PREC>::E;
+    constexpr int CW = PREC == PREC_F64 ? 2 : 4;     // A columns per wave pass
+    constexpr int N = kSmallN;
+    constexpr int NT = kSmallWG;
+    constexpr int NWV = NT / 64;
+    constexpr int TRI = P * (P + 1) / 2;
+    constexpr int NE1 = TRI + P * P;                 // G (lower triangle), S
+    constexpr int NE2 = P * P + P;                   // (AD)^T R_new, diag(R_new^T R_new)
+    constexpr int NV = CW * P;
+    constexpr int PER = P * N / NT;                  // elements per thread
+    static_assert(P <= kSmallMaxP && NV <= 64 && PER * NT == P * N, "tier shape");
+    __shared__ TV dsh[P * N], adsh[P * N], rsh[P * N];   // agent-major: [j * N + k]
+    __shared__ double part[NT];
+    __shared__ double g1[NE1], g2[NE2];
+    __shared__ double sm[4 * kMaxP * kMaxP];
+    __shared__ double gscr[NT];
+    __shared__ int ish[128];
+    __shared__ double al[P * P], be[P * P];
+    __shared__ double Lsh[P * P], rinv[P], lred[64];
+    __shared__ int ctl;
+    DevState* st = a.st;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n;
+    TV* X = static_cast<TV*>(a.X);
+    TV* R = static_cast<TV*>(a.R);
+    TV* D = static_cast<TV*>(a.D);
+    const int64_t lda = a.lda;
+    // the blocks are agent-major with N rows, so LDS and global share the index
+    for (int idx = tid; idx < P * N; idx += NT) {
+        dsh[idx] = D[idx];
+        rsh[idx] = R[idx];
+        adsh[idx] = TV(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < steps; ++s) {
+        if (tid == 0) ctl = st->done == RUNNING ? 1 : 0;
+        __syncthreads();
+        if (!ctl) break;
+        const StepState0 s0 = read_state0(st);
+        // ---- AD = A D: wave w takes A columns (= AD rows, A symmetric) w*CW, w*CW +
+        //      NWV*CW, ...; its lanes split the contraction index; one xor fold
+        for (int i0 = wave * CW; i0 < n; i0 += NWV * CW) {
+            const TA* colhi[CW];
+            const TA* collo[CW];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int i = min(i0 + c, n - 1);     // columns >= n: a copy, never stored
+                colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
+                collo[c] = PREC == PREC_BF16X2 ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
+            }
+            TACC acc[CW][P];
+#pragma unroll
+            for (int c = 0; c < CW; ++c)
+#pragma unroll
+                for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
+            // every load of the pass first (KI contraction steps of 64 E elements),
+            // then the products, one contraction step after the other
+            constexpr int KI = N / (64 * E);
+            TACC av[KI][CW][E];
+#pragma unroll
+            for (int it = 0; it < KI; ++it) {
+                const int k0 = it * 64 * E + lane * E;
+                if (k0 + E <= n) {
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) Loader<PREC, true>::load(colhi[c] + k0, collo[c] + k0, av[it][c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            av[it][c][e] = (k0 + e < n)
+                                               ? Loader<PREC, true>::load1(colhi[c] + k0 + e, collo[c] + k0 + e)
+                                               : TACC(0);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < KI; ++it) {
+                const int k0 = it * 64 * E + lane * E;
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    TACC d[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) d[e] = TACC(dsh[j * N + k0 + e]);
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[it][c][e], d[e], acc[c][j]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            TACC v[NV];
+#pragma unroll
+            for (int c = 0; c < CW; ++c)
+#pragma unroll
+                for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
+            const int idx = wave_fold<NV>(v, lane);
+            constexpr int REP = 64 / NV;
+            if (lane % REP == 0) {
+                const int c = idx / P, j = idx - (idx / P) * P;
+                const int i = i0 + c;
+                if (i < n) adsh[j * N + i] = TV(v[0]);
+            }
+        }
+        __syncthreads();
+        // ---- G = D^T AD (lower triangle) and S = D^T R, then the rank step and alpha
+        small_rows_sum<NE1>(
+            [&](int e, int k, double acc) {
+                if (e < TRI) {
+                    int x = 0;
+                    while ((x + 1) * (x + 2) / 2 <= e) ++x;
+                    const int y = e - x * (x + 1) / 2;
+                    return fma(double(dsh[x * N + k]), double(adsh[y * N + k]), acc);
+                }
+                const int t = e - TRI, x = t / P, y = t - (t / P) * P;
+                return fma(double(dsh[x * N + k]), double(rsh[y * N + k]), acc);
+            },
+            part, g1);
+        if (tid == 0) st->ad_streams += 1;
+        if (s0.iter >= s0.maxit) {                    // (the stop rule ends the steps first)
+            if (tid == 0) st->done = MAXIT;
+            break;
+        }
+        const bool go = step_alpha<P, NT>(g1, s0, st, sm, gscr, ish);
+        __syncthreads();
+        if (!go) break;
+        if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+        if (tid < P * P) Lsh[tid] = st->L[(tid / P) * kMaxP + (tid % P)];
+        const unsigned mask = st->mask;
+        __syncthreads();
+        // ---- X += D alpha, R_new = R - AD alpha
+#pragma unroll 1
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            const int j = idx / N, k = idx - (idx / N) * N;
+            double sx = 0.0, sr = 0.0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                sx = fma(double(dsh[l * N + k]), al[l * P + j], sx);
+                sr = fma(double(adsh[l * N + k]), al[l * P + j], sr);
+            }
+            X[idx] = TV(double(X[idx]) + sx);
+            const TV rn = TV(double(rsh[idx]) - sr);
+            rsh[idx] = rn;
+            R[idx] = rn;
+        }
+        if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+        __syncthreads();
+        // ---- (AD)^T R_new and the new residual norms; beta and the stop rule
+        small_rows_sum<NE2>(
+            [&](int e, int k, double acc) {
+                if (e < P * P) {
+                    const int x = e / P, y = e - (e / P) * P;
+                    return fma(double(adsh[x * N + k]), double(rsh[y * N + k]), acc);
+                }
+                const int y = e - P * P;
+                return fma(double(rsh[y * N + k]), double(rsh[y * N + k]), acc);
+            },
+            part, g2);
+        if (wave == 0) {
+            if (lane < P) {
+                const int c = lane;
+                const bool ac = (mask >> c) & 1u;
+                double w[P];
+#pragma unroll
+                for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -g2[x * P + c] : 0.0;
+                col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+                for (int x = 0; x < P; ++x) {
+                    be[x * P + c] = w[x];
+                    st->beta[x * kMaxP + c] = w[x];
+                }
+            }
+            double qv = INFINITY, bad = 0.0;
+            if (lane < P && ((mask >> lane) & 1u)) {
+                const double nr = sqrt(g2[P * P + lane]);
+                st->norms[lane] = nr;
+                if (!isfinite(nr)) bad = 1.0;
+                qv = nr / s0.nb;
+            }
+            if (lane < P) {
+                lred[lane] = qv;
+                lred[32 + lane] = bad;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (lane == 0) {
+                double mn = INFINITY, anybad = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < P; ++jj) {
+                    mn = fmin(mn, lred[jj]);
+                    anybad += lred[32 + jj];
+                }
+                const int it = s0.iter + 1;
+                st->minres = mn;
+                st->iter = it;
+                if (anybad > 0.0) fail_state(st, -2);
+                else if (mn <= s0.tol) st->done = RECUR_CONV;
+                else if (it >= s0.maxit) st->done = MAXIT;
+            }
+        }
+        __syncthreads();
+        // ---- D = R_new + D beta (masked to the active agents), built in adsh (AD is
+        //      spent; its rows >= n stay zero, as R's and D's do)
+#pragma unroll 1
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            const int j = idx / N, k = idx - (idx / N) * N;
+            double sd = double(rsh[idx]);
+#pragma unroll
+            for (int l = 0; l < P; ++l) sd = fma(double(dsh[l * N + k]), be[l * P + j], sd);
+            adsh[idx] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            const TV v = adsh[idx];
+            dsh[idx] = v;
+            D[idx] = v;
+            adsh[idx] = TV(0);
+        }
+        __syncthreads();
+    }
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kSmallWG) void k_small(SmallArgs a, int steps) {
+    small_steps<PREC, P>(a, steps);
+}
+
+// Many systems: workgroup w runs system items[w].x.
+template <int PREC, int P>
+__global__ __launch_bounds__(kSmallWG) void k_small_batch(const SmallArgs* __restrict__ sys,
+                                                          const int4* __restrict__ items, int steps) {
+    const SmallArgs a = sys[items[blockIdx.x].x];
+    small_steps<PREC, P>(a, steps);
+}
+
+hipError_t launch_small_f64(int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
+                            int steps, hipStream_t s);
+hipError_t launch_small_f32(int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
+                            int steps, hipStream_t s);
+hipError_t launch_small_bf16(int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
+                             int steps, hipStream_t s);
+
+template <int PREC>
+inline hipError_t launch_small_prec(int P, const SmallArgs* one, const SmallArgs* sys, const int4* items,
+                                    int nitems, int steps, hipStream_t s) {
+#define CCG_SMALL(PP)                                                                                       \
+    if (one) {                                                                                              \
+        hipLaunchKernelGGL((k_small<PREC, PP>), dim3(1), dim3(kSmallWG), 0, s, *one, steps);                \
+    } else {                                                                                                \
+        hipLaunchKernelGGL((k_small_batch<PREC, PP>), dim3(nitems), dim3(kSmallWG), 0, s, sys, items, steps); \
+    }                                                                                                       \
+    return hipGetLastError();
+    switch (P) {
+        case 1: { CCG_SMALL(1) }
+        case 2: { CCG_SMALL(2) }
+        case 4: { CCG_SMALL(4) }
+        case 8: { CCG_SMALL(8) }
+        default: return hipErrorInvalidValue;
+    }
+#undef CCG_SMALL
+}
 
 }  // namespace ccg

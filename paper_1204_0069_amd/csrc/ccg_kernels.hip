@@ -256,6 +256,17 @@ hipError_t launch_ad_cw(int prec, int P, int cw, int nw, const AdArgs& a, hipStr
     return launch_ad_any(prec, P, cw, nw, &a, nullptr, nullptr, 0, s, e0, e1);
 }
 
+hipError_t launch_small(int prec, int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
+                        int steps, hipStream_t s) {
+    if (!one && nitems <= 0) return hipSuccess;
+    switch (prec) {
+        case PREC_F64: return launch_small_f64(P, one, sys, items, nitems, steps, s);
+        case PREC_F32: return launch_small_f32(P, one, sys, items, nitems, steps, s);
+        case PREC_BF16X2: return launch_small_bf16(P, one, sys, items, nitems, steps, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0,
                       hipEvent_t e1) {
     return launch_sym_f64(P, sa, a, nunits, s, e0, e1);

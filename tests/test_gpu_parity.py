@@ -463,3 +463,43 @@ def test_reinflation_budget_and_rejections(gpu_ctx):
     assert bad["status"] == -1
     res = gpu_ctx.solve_batched([dict(A=_t(A), b=_t(b), X0=_t(X0), tol=1e-10, maxit=5000, flags=CCG_REINFLATE)])
     assert res[0][1]["status"] == -1
+
+
+# ------------------------------- the small-system tier (n <= 512, p <= 8: one workgroup)
+
+TIER_CASES = [(512, 8, 1e3, 10), (511, 5, 1e3, 8), (500, 8, 1e4, 6), (64, 2, 1e2, 12), (1, 1, 1.0, 1)]
+
+
+@pytest.mark.parametrize("n,p,kappa,k", TIER_CASES)
+def test_tier_steps_match_oracle(gpu_ctx, n, p, kappa, k):
+    """Systems with n <= 512 and p <= 8 run whole block steps in one workgroup; their
+    steps are held to the oracle as the other sizes are (1e-10 per step)."""
+    print(f"case tier debug_step n={n} p={p} k={k}", flush=True)
+    A, b, X0 = ci.system(n, p, kappa, seed=303)
+    orc = oracle.ccg(A, b, X0, tol=0.0, maxit=k, trace_k=k, want_rd=True)
+    g = gpu_ctx.debug_step(_t(A), _t(b), _t(X0), k)
+    for s in range(k):
+        sa = np.abs(orc["alphas"][s]).max()
+        sb = np.abs(orc["betas"][s]).max()
+        assert np.abs(g["alphas"][s] - orc["alphas"][s]).max() <= 1e-10 * sa, ("alpha", s)
+        if sb > 0:
+            assert np.abs(g["betas"][s] - orc["betas"][s]).max() <= 1e-10 * sb, ("beta", s)
+    assert _rel(g["X"].numpy(), orc["X"]) <= 1e-10
+    if np.linalg.norm(orc["R"]) > 0:
+        assert _rel(g["R"].numpy(), orc["R"]) <= 1e-10
+
+
+def test_tier_round_lengths_and_boundary(gpu_ctx):
+    """A round is one launch of up to graph_k steps in the tier: where rounds end does
+    not change the result; n = 512 (tier) and n = 513 (several workgroups per step)
+    both meet the target and match the oracle's same-step agents at tol 1e-11."""
+    A, b, X0 = ci.system(480, 6, 1e4, seed=304)
+    runs = [gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 20000, graph_k=kk) for kk in (16, 1, 5)]
+    for X, info in runs[1:]:
+        assert info["iters"] == runs[0][1]["iters"] and torch.equal(X, runs[0][0])
+    for n in (512, 513):
+        A, b, X0 = ci.system(n, 8, 1e3, seed=305)
+        orc = oracle.ccg(A, b, X0, tol=1e-11, maxit=20000)
+        X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-11, 20000)
+        assert info["status"] == 0
+        _check_against_oracle(A, b, X0, X, info, 1e-11, orc)
