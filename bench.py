@@ -63,7 +63,9 @@ def parse():
                     help="time every A.D launch (all block steps launched directly)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "paper"])
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "paper", "psweep", "tier"])
+    ap.add_argument("--psweep", default="1,2,3,4,5,6,8,10,12,16",
+                    help="psweep mode: agent counts")
     ap.add_argument("--paper-sizes", default="1000,1500,2000,2500,3000,3500,4000,4500,5000,6000,7000,8000,"
                                              "9000,10000,11000,12000,13000,14000,15000,16000,17000,18000,"
                                              "19000,20000,21000,22000,23000,24000,25000",
@@ -165,6 +167,10 @@ def main():
         return run_served(args)
     if args.mode == "paper":
         return run_paper(args)
+    if args.mode == "psweep":
+        return run_psweep(args)
+    if args.mode == "tier":
+        return run_tier(args)
 
     import numpy as np
     import torch
@@ -502,6 +508,87 @@ def run_paper(args):
                       "seconds": round(time.perf_counter() - t_all, 1)}))
 
 
+def run_tier(args):
+    """Single solves of small systems on the small-system tier (the default where it
+    applies) and on the multi-workgroup path (CCG_NO_TIER): milliseconds per solve over
+    10 solves after one warm-up, and per block step.  One JSON line."""
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import CCG_NO_TIER, Context
+
+    dev = "cuda:0"
+    ctx = Context(0)
+    rows = []
+    for n, p, kappa in [(64, 4, 1e3), (96, 4, 1e3), (128, 4, 1e3), (256, 3, 1e3), (256, 8, 1e4), (512, 8, 1e4)]:
+        A, b, X0 = (torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+                    for x in ci.system(n, p, kappa, seed=7))
+        for prec in ("fp64", "fp32"):
+            for fl in (0, CCG_NO_TIER):
+                ctx.solve(A, b, X0, 1e-10, 100000, prec=prec, flags=fl)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    X, info = ctx.solve(A, b, X0, 1e-10, 100000, prec=prec, flags=fl)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / 10
+                rows.append({"n": n, "p": p, "prec": prec, "path": "multi" if fl else "default",
+                             "ms": round(dt * 1e3, 3), "iters": info["iters"],
+                             "us_per_step": round(dt * 1e6 / max(1, info["iters"]), 2)})
+                print(json.dumps({"progress": "tier", **rows[-1]}), file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps({"mode": "tier", "rows": rows,
+                      "note": "default = the small-system tier where n <= 96 and p <= 4, else the "
+                              "multi-workgroup step; multi = CCG_NO_TIER"}))
+
+
+def run_psweep(args):
+    """Corollary 2 of the paper on the GPU: the agent count that minimises the time to
+    a solution.  For each p, the block steps to --tol and the time per step (A.D
+    launches timed per step with events, and whole solves) on the --n, --kappa system;
+    the time to solution is their product.  One JSON line."""
+    import numpy as np
+    import torch
+
+    import ccg_inputs as ci
+    from paper_1204_0069_amd import CCG_PROFILE, Context
+
+    dev = "cuda:0"
+    n = args.n
+    seed = ci.BASE_SEED if args.seed is None else args.seed
+    A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", seed, base=n), device=dev)
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", seed, base=n)), device=dev)
+    X16 = torch.as_tensor(ci.normal_block(n, 16, ci.item_seed("X0", seed, base=n)), device=dev)
+    ctx = Context(0)
+    rows = []
+    for p in [int(v) for v in args.psweep.split(",") if v]:
+        X0 = X16[:, :p].contiguous()
+        ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            X, info = ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec)
+        torch.cuda.synchronize()
+        per_solve = (time.perf_counter() - t0) / reps
+        ctx.kernel_time(reset=True)
+        ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec, flags=CCG_PROFILE)
+        ad_ms, ad_n = ctx.kernel_time(reset=True)
+        rows.append({"p": p, "iters": info["iters"], "ms_per_solve": round(per_solve * 1e3, 3),
+                     "us_per_step": round(per_solve * 1e6 / max(1, info["iters"]), 2),
+                     "ad_us": round(ad_ms * 1e3 / max(1, ad_n), 2), "rel_res": info["rel_res"],
+                     "status": info["status_name"]})
+        print(json.dumps({"progress": "p", "p": p, "iters": info["iters"]}), file=sys.stderr, flush=True)
+    ctx.close()
+    best = min(rows, key=lambda r: r["ms_per_solve"])
+    print(json.dumps({"mode": "psweep", "workload": f"dense SPD n={n}, kappa={args.kappa:g} (log-uniform "
+                                                    f"spectrum), {args.prec.upper()} A, tol {args.tol:g}",
+                      "rows": rows, "fastest_p": best["p"],
+                      "paper": "Corollary 2 (Sec. 4): the optimal agent count, from the multiplication "
+                               "count of Table 1 with A streamed once per agent"}))
+
+
 def _oracle_rate(samples):
     """Oracle seconds per block step per n^2, from a few (A, b, X0, steps) samples."""
     import oracle
@@ -534,6 +621,14 @@ def stream_ceiling(args):
                     rows.append({"cols_per_workgroup": cols, "waves": waves, "direction_cols": dcols,
                                  "stagger": stagger, "median_us": round(us, 2),
                                  "GB_s": round(8.0 * n * n / (us * 1e-6) / 1e9, 1)})
+    # the plain grid-stride read of the same bytes, 1 to 8 workgroups per CU
+    for waves in (4, 8, 16):
+        for wgs in (256, 512, 1024, 2048):
+            if n % wgs:
+                continue
+            us = ctx.stream_probe(n, n // wgs, 0, stagger=2, reps=20, waves=waves)
+            rows.append({"grid_stride_workgroups": wgs, "waves": waves, "median_us": round(us, 2),
+                         "GB_s": round(8.0 * n * n / (us * 1e-6) / 1e9, 1)})
     ctx.close()
     print(json.dumps({"probe": "ccg_stream_probe", "n": n, "matrix_bytes": 8 * n * n, "rows": rows}))
 

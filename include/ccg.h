@@ -76,6 +76,10 @@ typedef enum {
                                  agents (Alg. 3), re-inflate them instead, at most
                                  opts->max_reinflate times (see ccg_solve); batched and
                                  served problems with it get CCG_ERR_ARG */
+#define CCG_NO_TIER   0x80u  /* run the block steps of a system with n <= 96 and p <= 4
+                                 on the multi-workgroup path instead of the small-system
+                                 tier (one workgroup per system); single, batched and
+                                 served solves alike */
 
 /* Solver options; a zero-initialised struct selects the defaults shown. */
 typedef struct {
@@ -93,6 +97,12 @@ typedef struct {
     unsigned flags;      /* CCG_HOST_PTRS | CCG_NO_GRAPH | CCG_PROFILE | CCG_PROFILE_SAMPLED |
                             CCG_ESCALATE | CCG_SYM_AD | CCG_REINFLATE */
     int max_reinflate;   /* CCG_REINFLATE: re-inflation events allowed (default 3) */
+    int ad_cw, ad_nw;    /* A.D tile shape of the block steps: A columns per wave and
+                            waves per workgroup (0: the tuned table's choice for the
+                            precision, p and n).  Rounded to a shape the library runs:
+                            cw 1, 2 or 4, nw 4, 8 or 16; FP64 at 9 <= p <= 16 runs the
+                            matrix-core tile where cw * nw >= 16 (16 or 32 rows per
+                            workgroup).  Applies to single and batched solves alike. */
 } ccg_opts;
 
 /* Per-solve report. */
@@ -273,8 +283,10 @@ ccg_status ccg_tune_ad(ccg_ctx *ctx, int prec, int p, int n, int cw, int nw, int
  * `cols` whole columns per workgroup of `waves` x 64 threads (cols divides n; waves
  * 4, 8 or 16), with 16-byte non-temporal loads, and, when dcols > 0 (at most 16), also
  * the whole of an n x dcols FP64 block in every workgroup, as the A.D tile kernel
- * reads the direction block.  stagger != 0 rotates each workgroup's starting offset in
- * its columns as the A.D kernel does.  The floor that the memory system sets for that
+ * reads the direction block.  stagger = 1 rotates each workgroup's starting offset in
+ * its columns as the A.D kernel does; stagger = 2 (dcols = 0 only) reads the same
+ * bytes with n / cols workgroups in a grid-stride loop instead (each pass of the grid
+ * one contiguous span), the device's plain streaming ceiling.  The floor that the memory system sets for that
  * traffic, to set A.D timings against (not in the paper).  Allocates and frees its
  * own n^2 + n dcols doubles.  CCG_ERR_ARG for arguments outside these ranges. */
 ccg_status ccg_stream_probe(ccg_ctx *ctx, int n, int cols, int dcols, int stagger, int waves, int reps,

@@ -20,6 +20,7 @@ CCG_PROFILE_SAMPLED = 0x10
 CCG_ESCALATE = 0x8
 CCG_SYM_AD = 0x20
 CCG_REINFLATE = 0x40
+CCG_NO_TIER = 0x80
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 
@@ -37,7 +38,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_maxit", ctypes.c_int), ("max_refine", ctypes.c_int),
                 ("rank_tau", ctypes.c_double), ("graph_k", ctypes.c_int),
-                ("flags", ctypes.c_uint), ("max_reinflate", ctypes.c_int)]
+                ("flags", ctypes.c_uint), ("max_reinflate", ctypes.c_int),
+                ("ad_cw", ctypes.c_int), ("ad_nw", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -138,10 +140,10 @@ def _colmajor_matrix(A: torch.Tensor):
 
 
 def make_opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_refine=0, rank_tau=0.0,
-              graph_k=0, flags=0, max_reinflate=0) -> Opts:
+              graph_k=0, flags=0, max_reinflate=0, ad_cw=0, ad_nw=0) -> Opts:
     return Opts(PREC[prec] if isinstance(prec, str) else int(prec), float(inner_tol),
                 int(inner_maxit), int(max_refine), float(rank_tau), int(graph_k), int(flags),
-                int(max_reinflate))
+                int(max_reinflate), int(ad_cw), int(ad_nw))
 
 
 def _problem(A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, tol: float, maxit: int, opts: dict):
@@ -295,7 +297,7 @@ class Context:
         return info.as_dict()
 
     def debug_step(self, A: torch.Tensor, b: torch.Tensor, X0: torch.Tensor, ksteps: int,
-                   rank_tau: float = 0.0, flags: int = 0):
+                   rank_tau: float = 0.0, flags: int = 0, **opts):
         """Exactly ksteps FP64 block steps; returns dict of X, R, D (n x p, CPU float64)
         and alphas, betas (ksteps x p x p, [step, row, col])."""
         aptr, lda, keep = _colmajor_matrix(A)
@@ -307,7 +309,7 @@ class Context:
         D = torch.zeros(p, n, dtype=torch.float64, device=A.device)
         al = (ctypes.c_double * max(1, ksteps * p * p))()
         be = (ctypes.c_double * max(1, ksteps * p * p))()
-        o = make_opts(rank_tau=rank_tau, flags=flags)
+        o = make_opts(rank_tau=rank_tau, flags=flags, **opts)
         torch.cuda.synchronize(A.device)
         dptr = ctypes.POINTER(ctypes.c_double)
         st = self.lib.ccg_debug_step(self.h, n, p, aptr, lda, b.data_ptr(), Xt.data_ptr(), n,
@@ -353,11 +355,12 @@ class Context:
             raise self._err(st)
         return us.value
 
-    def stream_probe(self, n: int, cols: int, dcols: int = 0, stagger: bool = True, reps: int = 20,
+    def stream_probe(self, n: int, cols: int, dcols: int = 0, stagger=True, reps: int = 20,
                      waves: int = 4) -> float:
         """Median microseconds of the read-only stream of an n x n FP64 matrix, cols
         columns per workgroup of waves x 64 threads, plus an n x dcols block per
-        workgroup (ccg_stream_probe)."""
+        workgroup (ccg_stream_probe); stagger=2: the grid-stride read of the same
+        bytes by n / cols workgroups."""
         us = ctypes.c_double()
         st = self.lib.ccg_stream_probe(self.h, n, cols, dcols, int(stagger), waves, reps, ctypes.byref(us))
         if st != 0:

@@ -218,6 +218,19 @@ struct Sys {
     bool cancel = false;
 };
 
+// The block step's A.D tile shape of a system: the caller's (ccg_opts ad_cw, ad_nw;
+// fitted to a shape the launchers run), else the tuned table's.
+void step_shape(Sys& sy, const ccg_opts& o) {
+    if (o.ad_cw > 0 || o.ad_nw > 0) {
+        const int nw = o.ad_nw > 0 ? o.ad_nw : 4;
+        sy.nw_step = ad_fit_nw(sy.prec, sy.P, nw);
+        sy.cw_step = ad_fit_cw(sy.prec, sy.P, o.ad_cw > 0 ? o.ad_cw : 2, nw);
+    } else {
+        sy.cw_step = ad_cw(sy.prec, sy.P, sy.n);
+        sy.nw_step = ad_nw(sy.prec, sy.P, sy.n);
+    }
+}
+
 struct Finished {
     uint64_t tag;
     ccg_status status;
@@ -310,9 +323,8 @@ class Engine {
         sy.p = pr.p;
         sy.P = pad_agents(pr.p);
         sy.prec = o.prec == CCG_FP64 ? PREC_F64 : (o.prec == CCG_FP32 ? PREC_F32 : PREC_BF16X2);
-        sy.cw_step = ad_cw(sy.prec, sy.P, pr.n);
-        sy.nw_step = ad_nw(sy.prec, sy.P, pr.n);
-        if (small_tier(sy.P, (int)round_up(pr.n, kRowAlign))) sy.cw_step = sy.nw_step = 0;   // the tier's class
+        step_shape(sy, o);
+        if (small_tier(sy.P, pr.n, o.flags)) sy.cw_step = sy.nw_step = 0;   // the tier's class
         sy.cw_res = ad_cw(PREC_F64, sy.P, pr.n);
         sy.nw_res = ad_nw(PREC_F64, sy.P, pr.n);
         sy.tol = pr.tol;
@@ -517,9 +529,8 @@ class Engine {
         } else {
             sy.prec = PREC_F64;
         }
-        sy.cw_step = ad_cw(sy.prec, sy.P, sy.n);
-        sy.nw_step = ad_nw(sy.prec, sy.P, sy.n);
-        if (small_tier(sy.P, sy.w.n_pad)) sy.cw_step = sy.nw_step = 0;
+        step_shape(sy, sy.o);
+        if (small_tier(sy.P, sy.n, sy.o.flags)) sy.cw_step = sy.nw_step = 0;
         write_records(sy);
         start_stage(sy);
         items_dirty_ = true;

@@ -92,7 +92,19 @@ struct Solve {
     int profile_every;     // time the A.D launches of every n-th round of steps (0: none)
     bool sym_ad = false;   // CCG_SYM_AD: symmetric A.D pass where eligible
     int rounds = 0;        // rounds of block steps run so far
+    int ad_cw = 0, ad_nw = 0;   // A.D tile shape (0: the tuned table's)
+    unsigned flags = 0;         // the caller's CCG_NO_TIER
 };
+
+// The A.D tile shape the block steps of a solve run: the caller's (fitted), else 0
+// (the table's choice); and whether the small-system tier may run them.
+void set_shape(Solve& s, const ccg_opts& o) {
+    s.flags = o.flags & CCG_NO_TIER;
+    if (o.ad_cw <= 0 && o.ad_nw <= 0) return;
+    const int nw = o.ad_nw > 0 ? o.ad_nw : 4;
+    s.ad_nw = ad_fit_nw(s.prec, s.P, nw);
+    s.ad_cw = ad_fit_cw(s.prec, s.P, o.ad_cw > 0 ? o.ad_cw : 2, nw);
+}
 
 // Block steps of this solve run the symmetric A.D pass.
 bool use_sym(const Solve& s) {
@@ -100,7 +112,7 @@ bool use_sym(const Solve& s) {
 }
 
 // Block steps of this solve run in the small-system tier (one workgroup per step).
-bool use_small(const Solve& s) { return small_tier(s.P, s.c->ws.n_pad); }
+bool use_small(const Solve& s) { return small_tier(s.P, s.n, s.flags); }
 
 // Bytes of A one block step streams, and the algorithmic bytes of its A.D pass
 // (A, or its upper triangle, plus the D and R rows) for the kernel timing.
@@ -236,7 +248,10 @@ void enqueue_step(const Solve& s, size_t ev_slot, bool timed) {
     if (use_sym(s)) {
         HIP_OK(launch_sym(s.P, sym_args(s), ad_args(s, false), sym_units(sym_blocks(s.n)), s.c->stream, e0, e1));
     } else {
-        HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, e0, e1));
+        if (s.ad_cw)
+            HIP_OK(launch_ad_cw(s.prec, s.P, s.ad_cw, s.ad_nw, ad_args(s, false), s.c->stream, e0, e1));
+        else
+            HIP_OK(launch_ad(s.prec, s.P, ad_args(s, false), s.c->stream, e0, e1));
     }
     const Blocks b = blocks(s);
     UpdArgs u;
@@ -407,6 +422,7 @@ ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda,
                       double* X, int64_t ldx, double tol, int maxit, const ccg_opts& o, ccg_info& info) {
     const int P = pad_agents(p);
     Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, profile_every(o), (o.flags & CCG_SYM_AD) != 0};
+    set_shape(s, o);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -570,6 +586,7 @@ ccg_status solve_mixed(ccg_ctx* c, int n, int p, const double* A, int64_t lda, c
     ensure_workspace(c, n, P);
     const LowCopy lc = low_copy(c, n, A64, lda, prec);
     Solve s{c, n, p, P, prec, lc.hi, lc.lo, lc.ld, A64, lda, profile_every(o)};
+    set_shape(s, o);
     Workspace& w = c->ws;
     HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));
     HIP_OK(launch_pad_vec(n, w.n_pad, b, w.bp, c->stream));
@@ -880,6 +897,7 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         const int P = pad_agents(p);
         const double* Ause = aligned_matrix(c, n, A, lda);
         Solve s{c, n, p, P, PREC_F64, Ause, nullptr, lda, Ause, lda, 0, (o.flags & CCG_SYM_AD) != 0};
+        set_shape(s, o);
         ensure_workspace(c, n, P, s.sym_ad);
         Workspace& w = c->ws;
         HIP_OK(launch_pack(n, w.n_pad, p, P, X, ldx, w.Xr, c->stream));

@@ -44,6 +44,8 @@ hipError_t launch_upd_batch(int prec, int P, const UpdArgs* sys, const int4* ite
 hipError_t launch_dir_batch(int prec, int P, const UpdArgs* sys, const int4* items, int nitems, hipStream_t s);
 hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int nitems, hipStream_t s);
 int ad_fit_rows(int prec, int P, int cw, int nw);
+int ad_fit_cw(int prec, int P, int cw, int nw);
+int ad_fit_nw(int prec, int P, int nw);
 int ad_workgroups(int n);
 int row_workgroups(int n_pad, int P);
 hipError_t launch_sym(int P, const SymArgs& sa, const AdArgs& a, int nunits, hipStream_t s, hipEvent_t e0 = nullptr,
@@ -52,9 +54,17 @@ hipError_t launch_sym_units(int nb, int2* units, hipStream_t s);
 // the small-system tier: one system (one != nullptr) or a batch of (system) items
 hipError_t launch_small(int prec, int P, const SmallArgs* one, const SmallArgs* sys, const int4* items, int nitems,
                         int steps, hipStream_t s);
-// Systems with n <= kSmallN (n_pad == kSmallN) and P <= kSmallMaxP run their block
-// steps in the small-system tier, in every path.
-inline bool small_tier(int P, int n_pad) { return n_pad == kSmallN && P <= kSmallMaxP; }
+// Systems with n <= kTierMaxN and P <= kTierMaxP run their block steps in the
+// small-system tier, in every path (single, batched, served), unless the caller sets
+// CCG_NO_TIER.  The bounds are where one workgroup per step was measured faster than
+// the multi-workgroup step on MI355X: from n = 128 on, or at P = 8, the one
+// workgroup's latency-bound stream of A costs more than the three launches.
+constexpr int kTierMaxN = 96;
+constexpr int kTierMaxP = 4;
+static_assert(kTierMaxN <= kSmallN && kTierMaxP <= kSmallMaxP, "tier bounds within the kernels' shapes");
+inline bool small_tier(int P, int n, unsigned flags) {
+    return n <= kTierMaxN && P <= kTierMaxP && !(flags & CCG_NO_TIER);
+}
 // allocation-free solve: the device scratch array (ccg_noalloc.hip)
 size_t scratch_bytes();
 hipError_t scratch_setup(int device, void** ptr);

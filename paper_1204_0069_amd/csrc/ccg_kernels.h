@@ -536,10 +536,13 @@ __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
 // gtot (the lower triangle of G = D^T AD, then S = D^T R, FP64), run by all WG
 // threads of the workgroup that holds them.  Writes alpha, the Cholesky factor of G
 // (kept for beta) and, on a rank drop, the active set to the state.  Returns false
-// (uniform) when the step stops: a failure, a re-inflation, or no agent left.
+// (uniform) when the step stops: a failure, a re-inflation, or no agent left.  After
+// the caller's next barrier, ish[122] holds the active set, the factor of G is in
+// sm + kMaxP^2 (row-major, stride P) with 1 / L[i][i] at sm + 2 kMaxP^2, and alpha
+// also in aout[x * P + c] when aout is given (LDS).
 template <int P, int WG>
 __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0& s0, DevState* st, double* sm,
-                                           double* gscr, int* ish) {
+                                           double* gscr, int* ish, double* aout = nullptr) {
     constexpr int OS = P * (P + 1) / 2;
     const double* St = gtot + OS;
     const int tid = threadIdx.x;
@@ -654,6 +657,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
             return false;
         }
     }
+    if (tid == 0) ish[122] = (int)mask;
     if (wave != 0 || lane >= P) return true;
     // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c] in this lane's registers; the factor
     // is kept for beta, which is solved from the new residual
@@ -668,6 +672,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
         for (int x = 0; x < P; ++x) {
             st->alpha[x * kMaxP + c] = y[x];
             st->L[x * kMaxP + c] = Lsh[x * P + c];
+            if (aout) aout[x * P + c] = y[x];
         }
     } else {
         double* Yc = sm + 3 * kMaxP * kMaxP;   // column c of alpha at Yc[x * P + c]
@@ -678,6 +683,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
         for (int x = 0; x < P; ++x) {
             st->alpha[x * kMaxP + c] = Yc[x * P + c];
             st->L[x * kMaxP + c] = Lsh[x * P + c];
+            if (aout) aout[x * P + c] = Yc[x * P + c];
         }
     }
     return true;
@@ -705,12 +711,21 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
 
     // ---- the workgroup's share of the products over its rows, packed as
     //   G = D^T AD (lower triangle) and S = D^T R (full)
-    static_assert(kAdCols * P <= WG, "one D and R value per thread");
-    if (tid < kAdCols * P) {
-        const DRval v = dr.early ? dr : load_dr<PREC, P, ROWS>(a, i0);
-        const int r = tid / P, j = tid - (tid / P) * P;
-        drw[r * kMaxP + j] = v.d;
-        rrw[r * kMaxP + j] = v.r;
+    if (dr.early) {                       // one D and R value per thread (load_dr)
+        if (tid < kAdCols * P) {
+            const int r = tid / P, j = tid - (tid / P) * P;
+            drw[r * kMaxP + j] = dr.d;
+            rrw[r * kMaxP + j] = dr.r;
+        }
+    } else {
+        using TV = typename PT<PREC>::TV;
+        for (int t = tid; t < kAdCols * P; t += WG) {
+            const int r = t / P, j = t - (t / P) * P;
+            const int i = i0 + r;
+            const int64_t o = (int64_t)j * a.n_pad + i;
+            drw[r * kMaxP + j] = i < a.n ? double(static_cast<const TV*>(a.V)[o]) : 0.0;
+            rrw[r * kMaxP + j] = i < a.n ? double(static_cast<const TV*>(a.R)[o]) : 0.0;
+        }
     }
     __syncthreads();
     constexpr int TRI = P * (P + 1) / 2;
@@ -765,6 +780,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     constexpr int PER = (P * KC + WG - 1) / WG;   // staged D values per thread per chunk
     constexpr bool PART = PER * WG != P * KC;     // the last round of staging is partial
     static_assert(NV <= 64, "lane sums per wave");
+    static_assert(PREC != PREC_F64 || kAdCols * P <= WG, "one early D and R value per thread (load_dr)");
     static_assert(512 % KC == 0, "chunks must tile the padded length");
 
     __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
@@ -917,6 +933,218 @@ void k_ad_batch(const AdArgs* __restrict__ sys, const int4* __restrict__ items) 
     const int4 it = items[blockIdx.x];
     const AdArgs a = sys[it.x];
     ad_tile<PREC, P, CFG>(a, it.y, ad_tiles<CFG>(a.n));
+}
+
+// ------------------------------- A.D on the matrix cores (FP64, P = 16 or 8 agents)
+//
+// At P = 16 every 8-byte element of A meets 16 multiply-adds, 4 flops per byte: at
+// 8 TB/s that is 32 TFLOP/s, which the vector FMA path cannot reach while it also
+// reads every D value it multiplies from LDS.  v_mfma_f64_16x16x4_f64 takes a 16 x 4
+// slice of A (16 AD rows, 4 contraction indices k) and a 4 x 16 slice of D from one
+// register per lane and adds their 16 x 16 product into four accumulator registers:
+// lane l holds A(row l % 16, k-slot l / 16), D(k-slot l / 16, agent l % 16) and the
+// results (rows l / 16 + 4 v, agent l % 16), v = 0..3 (checked on the device).
+//
+// The MFMA operand layout spreads a wave's lanes over 16 columns of A; loaded
+// straight from memory that makes every load touch 16 columns 64 KB apart, and the
+// stream ran at 0.42 of the HBM peak.  So A is staged: a workgroup owns 16 RB
+// consecutive columns (AD rows), a contiguous stretch of A, and reads chunks of
+// KC = 128 contraction indices of all of them, each wave load one whole kilobyte of
+// one column, into LDS (double buffered, the next chunk's loads in flight while the
+// current one is multiplied); the D rows of the chunk are staged beside it.  The
+// workgroup's NW waves split each chunk's 32 k-steps of 4 between them, each keeping
+// its own accumulators; after the stream their partial tiles are added in LDS by a
+// fixed binary tree (waves w + h into w for h = NW/2, .., 1), so the result is the
+// same on every run, alone or batched.  The tile then goes through the same
+// products, reduction and rank step as the vector path (ad_tail).  At P = 8 the
+// lanes of agents 8..15 carry zeros: the matrix cores do twice the useful work,
+// still far inside their FP64 rate at the HBM stream rate (2 flops per byte of A).
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int P, int RB, int NW>
+__device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, const int ntiles) {
+    static_assert(P == 8 || P == 16, "one agent block of 16 (P = 8: agents 8..15 zero)");
+    constexpr int ROWS = 16 * RB;
+    constexpr int WG = 64 * NW;
+    constexpr int KC = 128;                   // contraction indices per chunk: one 16-byte
+                                              // load per lane of a wave covers a column
+    constexpr int LD = KC + 4;                // LDS row stride in doubles (spreads banks)
+    constexpr int KS = KC / 4 / NW;           // k-steps of 4 per wave per chunk
+    constexpr int CA = ROWS / NW;             // A columns a wave loads per chunk
+    constexpr int CD = (P + NW - 1) / NW;     // D agent rows a wave loads per chunk
+    static_assert(KS >= 1 && CA >= 1 && ROWS % NW == 0 && KC == 2 * 64, "tile shape");
+    __shared__ double Ash[2][ROWS * LD];      // A chunk, [column][k]
+    __shared__ double Dsh[2][16 * LD];        // D chunk, [agent][k]; agents >= P zero
+    __shared__ double adt[ROWS * kMaxP];      // AD rows of this workgroup
+
+    if (tile == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
+    if (!a.product_only && a.st->done != RUNNING) return;
+    const StepState0 s0 = read_state0(a.st);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = lane & 15, g = lane >> 4;
+    const int n = a.n;
+    const int i0 = tile * ROWS;
+    const double* __restrict__ A = static_cast<const double*>(a.A);
+    const double* __restrict__ V = static_cast<const double*>(a.V);
+    if (P < 16) {
+        for (int t = tid; t < 2 * (16 - P) * LD; t += WG) {
+            const int bf = t / ((16 - P) * LD), o = t - bf * ((16 - P) * LD);
+            Dsh[bf][P * LD + o] = 0.0;
+        }
+    }
+    // this wave's share of a chunk: A columns wave + NW q (q < CA), lane l holding
+    // k = 2 l, 2 l + 1 of the chunk; D agents wave + NW q (q < CD; a wave whose agent
+    // is >= P loads agent P - 1 and does not store it)
+    const double* colp[CA];
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+        const int i = min(i0 + wave + NW * q, n - 1);   // rows >= n compute a copy, never stored
+        colp[q] = A + (int64_t)i * a.lda;
+    }
+    const double* dcol[CD];
+#pragma unroll
+    for (int q = 0; q < CD; ++q) dcol[q] = V + (int64_t)min(wave + NW * q, P - 1) * a.n_pad;
+    // whole chunks: branch-free loads, so that the loads of the next chunks stay in
+    // flight (counted exactly) while the current one is multiplied
+    auto load_full = [&](int ch, d2v (&ra)[CA], d2v (&rd)[CD]) {
+        const int k = ch * KC + 2 * lane;
+#pragma unroll
+        for (int q = 0; q < CA; ++q) ra[q] = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(colp[q] + k));
+#pragma unroll
+        for (int q = 0; q < CD; ++q) rd[q] = *reinterpret_cast<const d2v*>(dcol[q] + k);
+    };
+    auto store_chunk = [&](int bf, const d2v (&ra)[CA], const d2v (&rd)[CD]) {
+#pragma unroll
+        for (int q = 0; q < CA; ++q)
+            *reinterpret_cast<d2v*>(&Ash[bf][(wave + NW * q) * LD + 2 * lane]) = ra[q];
+#pragma unroll
+        for (int q = 0; q < CD; ++q) {
+            const int j = wave + NW * q;
+            if (j < P) *reinterpret_cast<d2v*>(&Dsh[bf][j * LD + 2 * lane]) = rd[q];
+        }
+    };
+    d4v acc[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    auto mul_chunk = [&](int bf) {
+        const double* As = Ash[bf];
+        const double* Ds = Dsh[bf];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int kk = 4 * (wave * KS + s) + g;
+            const double dv = Ds[r * LD + kk];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(16 * b + r) * LD + kk], dv, acc[b], 0, 0, 0);
+        }
+    };
+
+    // the whole chunks, two in flight in registers (ring a0/d0, a1/d1) while the one
+    // in LDS is multiplied; the loads past the last chunk repeat it (never stored).
+    // The scheduling barriers keep each chunk's loads issued ahead of the products of
+    // the chunk before it, where the compiler would sink them.  (A third chunk in
+    // flight measured no faster.)
+    const int nf = n / KC;
+    if (nf > 0) {
+        d2v a0[CA], d0[CD], a1[CA], d1[CD];
+        load_full(0, a0, d0);
+        load_full(min(1, nf - 1), a1, d1);
+        store_chunk(0, a0, d0);
+        __syncthreads();
+        for (int c = 0;; c += 2) {
+            load_full(min(c + 2, nf - 1), a0, d0);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(0);                            // chunk c
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 >= nf) break;
+            store_chunk(1, a1, d1);                  // chunk c + 1
+            __syncthreads();
+            load_full(min(c + 3, nf - 1), a1, d1);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(1);                            // chunk c + 1
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 2 >= nf) break;
+            store_chunk(0, a0, d0);                  // chunk c + 2
+            __syncthreads();
+        }
+    }
+    // the last, partial chunk (n % KC != 0): loads guarded by k < n
+    if (n % KC) {
+        d2v ra[CA], rd[CD];
+        const int k = nf * KC + 2 * lane;
+#pragma unroll
+        for (int q = 0; q < CA; ++q) {
+            ra[q].x = k < n ? colp[q][k] : 0.0;
+            ra[q].y = k + 1 < n ? colp[q][k + 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < CD; ++q) {
+            rd[q].x = k < n ? dcol[q][k] : 0.0;
+            rd[q].y = k + 1 < n ? dcol[q][k + 1] : 0.0;
+        }
+        __syncthreads();                             // every wave is done with both buffers
+        store_chunk(0, ra, rd);
+        __syncthreads();
+        mul_chunk(0);
+    }
+    __syncthreads();
+
+    // ---- the waves' partial tiles, added by a fixed tree in the (now free) A
+    // buffers; lane (c, g) holds rows g + 4 v of each row block, agent c
+    double* part = &Ash[0][0];
+    static_assert((NW / 2) * ROWS * P <= 2 * ROWS * LD, "tree partials fit the A buffers");
+    const bool dl = r < P;
+#pragma unroll
+    for (int h = NW / 2; h >= 1; h >>= 1) {
+        if (wave >= h && wave < 2 * h && dl) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    part[((wave - h) * ROWS + 16 * b + g + 4 * v) * P + r] = acc[b][v];
+        }
+        __syncthreads();
+        if (wave < h && dl) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[b][v] += part[(wave * ROWS + 16 * b + g + 4 * v) * P + r];
+        }
+        __syncthreads();
+    }
+    if (wave == 0 && dl) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * b + g + 4 * v;
+                adt[row * kMaxP + r] = (i0 + row < n) ? acc[b][v] : 0.0;   // rows >= n hold copies
+            }
+    }
+    __syncthreads();
+    // AD rows to memory, each agent's ROWS rows contiguous
+    for (int t = tid; t < ROWS * P; t += WG) {
+        const int j = t / ROWS, row = t - (t / ROWS) * ROWS;
+        if (i0 + row < n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i0 + row] = adt[row * kMaxP + j];
+    }
+    if (a.product_only) return;
+    ad_tail<PREC_F64, P, ROWS, WG>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false});
+}
+
+template <int P, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ad_mfma(AdArgs a) {
+    ad_tile_mfma<P, RB, NW>(a, blockIdx.x, gridDim.x);
+}
+
+template <int P, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ad_mfma_batch(const AdArgs* __restrict__ sys,
+                                                            const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const AdArgs a = sys[it.x];
+    ad_tile_mfma<P, RB, NW>(a, it.y, (a.n + 16 * RB - 1) / (16 * RB));
 }
 
 // -------------------------------------------- cross-lane sums of FP64 values (gfx950)
@@ -1534,20 +1762,66 @@ inline hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int ni
     return hipGetLastError();
 }
 
-// Widths that fit the register budget: 4 columns per wave only where the
-// accumulators stay small (FP64 up to P = 4, FP32 / BF16 up to P = 8); P = 16 at
-// most 2.  ad_cw_fit gives the width a request runs at.
+// Tile shapes (A columns per wave cw, waves per workgroup nw; a workgroup owns
+// cw * nw rows of AD) as the launchers run a request.
+//
+// Vector tiles: 4 columns per wave only where the accumulators stay small (FP64 up
+// to P = 4, FP32 / BF16 up to P = 8), P = 16 at most 2; 8 or 16 waves (one staged D
+// chunk shared by more columns, so fewer re-reads of D) only up to P = 8, where a
+// thread's registers still fit a quarter of a SIMD's file.
+//
+// FP64 at P = 16 and P = 8 also has the matrix-core tile (ad_tile_mfma), with 16
+// or 32 rows per workgroup (cw * nw) and nw waves splitting the contraction: at
+// P = 16 every shape with cw * nw >= 16, (4, 4), (2, 8), (4, 8), (1, 16), (2, 16);
+// at P = 8 the shapes with 4 columns per wave, which the vector tile does not run
+// there, (4, 4) and (4, 8).
 __host__ __device__ constexpr bool ad_cw4_fits(int prec, int P) {
     return P < 16 && (prec != PREC_F64 || P <= 4);
 }
-__host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw) {
+__host__ __device__ constexpr bool ad_has_mfma(int prec, int P) { return prec == PREC_F64 && (P == 16 || P == 8); }
+__host__ __device__ constexpr int ad_nw_fit(int prec, int P, int nw) {
+    return (P >= 16 && !ad_has_mfma(prec, P)) ? 4 : (nw >= 16 ? 16 : (nw >= 8 ? 8 : 4));
+}
+__host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw, int nw) {
+    if (ad_has_mfma(prec, P) && P == 8) {       // 4 columns per wave: the matrix-core tile
+        const int w = ad_nw_fit(prec, P, nw);
+        return (cw >= 4 && w <= 8) ? 4 : (cw >= 2 ? 2 : 1);
+    }
+    if (ad_has_mfma(prec, P)) {
+        const int w = ad_nw_fit(prec, P, nw);
+        if (w == 4) return cw >= 4 ? 4 : (cw >= 2 ? 2 : 1);   // 4: matrix cores; 1, 2: vector
+        if (w == 8) return cw >= 4 ? 4 : 2;
+        return cw >= 2 ? 2 : 1;
+    }
     return cw >= 4 ? (ad_cw4_fits(prec, P) ? 4 : 2) : (cw >= 2 ? 2 : 1);
 }
-// Waves per workgroup: 4, 8 or 16 (one staged D chunk shared by more columns, so
-// fewer re-reads of D), 16 only up to P = 8, where a thread's registers still fit
-// a quarter of a SIMD's file; P = 16 runs 4.
-__host__ __device__ constexpr int ad_nw_fit(int P, int nw) {
-    return P >= 16 ? 4 : (nw >= 16 ? 16 : (nw >= 8 ? 8 : 4));
+
+template <int P, int RB, int NW>
+inline hipError_t launch_ad_mfma_t(const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
+                                   hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (!one) {
+        hipLaunchKernelGGL((k_ad_mfma_batch<P, RB, NW>), dim3(nitems), dim3(64 * NW), 0, s, sys, items);
+        return hipGetLastError();
+    }
+    const dim3 grid((one->n + 16 * RB - 1) / (16 * RB));
+    if (e0) {
+        hipExtLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, e0, e1, 0, *one);
+    } else {
+        hipLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, *one);
+    }
+    return hipGetLastError();
+}
+
+// rows: 16 or 32 per workgroup; nw: 4, 8 or 16 waves (fitted shapes only)
+template <int P>
+inline hipError_t launch_ad_mfma(int rows, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
+                                 int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (rows == 16 && nw == 4) return launch_ad_mfma_t<P, 1, 4>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 16 && nw == 8) return launch_ad_mfma_t<P, 1, 8>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 32 && nw == 8) return launch_ad_mfma_t<P, 2, 8>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 16 && nw == 16) return launch_ad_mfma_t<P, 1, 16>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 32 && nw == 16) return launch_ad_mfma_t<P, 2, 16>(one, sys, items, nitems, s, e0, e1);
+    return hipErrorInvalidValue;
 }
 
 template <int PREC, int P, int CW>
@@ -1567,6 +1841,10 @@ inline hipError_t launch_ad_w(int nw, const AdArgs* one, const AdArgs* sys, cons
 template <int PREC, int P>
 inline hipError_t launch_ad_pc(int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                                int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (ad_has_mfma(PREC, P)) {
+        const int w = ad_nw_fit(PREC, P, nw), c = ad_cw_fit(PREC, P, cw, nw);
+        if (P == 16 ? c * w >= 16 : c == 4) return launch_ad_mfma<P>(c * w, w, one, sys, items, nitems, s, e0, e1);
+    }
     constexpr int W4 = ad_cw4_fits(PREC, P) ? 4 : 2;
     if (cw >= 4) return launch_ad_w<PREC, P, W4>(nw, one, sys, items, nitems, s, e0, e1);
     if (cw >= 2) return launch_ad_w<PREC, P, 2>(nw, one, sys, items, nitems, s, e0, e1);
@@ -1631,31 +1909,38 @@ namespace ccg {
 // a system's result does not depend on the launch it shares or the round lengths.
 // Every solve of such a size (single, batched, served) runs this tier.
 
-// out[e] = sum over the kSmallN rows of f(e, k, .) for e < NE: each entry's rows in
-// RT slices of consecutive rows (an FMA chain within a slice), then the slices in
-// order.  part: kSmallWG doubles of LDS.
+// out[e] = sum over rows k < nr of f(e, k, .) for e < NE (nr: n rounded up to 64;
+// the rows from n on are zero): each entry's rows in RT slices of consecutive rows
+// (an FMA chain within a slice), then the slices in order.  part: kSmallWG doubles of
+// LDS.
 template <int NE, class F>
-__device__ __forceinline__ void small_rows_sum(F f, double* part, double* out) {
-    constexpr int RT0 = kSmallWG / NE >= 32 ? 32 : (kSmallWG / NE >= 16 ? 16 : (kSmallWG / NE >= 8 ? 8
-                        : (kSmallWG / NE >= 4 ? 4 : (kSmallWG / NE >= 2 ? 2 : 1))));
-    constexpr int SL = kSmallN / RT0;
+__device__ __forceinline__ void small_rows_sum(F f, const int nr, double* part, double* out) {
+    constexpr int RT = kSmallWG / NE >= 32 ? 32 : (kSmallWG / NE >= 16 ? 16 : (kSmallWG / NE >= 8 ? 8
+                       : (kSmallWG / NE >= 4 ? 4 : (kSmallWG / NE >= 2 ? 2 : 1))));
+    const int sl = nr / RT;
     const int tid = threadIdx.x;
-    for (int t = tid; t < NE * RT0; t += kSmallWG) {
-        const int e = t / RT0, q = t - (t / RT0) * RT0;
+    for (int t = tid; t < NE * RT; t += kSmallWG) {
+        const int e = t / RT, q = t - (t / RT) * RT;
         double s = 0.0;
 #pragma unroll 4
-        for (int k = q * SL; k < (q + 1) * SL; ++k) s = f(e, k, s);
+        for (int k = q * sl; k < (q + 1) * sl; ++k) s = f(e, k, s);
         part[t] = s;
     }
     __syncthreads();
     for (int e = tid; e < NE; e += kSmallWG) {
-        double s = part[e * RT0];
-        for (int q = 1; q < RT0; ++q) s += part[e * RT0 + q];
+        double s = part[e * RT];
+        for (int q = 1; q < RT; ++q) s += part[e * RT + q];
         out[e] = s;
     }
     __syncthreads();
 }
 
+// A workgroup runs up to `steps` block steps of its system with no memory round trip
+// on the step's critical path other than the stream of A: X, D, AD and R stay in LDS
+// for the whole launch (written back when it ends), the step
+// state lives in LDS (the device state is written for the host as the steps go), and
+// each wave loads the A columns of its next pass before it multiplies the current
+// ones.  Work runs over the rows below n only (rounded up to 64 for the products).
 template <int PREC, int P>
 __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps) {
     using TA = typename PT<PREC>::TA;
@@ -1670,16 +1955,18 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
     constexpr int NE1 = TRI + P * P;                 // G (lower triangle), S
     constexpr int NE2 = P * P + P;                   // (AD)^T R_new, diag(R_new^T R_new)
     constexpr int NV = CW * P;
-    constexpr int PER = P * N / NT;                  // elements per thread
+    constexpr int PER = P * N / NT;                  // block elements per thread
+    constexpr int KI = N / (64 * E);                 // contraction steps of a pass
     static_assert(P <= kSmallMaxP && NV <= 64 && PER * NT == P * N, "tier shape");
-    __shared__ TV dsh[P * N], adsh[P * N], rsh[P * N];   // agent-major: [j * N + k]
+    __shared__ TV dsh[P * N], adsh[P * N], rsh[P * N], xsh[P * N];   // agent-major: [j * N + k]
     __shared__ double part[NT];
     __shared__ double g1[NE1], g2[NE2];
     __shared__ double sm[4 * kMaxP * kMaxP];
     __shared__ double gscr[NT];
     __shared__ int ish[128];
     __shared__ double al[P * P], be[P * P];
-    __shared__ double Lsh[P * P], rinv[P], lred[64];
+    __shared__ double lred[64];
+    __shared__ StepState0 ss;
     __shared__ int ctl;
     DevState* st = a.st;
     const int tid = threadIdx.x;
@@ -1690,80 +1977,98 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
     TV* R = static_cast<TV*>(a.R);
     TV* D = static_cast<TV*>(a.D);
     const int64_t lda = a.lda;
+    const int nr = (n + 63) & ~63;
+    const double* Lf = sm + kMaxP * kMaxP;        // step_alpha's factor of G, stride P
+    const double* rinv = sm + 2 * kMaxP * kMaxP;
+    if (tid == 0) {
+        ss = read_state0(st);
+        ctl = st->done == RUNNING ? 1 : 0;
+    }
     // the blocks are agent-major with N rows, so LDS and global share the index
-    for (int idx = tid; idx < P * N; idx += NT) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NT;
         dsh[idx] = D[idx];
         rsh[idx] = R[idx];
         adsh[idx] = TV(0);
+        xsh[idx] = X[idx];
     }
     __syncthreads();
-    for (int s = 0; s < steps; ++s) {
-        if (tid == 0) ctl = st->done == RUNNING ? 1 : 0;
-        __syncthreads();
-        if (!ctl) break;
-        const StepState0 s0 = read_state0(st);
-        // ---- AD = A D: wave w takes A columns (= AD rows, A symmetric) w*CW, w*CW +
-        //      NWV*CW, ...; its lanes split the contraction index; one xor fold
-        for (int i0 = wave * CW; i0 < n; i0 += NWV * CW) {
-            const TA* colhi[CW];
-            const TA* collo[CW];
+
+    // one pass of a wave: A columns i0 .. i0 + CW - 1 (AD rows; columns >= n are a copy
+    // of column n - 1, never stored), the KI contraction steps of the whole column
+    auto load_pass = [&](int i0, TACC (&av)[KI][CW][E]) {
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                const int i = min(i0 + c, n - 1);     // columns >= n: a copy, never stored
-                colhi[c] = static_cast<const TA*>(a.A) + (int64_t)i * lda;
-                collo[c] = PREC == PREC_BF16X2 ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : colhi[c];
-            }
-            TACC acc[CW][P];
-#pragma unroll
-            for (int c = 0; c < CW; ++c)
-#pragma unroll
-                for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
-            // every load of the pass first (KI contraction steps of 64 E elements),
-            // then the products, one contraction step after the other
-            constexpr int KI = N / (64 * E);
-            TACC av[KI][CW][E];
+        for (int c = 0; c < CW; ++c) {
+            const int i = min(i0 + c, n - 1);
+            const TA* hi = static_cast<const TA*>(a.A) + (int64_t)i * lda;
+            const TA* lo = PREC == PREC_BF16X2 ? static_cast<const TA*>(a.A_lo) + (int64_t)i * lda : hi;
 #pragma unroll
             for (int it = 0; it < KI; ++it) {
                 const int k0 = it * 64 * E + lane * E;
                 if (k0 + E <= n) {
-#pragma unroll
-                    for (int c = 0; c < CW; ++c) Loader<PREC, true>::load(colhi[c] + k0, collo[c] + k0, av[it][c]);
+                    Loader<PREC, false>::load(hi + k0, lo + k0, av[it][c]);
                 } else {
 #pragma unroll
-                    for (int c = 0; c < CW; ++c)
-#pragma unroll
-                        for (int e = 0; e < E; ++e)
-                            av[it][c][e] = (k0 + e < n)
-                                               ? Loader<PREC, true>::load1(colhi[c] + k0 + e, collo[c] + k0 + e)
-                                               : TACC(0);
+                    for (int e = 0; e < E; ++e)
+                        av[it][c][e] = (k0 + e < n) ? Loader<PREC, false>::load1(hi + k0 + e, lo + k0 + e) : TACC(0);
                 }
             }
+        }
+    };
+    auto mul_pass = [&](int i0, const TACC (&av)[KI][CW][E]) {
+        TACC acc[CW][P];
 #pragma unroll
-            for (int it = 0; it < KI; ++it) {
-                const int k0 = it * 64 * E + lane * E;
+        for (int c = 0; c < CW; ++c)
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    TACC d[E];
+            for (int j = 0; j < P; ++j) acc[c][j] = TACC(0);
 #pragma unroll
-                    for (int e = 0; e < E; ++e) d[e] = TACC(dsh[j * N + k0 + e]);
+        for (int it = 0; it < KI; ++it) {
+            const int k0 = it * 64 * E + lane * E;
 #pragma unroll
-                    for (int c = 0; c < CW; ++c)
+            for (int j = 0; j < P; ++j) {
+                TACC d[E];
 #pragma unroll
-                        for (int e = 0; e < E; ++e) acc[c][j] = fma(av[it][c][e], d[e], acc[c][j]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
+                for (int e = 0; e < E; ++e) d[e] = TACC(dsh[j * N + k0 + e]);
+#pragma unroll
+                for (int c = 0; c < CW; ++c)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[c][j] = fma(av[it][c][e], d[e], acc[c][j]);
             }
-            TACC v[NV];
+            __builtin_amdgcn_sched_barrier(0);   // one contraction step's D values live at a time
+        }
+        TACC v[NV];
 #pragma unroll
-            for (int c = 0; c < CW; ++c)
+        for (int c = 0; c < CW; ++c)
 #pragma unroll
-                for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
-            const int idx = wave_fold<NV>(v, lane);
-            constexpr int REP = 64 / NV;
-            if (lane % REP == 0) {
-                const int c = idx / P, j = idx - (idx / P) * P;
-                const int i = i0 + c;
-                if (i < n) adsh[j * N + i] = TV(v[0]);
+            for (int j = 0; j < P; ++j) v[c * P + j] = acc[c][j];
+        const int idx = wave_fold<NV>(v, lane);
+        constexpr int REP = 64 / NV;
+        if (lane % REP == 0) {
+            const int c = idx / P, j = idx - (idx / P) * P;
+            const int i = i0 + c;
+            if (i < n) adsh[j * N + i] = TV(v[0]);
+        }
+    };
+
+    for (int s = 0; s < steps; ++s) {
+        if (!ctl) break;
+        const StepState0 s0 = ss;
+        // ---- AD = A D: wave w takes A columns (= AD rows, A symmetric) w*CW, w*CW +
+        //      NWV*CW, ...; its lanes split the contraction index; one xor fold per pass
+        {
+            TACC b0[KI][CW][E], b1[KI][CW][E];
+            int i0 = wave * CW;
+            if (i0 < n) load_pass(i0, b0);
+            while (i0 < n) {
+                const int i1 = i0 + NWV * CW;
+                if (i1 < n) load_pass(i1, b1);
+                mul_pass(i0, b0);
+                if (i1 >= n) break;
+                const int i2 = i1 + NWV * CW;
+                if (i2 < n) load_pass(i2, b0);
+                mul_pass(i1, b1);
+                i0 = i2;
             }
         }
         __syncthreads();
@@ -1779,36 +2084,32 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
                 const int t = e - TRI, x = t / P, y = t - (t / P) * P;
                 return fma(double(dsh[x * N + k]), double(rsh[y * N + k]), acc);
             },
-            part, g1);
+            nr, part, g1);
         if (tid == 0) st->ad_streams += 1;
         if (s0.iter >= s0.maxit) {                    // (the stop rule ends the steps first)
             if (tid == 0) st->done = MAXIT;
             break;
         }
-        const bool go = step_alpha<P, NT>(g1, s0, st, sm, gscr, ish);
+        const bool go = step_alpha<P, NT>(g1, s0, st, sm, gscr, ish, al);
         __syncthreads();
         if (!go) break;
-        if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
-        if (tid < P * P) Lsh[tid] = st->L[(tid / P) * kMaxP + (tid % P)];
-        const unsigned mask = st->mask;
-        __syncthreads();
-        // ---- X += D alpha, R_new = R - AD alpha
+        const unsigned mask = (unsigned)ish[122];
+        // ---- X += D alpha, R_new = R - AD alpha (rows < n)
 #pragma unroll 1
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NT;
             const int j = idx / N, k = idx - (idx / N) * N;
-            double sx = 0.0, sr = 0.0;
+            if (k < n) {
+                double sx = 0.0, sr = 0.0;
 #pragma unroll
-            for (int l = 0; l < P; ++l) {
-                sx = fma(double(dsh[l * N + k]), al[l * P + j], sx);
-                sr = fma(double(adsh[l * N + k]), al[l * P + j], sr);
+                for (int l = 0; l < P; ++l) {
+                    sx = fma(double(dsh[l * N + k]), al[l * P + j], sx);
+                    sr = fma(double(adsh[l * N + k]), al[l * P + j], sr);
+                }
+                xsh[idx] = TV(double(xsh[idx]) + sx);
+                rsh[idx] = TV(double(rsh[idx]) - sr);
             }
-            X[idx] = TV(double(X[idx]) + sx);
-            const TV rn = TV(double(rsh[idx]) - sr);
-            rsh[idx] = rn;
-            R[idx] = rn;
         }
-        if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
         __syncthreads();
         // ---- (AD)^T R_new and the new residual norms; beta and the stop rule
         small_rows_sum<NE2>(
@@ -1820,7 +2121,7 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
                 const int y = e - P * P;
                 return fma(double(rsh[y * N + k]), double(rsh[y * N + k]), acc);
             },
-            part, g2);
+            nr, part, g2);
         if (wave == 0) {
             if (lane < P) {
                 const int c = lane;
@@ -1828,7 +2129,7 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
                 double w[P];
 #pragma unroll
                 for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -g2[x * P + c] : 0.0;
-                col_chol_solve<P>(Lsh, rinv, w);
+                col_chol_solve<P>(Lf, rinv, w);
 #pragma unroll
                 for (int x = 0; x < P; ++x) {
                     be[x * P + c] = w[x];
@@ -1837,10 +2138,10 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
             }
             double qv = INFINITY, bad = 0.0;
             if (lane < P && ((mask >> lane) & 1u)) {
-                const double nr = sqrt(g2[P * P + lane]);
-                st->norms[lane] = nr;
-                if (!isfinite(nr)) bad = 1.0;
-                qv = nr / s0.nb;
+                const double nrm = sqrt(g2[P * P + lane]);
+                st->norms[lane] = nrm;
+                if (!isfinite(nrm)) bad = 1.0;
+                qv = nrm / s0.nb;
             }
             if (lane < P) {
                 lred[lane] = qv;
@@ -1859,9 +2160,16 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
                 const int it = s0.iter + 1;
                 st->minres = mn;
                 st->iter = it;
+                int stop = 1;
                 if (anybad > 0.0) fail_state(st, -2);
                 else if (mn <= s0.tol) st->done = RECUR_CONV;
                 else if (it >= s0.maxit) st->done = MAXIT;
+                else stop = 0;
+                // the next step's state: one more step, the active set after the rank step
+                ss.iter = it;
+                ss.mask = mask;
+                ss.m = __popc(mask);
+                ctl = !stop;
             }
         }
         __syncthreads();
@@ -1871,21 +2179,33 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NT;
             const int j = idx / N, k = idx - (idx / N) * N;
-            double sd = double(rsh[idx]);
+            if (k < n) {
+                double sd = double(rsh[idx]);
 #pragma unroll
-            for (int l = 0; l < P; ++l) sd = fma(double(dsh[l * N + k]), be[l * P + j], sd);
-            adsh[idx] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+                for (int l = 0; l < P; ++l) sd = fma(double(dsh[l * N + k]), be[l * P + j], sd);
+                adsh[idx] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+            }
         }
         __syncthreads();
 #pragma unroll 1
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NT;
-            const TV v = adsh[idx];
-            dsh[idx] = v;
-            D[idx] = v;
-            adsh[idx] = TV(0);
+            const int k = idx - (idx / N) * N;
+            if (k < n) {
+                dsh[idx] = adsh[idx];
+                adsh[idx] = TV(0);
+            }
         }
         __syncthreads();
+    }
+    // ---- the blocks back to memory
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NT;
+        X[idx] = xsh[idx];
+        R[idx] = rsh[idx];
+        D[idx] = dsh[idx];
     }
 }
 

@@ -201,15 +201,17 @@ static const TuneRow* tune_row(int prec, int P, int n) {
 }
 int ad_cw(int prec, int P, int n) {
     const TuneRow* r = tune_row(prec, P, n);
-    return r ? ad_cw_fit(prec, P, r->cw) : 2;
+    return r ? ad_cw_fit(prec, P, r->cw, r->nw) : 2;
 }
 int ad_nw(int prec, int P, int n) {
     const TuneRow* r = tune_row(prec, P, n);
-    return r ? ad_nw_fit(P, r->nw) : 4;
+    return r ? ad_nw_fit(prec, P, r->nw) : 4;
 }
 
 // AD rows per A.D tile of a requested shape, as the launchers run it.
-int ad_fit_rows(int prec, int P, int cw, int nw) { return ad_cw_fit(prec, P, cw) * ad_nw_fit(P, nw); }
+int ad_fit_rows(int prec, int P, int cw, int nw) { return ad_cw_fit(prec, P, cw, nw) * ad_nw_fit(prec, P, nw); }
+int ad_fit_cw(int prec, int P, int cw, int nw) { return ad_cw_fit(prec, P, cw, nw); }
+int ad_fit_nw(int prec, int P, int nw) { return ad_nw_fit(prec, P, nw); }
 
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {

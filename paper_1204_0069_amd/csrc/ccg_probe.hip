@@ -7,7 +7,10 @@
 // kernel does with the direction block.  With `stagger`, workgroup b starts its
 // chunk at step (13 b) mod steps and wraps around, as the A.D kernel staggers its
 // tiles.  It does no other work, so its time is the floor that the memory system
-// sets for that pattern of traffic.
+// sets for that pattern of traffic.  k_grid_stride (stagger = 2) reads the same
+// bytes with no column ownership at all: on every pass the workgroups together
+// read one contiguous span of nwg * WG * 4 vectors, and the next pass starts where
+// it ended, the plain streaming ceiling of the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +57,29 @@ __global__ __launch_bounds__(WG) void k_stream(const dvec2* __restrict__ a, int6
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+template <int WG>
+__global__ __launch_bounds__(WG) void k_grid_stride(const dvec2* __restrict__ a, int64_t total, double* out) {
+    constexpr int U = 4;
+    const int64_t span = (int64_t)gridDim.x * WG * U;
+    double s = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * WG * U + threadIdx.x; base < total; base += span) {
+        dvec2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = (base + u * WG < total) ? __builtin_nontemporal_load(&a[base + u * WG]) : dvec2{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u].x + v[u].y;
+    }
+    __shared__ double red[WG];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 }  // namespace
 }  // namespace ccg
 
@@ -64,9 +90,10 @@ extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, i
                                        int reps, double* us) {
     return guarded(c, [&]() -> ccg_status {
         if (n < 2 || n % 2 || cols < 1 || n % cols || dcols < 0 || dcols > kMaxP || reps < 1 || !us ||
-            (waves != 4 && waves != 8 && waves != 16))
+            (waves != 4 && waves != 8 && waves != 16) || stagger < 0 || stagger > 2 || (stagger == 2 && dcols))
             throw CcgError{CCG_ERR_ARG,
-                           "bad probe argument (n even, cols dividing n, 0 <= dcols <= 16, waves 4, 8 or 16)"};
+                           "bad probe argument (n even, cols dividing n, 0 <= dcols <= 16, waves 4, 8 or 16, "
+                           "stagger 0, 1 or 2 (grid-stride, no D))"};
         const size_t elems = (size_t)n * n;
         const int nwg = n / cols;
         void* buf = nullptr;
@@ -93,7 +120,15 @@ extern "C" ccg_status ccg_stream_probe(ccg_ctx* c, int n, int cols, int dcols, i
         for (int r = 0; r < reps + 2 && st == CCG_OK; ++r) {
             if (hipEventRecord(e0, c->stream) != hipSuccess) { st = CCG_ERR_DEVICE; break; }
             const int sg = stagger ? 1 : 0;
-            if (waves == 4)
+            if (stagger == 2) {
+                const int64_t total = (int64_t)elems / 2;
+                if (waves == 4)
+                    hipLaunchKernelGGL(k_grid_stride<256>, dim3(nwg), dim3(256), 0, c->stream, a, total, out);
+                else if (waves == 8)
+                    hipLaunchKernelGGL(k_grid_stride<512>, dim3(nwg), dim3(512), 0, c->stream, a, total, out);
+                else
+                    hipLaunchKernelGGL(k_grid_stride<1024>, dim3(nwg), dim3(1024), 0, c->stream, a, total, out);
+            } else if (waves == 4)
                 hipLaunchKernelGGL(k_stream<256>, dim3(nwg), dim3(256), 0, c->stream, a, chunk, d, dlen, sg, out);
             else if (waves == 8)
                 hipLaunchKernelGGL(k_stream<512>, dim3(nwg), dim3(512), 0, c->stream, a, chunk, d, dlen, sg, out);

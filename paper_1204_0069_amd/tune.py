@@ -45,14 +45,23 @@ def fits4(prec: str, P: int) -> bool:
 WIDE_P = (8,)
 
 
+# Shapes that run the FP64 matrix-core tile (ad_has_mfma, ad_cw_fit): 16 or 32 rows
+# per workgroup (cw * nw), nw waves splitting the contraction.
+MFMA_SHAPES = {8: ((4, 4), (4, 8)), 16: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16))}
+
+
 def shapes(prec: str, P: int):
     """Candidate (columns per wave, waves per workgroup), as the library runs them
-    (ad_cw_fit, ad_nw_fit): 4 columns where they fit, more than 4 waves at WIDE_P."""
+    (ad_cw_fit, ad_nw_fit): vector tiles with 4 columns where they fit and more than
+    4 waves at WIDE_P, then the FP64 matrix-core shapes."""
     ws = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
     if P >= 16:
         ws = [w for w in ws if w <= 2]
     nws = WAVES if P in WIDE_P else (4,)
-    return [(w, nw) for nw in nws for w in ws]
+    out = [(w, nw) for nw in nws for w in ws]
+    if prec == "fp64":
+        out += [sh for sh in MFMA_SHAPES.get(P, ()) if sh not in out]
+    return out
 
 
 MARGIN = 0.03   # another shape must beat the default (2, 4) by 3 % to be chosen
@@ -84,12 +93,14 @@ def rows_from(best_by_class):
     return rows
 
 
-def tune(ctx, reps: int, log=print):
+def tune(ctx, reps: int, log=print, precs=None, agents=AGENTS, sizes=SIZES):
     best_by_class = {}
     for prec, cname in PRECS:
-        for P in AGENTS:
+        if precs and prec not in precs:
+            continue
+        for P in agents:
             best = []
-            for n in SIZES:
+            for n in sizes:
                 if P > n:
                     continue
                 ts = {sh: ctx.tune_ad(prec, P, n, sh[0], reps, nw=sh[1]) for sh in shapes(prec, P)}
@@ -157,6 +168,10 @@ def main():
     ap.add_argument("--out", default=OUT)
     ap.add_argument("--from-log", default=None, help="re-tabulate a saved tuner log")
     ap.add_argument("--device", default="AMD Instinct MI355X", help="device name for --from-log")
+    ap.add_argument("--prec", default=None, help="comma-separated precisions to time (default: all)")
+    ap.add_argument("--agents", default=None, help="comma-separated padded agent counts (default: all)")
+    ap.add_argument("--sizes", default=None, help="comma-separated n (default: the full ladder)")
+    ap.add_argument("--no-write", action="store_true", help="print the timings only")
     args = ap.parse_args()
     if args.from_log:
         rows = rows_from_log(args.from_log)
@@ -166,9 +181,13 @@ def main():
     import torch
     from .ccg import Context
     ctx = Context(0)
-    rows = tune(ctx, args.reps, log=lambda s: print(s, flush=True))
-    write_table(rows, torch.cuda.get_device_name(0), args.out)
-    print(f"wrote {len(rows)} rows to {args.out}")
+    precs = args.prec.split(",") if args.prec else None
+    agents = tuple(int(v) for v in args.agents.split(",")) if args.agents else AGENTS
+    sizes = tuple(int(v) for v in args.sizes.split(",")) if args.sizes else SIZES
+    rows = tune(ctx, args.reps, log=lambda s: print(s, flush=True), precs=precs, agents=agents, sizes=sizes)
+    if not args.no_write:
+        write_table(rows, torch.cuda.get_device_name(0), args.out)
+        print(f"wrote {len(rows)} rows to {args.out}")
     ctx.close()
 
 

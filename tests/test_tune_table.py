@@ -36,13 +36,20 @@ def _rows_for(rows, c, P):
 
 
 def test_candidate_shapes_follow_the_register_rules():
-    assert (4, 16) in tune.shapes("fp32", 8) and (4, 4) not in tune.shapes("fp64", 8)
-    assert all(nw == 4 and w <= 2 for w, nw in tune.shapes("fp64", 16))
+    assert (4, 16) in tune.shapes("fp32", 8)
+    # FP64, P = 8: 4 columns per wave only as the matrix-core tile
+    assert [sh for sh in tune.shapes("fp64", 8) if sh[0] == 4] == [(4, 4), (4, 8)]
+    # P = 16: the vector tile at most 2 columns and 4 waves; FP64 adds the matrix cores
+    for prec in ("fp32", "bf16x2"):
+        assert all(nw == 4 and w <= 2 for w, nw in tune.shapes(prec, 16))
+    assert tune.shapes("fp64", 16) == [(1, 4), (2, 4)] + list(tune.MFMA_SHAPES[16])
     assert tune.DEFAULT in tune.shapes("bf16x2", 1)
-    # wider workgroups only where the engine was measured not to lose with them
+    # wider vector workgroups only where the engine was measured not to lose with them
     for prec in ("fp64", "fp32", "bf16x2"):
         for P in (1, 2, 4, 8, 16):
-            assert any(nw > 4 for _, nw in tune.shapes(prec, P)) == (P in tune.WIDE_P)
+            mfma = tune.MFMA_SHAPES.get(P, ()) if prec == "fp64" else ()
+            vec = [sh for sh in tune.shapes(prec, P) if sh not in mfma]
+            assert any(nw > 4 for _, nw in vec) == (P in tune.WIDE_P)
 
 
 def test_merge_and_limits():
@@ -53,10 +60,12 @@ def test_merge_and_limits():
     assert _rows_for(rows, "PREC_F32", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 8)]
     # P = 4 keeps 4 waves per workgroup
     assert all(nw == 4 for _, _, nw in _rows_for(rows, "PREC_F32", 4))
-    # FP64, P = 8 may not use 4 columns per wave: 2 from 1024 on
-    assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 2, 16)]
-    # P = 16 never times width 4 or more than 4 waves; no size below P is timed
-    assert not any(P == 16 and (w == 4 or nw != 4) for _, P, _, w, nw in ctx.calls)
+    # FP64, P = 8: 4 columns per wave only as the matrix-core tile, which wins from
+    # 8192 on at 8 waves
+    assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 8)]
+    # the vector tile at P = 16 never times width 4 or more than 4 waves; no size
+    # below P is timed
+    assert not any(P == 16 and prec != "fp64" and (w == 4 or nw != 4) for prec, P, _, w, nw in ctx.calls)
     assert all(P <= n for _, P, n, _, _ in ctx.calls)
 
 
