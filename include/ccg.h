@@ -144,7 +144,8 @@ const char *ccg_last_error(const ccg_ctx *ctx);
  * FP64 block steps of a system with n >= 1024 and p <= 8 form A D from the blocks
  * A(I, J), I <= J, of 128 x 128 (A(I, J) D(J) for rows I and A(I, J)^T D(I) for
  * rows J), so they read only the upper block triangle; the explicit residuals and
- * the other modes read all of A.
+ * the other modes read all of A.  (On MI355X this pass is slower than streaming all of
+ * A at the sizes measured; it is kept for comparison.)
  *
  * With CCG_REINFLATE (CCG_FP64 only; a policy beyond the paper, off by default), a
  * rank step that would drop some but not all agents instead re-inflates them, up to
@@ -153,8 +154,7 @@ const char *ccg_last_error(const ccg_ctx *ctx);
  * plus d, d_i = 2 (z_i >> 11) 2^-53 - 1 with z_i the (i+1)-th output of SplitMix64
  * (Steele, Lea, Flood 2014) from the state 0x1204 << 48 ^ e << 32 ^ j (e: the event,
  * from 0; j: the agent), and all p agents restart from R = D = B - A X (the start of
- * Alg. 2) in place of that step.  info->reinflations counts the events.  (On MI355X this pass is slower than streaming
- * all of A at the sizes measured; it is kept for comparison.)
+ * Alg. 2) in place of that step.  info->reinflations counts the events.
  *
  * opts->prec selects how A is streamed:
  *  - CCG_FP64: plain cCG on the FP64 matrix and FP64 agents.
