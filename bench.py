@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time A.D launches (graphs carry no event nodes)")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "paper", "psweep", "tier"])
-    ap.add_argument("--psweep", default="1,2,3,4,5,6,8,10,12,16",
+    ap.add_argument("--psweep", default="1,2,3,4,5,6,8,10,12,16,20,24,32",
                     help="psweep mode: agent counts")
     ap.add_argument("--paper-sizes", default="1000,1500,2000,2500,3000,3500,4000,4500,5000,6000,7000,8000,"
                                              "9000,10000,11000,12000,13000,14000,15000,16000,17000,18000,"
@@ -547,7 +547,8 @@ def run_psweep(args):
     """Corollary 2 of the paper on the GPU: the agent count that minimises the time to
     a solution.  For each p, the block steps to --tol and the time per step (A.D
     launches timed per step with events, and whole solves) on the --n, --kappa system;
-    the time to solution is their product.  One JSON line."""
+    the time to solution is their product.  The starting columns are the first p of
+    one block of 16 (32 when the sweep goes past 16).  One JSON line."""
     import numpy as np
     import torch
 
@@ -559,11 +560,13 @@ def run_psweep(args):
     seed = ci.BASE_SEED if args.seed is None else args.seed
     A = ci.spd_spectrum(n, args.kappa, ci.item_seed("A", seed, base=n), device=dev)
     b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", seed, base=n)), device=dev)
-    X16 = torch.as_tensor(ci.normal_block(n, 16, ci.item_seed("X0", seed, base=n)), device=dev)
+    ps = [int(v) for v in args.psweep.split(",") if v]
+    pmax = 32 if max(ps) > 16 else 16
+    Xall = torch.as_tensor(ci.normal_block(n, pmax, ci.item_seed("X0", seed, base=n)), device=dev)
     ctx = Context(0)
     rows = []
-    for p in [int(v) for v in args.psweep.split(",") if v]:
-        X0 = X16[:, :p].contiguous()
+    for p in ps:
+        X0 = Xall[:, :p].contiguous()
         ctx.solve(A, b, X0, args.tol, 100000, prec=args.prec)
         torch.cuda.synchronize()
         reps = max(1, args.steps // 5)

@@ -27,8 +27,10 @@
  *    result is available on that stream (the library synchronises it).
  *  - Nothing throws across this interface.  Every call returns a ccg_status; on
  *    failure ccg_last_error(ctx) describes it.  A context is not thread safe.
- *  - 1 <= p <= min(n, 16).  Agent counts are padded internally to 1, 2, 4, 8 or
- *    16; padded agents are inactive.
+ *  - 1 <= p <= min(n, 32) in CCG_FP64 single solves (ccg_solve, ccg_debug_step,
+ *    ccg_solve_noalloc); 1 <= p <= min(n, 16) in the low-precision modes and for
+ *    batched and served problems (CCG_ERR_ARG beyond).  Agent counts are padded
+ *    internally to 1, 2, 4, 8, 16 or 32; padded agents are inactive.
  */
 #ifndef CCG_H
 #define CCG_H
@@ -102,7 +104,9 @@ typedef struct {
                             precision, p and n).  Rounded to a shape the library runs:
                             cw 1, 2 or 4, nw 4, 8 or 16; FP64 at 9 <= p <= 16 runs the
                             matrix-core tile where cw * nw >= 16 (16 or 32 rows per
-                            workgroup).  Applies to single and batched solves alike. */
+                            workgroup), and at 17 <= p <= 32 always (a shape with
+                            cw * nw < 16 runs as cw = 4).  Applies to single and
+                            batched solves alike. */
 } ccg_opts;
 
 /* Per-solve report. */
@@ -191,7 +195,8 @@ ccg_status ccg_solve(ccg_ctx *ctx, int n, int p, const double *A, int64_t lda,
  * and CCG_REINFLATE, another precision or unaligned columns give CCG_ERR_ARG.  A size
  * whose workspace exceeds the array (vector blocks of n_pad * P elements, n_pad = n
  * rounded up to 512 and P = p rounded up to a power of two, plus the reduction
- * scratch: n up to 65536 at p <= 8, up to 32768 at p = 16) gives CCG_ERR_NOMEM
+ * scratch: n up to 65536 at p <= 8, up to 32768 at p = 16, up to 8192 at
+ * p = 32) gives CCG_ERR_NOMEM
  * with nothing launched.  Every call on a GPU, from any context
  * on it, uses that GPU's one array and clears it first: calls that overlap in time
  * on one GPU (other threads, other streams) race and must not be made. */

@@ -12,7 +12,8 @@
 
 namespace ccg {
 
-constexpr int kMaxP = 16;       // largest padded agent count
+constexpr int kMaxP = 32;       // largest padded agent count (FP64 single solves)
+constexpr int kLowMaxP = 16;    // ... in the low-precision modes and the batched engine
 constexpr int kWG = 256;        // threads per workgroup for every kernel
 constexpr int kRowAlign = 512;  // n_pad granularity
 constexpr int kGroup = 32;      // workgroups per first-level reduction group

@@ -305,6 +305,7 @@ class Engine {
     bool admit(const ccg_problem& pr, uint64_t tag) {
         const ccg_opts o = fill_defaults(&pr.opts);
         check_common(pr.n, pr.p, pr.A, pr.lda, pr.b, pr.X, pr.ldx);
+        if (pr.p > kLowMaxP) throw CcgError{CCG_ERR_ARG, "batched and served problems take p <= 16"};
         if (!(pr.tol > 0.0)) throw CcgError{CCG_ERR_ARG, "tol must be > 0"};
         if (pr.maxit < 0) throw CcgError{CCG_ERR_ARG, "maxit must be >= 0"};
         if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)

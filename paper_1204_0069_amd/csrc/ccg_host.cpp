@@ -471,7 +471,7 @@ ccg_status fp64_steps(ccg_ctx* c, int n, int p, const double* Ause, int64_t lda,
         if (h.done == REINFLATE) {
             // the agents outside the kept set restart from the best of those active
             // before the rank step, plus the draw; then the whole block restarts
-            const unsigned all = (1u << p) - 1u;
+            const unsigned all = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
             const unsigned dropped = all & ~h.mask;
             int best = -1;
             for (int j = 0; j < p; ++j)
@@ -793,6 +793,8 @@ ccg_status ccg_solve(ccg_ctx* c, int n, int p, const double* A, int64_t lda, con
         const ccg_opts o = fill_defaults(opts);
         if (o.prec != CCG_FP64 && o.prec != CCG_FP32 && o.prec != CCG_BF16X2)
             throw CcgError{CCG_ERR_ARG, "unknown precision mode"};
+        if (o.prec != CCG_FP64 && p > kLowMaxP)
+            throw CcgError{CCG_ERR_ARG, "p > 16 runs with CCG_FP64 only"};
         if ((o.flags & CCG_REINFLATE) && (o.prec != CCG_FP64 || (o.flags & CCG_ESCALATE)))
             throw CcgError{CCG_ERR_ARG, "CCG_REINFLATE runs with CCG_FP64 only"};
         const auto t0 = std::chrono::steady_clock::now();
@@ -906,7 +908,7 @@ ccg_status ccg_debug_step(ccg_ctx* c, int n, int p, const double* A, int64_t lda
         std::memset(&h, 0, sizeof(DevState));
         h.done = RUNNING;
         h.m = p;
-        h.mask = (1u << p) - 1u;
+        h.mask = (p >= 32) ? 0xffffffffu : ((1u << p) - 1u);
         for (int j = 0; j < p; ++j) h.keep[j] = j;
         h.maxit = ksteps + 1;   // never reached: every step runs to the end
         h.tol = -1.0;           // no stop test
@@ -946,7 +948,8 @@ ccg_status ccg_convert_matrix(ccg_ctx* c, int n, const double* A, int64_t lda, i
 
 ccg_status ccg_tune_ad(ccg_ctx* c, int prec, int p, int n, int cw, int nw, int batched, int reps, double* us) {
     return guarded(c, [&]() -> ccg_status {
-        if (n < 1 || p < 1 || p > kMaxP || p > n || reps < 1 || !us || (cw != 1 && cw != 2 && cw != 4) ||
+        if (n < 1 || p < 1 || p > (prec == CCG_FP64 ? kMaxP : kLowMaxP) || p > n || reps < 1 || !us ||
+            (cw != 1 && cw != 2 && cw != 4) ||
             (nw != 4 && nw != 8 && nw != 16) || (batched != 0 && batched != 1))
             throw CcgError{CCG_ERR_ARG, "bad tuning argument"};
         if (prec != CCG_FP64 && prec != CCG_FP32 && prec != CCG_BF16X2) throw CcgError{CCG_ERR_ARG, "bad precision"};

@@ -266,7 +266,7 @@ __device__ __forceinline__ bool group_reduce(const double* mine, int ne, const R
 
 // ------------------------------------------------------------ small p x p algebra
 //
-// Executed by all threads of one workgroup on LDS arrays (m <= 16), with barriers
+// Executed by all threads of one workgroup on LDS arrays (m <= 32), with barriers
 // between dependent phases.  Compact m x m matrices are row-major with stride m.
 
 // Greedy pivoted Cholesky of the diagonally scaled G (unit diagonal).  Writes the
@@ -275,8 +275,9 @@ __device__ __forceinline__ bool group_reduce(const double* mine, int ne, const R
 // never taken.  Same rule as the oracle's rank step.
 __device__ __forceinline__ int wg_rank_select(const double* G, int m, double tau, int* keep, double* H, int* sh) {
     const int tid = threadIdx.x;
+    const int nth = blockDim.x;
     // sh[0]: status, sh[1]: ncand, sh[2]: ntaken, sh[3]: pivot (or -1 to stop)
-    // sh[8..8+m): candidate list, sh[32..32+m): taken list
+    // sh[8..8+m): candidate list, sh[40..40+m): taken list; H: m * m doubles
     if (tid == 0) {
         int st = 0;
         for (int i = 0; i < m && st == 0; ++i) {
@@ -290,10 +291,10 @@ __device__ __forceinline__ int wg_rank_select(const double* G, int m, double tau
     }
     __syncthreads();
     if (sh[0] != 0) return sh[0];
-    if (tid < m * m) {
-        const int i = tid / m, j = tid % m;
+    for (int t = tid; t < m * m; t += nth) {
+        const int i = t / m, j = t % m;
         const double si = sqrt(G[i * m + i]), sj = sqrt(G[j * m + j]);
-        H[tid] = (si > 0.0 && sj > 0.0) ? G[tid] / (si * sj) : 0.0;
+        H[t] = (si > 0.0 && sj > 0.0) ? G[t] / (si * sj) : 0.0;
     }
     if (tid == 0) {
         int nc = 0;
@@ -315,7 +316,7 @@ __device__ __forceinline__ int wg_rank_select(const double* G, int m, double tau
                 const double d = H[cand * m + cand];
                 if (d > tau) {
                     piv = cand;
-                    sh[32 + sh[2]] = cand;
+                    sh[40 + sh[2]] = cand;
                     sh[2] += 1;
                     for (int c = best; c + 1 < nc; ++c) sh[8 + c] = sh[8 + c + 1];
                     sh[1] = nc - 1;
@@ -328,25 +329,23 @@ __device__ __forceinline__ int wg_rank_select(const double* G, int m, double tau
         if (piv < 0) break;
         const int nc = sh[1];
         const double r = sqrt(H[piv * m + piv]);
-        double upd = 0.0;
-        int ia = -1, ic = -1;
-        if (tid < nc * nc) {
-            ia = sh[8 + tid / nc];
-            ic = sh[8 + tid % nc];
+        // entries (ic, ia) of the remaining candidates; the pivot's column, which they
+        // read, is not among them, so each thread updates its entries in place
+        for (int t = tid; t < nc * nc; t += nth) {
+            const int ia = sh[8 + t / nc];
+            const int ic = sh[8 + t % nc];
             const double lc = H[ic * m + piv] / r;
             const double la = H[ia * m + piv] / r;
-            upd = H[ic * m + ia] - lc * la;
+            H[ic * m + ia] = H[ic * m + ia] - lc * la;
         }
-        __syncthreads();
-        if (ia >= 0) H[ic * m + ia] = upd;
         __syncthreads();
     }
     if (tid == 0) {
         const int nt = sh[2];
         for (int a = 0; a < nt; ++a)
             for (int c = a + 1; c < nt; ++c)
-                if (sh[32 + c] < sh[32 + a]) { const int t = sh[32 + a]; sh[32 + a] = sh[32 + c]; sh[32 + c] = t; }
-        for (int a = 0; a < nt; ++a) keep[a] = sh[32 + a];
+                if (sh[40 + c] < sh[40 + a]) { const int t = sh[40 + a]; sh[40 + a] = sh[40 + c]; sh[40 + c] = t; }
+        for (int a = 0; a < nt; ++a) keep[a] = sh[40 + a];
     }
     __syncthreads();
     return sh[2];
@@ -537,9 +536,10 @@ __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
 // threads of the workgroup that holds them.  Writes alpha, the Cholesky factor of G
 // (kept for beta) and, on a rank drop, the active set to the state.  Returns false
 // (uniform) when the step stops: a failure, a re-inflation, or no agent left.  After
-// the caller's next barrier, ish[122] holds the active set, the factor of G is in
-// sm + kMaxP^2 (row-major, stride P) with 1 / L[i][i] at sm + 2 kMaxP^2, and alpha
-// also in aout[x * P + c] when aout is given (LDS).
+// the caller's next barrier, ish[202] holds the active set, the factor of G is in
+// sm + P^2 (row-major, stride P) with 1 / L[i][i] at sm + 2 P^2, and alpha also in
+// aout[x * P + c] when aout is given (LDS).  LDS: sm 3 P^2 + P doubles, gscr at
+// least max(WG, P^2) doubles, ish 256 ints.
 template <int P, int WG>
 __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0& s0, DevState* st, double* sm,
                                            double* gscr, int* ish, double* aout = nullptr) {
@@ -553,8 +553,8 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
     const int m0 = s0.m;
     unsigned mask = mask0;
     double* Gs = sm;                          // full symmetric P x P
-    double* Lsh = sm + kMaxP * kMaxP;         // Cholesky factor, row-major stride P
-    double* rinv = sm + 2 * kMaxP * kMaxP;    // 1 / L[i][i]
+    double* Lsh = sm + P * P;                 // Cholesky factor, row-major stride P
+    double* rinv = sm + 2 * P * P;            // 1 / L[i][i]
     double* lred = gscr;                      // per-lane values reduced by lane 0
     // G is symmetric in exact arithmetic: expand its lower triangle
     for (int t = tid; t < P * P; t += WG) {
@@ -590,21 +590,21 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
             double det = ok ? 1.0 : 0.0;
 #pragma unroll
             for (int jj = 0; jj < P; ++jj) det *= lred[jj];
-            ish[120] = (ok && det > 2.0 * tau0) ? 1 : 0;
+            ish[200] = (ok && det > 2.0 * tau0) ? 1 : 0;
         }
     }
     __syncthreads();
-    const bool fast = ish[120] != 0;
+    const bool fast = ish[200] != 0;
     if (!fast) {
-        int* act = &ish[64];    // active agents (global indices), ascending
+        int* act = &ish[96];    // active agents (global indices), ascending
         const int m = m0;
         if (tid < m) act[tid] = st->keep[tid];
         __syncthreads();
-        double* Gc = sm + 3 * kMaxP * kMaxP;   // compact m x m (below: H)
+        double* Gc = sm + 2 * P * P + P;       // compact m x m (below: H)
         double* H = gscr;
-        if (tid < m * m) Gc[tid] = Gs[act[tid / m] * P + act[tid % m]];
+        for (int t = tid; t < m * m; t += WG) Gc[t] = Gs[act[t / m] * P + act[t % m]];
         __syncthreads();
-        int* kp = &ish[96];
+        int* kp = &ish[128];
         const int r = wg_rank_select(Gc, m, tau0, kp, H, &ish[0]);
         if (r < 0) {
             if (tid == 0) fail_state(st, r == -2 ? -2 : -3);
@@ -630,10 +630,10 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
                 st->m = r;
                 st->deflations += 1;
                 if (r == 0) st->done = FINISHED;
-                ish[121] = (int)nm;
+                ish[201] = (int)nm;
             }
             __syncthreads();
-            mask = (unsigned)ish[121];
+            mask = (unsigned)ish[201];
             if (r == 0) return false;
         }
         if (wave == 0) {
@@ -649,15 +649,15 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
                 }
                 rinv[lane] = 1.0 / dg;
             }
-            if (lane == 0) ish[123] = ok ? 0 : 1;
+            if (lane == 0) ish[203] = ok ? 0 : 1;
         }
         __syncthreads();
-        if (ish[123]) {
+        if (ish[203]) {
             if (tid == 0) fail_state(st, -3);
             return false;
         }
     }
-    if (tid == 0) ish[122] = (int)mask;
+    if (tid == 0) ish[202] = (int)mask;
     if (wave != 0 || lane >= P) return true;
     // lane c: alpha[:, c] = G^{-1} (D^T R)[:, c] in this lane's registers; the factor
     // is kept for beta, which is solved from the new residual
@@ -675,7 +675,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
             if (aout) aout[x * P + c] = y[x];
         }
     } else {
-        double* Yc = sm + 3 * kMaxP * kMaxP;   // column c of alpha at Yc[x * P + c]
+        double* Yc = sm + 2 * P * P + P;       // column c of alpha at Yc[x * P + c]
 #pragma unroll 1
         for (int x = 0; x < P; ++x) Yc[x * P + c] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
         col_chol_solve_lds<P>(Lsh, rinv, Yc, c);
@@ -689,22 +689,35 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
     return true;
 }
 
+// LDS of the A.D launch's tail (ad_tail): a kernel declares it __shared__, or lays it
+// over staging buffers that are free by the time the tail runs.
+template <int P, int ROWS, int WG>
+struct TailLds {
+    double drw[ROWS * P];                     // D rows of this workgroup
+    double rrw[ROWS * P];                     // R rows of this workgroup
+    double gmine[P * (P + 1) / 2 + P * P];    // this workgroup's product shares
+    double gtot[P * (P + 1) / 2 + P * P];     // grid totals (last workgroup)
+    double sm[3 * P * P + P];                 // the p x p algebra (step_alpha)
+    double gscr[WG > P * P ? WG : P * P];     // reduction scratch, rank-step matrix
+    int ish[256];
+};
+
 // The products D^T AD and D^T R over the ROWS AD rows of workgroup `tile` (in adt,
-// LDS, row stride kMaxP, zero for rows >= n) and the D and R rows (dr, see
-// load_dr), their fixed-order reduction over the `ntiles` workgroups, and in the
-// last workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G
-// kept in the state for beta.  WG threads.
+// LDS, row stride P, zero for rows >= n) and the D and R rows (dr, see load_dr),
+// their fixed-order reduction over the `ntiles` workgroups, and in the last
+// workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G kept in
+// the state for beta.  WG threads.
 template <int PREC, int P, int ROWS, int WG>
 __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
-                                        const StepState0& s0, const DRval dr) {
+                                        const StepState0& s0, const DRval dr, TailLds<P, ROWS, WG>& L) {
     constexpr int kAdCols = ROWS;
-    __shared__ double drw[kAdCols * kMaxP];   // D rows of this workgroup
-    __shared__ double rrw[kAdCols * kMaxP];   // R rows of this workgroup
-    __shared__ double gmine[P * (P + 1) / 2 + P * P];   // this workgroup's product shares
-    __shared__ double gtot[P * (P + 1) / 2 + P * P];    // grid totals (last workgroup)
-    __shared__ double sm[4 * kMaxP * kMaxP];
-    __shared__ double gscr[WG];
-    __shared__ int ish[128];
+    double* drw = L.drw;
+    double* rrw = L.rrw;
+    double* gmine = L.gmine;
+    double* gtot = L.gtot;
+    double* sm = L.sm;
+    double* gscr = L.gscr;
+    int* ish = L.ish;
     const int tid = threadIdx.x;
     const int i0 = tile * kAdCols;
     const int iter0 = s0.iter, maxit0 = s0.maxit;
@@ -714,8 +727,8 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
     if (dr.early) {                       // one D and R value per thread (load_dr)
         if (tid < kAdCols * P) {
             const int r = tid / P, j = tid - (tid / P) * P;
-            drw[r * kMaxP + j] = dr.d;
-            rrw[r * kMaxP + j] = dr.r;
+            drw[r * P + j] = dr.d;
+            rrw[r * P + j] = dr.r;
         }
     } else {
         using TV = typename PT<PREC>::TV;
@@ -723,8 +736,8 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
             const int r = t / P, j = t - (t / P) * P;
             const int i = i0 + r;
             const int64_t o = (int64_t)j * a.n_pad + i;
-            drw[r * kMaxP + j] = i < a.n ? double(static_cast<const TV*>(a.V)[o]) : 0.0;
-            rrw[r * kMaxP + j] = i < a.n ? double(static_cast<const TV*>(a.R)[o]) : 0.0;
+            drw[r * P + j] = i < a.n ? double(static_cast<const TV*>(a.V)[o]) : 0.0;
+            rrw[r * P + j] = i < a.n ? double(static_cast<const TV*>(a.R)[o]) : 0.0;
         }
     }
     __syncthreads();
@@ -746,7 +759,7 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
             Wv = rrw;
         }
         double s = 0.0;
-        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * kMaxP + x], Wv[r * kMaxP + y], s);
+        for (int r = 0; r < kAdCols; ++r) s = fma(drw[r * P + x], Wv[r * P + y], s);
         gmine[e] = s;
     }
     __syncthreads();
@@ -784,7 +797,8 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
     static_assert(512 % KC == 0, "chunks must tile the padded length");
 
     __shared__ TV dch[2][P * KC];             // D chunk, agent-major: dch[b][j*KC + kk]
-    __shared__ double adt[kAdCols * kMaxP];   // AD rows of this workgroup
+    __shared__ double adt[kAdCols * P];       // AD rows of this workgroup
+    __shared__ TailLds<P, kAdCols, WG> tl;
 
     // every A.D launch follows the direction launch of the previous block step (if
     // any): its flag is spent
@@ -912,10 +926,10 @@ __device__ __forceinline__ void ad_tile(const AdArgs& a, const int tile, const i
         const int i = iw + c;
         const TV y = TV(v[0]);
         if (i < n) static_cast<TV*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
-        adt[(wave * kCW + c) * kMaxP + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
+        adt[(wave * kCW + c) * P + j] = (i < n) ? double(y) : 0.0;   // rows >= n hold copies
     }
     if (a.product_only) return;
-    ad_tail<PREC, P, kAdCols, WG>(a, tile, ntiles, adt, s0, dr);
+    ad_tail<PREC, P, kAdCols, WG>(a, tile, ntiles, adt, s0, dr, tl);
 }
 
 template <class CFG>
@@ -964,7 +978,9 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 template <int P, int RB, int NW>
 __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, const int ntiles) {
-    static_assert(P == 8 || P == 16, "one agent block of 16 (P = 8: agents 8..15 zero)");
+    static_assert(P == 8 || P == 16 || P == 32, "agent blocks of 16 (P = 8: agents 8..15 zero)");
+    constexpr int NB = P > 16 ? P / 16 : 1;   // agent blocks of 16
+    constexpr int PD = 16 * NB;               // staged agent rows
     constexpr int ROWS = 16 * RB;
     constexpr int WG = 64 * NW;
     constexpr int KC = 128;                   // contraction indices per chunk: one 16-byte
@@ -973,10 +989,17 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
     constexpr int KS = KC / 4 / NW;           // k-steps of 4 per wave per chunk
     constexpr int CA = ROWS / NW;             // A columns a wave loads per chunk
     constexpr int CD = (P + NW - 1) / NW;     // D agent rows a wave loads per chunk
+    constexpr int ASZ = ROWS * LD, DSZ = PD * LD;
     static_assert(KS >= 1 && CA >= 1 && ROWS % NW == 0 && KC == 2 * 64, "tile shape");
-    __shared__ double Ash[2][ROWS * LD];      // A chunk, [column][k]
-    __shared__ double Dsh[2][16 * LD];        // D chunk, [agent][k]; agents >= P zero
-    __shared__ double adt[ROWS * kMaxP];      // AD rows of this workgroup
+    using Tail = TailLds<P, ROWS, WG>;
+    static_assert(sizeof(Tail) <= sizeof(double) * 2 * (ASZ + DSZ), "the tail's LDS fits the staging buffers");
+    static_assert((NW / 2) * ROWS * P <= 2 * (ASZ + DSZ), "tree partials fit the staging buffers");
+    // two chunk buffers of A ([column][k]) and of D ([agent][k]; agents >= P zero),
+    // later the tree's partials and the tail's LDS
+    __shared__ double stage[2 * (ASZ + DSZ)];
+    __shared__ double adt[ROWS * P];          // AD rows of this workgroup
+    double* const Ash0 = stage;
+    double* const Dsh0 = stage + 2 * ASZ;
 
     if (tile == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
     if (!a.product_only && a.st->done != RUNNING) return;
@@ -992,7 +1015,7 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
     if (P < 16) {
         for (int t = tid; t < 2 * (16 - P) * LD; t += WG) {
             const int bf = t / ((16 - P) * LD), o = t - bf * ((16 - P) * LD);
-            Dsh[bf][P * LD + o] = 0.0;
+            Dsh0[bf * DSZ + P * LD + o] = 0.0;
         }
     }
     // this wave's share of a chunk: A columns wave + NW q (q < CA), lane l holding
@@ -1019,26 +1042,33 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
     auto store_chunk = [&](int bf, const d2v (&ra)[CA], const d2v (&rd)[CD]) {
 #pragma unroll
         for (int q = 0; q < CA; ++q)
-            *reinterpret_cast<d2v*>(&Ash[bf][(wave + NW * q) * LD + 2 * lane]) = ra[q];
+            *reinterpret_cast<d2v*>(&Ash0[bf * ASZ + (wave + NW * q) * LD + 2 * lane]) = ra[q];
 #pragma unroll
         for (int q = 0; q < CD; ++q) {
             const int j = wave + NW * q;
-            if (j < P) *reinterpret_cast<d2v*>(&Dsh[bf][j * LD + 2 * lane]) = rd[q];
+            if (j < P) *reinterpret_cast<d2v*>(&Dsh0[bf * DSZ + j * LD + 2 * lane]) = rd[q];
         }
     };
-    d4v acc[RB];
+    d4v acc[RB][NB];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) acc[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[b][c] = d4v{0.0, 0.0, 0.0, 0.0};
     auto mul_chunk = [&](int bf) {
-        const double* As = Ash[bf];
-        const double* Ds = Dsh[bf];
+        const double* As = Ash0 + bf * ASZ;
+        const double* Ds = Dsh0 + bf * DSZ;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int kk = 4 * (wave * KS + s) + g;
-            const double dv = Ds[r * LD + kk];
+            double dv[NB];
 #pragma unroll
-            for (int b = 0; b < RB; ++b)
-                acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(16 * b + r) * LD + kk], dv, acc[b], 0, 0, 0);
+            for (int c = 0; c < NB; ++c) dv[c] = Ds[(16 * c + r) * LD + kk];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const double av = As[(16 * b + r) * LD + kk];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, dv[c], acc[b][c], 0, 0, 0);
+            }
         }
     };
 
@@ -1092,10 +1122,9 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
     }
     __syncthreads();
 
-    // ---- the waves' partial tiles, added by a fixed tree in the (now free) A
-    // buffers; lane (c, g) holds rows g + 4 v of each row block, agent c
-    double* part = &Ash[0][0];
-    static_assert((NW / 2) * ROWS * P <= 2 * ROWS * LD, "tree partials fit the A buffers");
+    // ---- the waves' partial tiles, added by a fixed tree in the (now free) staging
+    // buffers; lane (c, g) holds rows g + 4 v of each row block, agent 16 blk + c
+    double* part = stage;
     const bool dl = r < P;
 #pragma unroll
     for (int h = NW / 2; h >= 1; h >>= 1) {
@@ -1103,15 +1132,20 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
 #pragma unroll
             for (int b = 0; b < RB; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    part[((wave - h) * ROWS + 16 * b + g + 4 * v) * P + r] = acc[b][v];
+                for (int c = 0; c < NB; ++c)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        part[((wave - h) * ROWS + 16 * b + g + 4 * v) * P + 16 * c + r] = acc[b][c][v];
         }
         __syncthreads();
         if (wave < h && dl) {
 #pragma unroll
             for (int b = 0; b < RB; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[b][v] += part[(wave * ROWS + 16 * b + g + 4 * v) * P + r];
+                for (int c = 0; c < NB; ++c)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[b][c][v] += part[(wave * ROWS + 16 * b + g + 4 * v) * P + 16 * c + r];
         }
         __syncthreads();
     }
@@ -1119,19 +1153,22 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
 #pragma unroll
         for (int b = 0; b < RB; ++b)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * b + g + 4 * v;
-                adt[row * kMaxP + r] = (i0 + row < n) ? acc[b][v] : 0.0;   // rows >= n hold copies
-            }
+            for (int c = 0; c < NB; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * b + g + 4 * v;
+                    adt[row * P + 16 * c + r] = (i0 + row < n) ? acc[b][c][v] : 0.0;   // rows >= n hold copies
+                }
     }
     __syncthreads();
     // AD rows to memory, each agent's ROWS rows contiguous
     for (int t = tid; t < ROWS * P; t += WG) {
         const int j = t / ROWS, row = t - (t / ROWS) * ROWS;
-        if (i0 + row < n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i0 + row] = adt[row * kMaxP + j];
+        if (i0 + row < n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i0 + row] = adt[row * P + j];
     }
     if (a.product_only) return;
-    ad_tail<PREC_F64, P, ROWS, WG>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false});
+    ad_tail<PREC_F64, P, ROWS, WG>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false},
+                                   *reinterpret_cast<Tail*>(stage));
 }
 
 template <int P, int RB, int NW>
@@ -1409,8 +1446,9 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
     constexpr int NO = kFinRows * P;          // outputs of the workgroup
     constexpr int TPO = kWG / NO;             // threads per output
     constexpr int U = 16;                     // loads in flight per thread
-    __shared__ double adt[kFinRows * kMaxP];
+    __shared__ double adt[kFinRows * P];
     __shared__ double sub[kWG];
+    __shared__ TailLds<P, kFinRows, kWG> tl;
     // (k_sym does not read the state: this launch spends the direction flag)
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
     if (a.st->done != RUNNING) return;
@@ -1440,10 +1478,10 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
         const int r = tid / P, j = tid - (tid / P) * P;
         const int i = i0 + r;
         if (i < a.n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i] = y;
-        adt[r * kMaxP + j] = (i < a.n) ? y : 0.0;
+        adt[r * P + j] = (i < a.n) ? y : 0.0;
     }
     // ad_tail's first barrier orders these adt writes before their use
-    ad_tail<PREC_F64, P, kFinRows, kWG>(a, blockIdx.x, gridDim.x, adt, s0, dr);
+    ad_tail<PREC_F64, P, kFinRows, kWG>(a, blockIdx.x, gridDim.x, adt, s0, dr, tl);
 }
 
 // ============ k_upd: X += D alpha, R -= AD alpha, and the products of the new residual
@@ -1452,7 +1490,66 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // RB = 256 / P rows.  Each workgroup forms its rows' share of (AD)^T R_new (P x P)
 // and of diag(R_new^T R_new) (P values), summed in row order; the last workgroup of
 // each group of kGroup blocks adds up its group's shares in block order.  The
-// direction launch adds up the group sums.
+// direction launch adds up the group sums.  At P = 32 the group sums are P^2 + P =
+// 1056 values, and every direction workgroup adding all of them up would read
+// about a quarter of a gigabyte per step at n = 8192: there the update's reduction
+// runs to the grid total, and its last workgroup solves beta and runs the stop test
+// once (beta_step); the direction launch reads beta from the state.
+
+// beta = -G^{-1} (AD)^T R_new (tot: the totals, P x P then the P squared norms) with
+// the factor of G the A.D launch kept in the state, the new norms, and the stop test
+// at the top of the next step (Alg. 4: smallest agent residual relative to ||b||),
+// by one workgroup of NTH threads.  Writes beta, the norms, the step count and the
+// stop decision to the state.  LDS: Lsh, wsh P^2, rinv P, lred 64 doubles.
+template <int P, int NTH>
+__device__ __forceinline__ void beta_step(const double* tot, DevState* st, double* Lsh, double* wsh, double* rinv,
+                                          double* lred) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const unsigned mask = st->mask;
+    for (int t = tid; t < P * P; t += NTH) Lsh[t] = st->L[(t / P) * kMaxP + (t % P)];
+    __syncthreads();
+    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+    __syncthreads();
+    if (wave != 0) return;
+    if (lane < P) {
+        const int c = lane;
+        const bool ac = (mask >> c) & 1u;
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
+#pragma unroll 1
+        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = wsh[x * P + c];
+    }
+    double q = INFINITY, bad = 0.0;
+    if (lane < P && ((mask >> lane) & 1u)) {
+        const double nr = sqrt(tot[P * P + lane]);
+        st->norms[lane] = nr;
+        if (!isfinite(nr)) bad = 1.0;
+        q = nr / st->nb;
+    }
+    if (lane < P) {
+        lred[lane] = q;
+        lred[32 + lane] = bad;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane == 0) {
+        double mn = INFINITY, anybad = 0.0;
+        for (int jj = 0; jj < P; ++jj) {
+            mn = fmin(mn, lred[jj]);
+            anybad += lred[32 + jj];
+        }
+        const int it = st->iter + 1;
+        st->minres = mn;
+        st->iter = it;
+        if (anybad > 0.0) fail_state(st, -2);
+        else if (mn <= st->tol) st->done = RECUR_CONV;
+        else if (it >= st->maxit) st->done = MAXIT;
+    }
+}
 
 template <int PREC, int P>
 __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
@@ -1471,7 +1568,7 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
     const int64_t i = (int64_t)tile * RB + r;
     const int64_t o = (int64_t)j * a.n_pad + i;
     if (tile == 0 && tid == 0) st->dir_pending = 1;
-    if (tid < P * P) al[tid] = st->alpha[(tid / P) * kMaxP + (tid % P)];
+    for (int t = tid; t < P * P; t += kWG) al[t] = st->alpha[(t / P) * kMaxP + (t % P)];
     TV* X = static_cast<TV*>(a.X);
     TV* R = static_cast<TV*>(a.R);
     const double x0 = X[o];
@@ -1503,7 +1600,14 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
         mine[e] = s;
     }
     __syncthreads();
-    (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
+    if constexpr (P >= 32) {
+        if (!grid_reduce<kGroup, kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles)) return;
+        __syncthreads();
+        // (al, mine, adt, rt: free now) the beta step's LDS
+        beta_step<P, kWG>(gsum, st, al, mine, adt, rt);
+    } else {
+        (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
+    }
 }
 
 template <int PREC, int P>
@@ -1525,6 +1629,29 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
     constexpr int NE = P * P + P;
+    if constexpr (P >= 32) {
+        // beta, the norms and the stop decision come from the update's last workgroup
+        __shared__ double bs[P * P];
+        __shared__ double ds[RB * P];
+        DevState* st = a.st;
+        const int tid = threadIdx.x;
+        const int r = tid % RB, j = tid / RB;
+        const int64_t o = (int64_t)j * a.n_pad + (int64_t)blk * RB + r;
+        const int pending = st->dir_pending;
+        const unsigned mask = st->mask;
+        TV* D = static_cast<TV*>(a.D);
+        const double rv = double(static_cast<const TV*>(a.R)[o]);
+        const double dv = double(D[o]);
+        if (!pending) return;
+        for (int t = tid; t < P * P; t += kWG) bs[t] = st->beta[(t / P) * kMaxP + (t % P)];
+        ds[r * P + j] = dv;
+        __syncthreads();
+        double sd = rv;
+#pragma unroll
+        for (int l = 0; l < P; ++l) sd = fma(ds[r * P + l], bs[l * P + j], sd);
+        D[o] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+        return;
+    } else {
     __shared__ double tot[NE];
     __shared__ double be[P * P];
     __shared__ double Lsh[P * P], rinv[P], wsh[P * P];
@@ -1627,6 +1754,7 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
         if (anybad > 0.0) fail_state(st, -2);
         else if (mn <= st->tol) st->done = RECUR_CONV;
         else if (it >= st->maxit) st->done = MAXIT;
+    }
     }
 }
 
@@ -1778,7 +1906,9 @@ inline hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int ni
 __host__ __device__ constexpr bool ad_cw4_fits(int prec, int P) {
     return P < 16 && (prec != PREC_F64 || P <= 4);
 }
-__host__ __device__ constexpr bool ad_has_mfma(int prec, int P) { return prec == PREC_F64 && (P == 16 || P == 8); }
+__host__ __device__ constexpr bool ad_has_mfma(int prec, int P) {
+    return prec == PREC_F64 && (P == 32 || P == 16 || P == 8);
+}
 __host__ __device__ constexpr int ad_nw_fit(int prec, int P, int nw) {
     return (P >= 16 && !ad_has_mfma(prec, P)) ? 4 : (nw >= 16 ? 16 : (nw >= 8 ? 8 : 4));
 }
@@ -1789,6 +1919,7 @@ __host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw, int nw) {
     }
     if (ad_has_mfma(prec, P)) {
         const int w = ad_nw_fit(prec, P, nw);
+        if (w == 4 && P == 32) return 4;                      // matrix cores only
         if (w == 4) return cw >= 4 ? 4 : (cw >= 2 ? 2 : 1);   // 4: matrix cores; 1, 2: vector
         if (w == 8) return cw >= 4 ? 4 : 2;
         return cw >= 2 ? 2 : 1;
@@ -1841,6 +1972,14 @@ inline hipError_t launch_ad_w(int nw, const AdArgs* one, const AdArgs* sys, cons
 template <int PREC, int P>
 inline hipError_t launch_ad_pc(int cw, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                                int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (P == 32) {                  // FP64 matrix cores only
+        if constexpr (!ad_has_mfma(PREC, P)) {
+            return hipErrorInvalidValue;
+        } else {
+            const int w = ad_nw_fit(PREC, P, nw), c = ad_cw_fit(PREC, P, cw, nw);
+            return launch_ad_mfma<P>(c * w, w, one, sys, items, nitems, s, e0, e1);
+        }
+    }
     if constexpr (ad_has_mfma(PREC, P)) {
         const int w = ad_nw_fit(PREC, P, nw), c = ad_cw_fit(PREC, P, cw, nw);
         if (P == 16 ? c * w >= 16 : c == 4) return launch_ad_mfma<P>(c * w, w, one, sys, items, nitems, s, e0, e1);
@@ -1861,6 +2000,9 @@ inline hipError_t launch_ad_prec(int P, int cw, int nw, const AdArgs* one, const
         case 4: return launch_ad_pc<PREC, 4>(cw, nw, one, sys, items, nitems, s, e0, e1);
         case 8: return launch_ad_pc<PREC, 8>(cw, nw, one, sys, items, nitems, s, e0, e1);
         case 16: return launch_ad_pc<PREC, 16>(cw, nw, one, sys, items, nitems, s, e0, e1);
+        case 32:
+            if constexpr (PREC == PREC_F64) return launch_ad_pc<PREC, 32>(cw, nw, one, sys, items, nitems, s, e0, e1);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1961,9 +2103,9 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
     __shared__ TV dsh[P * N], adsh[P * N], rsh[P * N], xsh[P * N];   // agent-major: [j * N + k]
     __shared__ double part[NT];
     __shared__ double g1[NE1], g2[NE2];
-    __shared__ double sm[4 * kMaxP * kMaxP];
+    __shared__ double sm[3 * P * P + P];
     __shared__ double gscr[NT];
-    __shared__ int ish[128];
+    __shared__ int ish[256];
     __shared__ double al[P * P], be[P * P];
     __shared__ double lred[64];
     __shared__ StepState0 ss;
@@ -1978,8 +2120,8 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
     TV* D = static_cast<TV*>(a.D);
     const int64_t lda = a.lda;
     const int nr = (n + 63) & ~63;
-    const double* Lf = sm + kMaxP * kMaxP;        // step_alpha's factor of G, stride P
-    const double* rinv = sm + 2 * kMaxP * kMaxP;
+    const double* Lf = sm + P * P;                // step_alpha's factor of G, stride P
+    const double* rinv = sm + 2 * P * P;
     if (tid == 0) {
         ss = read_state0(st);
         ctl = st->done == RUNNING ? 1 : 0;
@@ -2093,7 +2235,7 @@ __device__ __forceinline__ void small_steps(const SmallArgs& a, const int steps)
         const bool go = step_alpha<P, NT>(g1, s0, st, sm, gscr, ish, al);
         __syncthreads();
         if (!go) break;
-        const unsigned mask = (unsigned)ish[122];
+        const unsigned mask = (unsigned)ish[202];
         // ---- X += D alpha, R_new = R - AD alpha (rows < n)
 #pragma unroll 1
         for (int q = 0; q < PER; ++q) {

@@ -239,6 +239,18 @@ static hipError_t launch_res_t(const ResArgs& a, hipStream_t s) {
         default: return hipErrorInvalidValue;                          \
     }
 
+// FP64 single systems also run P = 32 (the batched engine takes p <= 16)
+#define CCG_DISPATCH_P64(P, CALL)                                      \
+    switch (P) {                                                       \
+        case 1: return CALL(1);                                        \
+        case 2: return CALL(2);                                        \
+        case 4: return CALL(4);                                        \
+        case 8: return CALL(8);                                        \
+        case 16: return CALL(16);                                      \
+        case 32: return CALL(32);                                      \
+        default: return hipErrorInvalidValue;                          \
+    }
+
 static hipError_t launch_ad_any(int prec, int P, int cw, int nw, const AdArgs* one, const AdArgs* sys,
                                 const int4* items, int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (prec) {
@@ -294,7 +306,7 @@ hipError_t launch_upd(int prec, int P, const UpdArgs& a, hipStream_t s) {
     switch (prec) {
 #define C64(PP) launch_upd_t<PREC_F64, PP>(a, s)
 #define C32(PP) launch_upd_t<PREC_F32, PP>(a, s)
-        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F64: CCG_DISPATCH_P64(P, C64)
         case PREC_F32:
         case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
 #undef C64
@@ -307,7 +319,7 @@ hipError_t launch_dir(int prec, int P, const UpdArgs& a, hipStream_t s) {
     switch (prec) {
 #define C64(PP) launch_dir_t<PREC_F64, PP>(a, s)
 #define C32(PP) launch_dir_t<PREC_F32, PP>(a, s)
-        case PREC_F64: CCG_DISPATCH_P(P, C64)
+        case PREC_F64: CCG_DISPATCH_P64(P, C64)
         case PREC_F32:
         case PREC_BF16X2: CCG_DISPATCH_P(P, C32)
 #undef C64
@@ -377,7 +389,7 @@ hipError_t launch_res_batch(int P, const ResArgs* sys, const int4* items, int ni
 
 hipError_t launch_res(int P, const ResArgs& a, hipStream_t s) {
 #define CR(PP) launch_res_t<PP>(a, s)
-    CCG_DISPATCH_P(P, CR)
+    CCG_DISPATCH_P64(P, CR)
 #undef CR
 }
 

@@ -40,6 +40,7 @@ static const TuneRow kTuneTable[] = {
     {PREC_F64, 8, 1073741824, 2, 8},
     {PREC_F64, 16, 3072, 2, 8},
     {PREC_F64, 16, 1073741824, 4, 8},
+    {PREC_F64, 32, 1073741824, 4, 8},
     {PREC_F32, 1, 192, 1, 4},
     {PREC_F32, 1, 384, 2, 4},
     {PREC_F32, 1, 1536, 4, 4},

@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "csrc", "ccg_tune_table.h")
 
 PRECS = (("fp64", "PREC_F64"), ("fp32", "PREC_F32"), ("bf16x2", "PREC_BF16X2"))
-AGENTS = (1, 2, 4, 8, 16)
+AGENTS = (1, 2, 4, 8, 16)      # (32: FP64 only, timed with --agents 32 --prec fp64)
 SIZES = (128, 256, 512, 1024, 2048, 4096, 8192, 16384)
 WIDTHS = (1, 2, 4)
 WAVES = (4, 8, 16)
@@ -47,13 +47,16 @@ WIDE_P = (8,)
 
 # Shapes that run the FP64 matrix-core tile (ad_has_mfma, ad_cw_fit): 16 or 32 rows
 # per workgroup (cw * nw), nw waves splitting the contraction.
-MFMA_SHAPES = {8: ((4, 4), (4, 8)), 16: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16))}
+MFMA_SHAPES = {8: ((4, 4), (4, 8)), 16: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16)),
+               32: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16))}
 
 
 def shapes(prec: str, P: int):
     """Candidate (columns per wave, waves per workgroup), as the library runs them
     (ad_cw_fit, ad_nw_fit): vector tiles with 4 columns where they fit and more than
     4 waves at WIDE_P, then the FP64 matrix-core shapes."""
+    if P == 32:                # the matrix-core tile only (FP64)
+        return list(MFMA_SHAPES[32]) if prec == "fp64" else []
     ws = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
     if P >= 16:
         ws = [w for w in ws if w <= 2]

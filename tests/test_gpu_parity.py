@@ -309,7 +309,7 @@ def test_errors_are_reported(gpu_ctx):
     with pytest.raises(CcgError):
         gpu_ctx.solve(_t(A), _t(b), _t(X0), -1.0, 100)
     with pytest.raises(CcgError):
-        gpu_ctx.solve(_t(A), _t(b), _t(np.zeros((64, 17))), 1e-10, 100)
+        gpu_ctx.solve(_t(A), _t(b), _t(np.zeros((64, 33))), 1e-10, 100)   # p <= 32
     # the context still works afterwards
     X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 200)
     assert info["status"] == 0
@@ -614,3 +614,71 @@ def test_mfma_batched_equals_single(gpu_ctx):
         X1, i1 = gpu_ctx.solve(sy["A"], sy["b"], sy["X0"], 1e-10, 20000, ad_cw=4, ad_nw=8)
         assert ib["status"] == i1["status"] == 0
         assert ib["iters"] == i1["iters"] and torch.equal(Xb, X1)
+
+
+# ------------------------------------- 32 agents (FP64 single solves, matrix-core A.D)
+
+P32_SHAPES = [(4, 4), (2, 8), (4, 8), (1, 16), (2, 16)]
+# p padded to 32 from 17 and 20; several tiles with a ragged last one; the last
+# 128-index chunk partial (n = 2085, 1000, 300)
+P32_CASES = [(2085, 32, 1e4, 4), (1000, 20, 1e3, 4), (640, 32, 1e2, 4), (300, 17, 1e2, 3)]
+_P32_ORACLE = {}
+
+
+def _p32_oracle(n, p, kappa, k):
+    key = (n, p, kappa, k)
+    if key not in _P32_ORACLE:
+        A, b, X0 = ci.system(n, p, kappa, seed=408)
+        f64 = oracle.ccg(A, b, X0, tol=0.0, maxit=k, trace_k=k, want_rd=True)
+        ext = oracle.ccg(A, b, X0, tol=0.0, maxit=k, trace_k=k, want_rd=True, lib=oracle.extended())
+        _P32_ORACLE[key] = (A, b, X0, f64, ext)
+    return _P32_ORACLE[key]
+
+
+@pytest.mark.parametrize("shape", P32_SHAPES)
+@pytest.mark.parametrize("n,p,kappa,k", P32_CASES)
+def test_p32_steps_match_oracle(gpu_ctx, n, p, kappa, k, shape):
+    """p = 17..32 (P = 32): A.D on the matrix cores with two agent blocks, the update
+    launch's grid-wide reduction and its beta step, the direction launch reading beta
+    from the state; each step held to the oracle by the rule of _steps_close."""
+    print(f"case p32 debug_step n={n} p={p} k={k} shape={shape}", flush=True)
+    A, b, X0, f64, ext = _p32_oracle(n, p, kappa, k)
+    g = gpu_ctx.debug_step(_t(A), _t(b), _t(X0), k, ad_cw=shape[0], ad_nw=shape[1])
+    _steps_close(g, f64, ext, k)
+
+
+def test_p32_solve_at_benchmark_tolerance(gpu_ctx):
+    """p = 32 to tol 1e-10: every agent column within 1e-10 of the extended-precision
+    run for the same steps, or as close as the FP64 oracle; the stopping step within 5 %
+    of the oracle's; the explicit residual meets tol; a rerun is bit-identical."""
+    n, p = 2000, 32
+    A, b, X0 = ci.system(n, p, 1e3, seed=409)
+    tol = 1e-10
+    orc = oracle.ccg(A, b, X0, tol=tol, maxit=20000)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 20000)
+    assert info["status"] == 0 and info["restarts"] == 0, info
+    _check_against_oracle(A, b, X0, X, info, tol, orc, gap=np.inf)
+    k = info["iters"]
+    ext = oracle.ccg(A, b, X0, tol=0.0, maxit=k, lib=oracle.extended())
+    f64 = oracle.ccg(A, b, X0, tol=0.0, maxit=k)
+    Xg = X.cpu().numpy()
+    for j in range(p):
+        assert _rel(Xg[:, j], ext["X"][:, j]) <= max(1e-10, _rel(f64["X"][:, j], ext["X"][:, j])), j
+    X2, info2 = gpu_ctx.solve(_t(A), _t(b), _t(X0), tol, 20000)
+    assert info2["iters"] == k and torch.equal(X2, X)
+
+
+def test_p32_limits(gpu_ctx):
+    """p up to 32 in FP64 single solves; the low-precision modes and the batched
+    engine take p <= 16, and p = 33 is refused."""
+    A, b, X0 = ci.system(200, 33, 10.0, seed=410)
+    _, bad = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100, raise_on_error=False)
+    assert bad["status"] == -1
+    X17 = _t(X0[:, :17])
+    for prec in ("fp32", "bf16x2"):
+        _, lo = gpu_ctx.solve(_t(A), _t(b), X17, 1e-10, 100, raise_on_error=False, prec=prec)
+        assert lo["status"] == -1
+    res = gpu_ctx.solve_batched([dict(A=_t(A), b=_t(b), X0=X17, tol=1e-10, maxit=100)])
+    assert res[0][1]["status"] == -1
+    _, ok = gpu_ctx.solve(_t(A), _t(b), X17, 1e-10, 20000)
+    assert ok["status"] == 0

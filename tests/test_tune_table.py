@@ -44,6 +44,8 @@ def test_candidate_shapes_follow_the_register_rules():
         assert all(nw == 4 and w <= 2 for w, nw in tune.shapes(prec, 16))
     assert tune.shapes("fp64", 16) == [(1, 4), (2, 4)] + list(tune.MFMA_SHAPES[16])
     assert tune.DEFAULT in tune.shapes("bf16x2", 1)
+    # P = 32: FP64 on the matrix cores only
+    assert tune.shapes("fp64", 32) == list(tune.MFMA_SHAPES[32]) and tune.shapes("fp32", 32) == []
     # wider vector workgroups only where the engine was measured not to lose with them
     for prec in ("fp64", "fp32", "bf16x2"):
         for P in (1, 2, 4, 8, 16):
@@ -97,6 +99,7 @@ def test_committed_table_is_valid():
     last = {}
     for c, P, n_max, w, nw in rows:
         assert c in ("PREC_F64", "PREC_F32", "PREC_BF16X2")
-        assert P in (1, 2, 4, 8, 16) and w in (1, 2, 4) and nw in (4, 8, 16)
+        assert P in (1, 2, 4, 8, 16, 32) and w in (1, 2, 4) and nw in (4, 8, 16)
+        assert P < 32 or (c == "PREC_F64" and w * nw >= 16), "P = 32: FP64 matrix-core shapes only"
         assert n_max > last.get((c, P), 0), "rows of one class must grow in n"
         last[(c, P)] = n_max
