@@ -432,12 +432,15 @@ __device__ __forceinline__ void col_chol_solve_lds(const double* L, const double
 // the textbook order; each pivot divides through its reciprocal.
 template <int P>
 __device__ __forceinline__ void col_chol_solve(const double* L, const double* rinv, double (&y)[P]) {
+    // (above P = 8 a scheduling barrier per row keeps the compiler from hoisting
+    // every row's factor loads at once, which would not fit the registers)
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         double s = y[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
         y[i] = s * rinv[i];
+        if constexpr (P > 8) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = P - 1; i >= 0; --i) {
@@ -445,6 +448,7 @@ __device__ __forceinline__ void col_chol_solve(const double* L, const double* ri
 #pragma unroll
         for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * y[k];
         y[i] = s * rinv[i];
+        if constexpr (P > 8) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -540,7 +544,7 @@ __device__ __forceinline__ DRval load_dr(const AdArgs& a, int i0) {
 // sm + P^2 (row-major, stride P) with 1 / L[i][i] at sm + 2 P^2, and alpha also in
 // aout[x * P + c] when aout is given (LDS).  LDS: sm 3 P^2 + P doubles, gscr at
 // least max(WG, P^2) doubles, ish 256 ints.
-template <int P, int WG>
+template <int P, int WG, bool REG = (P <= 8)>
 __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0& s0, DevState* st, double* sm,
                                            double* gscr, int* ish, double* aout = nullptr) {
     constexpr int OS = P * (P + 1) / 2;
@@ -663,7 +667,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
     // is kept for beta, which is solved from the new residual
     const int c = lane;
     const bool ac = (mask >> c) & 1u;
-    if constexpr (P <= 8) {
+    if constexpr (REG) {
         double y[P];
 #pragma unroll
         for (int x = 0; x < P; ++x) y[x] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
@@ -707,7 +711,9 @@ struct TailLds {
 // their fixed-order reduction over the `ntiles` workgroups, and in the last
 // workgroup the rank step (Alg. 3) and alpha, with the Cholesky factor of G kept in
 // the state for beta.  WG threads.
-template <int PREC, int P, int ROWS, int WG>
+// REG: the alpha solve in registers (one right-hand side per lane) at every P; the
+// A.D kernels whose streams leave the registers for it (the matrix-core tile) set it.
+template <int PREC, int P, int ROWS, int WG, bool REG = (P <= 8)>
 __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const int ntiles, const double* adt,
                                         const StepState0& s0, const DRval dr, TailLds<P, ROWS, WG>& L) {
     constexpr int kAdCols = ROWS;
@@ -772,7 +778,7 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
         if (tid == 0) st->done = MAXIT;
         return;
     }
-    (void)step_alpha<P, WG>(gtot, s0, st, sm, gscr, ish);
+    (void)step_alpha<P, WG, REG>(gtot, s0, st, sm, gscr, ish);
 }
 
 // One tile (NW * CW rows of AD) of the block step of one system; `tile` of `ntiles`.
@@ -1167,8 +1173,8 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
         if (i0 + row < n) static_cast<double*>(a.AD)[(int64_t)j * a.n_pad + i0 + row] = adt[row * P + j];
     }
     if (a.product_only) return;
-    ad_tail<PREC_F64, P, ROWS, WG>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false},
-                                   *reinterpret_cast<Tail*>(stage));
+    ad_tail<PREC_F64, P, ROWS, WG, true>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false},
+                                         *reinterpret_cast<Tail*>(stage));
 }
 
 template <int P, int RB, int NW>
@@ -1500,10 +1506,9 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // the factor of G the A.D launch kept in the state, the new norms, and the stop test
 // at the top of the next step (Alg. 4: smallest agent residual relative to ||b||),
 // by one workgroup of NTH threads.  Writes beta, the norms, the step count and the
-// stop decision to the state.  LDS: Lsh, wsh P^2, rinv P, lred 64 doubles.
+// stop decision to the state.  LDS: Lsh P^2, rinv P, lred 64 doubles.
 template <int P, int NTH>
-__device__ __forceinline__ void beta_step(const double* tot, DevState* st, double* Lsh, double* wsh, double* rinv,
-                                          double* lred) {
+__device__ __forceinline__ void beta_step(const double* tot, DevState* st, double* Lsh, double* rinv, double* lred) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1516,11 +1521,12 @@ __device__ __forceinline__ void beta_step(const double* tot, DevState* st, doubl
     if (lane < P) {
         const int c = lane;
         const bool ac = (mask >> c) & 1u;
-#pragma unroll 1
-        for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-        col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
-#pragma unroll 1
-        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = wsh[x * P + c];
+        double w[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = w[x];
     }
     double q = INFINITY, bad = 0.0;
     if (lane < P && ((mask >> lane) & 1u)) {
@@ -1603,8 +1609,8 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
     if constexpr (P >= 32) {
         if (!grid_reduce<kGroup, kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles)) return;
         __syncthreads();
-        // (al, mine, adt, rt: free now) the beta step's LDS
-        beta_step<P, kWG>(gsum, st, al, mine, adt, rt);
+        // (al, adt, rt: free now) the beta step's LDS
+        beta_step<P, kWG>(gsum, st, al, adt, rt);
     } else {
         (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
     }
@@ -1654,7 +1660,7 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
     } else {
     __shared__ double tot[NE];
     __shared__ double be[P * P];
-    __shared__ double Lsh[P * P], rinv[P], wsh[P * P];
+    __shared__ double Lsh[P * P], rinv[P];
     __shared__ double lred[64];
     __shared__ double dt[RB * P];
     DevState* st = a.st;
@@ -1703,20 +1709,12 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
         // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
         const int c = lane;
         const bool ac = (mask >> c) & 1u;
-        if constexpr (P <= 8) {
-            double w[P];
+        double w[P];
 #pragma unroll
-            for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-            col_chol_solve<P>(Lsh, rinv, w);
+        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, w);
 #pragma unroll
-            for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
-        } else {
-#pragma unroll 1
-            for (int x = 0; x < P; ++x) wsh[x * P + c] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-            col_chol_solve_lds<P>(Lsh, rinv, wsh, c);
-#pragma unroll 1
-            for (int x = 0; x < P; ++x) be[x * P + c] = wsh[x * P + c];
-        }
+        for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
     }
     __syncthreads();
     double sd = rv;

@@ -2,8 +2,8 @@
 // agent count and system size.  Written by `python -m paper_1204_0069_amd.tune`
 // from timings of every candidate shape on the GPU; the first row whose (prec, P)
 // match and whose n_max >= n applies, and a size no row covers uses 2 and 4.
-// Tuned on: AMD Instinct MI355X (timings of tune_ad_widths_mi355x.txt; FP64 P = 16:
-// the matrix-core shapes of mfma_ad_tile_shapes_fp64.md), 2026-12-03.
+// Tuned on: AMD Instinct MI355X (timings of tune_ad_widths_mi355x.txt; FP64 P = 16 and
+// P = 32: the matrix-core shapes of mfma_ad_tile_shapes_fp64.md), 2026-12-03.
 #pragma once
 
 namespace ccg {
@@ -40,7 +40,8 @@ static const TuneRow kTuneTable[] = {
     {PREC_F64, 8, 1073741824, 2, 8},
     {PREC_F64, 16, 3072, 2, 8},
     {PREC_F64, 16, 1073741824, 4, 8},
-    {PREC_F64, 32, 1073741824, 4, 8},
+    {PREC_F64, 32, 3072, 1, 16},
+    {PREC_F64, 32, 1073741824, 2, 16},
     {PREC_F32, 1, 192, 1, 4},
     {PREC_F32, 1, 384, 2, 4},
     {PREC_F32, 1, 1536, 4, 4},
