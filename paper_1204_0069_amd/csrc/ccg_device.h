@@ -20,9 +20,17 @@ constexpr int kGroup = 32;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 
-// Row tiling of the update and direction launches: one workgroup per block of
-// kWG / P rows (one element per thread).
-__host__ __device__ inline int upd_blocks(int n_pad, int P) { return n_pad / (256 / P); }
+// Row tiling of the update and direction launches (the same for both): one workgroup per block of
+// kWG / P rows (one element per thread), or at P = 32, where both run on the matrix
+// cores, per block of kUpdWideRows rows (4 waves of 16).
+constexpr int kUpdWideRows = 64;
+static_assert(kRowAlign % kUpdWideRows == 0, "wide update tiles must divide the row padding");
+__host__ __device__ inline int upd_blocks(int n_pad, int P) {
+    return P >= 32 ? n_pad / kUpdWideRows : n_pad / (256 / P);
+}
+// Workgroups per first-level group of the update's product reduction: at P = 32 the
+// 1056 values per workgroup make a group of 16 one round of loads for its summer.
+__host__ __device__ constexpr int upd_group(int P) { return P >= 32 ? 16 : kGroup; }
 
 // Device iteration state, one per solve.  Written only by "last workgroup"
 // epilogues and by the residual kernel; read by every kernel at entry.

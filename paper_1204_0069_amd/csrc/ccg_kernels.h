@@ -203,6 +203,36 @@ __device__ __forceinline__ void sum_table(const double* src, int ne, int cnt, do
     }
 }
 
+// The same for ne <= K * NTH with every thread owning the K entries tid + k * NTH:
+// the rows are loaded B at a time for all K entries together (K * B loads in flight)
+// and added in row order, so each entry gets the bits sum_table gives it.
+template <int K, int B, int NTH>
+__device__ __forceinline__ void sum_table_k(const double* src, int ne, int cnt, double* out) {
+    const int tid = threadIdx.x;
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int base = 0; base < cnt; base += B) {
+        double v[K][B];
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int e = tid + k * NTH;
+                v[k][q] = (base + q < cnt && e < ne) ? ld_agent(&src[(int64_t)(base + q) * ne + e]) : 0.0;
+            }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (base + q < cnt) s[k] += v[k][q];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (tid + k * NTH < ne) out[tid + k * NTH] = s[k];
+    __syncthreads();
+}
+
 // Sum `ne` values per tile (mine[], LDS) over the nwg tiles of one system, in tile
 // order within groups of kGroup and in group order across groups.  Returns true in
 // the one workgroup that ends up holding the totals in out[] (LDS).  Tickets are
@@ -242,16 +272,16 @@ __device__ __forceinline__ bool grid_reduce(const double* mine, int ne, const Re
     return true;
 }
 
-// The first level of grid_reduce alone: the last workgroup of each group of kGroup
+// The first level of grid_reduce alone: the last workgroup of each group of GS
 // tiles sums its group's rows (tile order) into rb.l2[grp].  Returns true in that
 // workgroup.  The group sums are read by a later launch, which adds them up in
-// group order.
-template <int B, int NTH>
+// group order.  K > 0 (ne <= K * NTH): the rows go through sum_table_k, B at a time.
+template <int B, int NTH, int GS = kGroup, int K = 0>
 __device__ __forceinline__ bool group_reduce(const double* mine, int ne, const RedBuf rb, double* out,
                                              int* s_flag, double* scratch, int bid, int nwg) {
     const int tid = threadIdx.x;
-    const int grp = bid / kGroup;
-    const int gsize = min(kGroup, nwg - grp * kGroup);
+    const int grp = bid / GS;
+    const int gsize = min(GS, nwg - grp * GS);
     for (int e = tid; e < ne; e += NTH) st_agent(&rb.l1[(int64_t)bid * ne + e], mine[e]);
     stores_done();
     __syncthreads();
@@ -259,7 +289,8 @@ __device__ __forceinline__ bool group_reduce(const double* mine, int ne, const R
     __syncthreads();
     if (!*s_flag) return false;
     if (tid == 0) reset_ticket(&rb.cnt[grp]);
-    sum_table<B, NTH>(rb.l1 + (int64_t)grp * kGroup * ne, ne, gsize, out, scratch);
+    if constexpr (K > 0) sum_table_k<K, B, NTH>(rb.l1 + (int64_t)grp * GS * ne, ne, gsize, out);
+    else sum_table<B, NTH>(rb.l1 + (int64_t)grp * GS * ne, ne, gsize, out, scratch);
     for (int e = tid; e < ne; e += NTH) st_agent(&rb.l2[(int64_t)grp * ne + e], out[e]);
     return true;
 }
@@ -428,26 +459,78 @@ __device__ __forceinline__ void col_chol_solve_lds(const double* L, const double
 }
 
 // y <- (L L^T)^{-1} y for one right-hand side held by this lane.  L is row-major
-// (stride P) in LDS, rinv[i] = 1 / L[i][i].  Forward then backward substitution in
-// the textbook order; each pivot divides through its reciprocal.
-template <int P>
+// (stride P) in LDS, rinv[i] = 1 / L[i][i].  Every entry receives its terms in the
+// textbook order (forward: k = 0, 1, ..., i - 1; backward: k = i + 1, ..., P - 1) and
+// is then scaled by its reciprocal pivot.
+// Forward, column-oriented: once y[k] is final, its multiples of column k are taken
+// off the entries below, so the P - 1 - k updates of one k are independent and the
+// dependent chain is two operations per k instead of one per term.  Backward, row by
+// row (a column order would add the terms from P - 1 down).  The factor entries of the
+// next column or row are loaded while the current one is used; a scheduling barrier
+// per step keeps the compiler from hoisting every step's loads at once.
+// LEAN: row by row in both halves without the look-ahead, one row's factor entries
+// live at a time, for kernels whose waves have 128 registers (16-wave workgroups),
+// where two columns in registers would spill at P = 32.
+template <int P, bool LEAN = false>
 __device__ __forceinline__ void col_chol_solve(const double* L, const double* rinv, double (&y)[P]) {
-    // (above P = 8 a scheduling barrier per row keeps the compiler from hoisting
-    // every row's factor loads at once, which would not fit the registers)
+    if constexpr (LEAN) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        double s = y[i];
+        for (int i = 0; i < P; ++i) {
+            double s = y[i];
 #pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
-        y[i] = s * rinv[i];
+            for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
+            y[i] = s * rinv[i];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = P - 1; i >= 0; --i) {
+            double s = y[i];
+#pragma unroll
+            for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * y[k];
+            y[i] = s * rinv[i];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
+    double c[P], ri;
+#pragma unroll
+    for (int i = 1; i < P; ++i) c[i] = L[i * P];
+    ri = rinv[0];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double nx[P], nri = 0.0;
+        if (k + 1 < P) {
+#pragma unroll
+            for (int i = k + 2; i < P; ++i) nx[i] = L[i * P + k + 1];
+            nri = rinv[k + 1];
+        }
+        y[k] = y[k] * ri;
+#pragma unroll
+        for (int i = k + 1; i < P; ++i) y[i] -= c[i] * y[k];
+#pragma unroll
+        for (int i = k + 2; i < P; ++i) c[i] = nx[i];
+        ri = nri;
         if constexpr (P > 8) __builtin_amdgcn_sched_barrier(0);
     }
+    // backward: row i takes column i of L below the diagonal, c[k] = L[k][i] (k > i)
+#pragma unroll
+    for (int k = 0; k < P; ++k) c[k] = 0.0;
+    ri = rinv[P - 1];
 #pragma unroll
     for (int i = P - 1; i >= 0; --i) {
+        double nx[P], nri = 0.0;
+        if (i > 0) {
+#pragma unroll
+            for (int k = i; k < P; ++k) nx[k] = L[k * P + i - 1];
+            nri = rinv[i - 1];
+        }
         double s = y[i];
 #pragma unroll
-        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * y[k];
-        y[i] = s * rinv[i];
+        for (int k = i + 1; k < P; ++k) s -= c[k] * y[k];
+        y[i] = s * ri;
+#pragma unroll
+        for (int k = i; k < P; ++k) c[k] = nx[k];
+        ri = nri;
         if constexpr (P > 8) __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -671,7 +754,7 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
         double y[P];
 #pragma unroll
         for (int x = 0; x < P; ++x) y[x] = (ac && ((mask >> x) & 1u)) ? St[x * P + c] : 0.0;
-        col_chol_solve<P>(Lsh, rinv, y);
+        col_chol_solve<P, (P > 16 && WG > 512)>(Lsh, rinv, y);
 #pragma unroll
         for (int x = 0; x < P; ++x) {
             st->alpha[x * kMaxP + c] = y[x];
@@ -1496,74 +1579,147 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // RB = 256 / P rows.  Each workgroup forms its rows' share of (AD)^T R_new (P x P)
 // and of diag(R_new^T R_new) (P values), summed in row order; the last workgroup of
 // each group of kGroup blocks adds up its group's shares in block order.  The
-// direction launch adds up the group sums.  At P = 32 the group sums are P^2 + P =
-// 1056 values, and every direction workgroup adding all of them up would read
-// about a quarter of a gigabyte per step at n = 8192: there the update's reduction
-// runs to the grid total, and its last workgroup solves beta and runs the stop test
-// once (beta_step); the direction launch reads beta from the state.
+// direction launch adds up the group sums.
+//
+// At P = 32 (FP64) both launches run on the matrix cores instead, 64 rows per
+// workgroup (upd_tile_mma, dir_tile_mma): with one element per thread the update's
+// LDS traffic for the 32-term row sums, not memory, set its time, and 64-row blocks
+// make 16 times fewer group shares of the P^2 + P = 1056 products for the direction
+// launch to add up.
 
-// beta = -G^{-1} (AD)^T R_new (tot: the totals, P x P then the P squared norms) with
-// the factor of G the A.D launch kept in the state, the new norms, and the stop test
-// at the top of the next step (Alg. 4: smallest agent residual relative to ||b||),
-// by one workgroup of NTH threads.  Writes beta, the norms, the step count and the
-// stop decision to the state.  LDS: Lsh P^2, rinv P, lred 64 doubles.
-template <int P, int NTH>
-__device__ __forceinline__ void beta_step(const double* tot, DevState* st, double* Lsh, double* rinv, double* lred) {
+// v_mfma_f64_16x16x4f64 operand layouts, lane l = 16 g + r (r = l % 16, g = l / 16):
+// A (16 x 4): A(r, g); B (4 x 16): B(g, r); C (16 x 16): C(g + 4 v, r), v = 0..3.
+//
+// The update of one wave's 16 rows i0.. (agents in blocks of 16, cb):
+//   X_new(i0 + g + 4v, 16 cb + r) = X(...) + sum_k D(i0 + r', k) alpha(k, 16 cb + r)
+// as P / 4 products with A = D(i0 + r, 4 kk + g), B = alpha(4 kk + g, 16 cb + r)
+// accumulated onto C = X (and R with AD and -alpha).  The products of the new residual,
+//   (AD)^T R_new (x, y) += sum over the 16 rows of AD(i, x) R_new(i, y),
+// take the rows as the contraction index in 4 steps s: A = AD(i0 + 4s + g, 16 xb + r)
+// (AD loaded a second time, in the C layout) and B = R_new(i0 + 4s + g, 16 yb + r),
+// which is the update's output element v = s in place.
+template <int P>
+__device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, const int ntiles) {
+    static_assert(P % 16 == 0 && kUpdWideRows == 64 && kWG == 256, "4 waves of 16 rows, agent blocks of 16");
+    constexpr int NB = P / 16;                  // agent blocks
+    constexpr int KK = P / 4;                   // k-steps of the update
+    constexpr int NE = P * P + P;               // (AD)^T R_new, then diag(R_new^T R_new)
+    __shared__ double part[4][NE];              // the waves' shares
+    __shared__ double nsh[4][4][P];             // norm partials [wave][g][agent]
+    __shared__ double gsum[NE];
+    __shared__ int ish[4];
+    DevState* st = a.st;
+    if (st->done != RUNNING) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const unsigned mask = st->mask;
-    for (int t = tid; t < P * P; t += NTH) Lsh[t] = st->L[(t / P) * kMaxP + (t % P)];
-    __syncthreads();
-    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
-    __syncthreads();
-    if (wave != 0) return;
-    if (lane < P) {
-        const int c = lane;
-        const bool ac = (mask >> c) & 1u;
-        double w[P];
+    const int r = lane & 15, g = lane >> 4;
+    if (tile == 0 && tid == 0) st->dir_pending = 1;
+    const int64_t np = a.n_pad;
+    const int64_t i0 = (int64_t)tile * kUpdWideRows + 16 * wave;
+    double* X = static_cast<double*>(a.X);
+    double* R = static_cast<double*>(a.R);
+    const double* D = static_cast<const double*>(a.D);
+    const double* AD = static_cast<const double*>(a.AD);
+    double da[KK], aa[KK], al[KK][NB];
+    d4v xc[NB], rc[NB], ac[NB];
 #pragma unroll
-        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-        col_chol_solve<P>(Lsh, rinv, w);
+    for (int kk = 0; kk < KK; ++kk) {
+        da[kk] = D[(4 * kk + g) * np + i0 + r];
+        aa[kk] = AD[(4 * kk + g) * np + i0 + r];
+    }
 #pragma unroll
-        for (int x = 0; x < P; ++x) st->beta[x * kMaxP + c] = w[x];
-    }
-    double q = INFINITY, bad = 0.0;
-    if (lane < P && ((mask >> lane) & 1u)) {
-        const double nr = sqrt(tot[P * P + lane]);
-        st->norms[lane] = nr;
-        if (!isfinite(nr)) bad = 1.0;
-        q = nr / st->nb;
-    }
-    if (lane < P) {
-        lred[lane] = q;
-        lred[32 + lane] = bad;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (lane == 0) {
-        double mn = INFINITY, anybad = 0.0;
-        for (int jj = 0; jj < P; ++jj) {
-            mn = fmin(mn, lred[jj]);
-            anybad += lred[32 + jj];
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t o = (16 * cb + r) * np + i0 + g + 4 * v;
+            xc[cb][v] = X[o];
+            rc[cb][v] = R[o];
+            ac[cb][v] = AD[o];
         }
-        const int it = st->iter + 1;
-        st->minres = mn;
-        st->iter = it;
-        if (anybad > 0.0) fail_state(st, -2);
-        else if (mn <= st->tol) st->done = RECUR_CONV;
-        else if (it >= st->maxit) st->done = MAXIT;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) al[kk][cb] = st->alpha[(4 * kk + g) * kMaxP + 16 * cb + r];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            xc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], al[kk][cb], xc[cb], 0, 0, 0);
+            rc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[kk], -al[kk][cb], rc[cb], 0, 0, 0);
+        }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t o = (16 * cb + r) * np + i0 + g + 4 * v;
+            X[o] = xc[cb][v];
+            R[o] = rc[cb][v];
+        }
+    d4v pg[NB][NB];
+#pragma unroll
+    for (int xb = 0; xb < NB; ++xb)
+#pragma unroll
+        for (int yb = 0; yb < NB; ++yb) pg[xb][yb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int xb = 0; xb < NB; ++xb)
+#pragma unroll
+            for (int yb = 0; yb < NB; ++yb)
+                pg[xb][yb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[xb][s], rc[yb][s], pg[xb][yb], 0, 0, 0);
+#pragma unroll
+    for (int xb = 0; xb < NB; ++xb)
+#pragma unroll
+        for (int yb = 0; yb < NB; ++yb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[wave][(16 * xb + g + 4 * v) * P + 16 * yb + r] = pg[xb][yb][v];
+#pragma unroll
+    for (int yb = 0; yb < NB; ++yb) {
+        double q = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q = fma(rc[yb][v], rc[yb][v], q);
+        nsh[wave][g][16 * yb + r] = q;
     }
+    __syncthreads();
+    // the workgroup's share: waves in order (the norms: each wave's rows g + 4v by g)
+    double* mine = &part[0][0];
+    for (int e = tid; e < NE; e += kWG) {
+        double t;
+        if (e < P * P) {
+            t = part[0][e] + part[1][e] + part[2][e] + part[3][e];
+        } else {
+            const int y = e - P * P;
+            t = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) t += nsh[w][gg][y];
+        }
+        mine[e] = t;          // (entry e of wave 0's share: read above by this thread only)
+    }
+    __syncthreads();
+    // (a group's 16 rows for the thread's NE / kWG entries: one round of loads)
+    (void)group_reduce<upd_group(P), kWG, upd_group(P), (NE + kWG - 1) / kWG>(mine, NE, a.red, gsum, &ish[0], nullptr,
+                                                                            tile, ntiles);
 }
 
 template <int PREC, int P>
 __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
+    if constexpr (P >= 32) {
+        static_assert(PREC == PREC_F64, "32 agents: FP64 only");
+        upd_tile_mma<P>(a, tile, ntiles);
+        return;
+    } else {
     using TV = typename PT<PREC>::TV;
     constexpr int RB = kWG / P;
+    // Row stride of the row blocks in LDS: P + 1, so that the RB rows read together in
+    // the update (one address per row, all lanes of a row alike) fall in distinct banks;
+    // with stride P they share one bank and every such read is an RB-way conflict.
+    constexpr int PS = P + 1;
     constexpr int NE = P * P + P;       // (AD)^T R_new, then diag(R_new^T R_new)
     __shared__ double al[P * P];
-    __shared__ double dt[RB * P], adt[RB * P], rt[RB * P];
+    __shared__ double dt[RB * PS], adt[RB * PS], rt[RB * PS];
     __shared__ double mine[NE], gsum[NE];
     __shared__ double gscr[kWG];
     __shared__ int ish[4];
@@ -1579,40 +1735,34 @@ __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const
     TV* R = static_cast<TV*>(a.R);
     const double x0 = X[o];
     const double r0 = R[o];
-    dt[r * P + j] = static_cast<const TV*>(a.D)[o];
-    adt[r * P + j] = static_cast<const TV*>(a.AD)[o];
+    dt[r * PS + j] = static_cast<const TV*>(a.D)[o];
+    adt[r * PS + j] = static_cast<const TV*>(a.AD)[o];
     __syncthreads();
     double sx = 0.0, sr = 0.0;
 #pragma unroll
     for (int l = 0; l < P; ++l) {
-        sx = fma(dt[r * P + l], al[l * P + j], sx);
-        sr = fma(adt[r * P + l], al[l * P + j], sr);
+        sx = fma(dt[r * PS + l], al[l * P + j], sx);
+        sr = fma(adt[r * PS + l], al[l * P + j], sr);
     }
     const TV xn = TV(x0 + sx);
     const TV rn = TV(r0 - sr);
     X[o] = xn;
     R[o] = rn;
-    rt[r * P + j] = double(rn);
+    rt[r * PS + j] = double(rn);
     __syncthreads();
     for (int e = tid; e < NE; e += kWG) {
         double s = 0.0;
         if (e < P * P) {
             const int x = e / P, y = e - (e / P) * P;
-            for (int q = 0; q < RB; ++q) s = fma(adt[q * P + x], rt[q * P + y], s);
+            for (int q = 0; q < RB; ++q) s = fma(adt[q * PS + x], rt[q * PS + y], s);
         } else {
             const int y = e - P * P;
-            for (int q = 0; q < RB; ++q) s = fma(rt[q * P + y], rt[q * P + y], s);
+            for (int q = 0; q < RB; ++q) s = fma(rt[q * PS + y], rt[q * PS + y], s);
         }
         mine[e] = s;
     }
     __syncthreads();
-    if constexpr (P >= 32) {
-        if (!grid_reduce<kGroup, kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles)) return;
-        __syncthreads();
-        // (al, adt, rt: free now) the beta step's LDS
-        beta_step<P, kWG>(gsum, st, al, adt, rt);
-    } else {
-        (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
+    (void)group_reduce<(P >= 8 ? kGroup : 16), kWG>(mine, NE, a.red, gsum, &ish[0], gscr, tile, ntiles);
     }
 }
 
@@ -1630,99 +1780,14 @@ __global__ __launch_bounds__(kWG) void k_upd(UpdArgs a) {
 // active agents).  Workgroup 0 also ends the step in the state: the stop test on the
 // new residual norms (Alg. 4: smallest agent residual relative to ||b||), beta,
 // and the step count.
-template <int PREC, int P>
-__device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const int ngrp) {
-    using TV = typename PT<PREC>::TV;
-    constexpr int RB = kWG / P;
-    constexpr int NE = P * P + P;
-    if constexpr (P >= 32) {
-        // beta, the norms and the stop decision come from the update's last workgroup
-        __shared__ double bs[P * P];
-        __shared__ double ds[RB * P];
-        DevState* st = a.st;
-        const int tid = threadIdx.x;
-        const int r = tid % RB, j = tid / RB;
-        const int64_t o = (int64_t)j * a.n_pad + (int64_t)blk * RB + r;
-        const int pending = st->dir_pending;
-        const unsigned mask = st->mask;
-        TV* D = static_cast<TV*>(a.D);
-        const double rv = double(static_cast<const TV*>(a.R)[o]);
-        const double dv = double(D[o]);
-        if (!pending) return;
-        for (int t = tid; t < P * P; t += kWG) bs[t] = st->beta[(t / P) * kMaxP + (t % P)];
-        ds[r * P + j] = dv;
-        __syncthreads();
-        double sd = rv;
-#pragma unroll
-        for (int l = 0; l < P; ++l) sd = fma(ds[r * P + l], bs[l * P + j], sd);
-        D[o] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
-        return;
-    } else {
-    __shared__ double tot[NE];
-    __shared__ double be[P * P];
-    __shared__ double Lsh[P * P], rinv[P];
-    __shared__ double lred[64];
-    __shared__ double dt[RB * P];
-    DevState* st = a.st;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int r = tid % RB, j = tid / RB;
-    const int64_t i = (int64_t)blk * RB + r;
-    const int64_t o = (int64_t)j * a.n_pad + i;
-    // (loads only before the flag is tested: nothing is written unless it is set)
-    const int pending = st->dir_pending;
-    const unsigned mask = st->mask;
-    TV* D = static_cast<TV*>(a.D);
-    const double rv = double(static_cast<const TV*>(a.R)[o]);
-    const double dv = double(D[o]);
-    const double lv = tid < P * P ? st->L[(tid / P) * kMaxP + (tid % P)] : 0.0;
-    // totals of the update's products: its group sums added in group order (the
-    // loads of up to 32 groups in flight together)
-    double tv[2] = {0.0, 0.0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = tid + h * kWG;
-        if (e < NE) {
-            double s = 0.0;
-            for (int g0 = 0; g0 < ngrp; g0 += kGroup) {
-                double v[kGroup];
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t) v[t] = (g0 + t < ngrp) ? a.red.l2[(int64_t)(g0 + t) * NE + e] : 0.0;
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t)
-                    if (g0 + t < ngrp) s += v[t];
-            }
-            tv[h] = s;
-        }
-    }
-    if (!pending) return;
-    dt[r * P + j] = dv;
-    if (tid < P * P) Lsh[tid] = lv;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-        if (tid + h * kWG < NE) tot[tid + h * kWG] = tv[h];
-    __syncthreads();
-    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
-    __syncthreads();
-    if (wave == 0 && lane < P) {
-        // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
-        const int c = lane;
-        const bool ac = (mask >> c) & 1u;
-        double w[P];
-#pragma unroll
-        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
-        col_chol_solve<P>(Lsh, rinv, w);
-#pragma unroll
-        for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
-    }
-    __syncthreads();
-    double sd = rv;
-#pragma unroll
-    for (int l = 0; l < P; ++l) sd = fma(dt[r * P + l], be[l * P + j], sd);
-    D[o] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
-    if (blk != 0 || wave != 0) return;
-    // ---- workgroup 0: the step's report and the stop rule at the top of the next step
+// The step's report and the stop rule at the top of the next step (Alg. 4: smallest
+// agent residual relative to ||b||), by wave 0 of the direction launch's workgroup 0:
+// the norms from the totals tot (P x P products, then the P squared norms), beta
+// (be: row-major, stride P) to the state, the step count and the stop decision.
+// lred: 64 doubles of LDS.
+template <int P>
+__device__ __forceinline__ void dir_report(DevState* st, const double* tot, const double* be, double* lred,
+                                           const unsigned mask, const int lane) {
     double q = INFINITY, bad = 0.0;
     if (lane < P && ((mask >> lane) & 1u)) {
         const double nr = sqrt(tot[P * P + lane]);
@@ -1753,12 +1818,178 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
         else if (mn <= st->tol) st->done = RECUR_CONV;
         else if (it >= st->maxit) st->done = MAXIT;
     }
+}
+
+// Totals of the update's products: its ngrp group sums (rows of NE values in l2) added
+// in group order, for the entries tid + h * kWG of this thread, GB groups' loads in
+// flight together.
+template <int NE, int GB>
+__device__ __forceinline__ void sum_groups(const double* l2, const int ngrp, double (&tv)[(NE + kWG - 1) / kWG]) {
+    constexpr int NH = (NE + kWG - 1) / kWG;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) tv[h] = 0.0;
+    for (int g0 = 0; g0 < ngrp; g0 += GB) {
+        double v[NH][GB];
+#pragma unroll
+        for (int t = 0; t < GB; ++t)
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const int e = tid + h * kWG;
+                v[h][t] = (g0 + t < ngrp && e < NE) ? l2[(int64_t)(g0 + t) * NE + e] : 0.0;
+            }
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int t = 0; t < GB; ++t)
+                if (g0 + t < ngrp) tv[h] += v[h][t];
+    }
+}
+
+// P = 32 (FP64): the direction update on the matrix cores, 64 rows per workgroup, a
+// wave 16 of them: D_new = R_new + D beta as P / 4 products with A = D(i0 + r, 4 kk + g)
+// and B = beta(4 kk + g, 16 cb + r) accumulated onto C = R_new (layouts as in
+// upd_tile_mma).  Every workgroup adds up the group sums and solves beta itself.
+template <int P>
+__device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, const int ngrp) {
+    static_assert(P % 16 == 0 && kUpdWideRows == 64 && kWG == 256 && (P * P) % kWG == 0, "tile shape");
+    constexpr int NB = P / 16, KK = P / 4;
+    constexpr int NE = P * P + P;
+    constexpr int NH = (NE + kWG - 1) / kWG;
+    constexpr int NL = P * P / kWG;
+    __shared__ double tot[NE];
+    __shared__ double be[P * P];
+    __shared__ double Lsh[P * P], rinv[P];
+    __shared__ double lred[64];
+    DevState* st = a.st;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t np = a.n_pad;
+    const int64_t i0 = (int64_t)blk * kUpdWideRows + 16 * wave;
+    // (loads only before the flag is tested: nothing is written unless it is set)
+    const int pending = st->dir_pending;
+    const unsigned mask = st->mask;
+    double* D = static_cast<double*>(a.D);
+    const double* R = static_cast<const double*>(a.R);
+    double da[KK], lv[NL], tv[NH];
+    d4v dc[NB];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) da[kk] = D[(4 * kk + g) * np + i0 + r];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dc[cb][v] = R[(16 * cb + r) * np + i0 + g + 4 * v];
+#pragma unroll
+    for (int h = 0; h < NL; ++h) {
+        const int t = tid + h * kWG;
+        lv[h] = st->L[(t / P) * kMaxP + (t % P)];
+    }
+    sum_groups<NE, 16>(a.red.l2, ngrp, tv);
+    if (!pending) return;
+#pragma unroll
+    for (int h = 0; h < NL; ++h) Lsh[tid + h * kWG] = lv[h];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+        if (tid + h * kWG < NE) tot[tid + h * kWG] = tv[h];
+    __syncthreads();
+    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+    __syncthreads();
+    if (wave == 0 && lane < P) {
+        // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
+        const int c = lane;
+        const bool ac = (mask >> c) & 1u;
+        double w[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+            dc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], be[(4 * kk + g) * P + 16 * cb + r], dc[cb], 0, 0, 0);
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        const bool on = (mask >> (16 * cb + r)) & 1u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D[(16 * cb + r) * np + i0 + g + 4 * v] = on ? dc[cb][v] : 0.0;
+    }
+    if (blk != 0 || wave != 0) return;
+    dir_report<P>(st, tot, be, lred, mask, lane);
+}
+
+template <int PREC, int P>
+__device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const int ngrp) {
+    if constexpr (P >= 32) {
+        static_assert(PREC == PREC_F64, "32 agents: FP64 only");
+        dir_tile_mma<P>(a, blk, ngrp);
+        return;
+    } else {
+    using TV = typename PT<PREC>::TV;
+    constexpr int RB = kWG / P;
+    constexpr int PS = P + 1;           // LDS row stride (see upd_tile)
+    constexpr int NE = P * P + P;
+    constexpr int NH = (NE + kWG - 1) / kWG;
+    __shared__ double tot[NE];
+    __shared__ double be[P * P];
+    __shared__ double Lsh[P * P], rinv[P];
+    __shared__ double lred[64];
+    __shared__ double dt[RB * PS];
+    DevState* st = a.st;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = tid % RB, j = tid / RB;
+    const int64_t i = (int64_t)blk * RB + r;
+    const int64_t o = (int64_t)j * a.n_pad + i;
+    // (loads only before the flag is tested: nothing is written unless it is set)
+    const int pending = st->dir_pending;
+    const unsigned mask = st->mask;
+    TV* D = static_cast<TV*>(a.D);
+    const double rv = double(static_cast<const TV*>(a.R)[o]);
+    const double dv = double(D[o]);
+    const double lv = tid < P * P ? st->L[(tid / P) * kMaxP + (tid % P)] : 0.0;
+    // totals of the update's products (kGroup loads in flight per thread)
+    double tv[NH];
+    sum_groups<NE, kGroup / NH>(a.red.l2, ngrp, tv);
+    if (!pending) return;
+    dt[r * PS + j] = dv;
+    if (tid < P * P) Lsh[tid] = lv;
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+        if (tid + h * kWG < NE) tot[tid + h * kWG] = tv[h];
+    __syncthreads();
+    if (tid < P) rinv[tid] = 1.0 / Lsh[tid * P + tid];
+    __syncthreads();
+    if (wave == 0 && lane < P) {
+        // lane c: beta[:, c] = -G^{-1} ((AD)^T R_new)[:, c]
+        const int c = lane;
+        const bool ac = (mask >> c) & 1u;
+        double w[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) w[x] = (ac && ((mask >> x) & 1u)) ? -tot[x * P + c] : 0.0;
+        col_chol_solve<P>(Lsh, rinv, w);
+#pragma unroll
+        for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
+    }
+    __syncthreads();
+    double sd = rv;
+#pragma unroll
+    for (int l = 0; l < P; ++l) sd = fma(dt[r * PS + l], be[l * P + j], sd);
+    D[o] = ((mask >> j) & 1u) ? TV(sd) : TV(0);
+    if (blk != 0 || wave != 0) return;
+    dir_report<P>(st, tot, be, lred, mask, lane);
     }
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir(UpdArgs a) {
-    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P) + kGroup - 1) / kGroup);
+    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
 }
 
 template <int PREC, int P>
@@ -1772,7 +2003,7 @@ template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P) + kGroup - 1) / kGroup);
+    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
 }
 
 // ============================================ k_res: T = B - Y, norms, restart
