@@ -1581,11 +1581,11 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // each group of kGroup blocks adds up its group's shares in block order.  The
 // direction launch adds up the group sums.
 //
-// At P = 32 (FP64) both launches run on the matrix cores instead, 64 rows per
-// workgroup (upd_tile_mma, dir_tile_mma): with one element per thread the update's
-// LDS traffic for the 32-term row sums, not memory, set its time, and 64-row blocks
-// make 16 times fewer group shares of the P^2 + P = 1056 products for the direction
-// launch to add up.
+// At P = 32, and at P = 16 in FP64, both launches run on the matrix cores instead, 64
+// rows per workgroup (upd_tile_mma, dir_tile_mma): with one element per thread the
+// update's LDS traffic for the P-term row sums, not memory, set its time, and 64-row
+// blocks make 16 (P = 32) or 4 (P = 16) times fewer group shares of the P^2 + P
+// products for the direction launch to add up.
 
 // v_mfma_f64_16x16x4f64 operand layouts, lane l = 16 g + r (r = l % 16, g = l / 16):
 // A (16 x 4): A(r, g); B (4 x 16): B(g, r); C (16 x 16): C(g + 4 v, r), v = 0..3.
@@ -1706,8 +1706,8 @@ __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, c
 
 template <int PREC, int P>
 __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
-    if constexpr (P >= 32) {
-        static_assert(PREC == PREC_F64, "32 agents: FP64 only");
+    if constexpr (upd_mma(P, PREC)) {
+        static_assert(PREC == PREC_F64, "the matrix-core update is FP64");
         upd_tile_mma<P>(a, tile, ntiles);
         return;
     } else {
@@ -1846,7 +1846,7 @@ __device__ __forceinline__ void sum_groups(const double* l2, const int ngrp, dou
     }
 }
 
-// P = 32 (FP64): the direction update on the matrix cores, 64 rows per workgroup, a
+// P = 16 and 32 (FP64): the direction update on the matrix cores, 64 rows per workgroup, a
 // wave 16 of them: D_new = R_new + D beta as P / 4 products with A = D(i0 + r, 4 kk + g)
 // and B = beta(4 kk + g, 16 cb + r) accumulated onto C = R_new (layouts as in
 // upd_tile_mma).  Every workgroup adds up the group sums and solves beta itself.
@@ -1925,8 +1925,8 @@ __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, co
 
 template <int PREC, int P>
 __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const int ngrp) {
-    if constexpr (P >= 32) {
-        static_assert(PREC == PREC_F64, "32 agents: FP64 only");
+    if constexpr (upd_mma(P, PREC)) {
+        static_assert(PREC == PREC_F64, "the matrix-core update is FP64");
         dir_tile_mma<P>(a, blk, ngrp);
         return;
     } else {
@@ -1989,21 +1989,21 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir(UpdArgs a) {
-    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
+    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P, PREC) + upd_group(P) - 1) / upd_group(P));
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    upd_tile<PREC, P>(a, it.y, upd_blocks(a.n_pad, P));
+    upd_tile<PREC, P>(a, it.y, upd_blocks(a.n_pad, P, PREC));
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
+    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P, PREC) + upd_group(P) - 1) / upd_group(P));
 }
 
 // ============================================ k_res: T = B - Y, norms, restart
