@@ -232,7 +232,7 @@ inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P, bool sym 
 
 inline void check_common(int n, int p, const void* A, int64_t lda, const void* b, const void* X, int64_t ldx) {
     if (n < 1 || p < 1 || p > kMaxP || p > n)
-        throw CcgError{CCG_ERR_ARG, "need 1 <= p <= min(n, 16)"};
+        throw CcgError{CCG_ERR_ARG, "need 1 <= p <= min(n, 32)"};
     if (!A || !b || !X) throw CcgError{CCG_ERR_ARG, "null pointer argument"};
     if (lda < n || ldx < n) throw CcgError{CCG_ERR_ARG, "leading dimension smaller than n"};
 }

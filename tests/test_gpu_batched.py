@@ -27,7 +27,7 @@ def _t(x):
 MIXED = [  # n, p, kappa, prec
     (64, 2, 1e2, "fp64"), (256, 3, 1e3, "fp64"), (777, 2, 1e2, "fp64"), (1000, 5, 1e3, "fp64"),
     (129, 4, 10.0, "fp64"), (640, 16, 1e2, "fp64"), (300, 1, 1e3, "fp64"), (2085, 8, 1e4, "fp64"),
-    (500, 4, 1e3, "fp32"), (96, 2, 1e2, "fp32"), (1100, 8, 1e3, "fp32"),
+    (500, 4, 1e3, "fp32"), (96, 2, 1e2, "fp32"), (1100, 8, 1e3, "fp32"), (900, 12, 1e2, "fp32"),
     (400, 3, 1e2, "bf16x2"), (700, 8, 1e3, "bf16x2"),
 ]
 
@@ -55,7 +55,7 @@ def _same(a, b):
 
 
 def test_batched_equals_single_solves(gpu_ctx):
-    print("case batched mixed 13 systems", flush=True)
+    print(f"case batched mixed {len(MIXED)} systems", flush=True)
     systems = _systems(MIXED)
     singles = [_single(gpu_ctx, sy) for sy in systems]
     batched = gpu_ctx.solve_batched(systems)
@@ -133,7 +133,7 @@ def test_batched_workload_of_many_sizes(gpu_ctx):
 # ---------------------------------------------------------------- served mode
 
 def test_served_equals_single_solves(gpu_ctx):
-    print("case served 13 systems", flush=True)
+    print(f"case served {len(MIXED)} systems", flush=True)
     systems = _systems(MIXED, seed=1000)
     singles = [_single(gpu_ctx, sy) for sy in systems]
     ctx = Context(0)

@@ -37,8 +37,9 @@ def _same(Xs, is_, Xn, inn):
 
 
 def test_noalloc_matches_solve_on_two_calls(gpu_ctx):
-    # first a larger system, then a smaller one in the same scratch
-    for n, p, kappa, seed in [(2000, 8, 1e3, 71), (700, 3, 1e3, 72)]:
+    # first larger systems (P = 32 and P = 16 on the matrix-core update launches,
+    # then P = 8), then a smaller one in the same scratch
+    for n, p, kappa, seed in [(1500, 20, 1e2, 74), (1800, 12, 1e2, 75), (2000, 8, 1e3, 71), (700, 3, 1e3, 72)]:
         print(f"case noalloc n={n} p={p}", flush=True)
         A, b, X0 = ci.system(n, p, kappa, seed=seed)
         Xs, is_, Xn, inn = _both(gpu_ctx, _t(A), _t(b), _t(X0), 1e-10, 20000)
