@@ -580,6 +580,7 @@ struct StepState0 {
     unsigned mask;
     double nb, tol, tau;
     int iter, maxit, m;
+    int ad_streams;      // (only the A.D launch's last workgroup advances it)
 };
 __device__ __forceinline__ StepState0 read_state0(const DevState* st) {
     StepState0 s;
@@ -590,6 +591,7 @@ __device__ __forceinline__ StepState0 read_state0(const DevState* st) {
     s.iter = st->iter;
     s.maxit = st->maxit;
     s.m = st->m;
+    s.ad_streams = st->ad_streams;
     return s;
 }
 
@@ -650,15 +652,18 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
         Gs[t] = gtot[hi * (hi + 1) / 2 + lo];
     }
     __syncthreads();
-    // Fast path: when det of the diagonally scaled G exceeds 2 tau, every pivot of
-    // the greedy pivoted factorisation is larger than tau (each pivot of a unit-
-    // diagonal PSD matrix, in any order, is >= its determinant), so the rank step
-    // keeps every agent; the slow path below runs the greedy rule itself.
+    // Fast path: the greedy pivoted factorisation of the diagonally scaled G (Alg. 3)
+    // takes its pivots in non-increasing order (each elimination only lowers the
+    // remaining diagonal, and the largest is taken), and its last pivot is
+    // 1 / (G^-1)_ll of the scaled G for the index l taken last, so every pivot is at
+    // least 1 / max_l (scaled G^-1)_ll.  When that exceeds 2 tau (a margin for the
+    // rounding of the estimate) the rank step keeps every agent, and the factor of G in
+    // agent order is the one the slow path below would form after running the greedy
+    // rule itself.  (scaled G^-1)_ll = G_ll ||L^-1 e_l||^2: lane l solves L y = e_l.
     if (wave == 0) {
         double g[P];
         row_load<P>(g, Gs, P, mask, true, lane);
         const bool ok = row_cholesky<P>(g, lane);
-        double ratio = 1.0;
         if (lane < P) {
             double dg = 1.0;
 #pragma unroll
@@ -667,17 +672,36 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
                 if (b == lane) dg = g[b];
             }
             rinv[lane] = 1.0 / dg;
-            if (ok && ((mask >> lane) & 1u)) ratio = (dg * dg) / Gs[lane * P + lane];
-            lred[lane] = ratio;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane < P) {
+            double q = INFINITY;
+            if (ok) {
+                double y[P];
+                q = 0.0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    double t = (k == lane) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int j = 0; j < k; ++j) t -= Lsh[k * P + j] * y[j];
+                    y[k] = t * rinv[k];
+                    q = fma(y[k], y[k], q);
+                }
+                if ((mask >> lane) & 1u) q *= Gs[lane * P + lane];
+            }
+            lred[lane] = q;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         if (lane == 0) {
-            double det = ok ? 1.0 : 0.0;
+            double mq = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < P; ++jj) det *= lred[jj];
-            ish[200] = (ok && det > 2.0 * tau0) ? 1 : 0;
+            for (int jj = 0; jj < P; ++jj) mq = (lred[jj] > mq || lred[jj] != lred[jj]) ? lred[jj] : mq;
+            // (no factor: q = INFINITY; a NaN is kept: either way the test fails)
+            ish[200] = (ok && mq * (2.0 * tau0) < 1.0) ? 1 : 0;
         }
     }
     __syncthreads();
@@ -856,7 +880,9 @@ __device__ __forceinline__ void ad_tail(const AdArgs& a, const int tile, const i
 
     // ---- last workgroup: rank step (Alg. 3) and alpha
     DevState* st = a.st;
-    if (tid == 0) st->ad_streams += 1;
+    // (the count read at entry: a load here would hold wave 0, and so the rank step,
+    // for a memory round trip)
+    if (tid == 0) st->ad_streams = s0.ad_streams + 1;
     if (iter0 >= maxit0) {                    // (the update launch stops the steps first)
         if (tid == 0) st->done = MAXIT;
         return;
