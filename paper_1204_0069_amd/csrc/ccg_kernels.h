@@ -32,6 +32,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ccg {
 
@@ -1299,6 +1300,246 @@ __global__ __launch_bounds__(64 * NW) void k_ad_mfma_batch(const AdArgs* __restr
     ad_tile_mfma<P, RB, NW>(a, it.y, (a.n + 16 * RB - 1) / (16 * RB));
 }
 
+// ---------------- A.D on the matrix cores with FP32 operands (FP32 and BF16x2 A, P = 8 or 16)
+//
+// The low-precision modes stream A in 4 bytes per element (FP32, or the BF16 hi and lo
+// planes) and keep D in FP32.  At P = 16 that is 8 flops per byte of A, which the vector
+// path (FP32 FMAs on D values read from LDS) cannot sustain at the HBM rate.
+// v_mfma_f32_16x16x4_f32 multiplies FP32 operands with FP32 accumulation, so A enters
+// it as the value the vector path uses (for BF16x2, hi + lo, exact in FP32).  Lane l
+// supplies A(row l % 16, k-slot l / 16) and D(k-slot l / 16, agent l % 16), as in the
+// FP64 tile, but receives the result rows 4 (l / 16) + v, v = 0..3 (checked on the
+// device).  Chunks of KC = 256 contraction indices: one 16-byte load (FP32) or one
+// 8-byte load per plane (BF16x2) per lane covers a column; A is converted to FP32 as it
+// is stored to LDS.  Double buffering, the waves' split of the k-steps, the fixed tree
+// of the waves' partial tiles and the tail are those of the FP64 tile.  At P = 8 the
+// lanes of agents 8..15 carry zeros.
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+template <int PREC, int P, int RB, int NW>
+__device__ __forceinline__ void ad_tile_mma32(const AdArgs& a, const int tile, const int ntiles) {
+    static_assert((PREC == PREC_F32 || PREC == PREC_BF16X2) && (P == 8 || P == 16), "FP32 operands, one agent block");
+    constexpr bool BF = PREC == PREC_BF16X2;
+    constexpr int ROWS = 16 * RB;
+    constexpr int WG = 64 * NW;
+    constexpr int KC = 256;                   // contraction indices per chunk: 4 per lane
+    constexpr int LD = KC + 4;                // LDS row stride in floats (rows 4 banks apart)
+    constexpr int KS = KC / 4 / NW;           // k-steps of 4 per wave per chunk
+    constexpr int CA = ROWS / NW;             // A columns a wave loads per chunk
+    constexpr int CD = (P + NW - 1) / NW;     // D agent rows a wave loads per chunk
+    constexpr int ASZ = ROWS * LD, DSZ = 16 * LD;
+    static_assert(KS >= 1 && CA >= 1 && ROWS % NW == 0 && KC == 4 * 64, "tile shape");
+    using Tail = TailLds<P, ROWS, WG>;
+    static_assert(sizeof(Tail) <= sizeof(float) * 2 * (ASZ + DSZ), "the tail's LDS fits the staging buffers");
+    static_assert((NW / 2) * ROWS * P <= 2 * (ASZ + DSZ), "tree partials fit the staging buffers");
+    // A register slice of one column chunk: 4 FP32 values, or 4 hi and 4 lo BF16 values
+    struct ARegF { f4v v; };
+    struct ARegB { u2v h, l; };
+    using AR = typename std::conditional<BF, ARegB, ARegF>::type;
+    __shared__ __align__(16) float stage[2 * (ASZ + DSZ)];
+    __shared__ double adt[ROWS * P];          // AD rows of this workgroup
+    float* const Ash0 = stage;
+    float* const Dsh0 = stage + 2 * ASZ;
+
+    if (tile == 0 && threadIdx.x == 0 && a.st->dir_pending) a.st->dir_pending = 0;
+    if (!a.product_only && a.st->done != RUNNING) return;
+    const StepState0 s0 = read_state0(a.st);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = lane & 15, g = lane >> 4;
+    const int n = a.n;
+    const int i0 = tile * ROWS;
+    using TA = typename PT<PREC>::TA;
+    const float* __restrict__ V = static_cast<const float*>(a.V);
+    if (P < 16) {
+        for (int t = tid; t < 2 * (16 - P) * LD; t += WG) {
+            const int bf = t / ((16 - P) * LD), o = t - bf * ((16 - P) * LD);
+            Dsh0[bf * DSZ + P * LD + o] = 0.0f;
+        }
+    }
+    // this wave's share of a chunk: A columns wave + NW q (q < CA), lane l holding
+    // k = 4 l .. 4 l + 3 of the chunk; D agents wave + NW q (q < CD; a wave whose agent
+    // is >= P loads agent P - 1 and does not store it)
+    const TA* colp[CA];
+    const TA* colq[CA];
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+        const int i = min(i0 + wave + NW * q, n - 1);   // rows >= n compute a copy, never stored
+        colp[q] = static_cast<const TA*>(a.A) + (int64_t)i * a.lda;
+        colq[q] = BF ? static_cast<const TA*>(a.A_lo) + (int64_t)i * a.lda : colp[q];
+    }
+    const float* dcol[CD];
+#pragma unroll
+    for (int q = 0; q < CD; ++q) dcol[q] = V + (int64_t)min(wave + NW * q, P - 1) * a.n_pad;
+    auto load_full = [&](int ch, AR (&ra)[CA], f4v (&rd)[CD]) {
+        const int k = ch * KC + 4 * lane;
+#pragma unroll
+        for (int q = 0; q < CA; ++q) {
+            if constexpr (BF) {
+                ra[q].h = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(colp[q] + k));
+                ra[q].l = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(colq[q] + k));
+            } else {
+                ra[q].v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(colp[q] + k));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CD; ++q) rd[q] = *reinterpret_cast<const f4v*>(dcol[q] + k);
+    };
+    // the last, partial chunk: every element guarded by k < n
+    auto load_part = [&](int ch, AR (&ra)[CA], f4v (&rd)[CD]) {
+        const int k = ch * KC + 4 * lane;
+#pragma unroll
+        for (int q = 0; q < CA; ++q) {
+            if constexpr (BF) {
+                unsigned hw[2] = {0u, 0u}, lw[2] = {0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k + e < n) {
+                        hw[e >> 1] |= (unsigned)colp[q][k + e] << (16 * (e & 1));
+                        lw[e >> 1] |= (unsigned)colq[q][k + e] << (16 * (e & 1));
+                    }
+                ra[q].h = u2v{hw[0], hw[1]};
+                ra[q].l = u2v{lw[0], lw[1]};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ra[q].v[e] = k + e < n ? colp[q][k + e] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CD; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rd[q][e] = k + e < n ? dcol[q][k + e] : 0.0f;
+    };
+    auto store_chunk = [&](int bf, const AR (&ra)[CA], const f4v (&rd)[CD]) {
+#pragma unroll
+        for (int q = 0; q < CA; ++q) {
+            f4v v;
+            if constexpr (BF) {
+                // hi + lo is exact in FP32 (8 significant bits each, lo below hi)
+                v.x = __uint_as_float(ra[q].h.x << 16) + __uint_as_float(ra[q].l.x << 16);
+                v.y = __uint_as_float(ra[q].h.x & 0xffff0000u) + __uint_as_float(ra[q].l.x & 0xffff0000u);
+                v.z = __uint_as_float(ra[q].h.y << 16) + __uint_as_float(ra[q].l.y << 16);
+                v.w = __uint_as_float(ra[q].h.y & 0xffff0000u) + __uint_as_float(ra[q].l.y & 0xffff0000u);
+            } else {
+                v = ra[q].v;
+            }
+            *reinterpret_cast<f4v*>(&Ash0[bf * ASZ + (wave + NW * q) * LD + 4 * lane]) = v;
+        }
+#pragma unroll
+        for (int q = 0; q < CD; ++q) {
+            const int j = wave + NW * q;
+            if (j < P) *reinterpret_cast<f4v*>(&Dsh0[bf * DSZ + j * LD + 4 * lane]) = rd[q];
+        }
+    };
+    f4v acc[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[b] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    auto mul_chunk = [&](int bf) {
+        const float* As = Ash0 + bf * ASZ;
+        const float* Ds = Dsh0 + bf * DSZ;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int kk = 4 * (wave * KS + s) + g;
+            const float dv = Ds[r * LD + kk];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[(16 * b + r) * LD + kk], dv, acc[b], 0, 0, 0);
+        }
+    };
+
+    // the whole chunks, two in flight in registers (ring a0/d0, a1/d1) while the one
+    // in LDS is multiplied; the loads past the last chunk repeat it (never stored)
+    const int nf = n / KC;
+    if (nf > 0) {
+        AR a0[CA], a1[CA];
+        f4v d0[CD], d1[CD];
+        load_full(0, a0, d0);
+        load_full(min(1, nf - 1), a1, d1);
+        store_chunk(0, a0, d0);
+        __syncthreads();
+        for (int c = 0;; c += 2) {
+            load_full(min(c + 2, nf - 1), a0, d0);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(0);                            // chunk c
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 >= nf) break;
+            store_chunk(1, a1, d1);                  // chunk c + 1
+            __syncthreads();
+            load_full(min(c + 3, nf - 1), a1, d1);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(1);                            // chunk c + 1
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 2 >= nf) break;
+            store_chunk(0, a0, d0);                  // chunk c + 2
+            __syncthreads();
+        }
+    }
+    if (n % KC) {
+        AR ra[CA];
+        f4v rd[CD];
+        load_part(nf, ra, rd);
+        __syncthreads();                             // every wave is done with both buffers
+        store_chunk(0, ra, rd);
+        __syncthreads();
+        mul_chunk(0);
+    }
+    __syncthreads();
+
+    // ---- the waves' partial tiles, added by a fixed tree in the (now free) staging
+    // buffers; lane (c, g) holds rows 4 g + v of each row block, agent c
+    float* part = stage;
+    const bool dl = r < P;
+#pragma unroll
+    for (int h = NW / 2; h >= 1; h >>= 1) {
+        if (wave >= h && wave < 2 * h && dl) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) part[((wave - h) * ROWS + 16 * b + 4 * g + v) * P + r] = acc[b][v];
+        }
+        __syncthreads();
+        if (wave < h && dl) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[b][v] += part[(wave * ROWS + 16 * b + 4 * g + v) * P + r];
+        }
+        __syncthreads();
+    }
+    if (wave == 0 && dl) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * b + 4 * g + v;
+                adt[row * P + r] = (i0 + row < n) ? double(acc[b][v]) : 0.0;   // rows >= n hold copies
+            }
+    }
+    __syncthreads();
+    // AD rows to memory (FP32), each agent's ROWS rows contiguous
+    for (int t = tid; t < ROWS * P; t += WG) {
+        const int j = t / ROWS, row = t - (t / ROWS) * ROWS;
+        if (i0 + row < n) static_cast<float*>(a.AD)[(int64_t)j * a.n_pad + i0 + row] = float(adt[row * P + j]);
+    }
+    if (a.product_only) return;
+    ad_tail<PREC, P, ROWS, WG, true>(a, tile, ntiles, adt, s0, DRval{0.0, 0.0, false},
+                                     *reinterpret_cast<Tail*>(stage));
+}
+
+template <int PREC, int P, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ad_mma32(AdArgs a) {
+    ad_tile_mma32<PREC, P, RB, NW>(a, blockIdx.x, gridDim.x);
+}
+
+template <int PREC, int P, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ad_mma32_batch(const AdArgs* __restrict__ sys,
+                                                             const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const AdArgs a = sys[it.x];
+    ad_tile_mma32<PREC, P, RB, NW>(a, it.y, (a.n + 16 * RB - 1) / (16 * RB));
+}
+
 // -------------------------------------------- cross-lane sums of FP64 values (gfx950)
 //
 // The same reduce-scatter as wave_fold, for doubles, with VALU lane exchanges only:
@@ -2157,12 +2398,14 @@ inline hipError_t launch_ad_batch_t(const AdArgs* sys, const int4* items, int ni
 // or 32 rows per workgroup (cw * nw) and nw waves splitting the contraction: at
 // P = 16 every shape with cw * nw >= 16, (4, 4), (2, 8), (4, 8), (1, 16), (2, 16);
 // at P = 8 the shapes with 4 columns per wave, which the vector tile does not run
-// there, (4, 4) and (4, 8).
+// there, (4, 4) and (4, 8).  FP32 and BF16x2 at P = 16 have the same shapes on the
+// FP32-operand matrix-core tile (ad_tile_mma32).
 __host__ __device__ constexpr bool ad_cw4_fits(int prec, int P) {
     return P < 16 && (prec != PREC_F64 || P <= 4);
 }
 __host__ __device__ constexpr bool ad_has_mfma(int prec, int P) {
-    return prec == PREC_F64 && (P == 32 || P == 16 || P == 8);
+    return (prec == PREC_F64 && (P == 32 || P == 16 || P == 8)) ||
+           ((prec == PREC_F32 || prec == PREC_BF16X2) && P == 16);
 }
 __host__ __device__ constexpr int ad_nw_fit(int prec, int P, int nw) {
     return (P >= 16 && !ad_has_mfma(prec, P)) ? 4 : (nw >= 16 ? 16 : (nw >= 8 ? 8 : 4));
@@ -2182,31 +2425,32 @@ __host__ __device__ constexpr int ad_cw_fit(int prec, int P, int cw, int nw) {
     return cw >= 4 ? (ad_cw4_fits(prec, P) ? 4 : 2) : (cw >= 2 ? 2 : 1);
 }
 
-template <int P, int RB, int NW>
+// FP64: k_ad_mfma (FP64 operands); FP32 and BF16x2: k_ad_mma32 (FP32 operands)
+template <int PREC, int P, int RB, int NW>
 inline hipError_t launch_ad_mfma_t(const AdArgs* one, const AdArgs* sys, const int4* items, int nitems,
                                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (!one) {
-        hipLaunchKernelGGL((k_ad_mfma_batch<P, RB, NW>), dim3(nitems), dim3(64 * NW), 0, s, sys, items);
-        return hipGetLastError();
-    }
-    const dim3 grid((one->n + 16 * RB - 1) / (16 * RB));
-    if (e0) {
-        hipExtLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, e0, e1, 0, *one);
+    const dim3 grid = one ? dim3((one->n + 16 * RB - 1) / (16 * RB)) : dim3(nitems);
+    if constexpr (PREC == PREC_F64) {
+        if (!one) hipLaunchKernelGGL((k_ad_mfma_batch<P, RB, NW>), grid, dim3(64 * NW), 0, s, sys, items);
+        else if (e0) hipExtLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, e0, e1, 0, *one);
+        else hipLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, *one);
     } else {
-        hipLaunchKernelGGL((k_ad_mfma<P, RB, NW>), grid, dim3(64 * NW), 0, s, *one);
+        if (!one) hipLaunchKernelGGL((k_ad_mma32_batch<PREC, P, RB, NW>), grid, dim3(64 * NW), 0, s, sys, items);
+        else if (e0) hipExtLaunchKernelGGL((k_ad_mma32<PREC, P, RB, NW>), grid, dim3(64 * NW), 0, s, e0, e1, 0, *one);
+        else hipLaunchKernelGGL((k_ad_mma32<PREC, P, RB, NW>), grid, dim3(64 * NW), 0, s, *one);
     }
     return hipGetLastError();
 }
 
 // rows: 16 or 32 per workgroup; nw: 4, 8 or 16 waves (fitted shapes only)
-template <int P>
+template <int PREC, int P>
 inline hipError_t launch_ad_mfma(int rows, int nw, const AdArgs* one, const AdArgs* sys, const int4* items,
                                  int nitems, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (rows == 16 && nw == 4) return launch_ad_mfma_t<P, 1, 4>(one, sys, items, nitems, s, e0, e1);
-    if (rows == 16 && nw == 8) return launch_ad_mfma_t<P, 1, 8>(one, sys, items, nitems, s, e0, e1);
-    if (rows == 32 && nw == 8) return launch_ad_mfma_t<P, 2, 8>(one, sys, items, nitems, s, e0, e1);
-    if (rows == 16 && nw == 16) return launch_ad_mfma_t<P, 1, 16>(one, sys, items, nitems, s, e0, e1);
-    if (rows == 32 && nw == 16) return launch_ad_mfma_t<P, 2, 16>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 16 && nw == 4) return launch_ad_mfma_t<PREC, P, 1, 4>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 16 && nw == 8) return launch_ad_mfma_t<PREC, P, 1, 8>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 32 && nw == 8) return launch_ad_mfma_t<PREC, P, 2, 8>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 16 && nw == 16) return launch_ad_mfma_t<PREC, P, 1, 16>(one, sys, items, nitems, s, e0, e1);
+    if (rows == 32 && nw == 16) return launch_ad_mfma_t<PREC, P, 2, 16>(one, sys, items, nitems, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
@@ -2232,12 +2476,12 @@ inline hipError_t launch_ad_pc(int cw, int nw, const AdArgs* one, const AdArgs* 
             return hipErrorInvalidValue;
         } else {
             const int w = ad_nw_fit(PREC, P, nw), c = ad_cw_fit(PREC, P, cw, nw);
-            return launch_ad_mfma<P>(c * w, w, one, sys, items, nitems, s, e0, e1);
+            return launch_ad_mfma<PREC, P>(c * w, w, one, sys, items, nitems, s, e0, e1);
         }
     }
     if constexpr (ad_has_mfma(PREC, P)) {
         const int w = ad_nw_fit(PREC, P, nw), c = ad_cw_fit(PREC, P, cw, nw);
-        if (P == 16 ? c * w >= 16 : c == 4) return launch_ad_mfma<P>(c * w, w, one, sys, items, nitems, s, e0, e1);
+        if (P == 16 ? c * w >= 16 : c == 4) return launch_ad_mfma<PREC, P>(c * w, w, one, sys, items, nitems, s, e0, e1);
     }
     constexpr int W4 = ad_cw4_fits(PREC, P) ? 4 : 2;
     if (cw >= 4) return launch_ad_w<PREC, P, W4>(nw, one, sys, items, nitems, s, e0, e1);

@@ -2,8 +2,9 @@
 // agent count and system size.  Written by `python -m paper_1204_0069_amd.tune`
 // from timings of every candidate shape on the GPU; the first row whose (prec, P)
 // match and whose n_max >= n applies, and a size no row covers uses 2 and 4.
-// Tuned on: AMD Instinct MI355X (timings of tune_ad_widths_mi355x.txt; FP64 P = 16 and
-// P = 32: the matrix-core shapes of mfma_ad_tile_shapes_fp64.md), 2026-12-03.
+// Tuned on: AMD Instinct MI355X (timings of tune_ad_widths_mi355x.txt, FP32 and BF16x2
+// at P = 16 with the matrix-core shapes; FP64 P = 16 and P = 32: the matrix-core shapes
+// of mfma_ad_tile_shapes_fp64.md), 2026-12-03.
 #pragma once
 
 namespace ccg {
@@ -64,7 +65,9 @@ static const TuneRow kTuneTable[] = {
     {PREC_F32, 8, 6144, 2, 4},
     {PREC_F32, 8, 12288, 2, 8},
     {PREC_F32, 8, 1073741824, 4, 8},
-    {PREC_F32, 16, 1073741824, 2, 4},
+    {PREC_F32, 16, 6144, 2, 8},
+    {PREC_F32, 16, 24576, 2, 16},
+    {PREC_F32, 16, 1073741824, 4, 8},
     {PREC_BF16X2, 1, 192, 1, 4},
     {PREC_BF16X2, 1, 384, 2, 4},
     {PREC_BF16X2, 1, 768, 4, 4},
@@ -82,7 +85,8 @@ static const TuneRow kTuneTable[] = {
     {PREC_BF16X2, 8, 768, 1, 4},
     {PREC_BF16X2, 8, 6144, 2, 4},
     {PREC_BF16X2, 8, 1073741824, 2, 16},
-    {PREC_BF16X2, 16, 1073741824, 2, 4},
+    {PREC_BF16X2, 16, 12288, 2, 8},
+    {PREC_BF16X2, 16, 1073741824, 2, 16},
 };
 
 }  // namespace ccg

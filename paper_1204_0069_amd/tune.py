@@ -45,8 +45,9 @@ def fits4(prec: str, P: int) -> bool:
 WIDE_P = (8,)
 
 
-# Shapes that run the FP64 matrix-core tile (ad_has_mfma, ad_cw_fit): 16 or 32 rows
-# per workgroup (cw * nw), nw waves splitting the contraction.
+# Shapes that run the matrix-core tiles (ad_has_mfma, ad_cw_fit): 16 or 32 rows per
+# workgroup (cw * nw), nw waves splitting the contraction.  FP64 at P = 8, 16 and 32;
+# FP32 and BF16x2 (FP32 operands) at P = 16.
 MFMA_SHAPES = {8: ((4, 4), (4, 8)), 16: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16)),
                32: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16))}
 
@@ -54,7 +55,7 @@ MFMA_SHAPES = {8: ((4, 4), (4, 8)), 16: ((4, 4), (2, 8), (4, 8), (1, 16), (2, 16
 def shapes(prec: str, P: int):
     """Candidate (columns per wave, waves per workgroup), as the library runs them
     (ad_cw_fit, ad_nw_fit): vector tiles with 4 columns where they fit and more than
-    4 waves at WIDE_P, then the FP64 matrix-core shapes."""
+    4 waves at WIDE_P, then the matrix-core shapes."""
     if P == 32:                # the matrix-core tile only (FP64)
         return list(MFMA_SHAPES[32]) if prec == "fp64" else []
     ws = [w for w in WIDTHS if w < 4 or fits4(prec, P)]
@@ -62,7 +63,7 @@ def shapes(prec: str, P: int):
         ws = [w for w in ws if w <= 2]
     nws = WAVES if P in WIDE_P else (4,)
     out = [(w, nw) for nw in nws for w in ws]
-    if prec == "fp64":
+    if prec == "fp64" or P == 16:
         out += [sh for sh in MFMA_SHAPES.get(P, ()) if sh not in out]
     return out
 

@@ -231,3 +231,28 @@ def test_full_size_n32768_refined_solve(gpu_ctx, c3_system, prec):
     t_host = b.cpu().numpy()[rows] - Ar @ xj
     scale = np.abs(b.cpu().numpy()[rows]) + np.abs(Ar) @ np.abs(xj)
     assert np.all(np.abs(t_host - T[rows, j].cpu().numpy()) <= 2.0 * n * 1.11e-16 * scale)
+
+
+# ------------- the FP32-operand matrix-core A.D tile (FP32 and BF16x2 A, P = 16)
+
+# (cw, nw) shapes that run it: 16 or 32 AD rows per workgroup, 4 to 16 waves
+MMA32_SHAPES = [(4, 4), (2, 8), (4, 8), (1, 16), (2, 16)]
+# n below one chunk of 256 contraction indices (the guarded partial chunk only), several
+# chunks with a ragged last one, p padded to 16
+
+
+@pytest.mark.parametrize("shape", MMA32_SHAPES)
+@pytest.mark.parametrize("n,p", [(200, 12), (1000, 16), (2085, 9)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_matrix_core_ad_refined_solve(gpu_ctx, prec, n, p, shape):
+    """Every matrix-core shape meets the explicit FP64 residual and the distance to the
+    direct solution, and needs about as many block steps as the vector tile (2, 4): a
+    wrong A.D product would cost the refinement loop far more steps or not converge."""
+    cw, nw = shape
+    print(f"case mma32 {prec} n={n} p={p} shape={shape}", flush=True)
+    A, b, X0 = ci.system(n, p, 1e2, seed=505)
+    X, info = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec=prec, ad_cw=cw, ad_nw=nw)
+    _check_refined(A, b, X, info, 1e-10, 1e2)
+    Xv, iv = gpu_ctx.solve(_t(A), _t(b), _t(X0), 1e-10, 100000, prec=prec, ad_cw=2, ad_nw=4)
+    assert iv["status"] == 0
+    assert info["iters"] <= 1.25 * iv["iters"] + 8, (info["iters"], iv["iters"])

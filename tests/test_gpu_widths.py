@@ -60,8 +60,8 @@ def _system(n, p, kappa, seed):
 
 
 FP64_CASES = _cases("PREC_F64", (1, 4, 8, 16), 8192)
-FP32_CASES = _cases("PREC_F32", (2, 8), 8192)
-LOW_CASES = [("fp32",) + c for c in FP32_CASES] + [("bf16x2",) + c for c in _cases("PREC_BF16X2", (4, 8), 8192)]
+FP32_CASES = _cases("PREC_F32", (2, 8, 16), 8192)
+LOW_CASES = [("fp32",) + c for c in FP32_CASES] + [("bf16x2",) + c for c in _cases("PREC_BF16X2", (4, 8, 16), 8192)]
 
 
 @pytest.mark.parametrize("P,n,w,nw", FP64_CASES)

@@ -39,17 +39,17 @@ def test_candidate_shapes_follow_the_register_rules():
     assert (4, 16) in tune.shapes("fp32", 8)
     # FP64, P = 8: 4 columns per wave only as the matrix-core tile
     assert [sh for sh in tune.shapes("fp64", 8) if sh[0] == 4] == [(4, 4), (4, 8)]
-    # P = 16: the vector tile at most 2 columns and 4 waves; FP64 adds the matrix cores
-    for prec in ("fp32", "bf16x2"):
-        assert all(nw == 4 and w <= 2 for w, nw in tune.shapes(prec, 16))
-    assert tune.shapes("fp64", 16) == [(1, 4), (2, 4)] + list(tune.MFMA_SHAPES[16])
+    # P = 16: the vector tile at most 2 columns and 4 waves, then the matrix cores
+    # (FP64 operands for FP64, FP32 operands for FP32 and BF16x2)
+    for prec in ("fp64", "fp32", "bf16x2"):
+        assert tune.shapes(prec, 16) == [(1, 4), (2, 4)] + list(tune.MFMA_SHAPES[16])
     assert tune.DEFAULT in tune.shapes("bf16x2", 1)
     # P = 32: FP64 on the matrix cores only
     assert tune.shapes("fp64", 32) == list(tune.MFMA_SHAPES[32]) and tune.shapes("fp32", 32) == []
     # wider vector workgroups only where the engine was measured not to lose with them
     for prec in ("fp64", "fp32", "bf16x2"):
         for P in (1, 2, 4, 8, 16):
-            mfma = tune.MFMA_SHAPES.get(P, ()) if prec == "fp64" else ()
+            mfma = tune.MFMA_SHAPES.get(P, ()) if prec == "fp64" or P == 16 else ()
             vec = [sh for sh in tune.shapes(prec, P) if sh not in mfma]
             assert any(nw > 4 for _, nw in vec) == (P in tune.WIDE_P)
 
@@ -65,9 +65,10 @@ def test_merge_and_limits():
     # FP64, P = 8: 4 columns per wave only as the matrix-core tile, which wins from
     # 8192 on at 8 waves
     assert _rows_for(rows, "PREC_F64", 8) == [(768, 1, 4), (6144, 2, 4), (1 << 30, 4, 8)]
-    # the vector tile at P = 16 never times width 4 or more than 4 waves; no size
-    # below P is timed
-    assert not any(P == 16 and prec != "fp64" and (w == 4 or nw != 4) for prec, P, _, w, nw in ctx.calls)
+    # at P = 16 the shapes timed are the vector tile's (at most 2 columns, 4 waves)
+    # and the matrix cores'; no size below P is timed
+    assert all((w <= 2 and nw == 4) or (w, nw) in tune.MFMA_SHAPES[16]
+               for prec, P, _, w, nw in ctx.calls if P == 16)
     assert all(P <= n for _, P, n, _, _ in ctx.calls)
 
 
