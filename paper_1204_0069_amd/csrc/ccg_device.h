@@ -20,19 +20,14 @@ constexpr int kGroup = 32;      // workgroups per first-level reduction group
 
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X2 = 2 };
 
-// Row tiling of the update and direction launches (the same for both): one workgroup per block of
-// kWG / P rows (one element per thread), or, where both run on the FP64 matrix cores
-// (P = 32, and P = 16 in FP64), per block of kUpdWideRows rows (4 waves of 16).
+// Row tiling of the update and direction launches (the same for both): one workgroup
+// per block of kWG / P rows (one element per thread), or from P = 16, where both run on
+// the FP64 matrix cores, per block of kUpdWideRows rows (4 waves of 16).
 constexpr int kUpdWideRows = 64;
 static_assert(kRowAlign % kUpdWideRows == 0, "wide update tiles must divide the row padding");
-__host__ __device__ constexpr bool upd_mma(int P, int prec) { return P >= 32 || (P == 16 && prec == PREC_F64); }
-__host__ __device__ inline int upd_blocks(int n_pad, int P, int prec) {
-    return upd_mma(P, prec) ? n_pad / kUpdWideRows : n_pad / (256 / P);
-}
-// The most update workgroups any precision launches at this P (the size of the
-// reduction scratch, which the FP64 and FP32 launches of one solve share).
-__host__ __device__ inline int upd_blocks_max(int n_pad, int P) {
-    return P >= 32 ? n_pad / kUpdWideRows : n_pad / (256 / P);
+__host__ __device__ constexpr bool upd_mma(int P) { return P >= 16; }
+__host__ __device__ inline int upd_blocks(int n_pad, int P) {
+    return upd_mma(P) ? n_pad / kUpdWideRows : n_pad / (256 / P);
 }
 // Workgroups per first-level group of the update's product reduction: at P = 32 the
 // 1056 values per workgroup make a group of 16 one round of loads for its summer.

@@ -861,14 +861,14 @@ class Engine {
                         r.up_off = st.size();
                         for (auto& sy : live_) {
                             if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
-                            const int t = upd_blocks(sy.w.n_pad, P, prec);
+                            const int t = upd_blocks(sy.w.n_pad, P);
                             for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
                         }
                         r.up_n = st.size() - r.up_off;
                         r.dir_off = st.size();
                         for (auto& sy : live_) {
                             if (sy.prec != prec || sy.P != P || sy.cw_step != cw || sy.nw_step != nw) continue;
-                            const int t = upd_blocks(sy.w.n_pad, P, prec);
+                            const int t = upd_blocks(sy.w.n_pad, P);
                             for (int i = 0; i < t; ++i) st.push_back(int4{sy.slot, i, 0, 0});
                         }
                         r.dir_n = st.size() - r.dir_off;

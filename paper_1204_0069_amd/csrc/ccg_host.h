@@ -218,7 +218,7 @@ inline size_t carve(Workspace& w, char* base, int n, int n_pad, int P, bool sym 
     w.Dl = cv.take<float>(blk);
     w.ADl = cv.take<float>(blk);
     w.red_ad = carve_red(cv, ad_workgroups(n_pad), P * (P + 1) / 2 + P * P);
-    w.red_up = carve_red(cv, upd_blocks_max(n_pad, P), P * P + P, upd_group(P));
+    w.red_up = carve_red(cv, upd_blocks(n_pad, P), P * P + P, upd_group(P));
     w.red_res = carve_red(cv, row_workgroups(n_pad, P), P * P + 1);
     w.st = cv.take<DevState>(1);
     if (sym && P <= kSymMaxP && n_pad >= kSymMinN) {

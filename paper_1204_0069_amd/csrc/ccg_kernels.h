@@ -1848,11 +1848,13 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // each group of kGroup blocks adds up its group's shares in block order.  The
 // direction launch adds up the group sums.
 //
-// At P = 32, and at P = 16 in FP64, both launches run on the matrix cores instead, 64
-// rows per workgroup (upd_tile_mma, dir_tile_mma): with one element per thread the
-// update's LDS traffic for the P-term row sums, not memory, set its time, and 64-row
-// blocks make 16 (P = 32) or 4 (P = 16) times fewer group shares of the P^2 + P
-// products for the direction launch to add up.
+// From P = 16 both launches run on the FP64 matrix cores instead, 64 rows per
+// workgroup (upd_tile_mma, dir_tile_mma; the FP32 vectors of the low-precision modes
+// are converted on load and rounded on store, the arithmetic staying FP64 as in the
+// vector tiles): with one element per thread the update's LDS traffic for the P-term
+// row sums, not memory, set its time, and 64-row blocks make 16 (P = 32) or 4
+// (P = 16) times fewer group shares of the P^2 + P products for the direction launch
+// to add up.
 
 // v_mfma_f64_16x16x4f64 operand layouts, lane l = 16 g + r (r = l % 16, g = l / 16):
 // A (16 x 4): A(r, g); B (4 x 16): B(g, r); C (16 x 16): C(g + 4 v, r), v = 0..3.
@@ -1865,7 +1867,7 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // take the rows as the contraction index in 4 steps s: A = AD(i0 + 4s + g, 16 xb + r)
 // (AD loaded a second time, in the C layout) and B = R_new(i0 + 4s + g, 16 yb + r),
 // which is the update's output element v = s in place.
-template <int P>
+template <int PREC, int P>
 __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, const int ntiles) {
     static_assert(P % 16 == 0 && kUpdWideRows == 64 && kWG == 256, "4 waves of 16 rows, agent blocks of 16");
     constexpr int NB = P / 16;                  // agent blocks
@@ -1884,25 +1886,26 @@ __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, c
     if (tile == 0 && tid == 0) st->dir_pending = 1;
     const int64_t np = a.n_pad;
     const int64_t i0 = (int64_t)tile * kUpdWideRows + 16 * wave;
-    double* X = static_cast<double*>(a.X);
-    double* R = static_cast<double*>(a.R);
-    const double* D = static_cast<const double*>(a.D);
-    const double* AD = static_cast<const double*>(a.AD);
+    using TV = typename PT<PREC>::TV;        // vectors in FP64, or FP32 (arithmetic in FP64)
+    TV* X = static_cast<TV*>(a.X);
+    TV* R = static_cast<TV*>(a.R);
+    const TV* D = static_cast<const TV*>(a.D);
+    const TV* AD = static_cast<const TV*>(a.AD);
     double da[KK], aa[KK], al[KK][NB];
     d4v xc[NB], rc[NB], ac[NB];
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
-        da[kk] = D[(4 * kk + g) * np + i0 + r];
-        aa[kk] = AD[(4 * kk + g) * np + i0 + r];
+        da[kk] = double(D[(4 * kk + g) * np + i0 + r]);
+        aa[kk] = double(AD[(4 * kk + g) * np + i0 + r]);
     }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t o = (16 * cb + r) * np + i0 + g + 4 * v;
-            xc[cb][v] = X[o];
-            rc[cb][v] = R[o];
-            ac[cb][v] = AD[o];
+            xc[cb][v] = double(X[o]);
+            rc[cb][v] = double(R[o]);
+            ac[cb][v] = double(AD[o]);
         }
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk)
@@ -1920,8 +1923,9 @@ __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, c
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t o = (16 * cb + r) * np + i0 + g + 4 * v;
-            X[o] = xc[cb][v];
-            R[o] = rc[cb][v];
+            X[o] = TV(xc[cb][v]);
+            R[o] = TV(rc[cb][v]);
+            rc[cb][v] = double(TV(rc[cb][v]));   // the products take R_new as stored
         }
     d4v pg[NB][NB];
 #pragma unroll
@@ -1973,9 +1977,8 @@ __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, c
 
 template <int PREC, int P>
 __device__ __forceinline__ void upd_tile(const UpdArgs& a, const int tile, const int ntiles) {
-    if constexpr (upd_mma(P, PREC)) {
-        static_assert(PREC == PREC_F64, "the matrix-core update is FP64");
-        upd_tile_mma<P>(a, tile, ntiles);
+    if constexpr (upd_mma(P)) {
+        upd_tile_mma<PREC, P>(a, tile, ntiles);
         return;
     } else {
     using TV = typename PT<PREC>::TV;
@@ -2113,11 +2116,11 @@ __device__ __forceinline__ void sum_groups(const double* l2, const int ngrp, dou
     }
 }
 
-// P = 16 and 32 (FP64): the direction update on the matrix cores, 64 rows per workgroup, a
+// P = 16 and 32: the direction update on the FP64 matrix cores, 64 rows per workgroup, a
 // wave 16 of them: D_new = R_new + D beta as P / 4 products with A = D(i0 + r, 4 kk + g)
 // and B = beta(4 kk + g, 16 cb + r) accumulated onto C = R_new (layouts as in
 // upd_tile_mma).  Every workgroup adds up the group sums and solves beta itself.
-template <int P>
+template <int PREC, int P>
 __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, const int ngrp) {
     static_assert(P % 16 == 0 && kUpdWideRows == 64 && kWG == 256 && (P * P) % kWG == 0, "tile shape");
     constexpr int NB = P / 16, KK = P / 4;
@@ -2138,16 +2141,17 @@ __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, co
     // (loads only before the flag is tested: nothing is written unless it is set)
     const int pending = st->dir_pending;
     const unsigned mask = st->mask;
-    double* D = static_cast<double*>(a.D);
-    const double* R = static_cast<const double*>(a.R);
+    using TV = typename PT<PREC>::TV;        // vectors in FP64, or FP32 (arithmetic in FP64)
+    TV* D = static_cast<TV*>(a.D);
+    const TV* R = static_cast<const TV*>(a.R);
     double da[KK], lv[NL], tv[NH];
     d4v dc[NB];
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) da[kk] = D[(4 * kk + g) * np + i0 + r];
+    for (int kk = 0; kk < KK; ++kk) da[kk] = double(D[(4 * kk + g) * np + i0 + r]);
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dc[cb][v] = R[(16 * cb + r) * np + i0 + g + 4 * v];
+        for (int v = 0; v < 4; ++v) dc[cb][v] = double(R[(16 * cb + r) * np + i0 + g + 4 * v]);
 #pragma unroll
     for (int h = 0; h < NL; ++h) {
         const int t = tid + h * kWG;
@@ -2184,7 +2188,7 @@ __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, co
     for (int cb = 0; cb < NB; ++cb) {
         const bool on = (mask >> (16 * cb + r)) & 1u;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) D[(16 * cb + r) * np + i0 + g + 4 * v] = on ? dc[cb][v] : 0.0;
+        for (int v = 0; v < 4; ++v) D[(16 * cb + r) * np + i0 + g + 4 * v] = on ? TV(dc[cb][v]) : TV(0);
     }
     if (blk != 0 || wave != 0) return;
     dir_report<P>(st, tot, be, lred, mask, lane);
@@ -2192,9 +2196,8 @@ __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, co
 
 template <int PREC, int P>
 __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const int ngrp) {
-    if constexpr (upd_mma(P, PREC)) {
-        static_assert(PREC == PREC_F64, "the matrix-core update is FP64");
-        dir_tile_mma<P>(a, blk, ngrp);
+    if constexpr (upd_mma(P)) {
+        dir_tile_mma<PREC, P>(a, blk, ngrp);
         return;
     } else {
     using TV = typename PT<PREC>::TV;
@@ -2256,21 +2259,21 @@ __device__ __forceinline__ void dir_tile(const UpdArgs& a, const int blk, const 
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir(UpdArgs a) {
-    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P, PREC) + upd_group(P) - 1) / upd_group(P));
+    dir_tile<PREC, P>(a, blockIdx.x, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_upd_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    upd_tile<PREC, P>(a, it.y, upd_blocks(a.n_pad, P, PREC));
+    upd_tile<PREC, P>(a, it.y, upd_blocks(a.n_pad, P));
 }
 
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_dir_batch(const UpdArgs* __restrict__ sys, const int4* __restrict__ items) {
     const int4 it = items[blockIdx.x];
     const UpdArgs a = sys[it.x];
-    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P, PREC) + upd_group(P) - 1) / upd_group(P));
+    dir_tile<PREC, P>(a, it.y, (upd_blocks(a.n_pad, P) + upd_group(P) - 1) / upd_group(P));
 }
 
 // ============================================ k_res: T = B - Y, norms, restart

@@ -215,12 +215,12 @@ int ad_fit_nw(int prec, int P, int nw) { return ad_nw_fit(prec, P, nw); }
 
 template <int PREC, int P>
 static hipError_t launch_upd_t(const UpdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(upd_blocks(a.n_pad, P, PREC)), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_upd<PREC, P>), dim3(upd_blocks(a.n_pad, P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int PREC, int P>
 static hipError_t launch_dir_t(const UpdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(upd_blocks(a.n_pad, P, PREC)), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_dir<PREC, P>), dim3(upd_blocks(a.n_pad, P)), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 template <int P>
