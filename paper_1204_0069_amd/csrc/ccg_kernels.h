@@ -1862,7 +1862,8 @@ __global__ __launch_bounds__(kWG) void k_fin(SymArgs sa, AdArgs a) {
 // The update of one wave's 16 rows i0.. (agents in blocks of 16, cb):
 //   X_new(i0 + g + 4v, 16 cb + r) = X(...) + sum_k D(i0 + r', k) alpha(k, 16 cb + r)
 // as P / 4 products with A = D(i0 + r, 4 kk + g), B = alpha(4 kk + g, 16 cb + r)
-// accumulated onto C = X (and R with AD and -alpha).  The products of the new residual,
+// accumulated from zero and then added to X (and AD alpha taken from R), whose C-layout
+// elements the lane loads.  The products of the new residual,
 //   (AD)^T R_new (x, y) += sum over the 16 rows of AD(i, x) R_new(i, y),
 // take the rows as the contraction index in 4 steps s: A = AD(i0 + 4s + g, 16 xb + r)
 // (AD loaded a second time, in the C layout) and B = R_new(i0 + 4s + g, 16 yb + r),
@@ -1911,21 +1912,30 @@ __device__ __forceinline__ void upd_tile_mma(const UpdArgs& a, const int tile, c
     for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) al[kk][cb] = st->alpha[(4 * kk + g) * kMaxP + 16 * cb + r];
+    // D alpha and AD alpha summed from zero, then added to X and R with one rounding
+    // each: accumulating the partial products onto X itself would round at the scale
+    // of X (far larger than its update late in a solve) once per k-step
+    d4v sx[NB], sr[NB];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb)
+    for (int cb = 0; cb < NB; ++cb) {
+        sx[cb] = d4v{0.0, 0.0, 0.0, 0.0};
+        sr[cb] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
-            xc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], al[kk][cb], xc[cb], 0, 0, 0);
-            rc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[kk], -al[kk][cb], rc[cb], 0, 0, 0);
+            sx[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], al[kk][cb], sx[cb], 0, 0, 0);
+            sr[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[kk], al[kk][cb], sr[cb], 0, 0, 0);
         }
+    }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t o = (16 * cb + r) * np + i0 + g + 4 * v;
-            X[o] = TV(xc[cb][v]);
-            R[o] = TV(rc[cb][v]);
-            rc[cb][v] = double(TV(rc[cb][v]));   // the products take R_new as stored
+            const TV xn = TV(xc[cb][v] + sx[cb][v]);
+            const TV rn = TV(rc[cb][v] - sr[cb][v]);
+            X[o] = xn;
+            R[o] = rn;
+            rc[cb][v] = double(rn);              // the products take R_new as stored
         }
     d4v pg[NB][NB];
 #pragma unroll
@@ -2118,8 +2128,8 @@ __device__ __forceinline__ void sum_groups(const double* l2, const int ngrp, dou
 
 // P = 16 and 32: the direction update on the FP64 matrix cores, 64 rows per workgroup, a
 // wave 16 of them: D_new = R_new + D beta as P / 4 products with A = D(i0 + r, 4 kk + g)
-// and B = beta(4 kk + g, 16 cb + r) accumulated onto C = R_new (layouts as in
-// upd_tile_mma).  Every workgroup adds up the group sums and solves beta itself.
+// and B = beta(4 kk + g, 16 cb + r) accumulated from zero and added to R_new (layouts as
+// in upd_tile_mma).  Every workgroup adds up the group sums and solves beta itself.
 template <int PREC, int P>
 __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, const int ngrp) {
     static_assert(P % 16 == 0 && kUpdWideRows == 64 && kWG == 256 && (P * P) % kWG == 0, "tile shape");
@@ -2179,16 +2189,16 @@ __device__ __forceinline__ void dir_tile_mma(const UpdArgs& a, const int blk, co
         for (int x = 0; x < P; ++x) be[x * P + c] = w[x];
     }
     __syncthreads();
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk)
-            dc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], be[(4 * kk + g) * P + 16 * cb + r], dc[cb], 0, 0, 0);
+    // D beta summed from zero, then added to R_new with one rounding
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
+        d4v sd = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+            sd = __builtin_amdgcn_mfma_f64_16x16x4f64(da[kk], be[(4 * kk + g) * P + 16 * cb + r], sd, 0, 0, 0);
         const bool on = (mask >> (16 * cb + r)) & 1u;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) D[(16 * cb + r) * np + i0 + g + 4 * v] = on ? TV(dc[cb][v]) : TV(0);
+        for (int v = 0; v < 4; ++v) D[(16 * cb + r) * np + i0 + g + 4 * v] = on ? TV(dc[cb][v] + sd[v]) : TV(0);
     }
     if (blk != 0 || wave != 0) return;
     dir_report<P>(st, tot, be, lred, mask, lane);
