@@ -668,6 +668,29 @@ def test_p32_solve_at_benchmark_tolerance(gpu_ctx):
     assert info2["iters"] == k and torch.equal(X2, X)
 
 
+def test_long_solves_on_the_matrix_core_update_keep_the_recurrence(gpu_ctx):
+    """A long solve at kappa = 1e6 (n = 8192, log-uniform spectrum, the agent sweep's
+    system) on the matrix-core update launches (P = 16 and 32) keeps the recurrence
+    residual close enough to b - AX that the explicit confirmation restarts the block
+    only now and then: p = 16 takes at most 3 x the block steps of p = 8 (the vector
+    launches) from the same starting block, and p = 32 fewer than p = 8.  An update that
+    accumulated its products onto X itself, rounding at the scale of X once per k-step,
+    took 7.3 x (84329 steps, 158 restarts)."""
+    n, seed = 8192, ci.BASE_SEED
+    print("case long solve n=8192 kappa=1e6 p=8,16,32", flush=True)
+    A = ci.spd_spectrum(n, 1e6, ci.item_seed("A", seed, base=n), device="cuda:0")
+    b = torch.as_tensor(ci.normal_block(n, 0, ci.item_seed("b", seed, base=n)), device="cuda:0")
+    Xall = torch.as_tensor(ci.normal_block(n, 32, ci.item_seed("X0", seed, base=n)), device="cuda:0")
+    steps = {}
+    for p in (8, 16, 32):
+        _, info = gpu_ctx.solve(A, b, Xall[:, :p].contiguous(), 1e-10, 200000)
+        assert info["status"] == 0, info
+        steps[p] = info["iters"]
+    print(f"block steps {steps}", flush=True)
+    assert steps[16] <= 3 * steps[8], steps
+    assert steps[32] < steps[8], steps
+
+
 def test_p32_limits(gpu_ctx):
     """p up to 32 in FP64 single solves; the low-precision modes and the batched
     engine take p <= 16, and p = 33 is refused."""
