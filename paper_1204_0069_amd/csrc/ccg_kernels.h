@@ -657,10 +657,13 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
     // takes its pivots in non-increasing order (each elimination only lowers the
     // remaining diagonal, and the largest is taken), and its last pivot is
     // 1 / (G^-1)_ll of the scaled G for the index l taken last, so every pivot is at
-    // least 1 / max_l (scaled G^-1)_ll.  When that exceeds 2 tau (a margin for the
-    // rounding of the estimate) the rank step keeps every agent, and the factor of G in
-    // agent order is the one the slow path below would form after running the greedy
-    // rule itself.  (scaled G^-1)_ll = G_ll ||L^-1 e_l||^2: lane l solves L y = e_l.
+    // least 1 / max_l (scaled G^-1)_ll, which is at least the determinant of the scaled
+    // G.  When the determinant exceeds 2 tau (a margin for rounding), or else that bound
+    // does, the rank step keeps every agent, and the factor of G in agent order is the
+    // one the slow path below would form after running the greedy rule itself.  The
+    // determinant is the product of the natural-order pivots; the bound is formed only
+    // when the determinant test fails: (scaled G^-1)_ll = G_ll ||L^-1 e_l||^2, lane l
+    // solving L y = e_l.
     if (wave == 0) {
         double g[P];
         row_load<P>(g, Gs, P, mask, true, lane);
@@ -673,15 +676,23 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
                 if (b == lane) dg = g[b];
             }
             rinv[lane] = 1.0 / dg;
+            lred[lane] = (ok && ((mask >> lane) & 1u)) ? (dg * dg) / Gs[lane * P + lane] : 1.0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane < P) {
-            double q = INFINITY;
-            if (ok) {
+        double det = ok ? 1.0 : 0.0;                 // the same reads and value in every lane
+#pragma unroll
+        for (int jj = 0; jj < P; ++jj) det *= lred[jj];
+        const bool by_det = ok && det > 2.0 * tau0;
+        bool keep = by_det;
+        if (ok && !by_det) {                         // (uniform)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (lane < P) {
                 double y[P];
-                q = 0.0;
+                double q = 0.0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     double t = (k == lane) ? 1.0 : 0.0;
@@ -691,19 +702,17 @@ __device__ __forceinline__ bool step_alpha(const double* gtot, const StepState0&
                     q = fma(y[k], y[k], q);
                 }
                 if ((mask >> lane) & 1u) q *= Gs[lane * P + lane];
+                lred[lane] = q;
             }
-            lred[lane] = q;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             double mq = 0.0;
 #pragma unroll
             for (int jj = 0; jj < P; ++jj) mq = (lred[jj] > mq || lred[jj] != lred[jj]) ? lred[jj] : mq;
-            // (no factor: q = INFINITY; a NaN is kept: either way the test fails)
-            ish[200] = (ok && mq * (2.0 * tau0) < 1.0) ? 1 : 0;
+            keep = mq * (2.0 * tau0) < 1.0;          // (a NaN is kept, and fails)
         }
+        if (lane == 0) ish[200] = keep ? 1 : 0;
     }
     __syncthreads();
     const bool fast = ish[200] != 0;

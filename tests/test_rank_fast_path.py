@@ -6,8 +6,10 @@ Cholesky factorisation takes its pivots in non-increasing order (an elimination 
 lowers the remaining diagonal, and the largest is taken next), and its last pivot is
 the Schur complement of the index taken last, 1 / (G^-1)_ll.  Every pivot is therefore
 at least 1 / max_l (G^-1)_ll, and when that bound exceeds 2 tau the greedy rule keeps
-every agent.  The kernel forms the bound from the natural-order Cholesky factor
-(lane l solves L y = e_l, (G^-1)_ll = G_ll ||y||^2 for the unscaled G).  Here a plain
+every agent.  The kernel first tests the determinant of the scaled G (a weaker bound:
+each 1 / (G^-1)_ll is at least the determinant) and, when that fails, forms the bound
+from the natural-order Cholesky factor (lane l solves L y = e_l, (G^-1)_ll = G_ll ||y||^2
+for the unscaled G).  Here a plain
 greedy factorisation, written from the rule (largest remaining pivot first, ties to
 the lowest index, stop at a pivot <= tau), checks both facts and the decision on
 random and nearly singular matrices around tau = 1e-14."""
