@@ -28,7 +28,7 @@ MIXED = [  # n, p, kappa, prec
     (64, 2, 1e2, "fp64"), (256, 3, 1e3, "fp64"), (777, 2, 1e2, "fp64"), (1000, 5, 1e3, "fp64"),
     (129, 4, 10.0, "fp64"), (640, 16, 1e2, "fp64"), (300, 1, 1e3, "fp64"), (2085, 8, 1e4, "fp64"),
     (500, 4, 1e3, "fp32"), (96, 2, 1e2, "fp32"), (1100, 8, 1e3, "fp32"), (900, 12, 1e2, "fp32"),
-    (400, 3, 1e2, "bf16x2"), (700, 8, 1e3, "bf16x2"),
+    (400, 3, 1e2, "bf16x2"), (700, 8, 1e3, "bf16x2"), (600, 14, 1e2, "bf16x2"),
 ]
 
 
