@@ -1296,9 +1296,19 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
                                          *reinterpret_cast<Tail*>(stage));
 }
 
+// Tile of workgroup b of nb: the workgroups of a launch are handed to the 8 XCDs in
+// turn, and this order gives each XCD a contiguous run of tiles (when 8 divides nb).
+// Only the placement changes: every tile, and every reduction group of tiles, is the
+// same.  Measured on the FP64 matrix-core tile, 3-5 % faster at P = 16 (n = 4096 to
+// 32768) and level at P = 32; the vector tile at P = 8 and the FP32-operand tile at
+// n = 8192 ran slower with it and keep the launch order.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
 template <int P, int RB, int NW>
 __global__ __launch_bounds__(64 * NW) void k_ad_mfma(AdArgs a) {
-    ad_tile_mfma<P, RB, NW>(a, blockIdx.x, gridDim.x);
+    ad_tile_mfma<P, RB, NW>(a, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 template <int P, int RB, int NW>
