@@ -1300,8 +1300,8 @@ __device__ __forceinline__ void ad_tile_mfma(const AdArgs& a, const int tile, co
 // turn, and this order gives each XCD a contiguous run of tiles (when 8 divides nb).
 // Only the placement changes: every tile, and every reduction group of tiles, is the
 // same.  Measured on the FP64 matrix-core tile, 3-5 % faster at P = 16 (n = 4096 to
-// 32768) and level at P = 32; the vector tile at P = 8 and the FP32-operand tile at
-// n = 8192 ran slower with it and keep the launch order.
+// 32768) and level at P = 32 and at n = 1024-2048; the vector tile at P = 8 ran slower
+// with it and keeps the launch order.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
@@ -1546,9 +1546,12 @@ __device__ __forceinline__ void ad_tile_mma32(const AdArgs& a, const int tile, c
                                      *reinterpret_cast<Tail*>(stage));
 }
 
+// (the XCD-grouped order of xcd_tile for the 32-row shapes only: 1.7 % faster for FP32
+// at n = 8192 and 4 % for BF16x2 at n = 32768; with 16 rows it was 7.8 % slower for
+// BF16x2 at n = 8192)
 template <int PREC, int P, int RB, int NW>
 __global__ __launch_bounds__(64 * NW) void k_ad_mma32(AdArgs a) {
-    ad_tile_mma32<PREC, P, RB, NW>(a, blockIdx.x, gridDim.x);
+    ad_tile_mma32<PREC, P, RB, NW>(a, RB == 2 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x, gridDim.x);
 }
 
 template <int PREC, int P, int RB, int NW>
